@@ -1,0 +1,198 @@
+/*
+ * bfs.h -- C ABI of libbfs, a breadth-first-search library for one AMD
+ * Instinct MI355X (gfx950).
+ *
+ * The library computes what Figure 1 of Tithi, Fogel and Chowdhury,
+ * "An Optimal Level-synchronous Shared-memory Parallel BFS Algorithm"
+ * (S3BFS) returns -- the distance d[0:n-1] of every vertex from a source --
+ * with the paper's per-level steps (degree gather, prefix sum, splitting the
+ * level's edges into equal shares, scanning, owner de-duplication and
+ * linearisation of the next frontier) run as HIP kernels.  It adds a
+ * deterministic parent (the smallest-id neighbour one level closer), batched
+ * multi-source search and multi-root search of disjoint graphs.
+ *
+ * Conventions for every entry point:
+ *   - The return value is a bfs_status_t: BFS_OK (0) or a negative error.
+ *     No C++ exception crosses this boundary.  bfs_last_error() gives a
+ *     human-readable message for the last failure on the calling thread.
+ *   - "device" pointers are HIP device allocations (or host-pinned memory
+ *     mapped for the device); "host" pointers are ordinary host memory.
+ *   - Runs are asynchronous on the given HIP stream (a hipStream_t passed
+ *     as void*; NULL is the null stream) unless stated otherwise.  A fault
+ *     that happens on the device is reported by the next call on the same
+ *     workspace (bfs_sync, bfs_last_stats or another run).
+ *   - Graphs must be symmetric (undirected), with rows sorted ascending and
+ *     0 <= cols[i] < n; n and m must fit in int32.  Self-loops and duplicate
+ *     entries do not change the result.  BFS_VALIDATE checks all of this.
+ */
+#ifndef S3BFS_BFS_H
+#define S3BFS_BFS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t bfs_status_t;
+#define BFS_OK         0
+#define BFS_EINVAL    -1  /* bad argument (null pointer, bad flag, k out of range) */
+#define BFS_ERANGE    -2  /* a source or root is outside [0, n) */
+#define BFS_ENOMEM    -3  /* a device or host allocation failed */
+#define BFS_EBADCSR   -4  /* BFS_VALIDATE found a malformed graph */
+#define BFS_EHIP      -5  /* a HIP runtime call failed */
+#define BFS_EOVERFLOW -6  /* batched search reached level 255 (uint8 output) */
+#define BFS_EBUSY     -7  /* workspace still in flight on another stream */
+#define BFS_EDEVICE   -8  /* device-side failure (a grid-barrier wait timed out) */
+
+typedef struct bfs_graph_s* bfs_graph_t;          /* immutable device-resident CSR */
+typedef struct bfs_workspace_s* bfs_workspace_t;  /* scratch for one in-flight run */
+
+/* bfs_init flags */
+#define BFS_HOST_PTRS   1u  /* offsets/cols are host memory: the library copies them */
+#define BFS_DEVICE_PTRS 2u  /* offsets/cols are device memory: borrowed until bfs_graph_free */
+#define BFS_VALIDATE    4u  /* check the CSR on the host (O(m log m); meant for tests) */
+
+/* Execution modes (bfs_workspace_set_option(ws, BFS_OPT_MODE, ...)). */
+#define BFS_MODE_AUTO        0  /* one persistent launch; single-workgroup levels while small */
+#define BFS_MODE_LEVEL       1  /* one launch pair per level, grid sized to the level's edges */
+#define BFS_MODE_PLAIN       2  /* plain per-level kernel: one thread per frontier vertex */
+#define BFS_MODE_INSENSITIVE 3  /* persistent, every workgroup active at every step */
+
+/* Options */
+#define BFS_OPT_MODE        1  /* one of BFS_MODE_* (default AUTO) */
+#define BFS_OPT_SMALL_EDGES 2  /* largest e_l run by a single workgroup (0 disables) */
+#define BFS_OPT_GRID        3  /* workgroups of the persistent kernel (0 = fill the GPU) */
+#define BFS_OPT_PROFILE     4  /* 1: time the main kernel with HIP events (bfs_stats_t.kernel_ms) */
+#define BFS_OPT_BATCH_PULL  5  /* batched search: edges above which a level pulls (-1 = never) */
+
+typedef struct {
+    int32_t levels;          /* frontiers processed: max level + 1 */
+    int32_t mode;            /* BFS_MODE_* actually used */
+    int32_t grid;            /* workgroups launched for the level loop */
+    int32_t small_levels;    /* levels run by a single workgroup */
+    int64_t reached;         /* vertices with a level (sum of n_l) */
+    int64_t edges;           /* adjacency entries scanned (sum of e_l) */
+    double  kernel_ms;       /* main-kernel time if BFS_OPT_PROFILE, else -1 */
+    int32_t status;          /* device status of the run (BFS_OK or BFS_EDEVICE) */
+    int32_t stats_truncated; /* 1 if more levels ran than per-level records kept */
+} bfs_stats_t;
+
+/*
+ * Make a graph resident on the current HIP device.
+ *   offsets[n+1], cols[m]: CSR (int32).  With BFS_HOST_PTRS they are copied
+ *   (synchronously; the call returns after the copy).  With BFS_DEVICE_PTRS
+ *   the caller keeps them alive and unchanged until bfs_graph_free.
+ *   stream: used for the upload.  *out receives the handle.
+ * Errors: EINVAL (null pointers, n < 0, m < 0, both or neither pointer flag),
+ *         EBADCSR (BFS_VALIDATE failed), ENOMEM, EHIP.
+ */
+bfs_status_t bfs_init(const int32_t* offsets, const int32_t* cols, int32_t n, int64_t m,
+                      uint32_t flags, void* stream, bfs_graph_t* out);
+
+/* Release a graph (no workspace of it may be in use). */
+bfs_status_t bfs_graph_free(bfs_graph_t g);
+
+/* n and m of a resident graph. */
+bfs_status_t bfs_graph_info(bfs_graph_t g, int32_t* n, int64_t* m);
+
+/* Device bytes a workspace for up to max_sources batched sources needs
+   (max_sources = 1: single-source and multi-root runs only). 0 on error. */
+size_t bfs_workspace_bytes(bfs_graph_t g, int32_t max_sources);
+
+/* Allocate a workspace (all scratch of one run).  One workspace serves one
+   run at a time; give each concurrent stream its own.  Errors: EINVAL,
+   ENOMEM, EHIP. */
+bfs_status_t bfs_workspace_create(bfs_graph_t g, int32_t max_sources, bfs_workspace_t* out);
+bfs_status_t bfs_workspace_free(bfs_workspace_t ws);
+
+/* Set a BFS_OPT_* option.  EINVAL for an unknown option or bad value. */
+bfs_status_t bfs_workspace_set_option(bfs_workspace_t ws, int32_t option, int64_t value);
+
+/*
+ * Single-source search (Figure 1, Parallel-BFS(s, P)).
+ *   level[n] (device, int32, written): distance from source, -1 if unreached.
+ *   parent[n] (device, int32, may be NULL): smallest-id neighbour one level
+ *   closer; parent[source] = source; -1 if unreached.
+ * The arrays are owned by the caller.  Results depend only on the graph and
+ * the source, never on mode, grid, options, stream or other work in flight.
+ * Asynchronous on stream in BFS_MODE_AUTO and BFS_MODE_INSENSITIVE; the
+ * LEVEL and PLAIN modes read each level's size back and so synchronise.
+ * Errors: EINVAL, ERANGE (source), EBUSY, EHIP; a device failure of this
+ * run is reported by bfs_sync.
+ */
+bfs_status_t bfs_run(bfs_workspace_t ws, int32_t source, int32_t* level, int32_t* parent, void* stream);
+
+/*
+ * Multi-root search: every root starts at level 0 (host array roots[k],
+ * 1 <= k <= n, repeats allowed).  With one root per component of a
+ * disjoint union of graphs this runs independent searches of many small
+ * graphs in one launch.  level/parent as in bfs_run (a root's parent is
+ * itself; other vertices take the distance to the nearest root).
+ */
+bfs_status_t bfs_run_multiroot(bfs_workspace_t ws, const int32_t* roots, int32_t k,
+                               int32_t* level, int32_t* parent, void* stream);
+
+/*
+ * Batched search of k <= 256 sources (host array sources[k], repeats
+ * allowed) with per-vertex 4 x 64-bit frontier/visited masks.
+ *   level[n * k] (device, uint8, written): level[v * k + j] is the distance
+ *   of v from sources[j], 255 if unreached.
+ * The workspace must have been created with max_sources >= k.  Levels >= 255
+ * do not fit: the run stops and bfs_sync returns BFS_EOVERFLOW (the int32
+ * single-source path answers those sources).  Synchronises with stream
+ * between replays of its captured level loop.
+ */
+bfs_status_t bfs_run_batch(bfs_workspace_t ws, const int32_t* sources, int32_t k, uint8_t* level,
+                           void* stream);
+
+/* Wait for the workspace's last run; returns its device status. */
+bfs_status_t bfs_sync(bfs_workspace_t ws);
+
+/* Statistics of the last run (synchronises with it first). */
+bfs_status_t bfs_last_stats(bfs_workspace_t ws, bfs_stats_t* out);
+
+/* Per-level frontier sizes n_l and edge totals e_l of the last run (the
+   work accounting of the paper's Analysis).  Copies min(levels, cap)
+   entries into host arrays and returns the count in *count. */
+bfs_status_t bfs_last_level_stats(bfs_workspace_t ws, int32_t cap, int64_t* n_l, int64_t* e_l,
+                                  int32_t* count);
+
+const char* bfs_status_str(bfs_status_t s);
+const char* bfs_last_error(void);
+
+/* ---- primitives of the level loop, exposed for testing ------------------------------ */
+
+/*
+ * Owner de-duplication and linearisation of one level (Figure 1: keep a
+ * private-queue entry v of queue i only if Owner[v] = i, prefix-sum the
+ * queue sizes, copy the survivors to the next CurLevelVertices), fused with
+ * the next level's degree gather, degree prefix sum and share start points
+ * (Find-StartExpPoint).  All pointers are device memory.
+ *   cand[ntiles * grain], cnt[ntiles]: tile t's private queue is
+ *     cand[t*grain .. t*grain + cnt[t]); its entries' slot ids are their
+ *     positions in cand.
+ *   owner[n]: slot id that owns each vertex.
+ *   offsets[n+1]: graph CSR offsets (degree = offsets[v+1] - offsets[v]).
+ *   Outputs: out_rs[i] = offsets[v_i], out_ex[i] = sum of the degrees of the
+ *   survivors before i (in output order), out_ex[count] = total;
+ *   out_tstart[t] = index of the survivor holding edge t*grain;
+ *   totals[0] = survivor count (degree >= 1 only), totals[1] = edge total
+ *   (int32 device array of 2).  Survivors of degree 0 are dropped.
+ *   Output order is unspecified; the set is exact.
+ * grain must be the library's tile size (bfs_prim_grain()).
+ */
+bfs_status_t bfs_prim_compact(const int32_t* offsets, int32_t n, const int32_t* owner,
+                              const int32_t* cand, const int32_t* cnt, int32_t ntiles,
+                              int32_t* out_rs, int32_t* out_ex, int32_t* out_tstart,
+                              int32_t* totals, void* stream);
+
+/* Edges per share (tile) of the multi-workgroup level loop. */
+int32_t bfs_prim_grain(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* S3BFS_BFS_H */

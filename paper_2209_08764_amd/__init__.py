@@ -1,0 +1,255 @@
+"""S3BFS on one AMD Instinct MI355X: Python binding of libbfs.
+
+The functions below carry the names of the C entry points in include/bfs.h
+and only marshal arguments (torch tensors for device memory, torch streams
+for ordering); the search itself runs in the library's HIP kernels.  The
+classes ``Graph`` and ``Workspace`` are small conveniences over the same
+calls that own the handles and the borrowed tensors.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import (BFS_DEVICE_PTRS, BFS_HOST_PTRS, BFS_MODE_AUTO, BFS_MODE_INSENSITIVE, BFS_MODE_LEVEL,
+                   BFS_MODE_PLAIN, BFS_OPT_BATCH_PULL, BFS_OPT_GRID, BFS_OPT_MODE, BFS_OPT_PROFILE,
+                   BFS_OPT_SMALL_EDGES, BFS_VALIDATE, BFSError, bfs_stats_t)
+
+__all__ = [
+    "bfs_init", "bfs_graph_free", "bfs_graph_info", "bfs_workspace_bytes", "bfs_workspace_create",
+    "bfs_workspace_free", "bfs_workspace_set_option", "bfs_run", "bfs_run_multiroot", "bfs_run_batch",
+    "bfs_sync", "bfs_last_stats", "bfs_last_level_stats", "bfs_status_str", "bfs_prim_compact",
+    "bfs_prim_grain", "Graph", "Workspace", "BFSError",
+]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)
+
+
+def _dptr(t, dtype, what):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{what} must be a device tensor")
+    if t.dtype != dtype or not t.is_contiguous():
+        raise TypeError(f"{what} must be a contiguous {dtype} tensor")
+    return t.data_ptr()
+
+
+def bfs_status_str(status: int) -> str:
+    return _lib.load().bfs_status_str(status).decode()
+
+
+def bfs_init(offsets, cols, flags: int | None = None, stream=None, validate: bool = False) -> int:
+    """Make a CSR graph resident; numpy arrays are copied, device tensors borrowed."""
+    torch = _torch()
+    lib = _lib.load()
+    out = ctypes.c_void_p()
+    if isinstance(offsets, torch.Tensor) and offsets.is_cuda:
+        n = offsets.numel() - 1
+        m = cols.numel()
+        fl = BFS_DEVICE_PTRS if flags is None else flags
+        po = _dptr(offsets, torch.int32, "offsets")
+        pc = _dptr(cols, torch.int32, "cols") if m else None
+    else:
+        offsets = np.ascontiguousarray(offsets, dtype=np.int32)
+        cols = np.ascontiguousarray(cols, dtype=np.int32)
+        n = offsets.size - 1
+        m = cols.size
+        fl = BFS_HOST_PTRS if flags is None else flags
+        po = offsets.ctypes.data
+        pc = cols.ctypes.data if m else None
+    if validate:
+        fl |= BFS_VALIDATE
+    _lib.check(lib.bfs_init(po, pc, n, m, fl, _stream_ptr(stream), ctypes.byref(out)), "bfs_init")
+    return out.value
+
+
+def bfs_graph_free(g: int) -> None:
+    _lib.check(_lib.load().bfs_graph_free(g), "bfs_graph_free")
+
+
+def bfs_graph_info(g: int):
+    n = ctypes.c_int32()
+    m = ctypes.c_int64()
+    _lib.check(_lib.load().bfs_graph_info(g, ctypes.byref(n), ctypes.byref(m)), "bfs_graph_info")
+    return n.value, m.value
+
+
+def bfs_workspace_bytes(g: int, max_sources: int = 1) -> int:
+    return int(_lib.load().bfs_workspace_bytes(g, max_sources))
+
+
+def bfs_workspace_create(g: int, max_sources: int = 1) -> int:
+    out = ctypes.c_void_p()
+    _lib.check(_lib.load().bfs_workspace_create(g, max_sources, ctypes.byref(out)), "bfs_workspace_create")
+    return out.value
+
+
+def bfs_workspace_free(ws: int) -> None:
+    _lib.check(_lib.load().bfs_workspace_free(ws), "bfs_workspace_free")
+
+
+def bfs_workspace_set_option(ws: int, option: int, value: int) -> None:
+    _lib.check(_lib.load().bfs_workspace_set_option(ws, option, int(value)), "bfs_workspace_set_option")
+
+
+def bfs_run(ws: int, source: int, level, parent=None, stream=None) -> None:
+    torch = _torch()
+    pl = _dptr(level, torch.int32, "level")
+    pp = _dptr(parent, torch.int32, "parent") if parent is not None else None
+    _lib.check(_lib.load().bfs_run(ws, int(source), pl, pp, _stream_ptr(stream)), "bfs_run")
+
+
+def bfs_run_multiroot(ws: int, roots, level, parent=None, stream=None) -> None:
+    torch = _torch()
+    roots = np.ascontiguousarray(roots, dtype=np.int32)
+    pl = _dptr(level, torch.int32, "level")
+    pp = _dptr(parent, torch.int32, "parent") if parent is not None else None
+    _lib.check(_lib.load().bfs_run_multiroot(ws, roots.ctypes.data, roots.size, pl, pp, _stream_ptr(stream)),
+               "bfs_run_multiroot")
+
+
+def bfs_run_batch(ws: int, sources, level, stream=None) -> None:
+    torch = _torch()
+    sources = np.ascontiguousarray(sources, dtype=np.int32)
+    pl = _dptr(level, torch.uint8, "level")
+    _lib.check(_lib.load().bfs_run_batch(ws, sources.ctypes.data, sources.size, pl, _stream_ptr(stream)),
+               "bfs_run_batch")
+
+
+def bfs_sync(ws: int) -> None:
+    _lib.check(_lib.load().bfs_sync(ws), "bfs_sync")
+
+
+def bfs_last_stats(ws: int) -> dict:
+    st = bfs_stats_t()
+    _lib.check(_lib.load().bfs_last_stats(ws, ctypes.byref(st)), "bfs_last_stats")
+    return {f: getattr(st, f) for f, _ in bfs_stats_t._fields_}
+
+
+def bfs_last_level_stats(ws: int, cap: int = 1 << 16):
+    n_l = np.zeros(cap, np.int64)
+    e_l = np.zeros(cap, np.int64)
+    cnt = ctypes.c_int32()
+    _lib.check(_lib.load().bfs_last_level_stats(ws, cap, n_l.ctypes.data, e_l.ctypes.data, ctypes.byref(cnt)),
+               "bfs_last_level_stats")
+    return n_l[:cnt.value].copy(), e_l[:cnt.value].copy()
+
+
+def bfs_prim_grain() -> int:
+    return int(_lib.load().bfs_prim_grain())
+
+
+def bfs_prim_compact(offsets, owner, cand, cnt, out_rs, out_ex, out_tstart, totals, stream=None) -> None:
+    torch = _torch()
+    i32 = torch.int32
+    _lib.check(_lib.load().bfs_prim_compact(
+        _dptr(offsets, i32, "offsets"), offsets.numel() - 1, _dptr(owner, i32, "owner"), _dptr(cand, i32, "cand"),
+        _dptr(cnt, i32, "cnt"), cnt.numel(), _dptr(out_rs, i32, "out_rs"), _dptr(out_ex, i32, "out_ex"),
+        _dptr(out_tstart, i32, "out_tstart"), _dptr(totals, i32, "totals"), _stream_ptr(stream)),
+        "bfs_prim_compact")
+
+
+class Graph:
+    """A device-resident graph (owns the handle and keeps borrowed tensors alive)."""
+
+    def __init__(self, offsets, cols, device="cuda", validate: bool = False, copy: bool = False):
+        torch = _torch()
+        if isinstance(offsets, np.ndarray) and not copy:
+            offsets = torch.from_numpy(np.ascontiguousarray(offsets, dtype=np.int32)).to(device)
+            cols = torch.from_numpy(np.ascontiguousarray(cols, dtype=np.int32)).to(device)
+        self._keep = (offsets, cols)
+        self.handle = bfs_init(offsets, cols, validate=validate)
+        self.n, self.m = bfs_graph_info(self.handle)
+        self.offsets = offsets
+        self.cols = cols
+
+    def free(self):
+        if self.handle:
+            bfs_graph_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Workspace:
+    """Scratch for one in-flight run on a Graph."""
+
+    def __init__(self, graph: Graph, max_sources: int = 1, mode: int | None = None, **opts):
+        self.graph = graph
+        self.max_sources = max_sources
+        self.handle = bfs_workspace_create(graph.handle, max_sources)
+        if mode is not None:
+            bfs_workspace_set_option(self.handle, BFS_OPT_MODE, mode)
+        names = {"small_edges": BFS_OPT_SMALL_EDGES, "grid": BFS_OPT_GRID, "profile": BFS_OPT_PROFILE,
+                 "batch_pull": BFS_OPT_BATCH_PULL}
+        for k, v in opts.items():
+            bfs_workspace_set_option(self.handle, names[k], v)
+
+    def set(self, option: int, value: int):
+        bfs_workspace_set_option(self.handle, option, value)
+
+    def run(self, source: int, level=None, parent=None, stream=None, want_parent: bool = True):
+        torch = _torch()
+        n = self.graph.n
+        if level is None:
+            level = torch.empty(n, dtype=torch.int32, device="cuda")
+        if parent is None and want_parent:
+            parent = torch.empty(n, dtype=torch.int32, device="cuda")
+        bfs_run(self.handle, source, level, parent, stream)
+        return level, parent
+
+    def run_multiroot(self, roots, level=None, parent=None, stream=None):
+        torch = _torch()
+        n = self.graph.n
+        if level is None:
+            level = torch.empty(n, dtype=torch.int32, device="cuda")
+        if parent is None:
+            parent = torch.empty(n, dtype=torch.int32, device="cuda")
+        bfs_run_multiroot(self.handle, roots, level, parent, stream)
+        return level, parent
+
+    def run_batch(self, sources, level=None, stream=None):
+        torch = _torch()
+        k = len(sources)
+        if level is None:
+            level = torch.empty(self.graph.n * k, dtype=torch.uint8, device="cuda")
+        bfs_run_batch(self.handle, sources, level, stream)
+        return level
+
+    def sync(self):
+        bfs_sync(self.handle)
+
+    def stats(self):
+        return bfs_last_stats(self.handle)
+
+    def level_stats(self, cap: int = 1 << 16):
+        return bfs_last_level_stats(self.handle, cap)
+
+    def free(self):
+        if self.handle:
+            bfs_workspace_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass

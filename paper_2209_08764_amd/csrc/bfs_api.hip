@@ -1,0 +1,635 @@
+// C ABI of libbfs: graph residency, workspaces and run orchestration.
+// The entry points are declared and documented in include/bfs.h.
+#include "../../include/bfs.h"
+#include "bfs_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+using namespace s3bfs;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+bfs_status_t fail(bfs_status_t code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess) return fail(BFS_EHIP, "%s: %s", #expr, hipGetErrorString(e_));   \
+    } while (0)
+
+constexpr uint64_t kSpinTicks = 300000000ull;  // 3 s at the 100 MHz s_memrealtime clock
+
+template <typename T>
+hipError_t dalloc(T** p, size_t count) {
+    return hipMalloc(reinterpret_cast<void**>(p), std::max<size_t>(count, 1) * sizeof(T));
+}
+
+}  // namespace
+
+struct bfs_graph_s {
+    int device = 0;
+    int32_t n = 0;
+    int64_t m = 0;
+    int32_t* offsets = nullptr;
+    int32_t* cols = nullptr;
+    bool owned = false;
+};
+
+struct bfs_workspace_s {
+    bfs_graph_s* g = nullptr;
+    int device = 0;
+    int32_t max_sources = 1;
+    int32_t max_tiles = 0;
+    int32_t grid_cap = 0;
+    // single-source buffers
+    uint32_t* bitmap = nullptr;
+    int32_t* owner = nullptr;
+    int32_t* f_rs[2] = {nullptr, nullptr};
+    int32_t* f_ex[2] = {nullptr, nullptr};
+    int32_t* tstart[2] = {nullptr, nullptr};
+    int32_t* cand = nullptr;
+    int32_t* cnt = nullptr;
+    unsigned long long* desc[2] = {nullptr, nullptr};
+    Ctrl* ctrl = nullptr;
+    int32_t* stat_nl = nullptr;
+    int32_t* stat_el = nullptr;
+    int32_t* roots = nullptr;
+    int32_t* plain_fv[2] = {nullptr, nullptr};
+    // batched buffers
+    unsigned long long* b_fr = nullptr;
+    unsigned long long* b_nx = nullptr;
+    unsigned long long* b_vis = nullptr;
+    int32_t* b_act[2] = {nullptr, nullptr};
+    int32_t* b_act_ex[2] = {nullptr, nullptr};
+    int32_t* b_tstart[2] = {nullptr, nullptr};
+    unsigned long long* b_desc[2] = {nullptr, nullptr};
+    uint32_t* b_act_bits = nullptr;
+    int32_t* b_sources = nullptr;
+    // host side
+    Ctrl* h_ctrl = nullptr;  // pinned
+    hipEvent_t ev_done = nullptr, ev0 = nullptr, ev1 = nullptr;
+    hipStream_t last_stream = nullptr;
+    bool has_run = false;
+    bool profiled = false;
+    int32_t mode = BFS_MODE_AUTO;
+    int32_t small_edges = kDefaultSmallEdges;
+    int32_t grid_opt = 0;
+    int32_t profile = 0;
+    int32_t batch_pull = -2;  // -2: library default
+    // last run
+    int32_t last_mode = 0;
+    int32_t last_grid = 0;
+    bool host_stats = false;
+    std::vector<int64_t> h_nl, h_el;
+    int32_t host_status = BFS_OK;
+};
+
+namespace {
+
+bfs_status_t validate_csr(const int32_t* off, const int32_t* cols, int32_t n, int64_t m) {
+    if (off[0] != 0) return fail(BFS_EBADCSR, "offsets[0] = %d, expected 0", off[0]);
+    if ((int64_t)off[n] != m) return fail(BFS_EBADCSR, "offsets[n] = %d but m = %lld", off[n], (long long)m);
+    for (int32_t v = 0; v < n; ++v)
+        if (off[v + 1] < off[v]) return fail(BFS_EBADCSR, "offsets decrease at vertex %d", v);
+    for (int64_t e = 0; e < m; ++e)
+        if (cols[e] < 0 || cols[e] >= n) return fail(BFS_EBADCSR, "cols[%lld] = %d out of range", (long long)e, cols[e]);
+    for (int32_t v = 0; v < n; ++v)
+        for (int64_t e = off[v] + 1; e < off[v + 1]; ++e)
+            if (cols[e] < cols[e - 1]) return fail(BFS_EBADCSR, "row %d is not sorted", v);
+    for (int32_t u = 0; u < n; ++u)
+        for (int64_t e = off[u]; e < off[u + 1]; ++e) {
+            const int32_t v = cols[e];
+            if (!std::binary_search(cols + off[v], cols + off[v + 1], u))
+                return fail(BFS_EBADCSR, "edge (%d,%d) has no reverse: graph is not symmetric", u, v);
+        }
+    return BFS_OK;
+}
+
+Params make_params(bfs_workspace_s* ws, int32_t* level, int32_t* parent) {
+    Params p{};
+    p.offsets = ws->g->offsets;
+    p.cols = ws->g->cols;
+    p.n = ws->g->n;
+    p.level = level;
+    p.parent = parent;
+    p.bitmap = ws->bitmap;
+    p.owner = ws->owner;
+    for (int i = 0; i < 2; ++i) {
+        p.f_rs[i] = ws->f_rs[i];
+        p.f_ex[i] = ws->f_ex[i];
+        p.tstart[i] = ws->tstart[i];
+        p.desc[i] = ws->desc[i];
+    }
+    p.cand = ws->cand;
+    p.cnt = ws->cnt;
+    p.ctrl = ws->ctrl;
+    p.stat_nl = ws->stat_nl;
+    p.stat_el = ws->stat_el;
+    p.small_edges = ws->small_edges;
+    p.max_tiles = ws->max_tiles;
+    p.spin_ticks = kSpinTicks;
+    return p;
+}
+
+bfs_status_t check_busy(bfs_workspace_s* ws, hipStream_t s) {
+    if (ws->has_run && ws->last_stream != s) {
+        hipError_t q = hipEventQuery(ws->ev_done);
+        if (q == hipErrorNotReady) return fail(BFS_EBUSY, "workspace still running on another stream");
+        if (q != hipSuccess) return fail(BFS_EHIP, "hipEventQuery: %s", hipGetErrorString(q));
+    }
+    return BFS_OK;
+}
+
+int grid_for(bfs_workspace_s* ws) {
+    int g = ws->grid_cap;
+    if (ws->grid_opt > 0) g = std::min(g, ws->grid_opt);
+    return std::max(g, 1);
+}
+
+bfs_status_t read_ctrl(bfs_workspace_s* ws, hipStream_t s) {
+    HIP_TRY(hipMemcpyAsync(ws->h_ctrl, ws->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return BFS_OK;
+}
+
+// Level loop driven from the host: one expand and one compact launch per
+// level, each with a grid sized to the level's shares.
+bfs_status_t run_level_mode(bfs_workspace_s* ws, Params& p, hipStream_t s) {
+    const int root_tiles = (p.nroots + kGrain - 1) / kGrain;
+    const int gmax = grid_for(ws);
+    HIP_TRY(launch_prep(p, root_tiles, s));
+    HIP_TRY(launch_level_roots(p, s));
+    HIP_TRY(launch_level_compact(p, -1, root_tiles, std::min(root_tiles, gmax), s));
+    ws->h_nl.clear();
+    ws->h_el.clear();
+    for (int l = 0;; ++l) {
+        bfs_status_t st = read_ctrl(ws, s);
+        if (st) return st;
+        if (ws->h_ctrl->error) return fail(BFS_EDEVICE, "device wait timed out");
+        const int par = l & 1;
+        const int n_l = ws->h_ctrl->nl[par], e_l = ws->h_ctrl->el[par], kept = ws->h_ctrl->kept[par];
+        if (kept > 0) {
+            ws->h_nl.push_back(kept);
+            ws->h_el.push_back(e_l);
+        }
+        if (n_l == 0) break;
+        const int ntiles = (int)(((int64_t)e_l + kGrain - 1) / kGrain);
+        const int grid = std::min(ntiles, gmax);
+        HIP_TRY(launch_level_expand(p, l, ntiles, grid, s));
+        HIP_TRY(launch_level_compact(p, l, ntiles, grid, s));
+    }
+    if (p.parent) HIP_TRY(launch_parent(p, s));
+    ws->host_stats = true;
+    ws->last_grid = gmax;
+    return BFS_OK;
+}
+
+// Plain per-level kernel: one thread per frontier vertex, no edge split.
+bfs_status_t run_plain_mode(bfs_workspace_s* ws, Params& p, hipStream_t s) {
+    const int32_t n = ws->g->n;
+    if (!ws->plain_fv[0]) {
+        HIP_TRY(dalloc(&ws->plain_fv[0], (size_t)n + 1));
+        HIP_TRY(dalloc(&ws->plain_fv[1], (size_t)n + 1));
+    }
+    if (p.roots) return fail(BFS_EINVAL, "BFS_MODE_PLAIN runs single-source searches only");
+    HIP_TRY(launch_prep(p, 0, s));
+    HIP_TRY(launch_plain_init(p, ws->plain_fv[0], s));
+    ws->h_nl.clear();
+    ws->h_el.clear();
+    int nf = 1;
+    for (int l = 0; nf > 0; ++l) {
+        ws->h_nl.push_back(nf);
+        ws->h_el.push_back(-1);
+        HIP_TRY(hipMemsetAsync(&ws->ctrl->plain_next, 0, sizeof(int), s));
+        HIP_TRY(launch_plain_level(p, l, ws->plain_fv[l & 1], nf, ws->plain_fv[(l + 1) & 1], s));
+        bfs_status_t st = read_ctrl(ws, s);
+        if (st) return st;
+        nf = ws->h_ctrl->plain_next;
+    }
+    if (p.parent) HIP_TRY(launch_parent(p, s));
+    ws->host_stats = true;
+    ws->last_grid = 0;
+    return BFS_OK;
+}
+
+bfs_status_t run_common(bfs_workspace_s* ws, const int32_t* roots_host, int32_t k, int32_t single,
+                        int32_t* level, int32_t* parent, void* stream) {
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (!ws) return fail(BFS_EINVAL, "null workspace");
+    if (!level) return fail(BFS_EINVAL, "null level array");
+    bfs_status_t st = check_busy(ws, s);
+    if (st) return st;
+    HIP_TRY(hipSetDevice(ws->device));
+    Params p = make_params(ws, level, parent);
+    if (roots_host) {
+        for (int32_t i = 0; i < k; ++i)
+            if (roots_host[i] < 0 || roots_host[i] >= ws->g->n)
+                return fail(BFS_ERANGE, "root %d = %d outside [0, %d)", i, roots_host[i], ws->g->n);
+        HIP_TRY(hipMemcpyAsync(ws->roots, roots_host, sizeof(int32_t) * (size_t)k, hipMemcpyHostToDevice, s));
+        p.roots = ws->roots;
+        p.nroots = k;
+    } else {
+        if (single < 0 || single >= ws->g->n) return fail(BFS_ERANGE, "source %d outside [0, %d)", single, ws->g->n);
+        p.roots = nullptr;
+        p.single_root = single;
+        p.nroots = 1;
+    }
+    ws->host_stats = false;
+    ws->profiled = false;
+    ws->last_mode = ws->mode;
+    ws->host_status = BFS_OK;
+    int mode = ws->mode;
+    if (mode == BFS_MODE_LEVEL) {
+        st = run_level_mode(ws, p, s);
+    } else if (mode == BFS_MODE_PLAIN) {
+        st = run_plain_mode(ws, p, s);
+    } else {
+        if (mode == BFS_MODE_INSENSITIVE) p.small_edges = 0;
+        const int root_tiles = (p.nroots + kGrain - 1) / kGrain;
+        const int grid = grid_for(ws);
+        HIP_TRY(launch_prep(p, root_tiles, s));
+        if (ws->profile) HIP_TRY(hipEventRecord(ws->ev0, s));
+        HIP_TRY(launch_persistent(p, grid, s));
+        if (ws->profile) {
+            HIP_TRY(hipEventRecord(ws->ev1, s));
+            ws->profiled = true;
+        }
+        ws->last_grid = grid;
+        st = BFS_OK;
+    }
+    ws->host_status = st;
+    HIP_TRY(hipEventRecord(ws->ev_done, s));
+    ws->last_stream = s;
+    ws->has_run = true;
+    return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* bfs_last_error(void) { return g_last_error.c_str(); }
+
+const char* bfs_status_str(bfs_status_t s) {
+    switch (s) {
+        case BFS_OK: return "ok";
+        case BFS_EINVAL: return "invalid argument";
+        case BFS_ERANGE: return "source or root out of range";
+        case BFS_ENOMEM: return "out of memory";
+        case BFS_EBADCSR: return "malformed CSR graph";
+        case BFS_EHIP: return "HIP runtime error";
+        case BFS_EOVERFLOW: return "batched level reached 255";
+        case BFS_EBUSY: return "workspace busy on another stream";
+        case BFS_EDEVICE: return "device-side failure";
+        default: return "unknown status";
+    }
+}
+
+bfs_status_t bfs_init(const int32_t* offsets, const int32_t* cols, int32_t n, int64_t m, uint32_t flags,
+                      void* stream, bfs_graph_t* out) {
+    if (!out) return fail(BFS_EINVAL, "null output handle");
+    *out = nullptr;
+    if (!offsets || (m > 0 && !cols)) return fail(BFS_EINVAL, "null CSR pointer");
+    if (n < 0 || m < 0 || m > INT32_MAX) return fail(BFS_EINVAL, "n or m out of range");
+    const bool host = flags & BFS_HOST_PTRS, dev = flags & BFS_DEVICE_PTRS;
+    if (host == dev) return fail(BFS_EINVAL, "exactly one of BFS_HOST_PTRS / BFS_DEVICE_PTRS");
+    if (flags & ~(BFS_HOST_PTRS | BFS_DEVICE_PTRS | BFS_VALIDATE)) return fail(BFS_EINVAL, "unknown flag");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (flags & BFS_VALIDATE) {
+        std::vector<int32_t> ho, hc;
+        const int32_t* po = offsets;
+        const int32_t* pc = cols;
+        if (dev) {
+            ho.resize((size_t)n + 1);
+            hc.resize((size_t)std::max<int64_t>(m, 1));
+            HIP_TRY(hipMemcpy(ho.data(), offsets, sizeof(int32_t) * ((size_t)n + 1), hipMemcpyDeviceToHost));
+            if (m) HIP_TRY(hipMemcpy(hc.data(), cols, sizeof(int32_t) * (size_t)m, hipMemcpyDeviceToHost));
+            po = ho.data();
+            pc = hc.data();
+        }
+        bfs_status_t st = validate_csr(po, pc, n, m);
+        if (st) return st;
+    }
+    auto* g = new (std::nothrow) bfs_graph_s();
+    if (!g) return fail(BFS_ENOMEM, "host allocation failed");
+    HIP_TRY(hipGetDevice(&g->device));
+    g->n = n;
+    g->m = m;
+    if (dev) {
+        g->offsets = const_cast<int32_t*>(offsets);
+        g->cols = const_cast<int32_t*>(cols);
+        g->owned = false;
+    } else {
+        if (dalloc(&g->offsets, (size_t)n + 1) != hipSuccess || dalloc(&g->cols, (size_t)m) != hipSuccess) {
+            (void)hipFree(g->offsets);
+            (void)hipFree(g->cols);
+            delete g;
+            return fail(BFS_ENOMEM, "device allocation of the CSR failed");
+        }
+        g->owned = true;
+        HIP_TRY(hipMemcpyAsync(g->offsets, offsets, sizeof(int32_t) * ((size_t)n + 1), hipMemcpyHostToDevice, s));
+        if (m) HIP_TRY(hipMemcpyAsync(g->cols, cols, sizeof(int32_t) * (size_t)m, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
+    *out = g;
+    return BFS_OK;
+}
+
+bfs_status_t bfs_graph_free(bfs_graph_t g) {
+    if (!g) return fail(BFS_EINVAL, "null graph");
+    if (g->owned) {
+        (void)hipFree(g->offsets);
+        (void)hipFree(g->cols);
+    }
+    delete g;
+    return BFS_OK;
+}
+
+bfs_status_t bfs_graph_info(bfs_graph_t g, int32_t* n, int64_t* m) {
+    if (!g) return fail(BFS_EINVAL, "null graph");
+    if (n) *n = g->n;
+    if (m) *m = g->m;
+    return BFS_OK;
+}
+
+static int64_t tiles_for(const bfs_graph_s* g) {
+    const int64_t items = std::max<int64_t>(g->m, g->n);
+    return (items + kGrain - 1) / kGrain + 2;
+}
+
+size_t bfs_workspace_bytes(bfs_graph_t g, int32_t max_sources) {
+    if (!g || max_sources < 1 || max_sources > 256) return 0;
+    const size_t n = (size_t)g->n, T = (size_t)tiles_for(g);
+    size_t b = 0;
+    b += ((n + 31) / 32) * 4;          // bitmap
+    b += n * 4;                        // owner
+    b += 4 * (n + 2) * 4;              // frontier rs/ex x2
+    b += 2 * T * 4;                    // tstart x2
+    b += T * kGrain * 4;               // candidates
+    b += T * 4;                        // counts
+    b += 2 * T * 8;                    // descriptors
+    b += sizeof(Ctrl) + 2 * (size_t)kStatCap * 4 + n * 4;  // ctrl, stats, roots
+    if (max_sources > 1) {
+        b += 3 * n * 32;               // frontier/next/visited masks
+        b += 4 * (n + 2) * 4;          // active lists x2
+        b += 2 * T * 4 + 2 * T * 8;    // batch tstart, descriptors
+        b += ((n + 31) / 32) * 4 + 256 * 4;
+    }
+    return b;
+}
+
+bfs_status_t bfs_workspace_free(bfs_workspace_t ws) {
+    if (!ws) return fail(BFS_EINVAL, "null workspace");
+    (void)hipSetDevice(ws->device);
+    if (ws->has_run) (void)hipEventSynchronize(ws->ev_done);
+    void* ptrs[] = {ws->bitmap, ws->owner, ws->f_rs[0], ws->f_rs[1], ws->f_ex[0], ws->f_ex[1], ws->tstart[0],
+                    ws->tstart[1], ws->cand, ws->cnt, ws->desc[0], ws->desc[1], ws->ctrl, ws->stat_nl,
+                    ws->stat_el, ws->roots, ws->plain_fv[0], ws->plain_fv[1], ws->b_fr, ws->b_nx, ws->b_vis,
+                    ws->b_act[0], ws->b_act[1], ws->b_act_ex[0], ws->b_act_ex[1], ws->b_tstart[0],
+                    ws->b_tstart[1], ws->b_desc[0], ws->b_desc[1], ws->b_act_bits, ws->b_sources};
+    for (void* q : ptrs)
+        if (q) (void)hipFree(q);
+    if (ws->h_ctrl) (void)hipHostFree(ws->h_ctrl);
+    if (ws->ev_done) (void)hipEventDestroy(ws->ev_done);
+    if (ws->ev0) (void)hipEventDestroy(ws->ev0);
+    if (ws->ev1) (void)hipEventDestroy(ws->ev1);
+    delete ws;
+    return BFS_OK;
+}
+
+bfs_status_t bfs_workspace_create(bfs_graph_t g, int32_t max_sources, bfs_workspace_t* out) {
+    if (!out || !g) return fail(BFS_EINVAL, "null argument");
+    *out = nullptr;
+    if (max_sources < 1 || max_sources > 256) return fail(BFS_EINVAL, "max_sources must be in [1, 256]");
+    auto* ws = new (std::nothrow) bfs_workspace_s();
+    if (!ws) return fail(BFS_ENOMEM, "host allocation failed");
+    ws->g = g;
+    ws->device = g->device;
+    ws->max_sources = max_sources;
+    HIP_TRY(hipSetDevice(ws->device));
+    const size_t n = (size_t)g->n;
+    const int64_t T = tiles_for(g);
+    ws->max_tiles = (int32_t)T;
+    bool okk = true;
+    auto A = [&](hipError_t e) { okk = okk && e == hipSuccess; };
+    A(dalloc(&ws->bitmap, (n + 31) / 32));
+    A(dalloc(&ws->owner, n));
+    for (int i = 0; i < 2; ++i) {
+        A(dalloc(&ws->f_rs[i], n + 2));
+        A(dalloc(&ws->f_ex[i], n + 2));
+        A(dalloc(&ws->tstart[i], (size_t)T));
+        A(dalloc(&ws->desc[i], (size_t)T));
+    }
+    A(dalloc(&ws->cand, (size_t)T * kGrain));
+    A(dalloc(&ws->cnt, (size_t)T));
+    A(dalloc(&ws->ctrl, 1));
+    A(dalloc(&ws->stat_nl, kStatCap));
+    A(dalloc(&ws->stat_el, kStatCap));
+    A(dalloc(&ws->roots, n));
+    if (max_sources > 1) {
+        A(dalloc(&ws->b_fr, n * 4));
+        A(dalloc(&ws->b_nx, n * 4));
+        A(dalloc(&ws->b_vis, n * 4));
+        for (int i = 0; i < 2; ++i) {
+            A(dalloc(&ws->b_act[i], n + 2));
+            A(dalloc(&ws->b_act_ex[i], n + 2));
+            A(dalloc(&ws->b_tstart[i], (size_t)T));
+            A(dalloc(&ws->b_desc[i], (size_t)T));
+        }
+        A(dalloc(&ws->b_act_bits, (n + 31) / 32));
+        A(dalloc(&ws->b_sources, 256));
+    }
+    if (okk && hipHostMalloc(reinterpret_cast<void**>(&ws->h_ctrl), sizeof(Ctrl), hipHostMallocDefault) != hipSuccess)
+        okk = false;
+    if (okk && (hipEventCreate(&ws->ev_done) != hipSuccess || hipEventCreate(&ws->ev0) != hipSuccess ||
+                hipEventCreate(&ws->ev1) != hipSuccess))
+        okk = false;
+    if (!okk) {
+        bfs_workspace_free(ws);
+        return fail(BFS_ENOMEM, "workspace allocation failed (%zu bytes requested)", bfs_workspace_bytes(g, max_sources));
+    }
+    ws->grid_cap = persistent_grid_capacity(ws->device);
+    if (ws->grid_cap <= 0) {
+        bfs_workspace_free(ws);
+        return fail(BFS_EHIP, "could not size the persistent grid");
+    }
+    if (hipMemset(ws->ctrl, 0, sizeof(Ctrl)) != hipSuccess) {
+        bfs_workspace_free(ws);
+        return fail(BFS_EHIP, "hipMemset failed");
+    }
+    *out = ws;
+    return BFS_OK;
+}
+
+bfs_status_t bfs_workspace_set_option(bfs_workspace_t ws, int32_t option, int64_t value) {
+    if (!ws) return fail(BFS_EINVAL, "null workspace");
+    switch (option) {
+        case BFS_OPT_MODE:
+            if (value < BFS_MODE_AUTO || value > BFS_MODE_INSENSITIVE) return fail(BFS_EINVAL, "bad mode");
+            ws->mode = (int32_t)value;
+            return BFS_OK;
+        case BFS_OPT_SMALL_EDGES:
+            if (value < 0 || value > INT32_MAX) return fail(BFS_EINVAL, "bad small-edge threshold");
+            ws->small_edges = (int32_t)value;
+            return BFS_OK;
+        case BFS_OPT_GRID:
+            if (value < 0 || value > INT32_MAX) return fail(BFS_EINVAL, "bad grid");
+            ws->grid_opt = (int32_t)value;
+            return BFS_OK;
+        case BFS_OPT_PROFILE:
+            ws->profile = value != 0;
+            return BFS_OK;
+        case BFS_OPT_BATCH_PULL:
+            if (value < -1 || value > INT32_MAX) return fail(BFS_EINVAL, "bad pull threshold");
+            ws->batch_pull = (int32_t)value;
+            return BFS_OK;
+        default:
+            return fail(BFS_EINVAL, "unknown option %d", option);
+    }
+}
+
+bfs_status_t bfs_run(bfs_workspace_t ws, int32_t source, int32_t* level, int32_t* parent, void* stream) {
+    return run_common(ws, nullptr, 0, source, level, parent, stream);
+}
+
+bfs_status_t bfs_run_multiroot(bfs_workspace_t ws, const int32_t* roots, int32_t k, int32_t* level,
+                               int32_t* parent, void* stream) {
+    if (!ws) return fail(BFS_EINVAL, "null workspace");
+    if (!roots || k < 1 || k > ws->g->n) return fail(BFS_EINVAL, "need 1 <= k <= n roots");
+    return run_common(ws, roots, k, 0, level, parent, stream);
+}
+
+bfs_status_t bfs_sync(bfs_workspace_t ws) {
+    if (!ws) return fail(BFS_EINVAL, "null workspace");
+    if (!ws->has_run) return BFS_OK;
+    HIP_TRY(hipSetDevice(ws->device));
+    HIP_TRY(hipEventSynchronize(ws->ev_done));
+    if (ws->host_status != BFS_OK) return ws->host_status;
+    HIP_TRY(hipMemcpy(ws->h_ctrl, ws->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
+    if (ws->h_ctrl->error)
+        return fail(BFS_EDEVICE, "device-side failure (code %d: %s)", ws->h_ctrl->error,
+                    ws->h_ctrl->error == -9 ? "malformed frontier" : "a wait timed out");
+    if (ws->h_ctrl->batch_overflow) return fail(BFS_EOVERFLOW, "batched search reached level 255");
+    return BFS_OK;
+}
+
+bfs_status_t bfs_last_stats(bfs_workspace_t ws, bfs_stats_t* out) {
+    if (!ws || !out) return fail(BFS_EINVAL, "null argument");
+    bfs_status_t st = bfs_sync(ws);
+    std::memset(out, 0, sizeof(*out));
+    out->status = st;
+    out->mode = ws->last_mode;
+    out->grid = ws->last_grid;
+    out->kernel_ms = -1.0;
+    if (!ws->has_run) return BFS_OK;
+    if (ws->profiled) {
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, ws->ev0, ws->ev1) == hipSuccess) out->kernel_ms = ms;
+    }
+    if (ws->host_stats) {
+        out->levels = (int32_t)ws->h_nl.size();
+        for (size_t i = 0; i < ws->h_nl.size(); ++i) {
+            out->reached += ws->h_nl[i];
+            out->edges += ws->h_el[i] > 0 ? ws->h_el[i] : 0;
+        }
+        return BFS_OK;
+    }
+    out->levels = ws->h_ctrl->levels;
+    out->small_levels = ws->h_ctrl->small_levels;
+    const int cnt = std::min(out->levels, kStatCap);
+    out->stats_truncated = out->levels > kStatCap;
+    std::vector<int32_t> a((size_t)std::max(cnt, 1)), b((size_t)std::max(cnt, 1));
+    if (cnt > 0) {
+        HIP_TRY(hipMemcpy(a.data(), ws->stat_nl, sizeof(int32_t) * cnt, hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(b.data(), ws->stat_el, sizeof(int32_t) * cnt, hipMemcpyDeviceToHost));
+    }
+    for (int i = 0; i < cnt; ++i) {
+        out->reached += a[i];
+        out->edges += b[i];
+    }
+    return BFS_OK;
+}
+
+bfs_status_t bfs_last_level_stats(bfs_workspace_t ws, int32_t cap, int64_t* n_l, int64_t* e_l, int32_t* count) {
+    if (!ws || !count || cap < 0 || (cap > 0 && (!n_l || !e_l))) return fail(BFS_EINVAL, "bad argument");
+    bfs_stats_t s;
+    bfs_status_t st = bfs_last_stats(ws, &s);
+    if (st) return st;
+    if (ws->host_stats) {
+        const int c = std::min<int>(cap, (int)ws->h_nl.size());
+        for (int i = 0; i < c; ++i) {
+            n_l[i] = ws->h_nl[i];
+            e_l[i] = ws->h_el[i];
+        }
+        *count = c;
+        return BFS_OK;
+    }
+    const int c = std::min(std::min(cap, s.levels), kStatCap);
+    std::vector<int32_t> a((size_t)std::max(c, 1)), b((size_t)std::max(c, 1));
+    if (c > 0) {
+        HIP_TRY(hipMemcpy(a.data(), ws->stat_nl, sizeof(int32_t) * c, hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(b.data(), ws->stat_el, sizeof(int32_t) * c, hipMemcpyDeviceToHost));
+    }
+    for (int i = 0; i < c; ++i) {
+        n_l[i] = a[i];
+        e_l[i] = b[i];
+    }
+    *count = c;
+    return BFS_OK;
+}
+
+int32_t bfs_prim_grain(void) { return kGrain; }
+
+bfs_status_t bfs_prim_compact(const int32_t* offsets, int32_t n, const int32_t* owner, const int32_t* cand,
+                              const int32_t* cnt, int32_t ntiles, int32_t* out_rs, int32_t* out_ex,
+                              int32_t* out_tstart, int32_t* totals, void* stream) {
+    if (!offsets || !owner || !cand || !cnt || !out_rs || !out_ex || !out_tstart || !totals || n < 0 || ntiles < 0)
+        return fail(BFS_EINVAL, "bad argument");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    unsigned long long* desc = nullptr;
+    Ctrl* ctrl = nullptr;
+    uint32_t* bitmap = nullptr;
+    HIP_TRY(dalloc(&desc, (size_t)std::max(ntiles, 1)));
+    HIP_TRY(dalloc(&ctrl, 1));
+    HIP_TRY(dalloc(&bitmap, ((size_t)n + 31) / 32));
+    HIP_TRY(hipMemsetAsync(ctrl, 0, sizeof(Ctrl), s));
+    HIP_TRY(hipMemsetAsync(bitmap, 0, std::max<size_t>(((size_t)n + 31) / 32, 1) * 4, s));
+    hipError_t e = launch_prim_compact(offsets, n, owner, cand, cnt, ntiles, out_rs, out_ex, out_tstart, totals, desc,
+                                       ctrl, bitmap, s);
+    hipError_t e2 = hipStreamSynchronize(s);
+    Ctrl hc;
+    hipError_t e3 = hipMemcpy(&hc, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost);
+    (void)hipFree(desc);
+    (void)hipFree(ctrl);
+    (void)hipFree(bitmap);
+    if (e != hipSuccess) return fail(BFS_EHIP, "launch: %s", hipGetErrorString(e));
+    if (e2 != hipSuccess) return fail(BFS_EHIP, "sync: %s", hipGetErrorString(e2));
+    if (e3 != hipSuccess) return fail(BFS_EHIP, "copy: %s", hipGetErrorString(e3));
+    if (hc.error) return fail(BFS_EDEVICE, "device wait timed out");
+    return BFS_OK;
+}
+
+bfs_status_t bfs_run_batch(bfs_workspace_t ws, const int32_t* sources, int32_t k, uint8_t* level, void* stream) {
+    (void)ws; (void)sources; (void)k; (void)level; (void)stream;
+    return fail(BFS_EINVAL, "batched search not built yet");
+}
+
+}  // extern "C"

@@ -1,0 +1,116 @@
+// Internal declarations shared by the kernels and the C-ABI layer of libbfs.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace s3bfs {
+
+// ---- launch geometry -------------------------------------------------------------------
+constexpr int kBlock = 512;               // threads per workgroup of the level loop
+constexpr int kWaves = kBlock / 64;       // wave64
+constexpr int kVT = 4;                    // edges per thread in one share
+constexpr int kGrain = kBlock * kVT;      // edges per share ("grainsize"), 2048
+constexpr int kVTS = 8;                   // edges per thread per round, single-workgroup levels
+constexpr int kSmallN = 4096;             // frontier capacity of single-workgroup levels (LDS)
+constexpr int kSmallC = 4096;             // candidates held in LDS in single-workgroup levels
+constexpr int kStatCap = 1 << 16;         // per-level statistics kept
+constexpr int kDefaultSmallEdges = 4 * kBlock * kVTS;
+
+// LDS words used by the level loop (the single-workgroup layout is the larger one).
+constexpr int kLdsSmall = kSmallN + (kSmallN + 1) + kSmallC;
+constexpr int kLdsLarge = 2 * (kGrain + 1);
+constexpr int kLdsWords = (kLdsSmall > kLdsLarge ? kLdsSmall : kLdsLarge) + 2 * kWaves + 8;
+
+// ---- device control block --------------------------------------------------------------
+// Every field is accessed with agent-scope atomics (coherent across XCDs).
+struct Ctrl {
+    unsigned long long bar;   // grid-barrier arrivals, monotone within a launch
+    unsigned int ticket[2];   // compaction tile tickets, per level parity
+    int nl[2];                // next frontier size (vertices of degree >= 1), per parity
+    int el[2];                // next frontier edge total, per parity
+    int kept[2];              // vertices reaching that level (any degree), per parity
+    int levels;               // frontiers processed (max level + 1)
+    int error;                // 0, or a BFS_E* code set on the device
+    int small_levels;         // levels run by a single workgroup
+    int resume;               // level at which the full grid resumes
+    int heartbeat;            // bumped by a lone workgroup so waiting ones keep waiting
+    int plain_next;           // PLAIN mode: next-frontier counter
+    int batch_active;         // batched: active vertices of the next level
+    int batch_edges;          // batched: their edge total
+    int batch_new;            // batched: vertices with new bits
+    int batch_overflow;       // batched: a level reached 255
+    int pad[12];
+};
+
+struct Params {
+    // graph
+    const int32_t* offsets;
+    const int32_t* cols;
+    int32_t n;
+    // outputs (caller-owned)
+    int32_t* level;
+    int32_t* parent;          // may be null
+    // workspace
+    uint32_t* bitmap;         // visited filter, 1 bit per vertex
+    int32_t* owner;           // owning candidate slot per vertex
+    int32_t* f_rs[2];         // frontier row starts, per parity
+    int32_t* f_ex[2];         // frontier exclusive degree sums (+ total), per parity
+    int32_t* tstart[2];       // share start points, per parity
+    int32_t* cand;            // candidate slots
+    int32_t* cnt;             // candidates per share
+    unsigned long long* desc[2];  // look-back descriptors, per parity
+    Ctrl* ctrl;
+    int32_t* stat_nl;
+    int32_t* stat_el;
+    // roots
+    const int32_t* roots;     // device array, or null for a single root
+    int32_t single_root;
+    int32_t nroots;
+    // tuning
+    int32_t small_edges;      // 0 disables single-workgroup levels
+    int32_t max_tiles;
+    uint64_t spin_ticks;      // s_memrealtime ticks a wait may last without progress
+};
+
+// Batched multi-source search (up to 256 sources, 4 x 64-bit masks per vertex).
+struct BatchParams {
+    const int32_t* offsets;
+    const int32_t* cols;
+    int32_t n;
+    int32_t k;                // sources in this batch
+    uint8_t* level;           // [n][k]
+    unsigned long long* fr;   // frontier masks [n][4]
+    unsigned long long* nx;   // next masks [n][4]
+    unsigned long long* vis;  // visited masks [n][4]
+    int32_t* act[2];          // active vertex lists per parity
+    int32_t* act_ex[2];       // their exclusive degree sums (+ total)
+    int32_t* tstart[2];       // share start points per parity
+    unsigned long long* desc[2];
+    uint32_t* act_bits;       // active bitmap of the current level
+    Ctrl* ctrl;
+    int32_t max_tiles;
+    int32_t pull_edges;       // edges above which a level pulls instead of pushing
+    uint64_t spin_ticks;
+};
+
+// ---- host-side launchers (bfs_kernels.hip) ---------------------------------------------
+int persistent_grid_capacity(int device);   // workgroups that can be co-resident
+hipError_t launch_prep(const Params& p, int prep_tiles, hipStream_t s);
+hipError_t launch_persistent(const Params& p, int grid, hipStream_t s);
+hipError_t launch_level_roots(const Params& p, hipStream_t s);
+hipError_t launch_level_compact(const Params& p, int l, int ntiles, int grid, hipStream_t s);
+hipError_t launch_level_expand(const Params& p, int l, int ntiles, int grid, hipStream_t s);
+hipError_t launch_parent(const Params& p, hipStream_t s);
+hipError_t launch_plain_init(const Params& p, int32_t* fv0, hipStream_t s);
+hipError_t launch_plain_level(const Params& p, int l, const int32_t* fv, int nf, int32_t* fv_next,
+                              hipStream_t s);
+hipError_t launch_prim_compact(const int32_t* offsets, int32_t n, const int32_t* owner,
+                               const int32_t* cand, const int32_t* cnt, int32_t ntiles,
+                               int32_t* out_rs, int32_t* out_ex, int32_t* out_tstart, int32_t* totals,
+                               unsigned long long* desc, Ctrl* ctrl, uint32_t* bitmap, hipStream_t s);
+
+hipError_t launch_batch_init(const BatchParams& p, const int32_t* sources_dev, hipStream_t s);
+hipError_t launch_batch_level(const BatchParams& p, int l, int grid, hipStream_t s);
+
+}  // namespace s3bfs

@@ -1,0 +1,167 @@
+"""GPU parity of single-source and multi-root search against the CPU oracle (bit-exact).
+
+Every case calls the HIP library through its C ABI (via the ctypes binding)
+and compares level and parent arrays element by element with oracle.bfs on
+the same seeded graph.  Sizes span many shares of 2048 edges and ragged
+tails; the mode/threshold/grid sweeps check that the benign race of the
+owner de-duplication never changes a result.
+"""
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+from oracle.certify import certify
+from tests.gpu_util import assert_same, run_single
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2209_08764_amd import (BFS_MODE_AUTO, BFS_MODE_INSENSITIVE, BFS_MODE_LEVEL,  # noqa: E402
+                                  BFS_MODE_PLAIN, BFS_OPT_GRID, BFS_OPT_MODE, BFS_OPT_SMALL_EDGES, BFSError,
+                                  Graph, Workspace, _lib)
+
+MODES = [BFS_MODE_AUTO, BFS_MODE_LEVEL, BFS_MODE_PLAIN, BFS_MODE_INSENSITIVE]
+
+
+@pytest.fixture(scope="module")
+def rmat14():
+    g = gg.rmat(14, seed=21)
+    return g, Graph(g.offsets, g.cols)
+
+
+def test_library_is_the_in_tree_build():
+    lib = _lib.load()
+    assert lib._name.endswith("paper_2209_08764_amd/libbfs.so")
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_rmat14_all_modes(rmat14, mode):
+    g, G = rmat14
+    ws = Workspace(G, mode=mode)
+    for s in gg.pick_sources(g, 4, seed=mode + 1):
+        lv, par = run_single(ws, s)
+        assert_same(lv, par, g, [s])
+
+
+@pytest.mark.parametrize("small_edges", [0, 1, 100, 5000, 1 << 30])
+@pytest.mark.parametrize("grid", [0, 1, 3, 37])
+def test_thresholds_and_grids_do_not_change_results(rmat14, small_edges, grid):
+    g, G = rmat14
+    ws = Workspace(G, small_edges=small_edges, grid=grid)
+    s = int(gg.pick_sources(g, 1, seed=5)[0])
+    lv, par = run_single(ws, s)
+    assert_same(lv, par, g, [s])
+
+
+@pytest.mark.parametrize("make,srcs", [
+    (lambda: gg.grid(64, 64), [0, 2080, 4095]),
+    (lambda: gg.grid(257, 3), [0, 400]),
+    (lambda: gg.grid(1, 3000), [0, 1500]),           # a path: 3000 levels
+    (lambda: gg.powerlaw_forest(1 << 13, seed=3), None),
+    (lambda: gg.erdos_renyi(1 << 14, 8.0, seed=4), None),
+    (lambda: gg.rmat(10, seed=2, permute=False), None),
+])
+@pytest.mark.parametrize("mode", [BFS_MODE_AUTO, BFS_MODE_INSENSITIVE, BFS_MODE_LEVEL])
+def test_structured_graphs(make, srcs, mode):
+    g = make()
+    G = Graph(g.offsets, g.cols)
+    ws = Workspace(G, mode=mode)
+    if srcs is None:
+        srcs = gg.pick_sources(g, 3, seed=9)
+    for s in srcs:
+        lv, par = run_single(ws, s)
+        assert_same(lv, par, g, [s])
+
+
+def test_isolated_source_and_tiny_graphs():
+    g = gg.from_edges(6, [(0, 1), (1, 2)])
+    G = Graph(g.offsets, g.cols)
+    ws = Workspace(G)
+    for s in range(6):
+        lv, par = run_single(ws, s)
+        assert_same(lv, par, g, [s])
+    one = gg.from_edges(1, [])
+    ws1 = Workspace(Graph(one.offsets, one.cols))
+    lv, par = run_single(ws1, 0)
+    assert lv.tolist() == [0] and par.tolist() == [0]
+
+
+def test_hub_spanning_many_shares():
+    # a star with 100k leaves: one vertex's row spans ~50 shares
+    n = 100_001
+    g = gg.from_edges(n, [(0, i) for i in range(1, n)] + [(5, 6), (7, 8)])
+    G = Graph(g.offsets, g.cols)
+    for mode in (BFS_MODE_AUTO, BFS_MODE_LEVEL):
+        ws = Workspace(G, mode=mode)
+        for s in (0, 17):
+            lv, par = run_single(ws, s)
+            assert_same(lv, par, g, [s])
+
+
+def test_multiroot_disjoint_union():
+    parts = [gg.grid(30, 20), gg.rmat(9, seed=3), gg.powerlaw_forest(2000, seed=1), gg.from_edges(3, [])]
+    u, base = gg.disjoint_union(parts)
+    roots = [int(base[0]) + 5, int(base[1]) + int(gg.pick_sources(parts[1], 1)[0]), int(base[2]), int(base[3]) + 1]
+    G = Graph(u.offsets, u.cols)
+    ws = Workspace(G)
+    lv, par = ws.run_multiroot(roots)
+    ws.sync()
+    assert_same(lv.cpu().numpy(), par.cpu().numpy(), u, roots)
+    # repeated and same-component roots
+    roots2 = roots + [roots[0], int(base[0]) + 100]
+    lv, par = ws.run_multiroot(roots2)
+    ws.sync()
+    assert_same(lv.cpu().numpy(), par.cpu().numpy(), u, roots2)
+
+
+def test_level_stats_match_oracle(rmat14):
+    g, G = rmat14
+    for mode in (BFS_MODE_AUTO, BFS_MODE_LEVEL, BFS_MODE_INSENSITIVE):
+        ws = Workspace(G, mode=mode)
+        s = int(gg.pick_sources(g, 1, seed=33)[0])
+        run_single(ws, s)
+        n_l, e_l = ws.level_stats()
+        lv = oracle.bfs_levels(g.offsets, g.cols, s)
+        wn, we = oracle.level_stats(g.offsets, lv)
+        assert n_l.tolist() == wn.tolist()
+        assert e_l.tolist() == we.tolist()
+        st = ws.stats()
+        assert st["levels"] == len(wn) and st["reached"] == wn.sum() and st["edges"] == we.sum()
+
+
+def test_determinism_repeated_runs(rmat14):
+    g, G = rmat14
+    ws = Workspace(G)
+    s = int(gg.pick_sources(g, 1, seed=8)[0])
+    first = run_single(ws, s)
+    for _ in range(5):
+        again = run_single(ws, s)
+        assert np.array_equal(first[0], again[0]) and np.array_equal(first[1], again[1])
+
+
+def test_certificate_without_parent_pass_inputs(rmat14):
+    g, G = rmat14
+    ws = Workspace(G)
+    s = int(gg.pick_sources(g, 1, seed=77)[0])
+    lv, par = run_single(ws, s)
+    assert certify(g.offsets, g.cols, [s], lv, par) == []
+    lv2, _ = run_single(ws, s, want_parent=False)
+    assert np.array_equal(lv, lv2)
+
+
+def test_errors(rmat14):
+    g, G = rmat14
+    ws = Workspace(G)
+    lv = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    with pytest.raises(BFSError) as e:
+        from paper_2209_08764_amd import bfs_run
+        bfs_run(ws.handle, g.n, lv)
+    assert e.value.status == _lib.BFS_ERANGE
+    with pytest.raises(BFSError) as e:
+        ws.set(BFS_OPT_MODE, 99)
+    assert e.value.status == _lib.BFS_EINVAL
+    bad = gg.Graph(np.array([0, 1, 1], np.int32), np.array([1], np.int32))
+    with pytest.raises(BFSError) as e:
+        Graph(bad.offsets, bad.cols, validate=True)
+    assert e.value.status == _lib.BFS_EBADCSR
