@@ -1,0 +1,262 @@
+#!/usr/bin/env python3
+"""Benchmark of the S3BFS hot path on one MI355X.
+
+Headline workload: R-MAT scale 24 (edge factor 16, a/b/c/d = .57/.19/.19/.05,
+symmetrised, deduplicated, vertex-permuted), 64 seeded sources run one at a
+time.  One "step" is one complete single-source search (init, every level,
+parent pass) from the next source; `value` is the harmonic mean over sources
+of GTEPS = (undirected edges in the source's component) / (time of the
+search), with the CSR already resident in HBM.
+
+Printed on one JSON line: the contract fields, a roofline object for the
+dominant kernel (the persistent level-loop kernel, timed with HIP events on
+its stream), the CPU oracle's throughput on a bounded sample, and extras
+(the plain per-level kernel, per-level launches and the work-insensitive
+variant on the same graph; the other workloads when implemented).
+Progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import threading
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "GTEPS single-source & 256-source batch vs plain; p50/p99 query latency"
+PROFILE_DIR = os.path.join(ROOT, "profiles")
+KERNEL_SRC = os.path.join(ROOT, "paper_2209_08764_amd", "csrc", "bfs_kernels.hip")
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def hmean(x):
+    x = np.asarray(x, dtype=np.float64)
+    return float(len(x) / np.sum(1.0 / x)) if len(x) else float("nan")
+
+
+def kernel_source_hash() -> str:
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def algorithmic_bytes(n: int, n_c: int, m_c: int):
+    """Bytes the search must move at least once (whole run, persistent kernel)."""
+    run = 4 * m_c + 8 * n + 16 * n_c
+    kernel = run - 4 * n          # the level fill is done by the preparation kernel
+    return run, kernel
+
+
+def stored_traffic(workload: str):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they match this kernel source."""
+    path = os.path.join(PROFILE_DIR, f"traffic_persistent_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except Exception:
+        return None
+    if d.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def time_single_source(ws, level, parent, sources, steps, torch, mc_half):
+    """Runs `steps` searches cycling over sources; returns per-step ms, wall ms, kernel ms."""
+    from paper_2209_08764_amd import bfs_kernel_times, bfs_run
+    ws_h = ws.handle
+    bfs_kernel_times(ws_h)  # forget earlier profiled runs
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        s = int(sources[i % len(sources)])
+        starts[i].record()
+        bfs_run(ws_h, s, level, parent)
+        ends[i].record()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3
+    ws.sync()
+    step_ms = np.array([a.elapsed_time(b) for a, b in zip(starts, ends)])
+    kms = bfs_kernel_times(ws_h)
+    return step_ms, wall, kms
+
+
+def per_source_hm(step_ms, sources, mc_half):
+    per = {}
+    for i, t in enumerate(step_ms):
+        per.setdefault(i % len(sources), []).append(t)
+    gteps = [mc_half[j] / (np.median(ts) * 1e-3) / 1e9 for j, ts in per.items()]
+    return hmean(gteps)
+
+
+def cpu_baseline(g, sources, threads: int):
+    """The oracle (plain sequential BFS + parent pass) on `threads` host threads, one source each."""
+    import oracle
+    oracle.build(force=False)
+    res = [None] * threads
+
+    def work(i):
+        s = int(sources[i % len(sources)])
+        lv, _, tb, tp = oracle.timed_bfs(g.offsets, g.cols, s)
+        mc = int(np.diff(g.offsets.astype(np.int64))[lv >= 0].sum())
+        res[i] = (mc // 2, tb, tp)
+
+    t0 = time.perf_counter()
+    th = [threading.Thread(target=work, args=(i,)) for i in range(threads)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    wall = time.perf_counter() - t0
+    edges = sum(r[0] for r in res)
+    single = hmean([r[0] / (r[1] + r[2]) / 1e9 for r in res])
+    return {
+        "value": round(edges / wall / 1e9, 5),
+        "unit": "GTEPS",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"{threads} of the workload's sources, one per host thread, search + parent pass each "
+                  f"({wall:.1f} s wall)",
+        "single_core_gteps_hmean": round(single, 5),
+        "search_s_mean": round(float(np.mean([r[1] for r in res])), 3),
+        "parent_s_mean": round(float(np.mean([r[2] for r in res])), 3),
+    }
+
+
+def host_cores() -> int:
+    try:
+        n = len(os.sched_getaffinity(0))
+    except Exception:
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
+def run(args):
+    import torch
+
+    import graphgen as gg
+    from graphgen import workloads as W
+    from paper_2209_08764_amd import (BFS_MODE_AUTO, BFS_MODE_INSENSITIVE, BFS_MODE_LEVEL, BFS_MODE_PLAIN,
+                                      BFS_OPT_MODE, BFS_OPT_PROFILE, Graph, Workspace, _lib)
+
+    _lib.load()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+
+    log(f"generating R-MAT scale {args.scale} ({gg.num_threads()} host threads)")
+    t = time.perf_counter()
+    g, sources = W.c3_rmat24(scale=args.scale, nsrc=64)
+    log(f"  n={g.n} m={g.m} in {time.perf_counter() - t:.1f} s")
+    G = Graph(g.offsets, g.cols)
+    ws = Workspace(G, profile=1)
+    n = g.n
+    level = torch.empty(n, dtype=torch.int32, device="cuda")
+    parent = torch.empty(n, dtype=torch.int32, device="cuda")
+
+    # per-source component sizes from one untimed pass (also the first warm-up)
+    mc_half, nc = [], []
+    for s in sources:
+        ws.run(int(s), level, parent)
+        st = ws.stats()
+        if st["status"] != 0:
+            raise RuntimeError(f"device status {st['status']} on source {s}")
+        mc_half.append(st["edges"] / 2)
+        nc.append(st["reached"])
+        levels_used = st["levels"]
+    for i in range(args.warmup):
+        ws.run(int(sources[i % len(sources)]), level, parent)
+    ws.sync()
+    log(f"timing {args.steps} searches")
+    step_ms, wall_ms, kms = time_single_source(ws, level, parent, sources, args.steps, torch, mc_half)
+    value = per_source_hm(step_ms, sources, mc_half)
+    # roofline of the persistent kernel
+    kbytes = []
+    for i in range(args.steps):
+        j = i % len(sources)
+        kbytes.append(algorithmic_bytes(n, nc[j], int(2 * mc_half[j]))[1])
+    kb = float(np.mean(kbytes))
+    kt = float(np.mean(kms)) if len(kms) else float("nan")
+    achieved = kb / (kt * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": stored_traffic("rmat24"),
+                "kernel": "k_persistent", "kernel_ms_mean": round(kt, 4),
+                "algorithmic_bytes_per_launch": int(kb)}
+    log(f"single-source: {value:.2f} GTEPS hm, {np.mean(step_ms):.3f} ms/search, kernel {kt:.3f} ms, "
+        f"{achieved:.0f} GB/s algorithmic")
+
+    extras = {"levels": levels_used, "n": n, "m": g.m, "step_ms_median": round(float(np.median(step_ms)), 4)}
+    if not args.quick:
+        ws.set(BFS_OPT_PROFILE, 0)
+        for name, mode, nsrc in [("plain", BFS_MODE_PLAIN, 8), ("level", BFS_MODE_LEVEL, 8),
+                                 ("insensitive", BFS_MODE_INSENSITIVE, 16)]:
+            ws.set(BFS_OPT_MODE, mode)
+            sub = sources[:nsrc]
+            for s in sub[:2]:
+                ws.run(int(s), level, parent)
+            ws.sync()
+            sm, _, _ = time_single_source(ws, level, parent, sub, len(sub), torch, mc_half)
+            extras[f"{name}_gteps_hm"] = round(per_source_hm(sm, sub, mc_half[:nsrc]), 3)
+            extras[f"{name}_ms_median"] = round(float(np.median(sm)), 3)
+            log(f"{name}: {extras[f'{name}_gteps_hm']} GTEPS")
+        ws.set(BFS_OPT_MODE, BFS_MODE_AUTO)
+        extras["speedup_vs_plain"] = round(value / extras["plain_gteps_hm"], 2)
+
+    cpu = None
+    if not args.no_cpu:
+        threads = host_cores()
+        log(f"CPU oracle baseline on {threads} host threads")
+        cpu = cpu_baseline(g, sources, threads)
+        log(f"  oracle {cpu['value']} GTEPS on {threads} threads")
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "GTEPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall_ms / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": f"rmat{args.scale}_64src_single", "graph": "R-MAT", "scale": args.scale,
+                   "edgefactor": 16, "abcd": [0.57, 0.19, 0.19, 0.05], "symmetrised": True, "permuted": True,
+                   "sources": 64, "mode": "auto", "gteps_edges": "undirected edges in the component"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "extras": extras,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=192)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--scale", type=int, default=24)
+    ap.add_argument("--quick", action="store_true", help="headline workload only")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build runs the search on a single MI355X "
+              "(sharding across GPUs is not implemented)", file=sys.stderr)
+        sys.exit(2)
+    run(args)
+
+
+if __name__ == "__main__":
+    main()

@@ -159,6 +159,13 @@ bfs_status_t bfs_last_stats(bfs_workspace_t ws, bfs_stats_t* out);
 bfs_status_t bfs_last_level_stats(bfs_workspace_t ws, int32_t cap, int64_t* n_l, int64_t* e_l,
                                   int32_t* count);
 
+/* Durations (ms, HIP events on the run's stream) of the main kernel of every
+   run made with BFS_OPT_PROFILE = 1 since the previous call: the persistent
+   level-loop kernel (single-source and multi-root) or the level kernels of a
+   batched run.  Synchronises, copies min(recorded, cap) values into ms[],
+   sets *count, and forgets them.  At most 4096 runs are remembered. */
+bfs_status_t bfs_kernel_times(bfs_workspace_t ws, int32_t cap, double* ms, int32_t* count);
+
 const char* bfs_status_str(bfs_status_t s);
 const char* bfs_last_error(void);
 
@@ -177,16 +184,18 @@ const char* bfs_last_error(void);
  *   offsets[n+1]: graph CSR offsets (degree = offsets[v+1] - offsets[v]).
  *   Outputs: out_rs[i] = offsets[v_i], out_ex[i] = sum of the degrees of the
  *   survivors before i (in output order), out_ex[count] = total;
- *   out_tstart[t] = index of the survivor holding edge t*grain;
+ *   out_tstart[t] = index of the survivor holding edge t*grain (tstart_cap
+ *   entries available; BFS_EDEVICE if the edge total needs more);
  *   totals[0] = survivor count (degree >= 1 only), totals[1] = edge total
  *   (int32 device array of 2).  Survivors of degree 0 are dropped.
- *   Output order is unspecified; the set is exact.
+ *   out_rs needs n entries and out_ex n + 1.  Output order is unspecified;
+ *   the set is exact.  Synchronises with stream.
  * grain must be the library's tile size (bfs_prim_grain()).
  */
 bfs_status_t bfs_prim_compact(const int32_t* offsets, int32_t n, const int32_t* owner,
                               const int32_t* cand, const int32_t* cnt, int32_t ntiles,
                               int32_t* out_rs, int32_t* out_ex, int32_t* out_tstart,
-                              int32_t* totals, void* stream);
+                              int32_t tstart_cap, int32_t* totals, void* stream);
 
 /* Edges per share (tile) of the multi-workgroup level loop. */
 int32_t bfs_prim_grain(void);

@@ -20,7 +20,8 @@ from ._lib import (BFS_DEVICE_PTRS, BFS_HOST_PTRS, BFS_MODE_AUTO, BFS_MODE_INSEN
 __all__ = [
     "bfs_init", "bfs_graph_free", "bfs_graph_info", "bfs_workspace_bytes", "bfs_workspace_create",
     "bfs_workspace_free", "bfs_workspace_set_option", "bfs_run", "bfs_run_multiroot", "bfs_run_batch",
-    "bfs_sync", "bfs_last_stats", "bfs_last_level_stats", "bfs_status_str", "bfs_prim_compact",
+    "bfs_sync", "bfs_last_stats", "bfs_last_level_stats", "bfs_kernel_times", "bfs_status_str",
+    "bfs_prim_compact",
     "bfs_prim_grain", "Graph", "Workspace", "BFSError",
 ]
 
@@ -149,6 +150,13 @@ def bfs_last_level_stats(ws: int, cap: int = 1 << 16):
     return n_l[:cnt.value].copy(), e_l[:cnt.value].copy()
 
 
+def bfs_kernel_times(ws: int, cap: int = 4096) -> np.ndarray:
+    ms = np.zeros(cap, np.float64)
+    cnt = ctypes.c_int32()
+    _lib.check(_lib.load().bfs_kernel_times(ws, cap, ms.ctypes.data, ctypes.byref(cnt)), "bfs_kernel_times")
+    return ms[:cnt.value].copy()
+
+
 def bfs_prim_grain() -> int:
     return int(_lib.load().bfs_prim_grain())
 
@@ -159,7 +167,7 @@ def bfs_prim_compact(offsets, owner, cand, cnt, out_rs, out_ex, out_tstart, tota
     _lib.check(_lib.load().bfs_prim_compact(
         _dptr(offsets, i32, "offsets"), offsets.numel() - 1, _dptr(owner, i32, "owner"), _dptr(cand, i32, "cand"),
         _dptr(cnt, i32, "cnt"), cnt.numel(), _dptr(out_rs, i32, "out_rs"), _dptr(out_ex, i32, "out_ex"),
-        _dptr(out_tstart, i32, "out_tstart"), _dptr(totals, i32, "totals"), _stream_ptr(stream)),
+        _dptr(out_tstart, i32, "out_tstart"), out_tstart.numel(), _dptr(totals, i32, "totals"), _stream_ptr(stream)),
         "bfs_prim_compact")
 
 
@@ -242,6 +250,9 @@ class Workspace:
 
     def level_stats(self, cap: int = 1 << 16):
         return bfs_last_level_stats(self.handle, cap)
+
+    def kernel_times(self):
+        return bfs_kernel_times(self.handle)
 
     def free(self):
         if self.handle:

@@ -83,11 +83,13 @@ _SIGS = {
     "bfs_last_stats": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(bfs_stats_t)]),
     "bfs_last_level_stats": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                               ctypes.POINTER(ctypes.c_int32)]),
+    "bfs_kernel_times": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                          ctypes.POINTER(ctypes.c_int32)]),
     "bfs_status_str": (ctypes.c_char_p, [ctypes.c_int32]),
     "bfs_last_error": (ctypes.c_char_p, []),
     "bfs_prim_compact": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                           ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
-                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+                                          ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
     "bfs_prim_grain": (ctypes.c_int32, []),
 }
 

@@ -100,6 +100,9 @@ struct bfs_workspace_s {
     bool host_stats = false;
     std::vector<int64_t> h_nl, h_el;
     int32_t host_status = BFS_OK;
+    // BFS_OPT_PROFILE: event pairs around the main kernel of each run
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev;
+    size_t prof_used = 0;
 };
 
 namespace {
@@ -128,6 +131,7 @@ Params make_params(bfs_workspace_s* ws, int32_t* level, int32_t* parent) {
     p.offsets = ws->g->offsets;
     p.cols = ws->g->cols;
     p.n = ws->g->n;
+    p.m = ws->g->m;
     p.level = level;
     p.parent = parent;
     p.bitmap = ws->bitmap;
@@ -230,6 +234,21 @@ bfs_status_t run_plain_mode(bfs_workspace_s* ws, Params& p, hipStream_t s) {
     return BFS_OK;
 }
 
+constexpr size_t kProfCap = 4096;
+
+// Next free event pair for a profiled run (created on first use).
+bfs_status_t profile_slot(bfs_workspace_s* ws, std::pair<hipEvent_t, hipEvent_t>** out) {
+    if (ws->prof_used >= kProfCap) return fail(BFS_EINVAL, "more than %zu profiled runs without bfs_kernel_times", kProfCap);
+    if (ws->prof_used == ws->prof_ev.size()) {
+        hipEvent_t a, b;
+        HIP_TRY(hipEventCreate(&a));
+        HIP_TRY(hipEventCreate(&b));
+        ws->prof_ev.emplace_back(a, b);
+    }
+    *out = &ws->prof_ev[ws->prof_used++];
+    return BFS_OK;
+}
+
 bfs_status_t run_common(bfs_workspace_s* ws, const int32_t* roots_host, int32_t k, int32_t single,
                         int32_t* level, int32_t* parent, void* stream) {
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -266,10 +285,15 @@ bfs_status_t run_common(bfs_workspace_s* ws, const int32_t* roots_host, int32_t 
         const int root_tiles = (p.nroots + kGrain - 1) / kGrain;
         const int grid = grid_for(ws);
         HIP_TRY(launch_prep(p, root_tiles, s));
-        if (ws->profile) HIP_TRY(hipEventRecord(ws->ev0, s));
-        HIP_TRY(launch_persistent(p, grid, s));
+        std::pair<hipEvent_t, hipEvent_t>* pe = nullptr;
         if (ws->profile) {
-            HIP_TRY(hipEventRecord(ws->ev1, s));
+            st = profile_slot(ws, &pe);
+            if (st) return st;
+            HIP_TRY(hipEventRecord(pe->first, s));
+        }
+        HIP_TRY(launch_persistent(p, grid, s));
+        if (pe) {
+            HIP_TRY(hipEventRecord(pe->second, s));
             ws->profiled = true;
         }
         ws->last_grid = grid;
@@ -411,6 +435,10 @@ bfs_status_t bfs_workspace_free(bfs_workspace_t ws) {
     if (ws->ev_done) (void)hipEventDestroy(ws->ev_done);
     if (ws->ev0) (void)hipEventDestroy(ws->ev0);
     if (ws->ev1) (void)hipEventDestroy(ws->ev1);
+    for (auto& pe : ws->prof_ev) {
+        (void)hipEventDestroy(pe.first);
+        (void)hipEventDestroy(pe.second);
+    }
     delete ws;
     return BFS_OK;
 }
@@ -471,7 +499,16 @@ bfs_status_t bfs_workspace_create(bfs_graph_t g, int32_t max_sources, bfs_worksp
         bfs_workspace_free(ws);
         return fail(BFS_EHIP, "could not size the persistent grid");
     }
-    if (hipMemset(ws->ctrl, 0, sizeof(Ctrl)) != hipSuccess) {
+    // defined contents everywhere, so no stale or never-written entry can hold an out-of-range index
+    bool zok = hipMemset(ws->cnt, 0, sizeof(int32_t) * (size_t)T) == hipSuccess &&
+               hipMemset(ws->cand, 0, sizeof(int32_t) * (size_t)T * kGrain) == hipSuccess &&
+               hipMemset(ws->owner, 0xff, sizeof(int32_t) * n) == hipSuccess;
+    for (int i = 0; i < 2 && zok; ++i)
+        zok = hipMemset(ws->tstart[i], 0, sizeof(int32_t) * (size_t)T) == hipSuccess &&
+              hipMemset(ws->f_rs[i], 0, sizeof(int32_t) * (n + 2)) == hipSuccess &&
+              hipMemset(ws->f_ex[i], 0, sizeof(int32_t) * (n + 2)) == hipSuccess &&
+              hipMemset(ws->desc[i], 0, sizeof(unsigned long long) * (size_t)T) == hipSuccess;
+    if (!zok || hipMemset(ws->ctrl, 0, sizeof(Ctrl)) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
         bfs_workspace_free(ws);
         return fail(BFS_EHIP, "hipMemset failed");
     }
@@ -540,9 +577,10 @@ bfs_status_t bfs_last_stats(bfs_workspace_t ws, bfs_stats_t* out) {
     out->grid = ws->last_grid;
     out->kernel_ms = -1.0;
     if (!ws->has_run) return BFS_OK;
-    if (ws->profiled) {
+    if (ws->profiled && ws->prof_used > 0) {
         float ms = 0;
-        if (hipEventElapsedTime(&ms, ws->ev0, ws->ev1) == hipSuccess) out->kernel_ms = ms;
+        const auto& pe = ws->prof_ev[ws->prof_used - 1];
+        if (hipEventElapsedTime(&ms, pe.first, pe.second) == hipSuccess) out->kernel_ms = ms;
     }
     if (ws->host_stats) {
         out->levels = (int32_t)ws->h_nl.size();
@@ -596,12 +634,29 @@ bfs_status_t bfs_last_level_stats(bfs_workspace_t ws, int32_t cap, int64_t* n_l,
     return BFS_OK;
 }
 
+bfs_status_t bfs_kernel_times(bfs_workspace_t ws, int32_t cap, double* ms, int32_t* count) {
+    if (!ws || !count || cap < 0 || (cap > 0 && !ms)) return fail(BFS_EINVAL, "bad argument");
+    HIP_TRY(hipSetDevice(ws->device));
+    int32_t c = 0;
+    for (size_t i = 0; i < ws->prof_used; ++i) {
+        const auto& pe = ws->prof_ev[i];
+        HIP_TRY(hipEventSynchronize(pe.second));
+        float t = 0;
+        HIP_TRY(hipEventElapsedTime(&t, pe.first, pe.second));
+        if (c < cap) ms[c++] = t;
+    }
+    ws->prof_used = 0;
+    *count = c;
+    return BFS_OK;
+}
+
 int32_t bfs_prim_grain(void) { return kGrain; }
 
 bfs_status_t bfs_prim_compact(const int32_t* offsets, int32_t n, const int32_t* owner, const int32_t* cand,
                               const int32_t* cnt, int32_t ntiles, int32_t* out_rs, int32_t* out_ex,
-                              int32_t* out_tstart, int32_t* totals, void* stream) {
-    if (!offsets || !owner || !cand || !cnt || !out_rs || !out_ex || !out_tstart || !totals || n < 0 || ntiles < 0)
+                              int32_t* out_tstart, int32_t tstart_cap, int32_t* totals, void* stream) {
+    if (!offsets || !owner || !cand || !cnt || !out_rs || !out_ex || !out_tstart || !totals || n < 0 || ntiles < 0 ||
+        tstart_cap < 0)
         return fail(BFS_EINVAL, "bad argument");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     unsigned long long* desc = nullptr;
@@ -612,8 +667,8 @@ bfs_status_t bfs_prim_compact(const int32_t* offsets, int32_t n, const int32_t* 
     HIP_TRY(dalloc(&bitmap, ((size_t)n + 31) / 32));
     HIP_TRY(hipMemsetAsync(ctrl, 0, sizeof(Ctrl), s));
     HIP_TRY(hipMemsetAsync(bitmap, 0, std::max<size_t>(((size_t)n + 31) / 32, 1) * 4, s));
-    hipError_t e = launch_prim_compact(offsets, n, owner, cand, cnt, ntiles, out_rs, out_ex, out_tstart, totals, desc,
-                                       ctrl, bitmap, s);
+    hipError_t e = launch_prim_compact(offsets, n, owner, cand, cnt, ntiles, out_rs, out_ex, out_tstart, tstart_cap,
+                                       totals, desc, ctrl, bitmap, s);
     hipError_t e2 = hipStreamSynchronize(s);
     Ctrl hc;
     hipError_t e3 = hipMemcpy(&hc, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost);

@@ -40,7 +40,8 @@ struct Ctrl {
     int batch_edges;          // batched: their edge total
     int batch_new;            // batched: vertices with new bits
     int batch_overflow;       // batched: a level reached 255
-    int pad[12];
+    int r_nl, r_el, r_kept;   // frontier handed back by a lone workgroup (level = resume)
+    int pad[9];
 };
 
 struct Params {
@@ -48,6 +49,7 @@ struct Params {
     const int32_t* offsets;
     const int32_t* cols;
     int32_t n;
+    int64_t m;
     // outputs (caller-owned)
     int32_t* level;
     int32_t* parent;          // may be null
@@ -107,8 +109,9 @@ hipError_t launch_plain_level(const Params& p, int l, const int32_t* fv, int nf,
                               hipStream_t s);
 hipError_t launch_prim_compact(const int32_t* offsets, int32_t n, const int32_t* owner,
                                const int32_t* cand, const int32_t* cnt, int32_t ntiles,
-                               int32_t* out_rs, int32_t* out_ex, int32_t* out_tstart, int32_t* totals,
-                               unsigned long long* desc, Ctrl* ctrl, uint32_t* bitmap, hipStream_t s);
+                               int32_t* out_rs, int32_t* out_ex, int32_t* out_tstart, int32_t tstart_cap,
+                               int32_t* totals, unsigned long long* desc, Ctrl* ctrl, uint32_t* bitmap,
+                               hipStream_t s);
 
 hipError_t launch_batch_init(const BatchParams& p, const int32_t* sources_dev, hipStream_t s);
 hipError_t launch_batch_level(const BatchParams& p, int l, int grid, hipStream_t s);

@@ -132,6 +132,12 @@ __device__ bool grid_barrier(Ctrl* c, uint64_t spin_ticks, int* s_flag) {
     return *s_flag != 0;
 }
 
+// Records an internal inconsistency; the caller then skips the access that
+// would have gone out of bounds and the run reports BFS_EDEVICE.
+__device__ __forceinline__ void flag_internal(Ctrl* c) {
+    __hip_atomic_store(&c->error, BFS_EINTERNAL_CODE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // ---- look-back descriptors ---------------------------------------------------------------
 // [63:62] status (0 empty, 1 tile aggregate, 2 inclusive prefix), [61:31] count, [30:0] edges.
 __device__ __forceinline__ unsigned long long pack_desc(unsigned st, unsigned cnt, unsigned sum) {
@@ -172,9 +178,13 @@ __device__ bool lookback(unsigned long long* desc, int k, int agg_c, int agg_s, 
 }
 
 // Marks every share that starts inside [e, e + d) as starting at frontier entry pos.
-__device__ __forceinline__ void scatter_starts(int32_t* tstart, int pos, int e, int d) {
+__device__ __forceinline__ void scatter_starts(const Params& p, int32_t* tstart, int pos, int e, int d) {
     int64_t t = ((int64_t)e + kGrain - 1) / kGrain;
-    const int64_t tend = ((int64_t)e + d + kGrain - 1) / kGrain;
+    int64_t tend = ((int64_t)e + d + kGrain - 1) / kGrain;
+    if (t < 0 || tend > p.max_tiles) {
+        flag_internal(p.ctrl);
+        return;
+    }
     for (; t < tend; ++t) tstart[t] = pos;
 }
 
@@ -191,7 +201,11 @@ __device__ bool compact_tile(const Params& p, int l, int k, int ntiles, int* lds
     int* s_b = s_wave2 + kWaves;
     const int par = l & 1;
     const int np = (l + 1) & 1;
-    const int c = p.cnt[k];
+    int c = p.cnt[k];
+    if (c < 0 || c > kGrain) {
+        if (threadIdx.x == 0) flag_internal(p.ctrl);
+        c = 0;
+    }
     int v[kVT], rs[kVT], d[kVT];
     int tc = 0, ts = 0, traw = 0;
 #pragma unroll
@@ -201,7 +215,8 @@ __device__ bool compact_tile(const Params& p, int l, int k, int ntiles, int* lds
         if (idx < c) {
             const int slot = k * kGrain + idx;
             const int vv = p.cand[slot];
-            if (p.owner[vv] == slot) v[i] = vv;
+            if ((unsigned)vv >= (unsigned)p.n) flag_internal(p.ctrl);
+            else if (p.owner[vv] == slot) v[i] = vv;
         }
     }
 #pragma unroll
@@ -229,7 +244,8 @@ __device__ bool compact_tile(const Params& p, int l, int k, int ntiles, int* lds
         if (ok && k == ntiles - 1) {
             st_rel(&p.ctrl->nl[np], pc + C);
             st_rel(&p.ctrl->el[np], ps + S);
-            p.f_ex[np][pc + C] = ps + S;
+            if (pc + C <= p.n) p.f_ex[np][pc + C] = ps + S;
+            else flag_internal(p.ctrl);
         }
     }
     __syncthreads();
@@ -247,9 +263,13 @@ __device__ bool compact_tile(const Params& p, int l, int k, int ntiles, int* lds
             __hip_atomic_fetch_or(&p.bitmap[v[i] >> 5], 1u << (v[i] & 31), __ATOMIC_RELAXED,
                                   __HIP_MEMORY_SCOPE_AGENT);
             if (d[i] > 0) {
-                frs[pos] = rs[i];
-                fex[pos] = e;
-                scatter_starts(tst, pos, e, d[i]);
+                if ((unsigned)pos < (unsigned)p.n) {
+                    frs[pos] = rs[i];
+                    fex[pos] = e;
+                    scatter_starts(p, tst, pos, e, d[i]);
+                } else {
+                    flag_internal(p.ctrl);
+                }
                 ++pos;
                 e += d[i];
             }
@@ -286,10 +306,13 @@ __device__ void expand_tile(const Params& p, int l, int k, int ntiles, int n_l, 
     const int j0 = tst[k];
     const int j1 = (k + 1 < ntiles) ? tst[k + 1] : n_l - 1;
     const int nv = j1 - j0 + 1;  // <= kGrain + 1: every frontier vertex has degree >= 1
-    if (j0 < 0 || j1 >= n_l || nv < 1 || nv > kGrain + 1) {
+    if (j0 < 0 || j1 >= n_l || nv < 1 || nv > kGrain + 1 || k >= p.max_tiles) {
         // cannot happen for a well-formed frontier; refuse rather than overrun LDS
-        if (threadIdx.x == 0)
-            __hip_atomic_store(&p.ctrl->error, BFS_EINTERNAL_CODE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (threadIdx.x == 0) {
+            flag_internal(p.ctrl);
+            p.cnt[k < p.max_tiles ? k : 0] = 0;
+        }
+        __syncthreads();
         return;
     }
     const int32_t* fex = p.f_ex[par];
@@ -310,7 +333,13 @@ __device__ void expand_tile(const Params& p, int l, int k, int ntiles, int n_l, 
                 const int mid = (lo + hi) >> 1;
                 if (s_ex[mid] <= g) lo = mid; else hi = mid;
             }
-            v[i] = __builtin_nontemporal_load(p.cols + s_rs[lo] + (g - s_ex[lo]));
+            const int idx = s_rs[lo] + (g - s_ex[lo]);
+            if ((unsigned)idx < (unsigned)p.m) {
+                v[i] = __builtin_nontemporal_load(p.cols + idx);
+                if ((unsigned)v[i] >= (unsigned)p.n) v[i] = -1;
+            } else {
+                flag_internal(p.ctrl);
+            }
         }
     }
 #pragma unroll
@@ -386,7 +415,13 @@ __device__ void small_levels(const Params& p, int l, int n_l, int e_l, int* lds)
                         const int mid = (lo + hi) >> 1;
                         if (s_ex[mid] <= g) lo = mid; else hi = mid;
                     }
-                    v[i] = p.cols[s_rs[lo] + (g - s_ex[lo])];
+                    const int idx = s_rs[lo] + (g - s_ex[lo]);
+                    if ((unsigned)idx < (unsigned)p.m) {
+                        v[i] = p.cols[idx];
+                        if ((unsigned)v[i] >= (unsigned)p.n) v[i] = -1;
+                    } else {
+                        flag_internal(p.ctrl);
+                    }
                 }
             }
 #pragma unroll
@@ -434,7 +469,8 @@ __device__ void small_levels(const Params& p, int l, int n_l, int e_l, int* lds)
                 v[i] = -1;
                 if (idx < ncand) {
                     const int vv = idx < kSmallC ? s_cand[idx] : p.cand[idx];
-                    if (p.owner[vv] == idx) v[i] = vv;
+                    if ((unsigned)vv >= (unsigned)p.n) flag_internal(p.ctrl);
+                    else if (p.owner[vv] == idx) v[i] = vv;
                 }
             }
 #pragma unroll
@@ -459,9 +495,13 @@ __device__ void small_levels(const Params& p, int l, int n_l, int e_l, int* lds)
                     __hip_atomic_fetch_or(&p.bitmap[v[i] >> 5], 1u << (v[i] & 31), __ATOMIC_RELAXED,
                                           __HIP_MEMORY_SCOPE_AGENT);
                     if (d[i] > 0) {
-                        p.f_rs[np][pos] = rs[i];
-                        p.f_ex[np][pos] = e;
-                        scatter_starts(p.tstart[np], pos, e, d[i]);
+                        if ((unsigned)pos < (unsigned)p.n) {
+                            p.f_rs[np][pos] = rs[i];
+                            p.f_ex[np][pos] = e;
+                            scatter_starts(p, p.tstart[np], pos, e, d[i]);
+                        } else {
+                            flag_internal(p.ctrl);
+                        }
                         if (pos < kSmallN) {
                             s_rs[pos] = rs[i];
                             s_ex[pos] = e;
@@ -479,7 +519,7 @@ __device__ void small_levels(const Params& p, int l, int n_l, int e_l, int* lds)
         ++l;
         ++done_levels;
         if (threadIdx.x == 0) {
-            p.f_ex[np][outc] = outs;
+            if (outc <= p.n) p.f_ex[np][outc] = outs;
             if (outr > 0 && l < kStatCap) {
                 p.stat_nl[l] = outr;
                 p.stat_el[l] = outs;
@@ -490,10 +530,13 @@ __device__ void small_levels(const Params& p, int l, int n_l, int e_l, int* lds)
         n_l = outc;
         e_l = outs;
         if (n_l == 0 || n_l > kSmallN || e_l > p.small_edges) {
+            // hand the frontier back through the resume slot: the parity slots
+            // may still be read by workgroups that have not left the level the
+            // stretch started at
             if (threadIdx.x == 0) {
-                st_rel(&p.ctrl->nl[np], n_l);
-                st_rel(&p.ctrl->el[np], e_l);
-                st_rel(&p.ctrl->kept[np], outr);
+                st_rel(&p.ctrl->r_nl, n_l);
+                st_rel(&p.ctrl->r_el, e_l);
+                st_rel(&p.ctrl->r_kept, outr);
                 st_rel(&p.ctrl->resume, l);
                 __hip_atomic_fetch_add(&p.ctrl->small_levels, done_levels, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
@@ -577,12 +620,15 @@ __global__ void __launch_bounds__(kBlock) k_persistent(Params p) {
     if (!compact_phase(p, -1, root_tiles, lds)) return;
     if (!grid_barrier(c, p.spin_ticks, s_flag)) return;
 
+    // The size of each level is read once, right after the barrier that
+    // publishes it, into loop-carried values: the slot it came from may be
+    // rewritten before every workgroup would otherwise have read it again.
     int l = 0;
+    int n_l = ld_acq(&c->nl[0]);
+    int e_l = ld_acq(&c->el[0]);
+    int kept = ld_acq(&c->kept[0]);
     for (;;) {
         const int par = l & 1;
-        const int n_l = ld_acq(&c->nl[par]);
-        const int e_l = ld_acq(&c->el[par]);
-        const int kept = ld_acq(&c->kept[par]);
         if (blockIdx.x == 0 && threadIdx.x == 0 && kept > 0) {
             if (l < kStatCap) { p.stat_nl[l] = kept; p.stat_el[l] = e_l; }
             st_rel(&c->levels, l + 1);
@@ -592,6 +638,9 @@ __global__ void __launch_bounds__(kBlock) k_persistent(Params p) {
             if (blockIdx.x == 0) small_levels(p, l, n_l, e_l, lds);
             if (!grid_barrier(c, p.spin_ticks, s_flag)) return;
             l = ld_acq(&c->resume);
+            n_l = ld_acq(&c->r_nl);
+            e_l = ld_acq(&c->r_el);
+            kept = ld_acq(&c->r_kept);
             continue;
         }
         const int ntiles = (int)(((int64_t)e_l + kGrain - 1) / kGrain);
@@ -608,6 +657,9 @@ __global__ void __launch_bounds__(kBlock) k_persistent(Params p) {
         if (!compact_phase(p, l, ntiles, lds)) return;
         if (!grid_barrier(c, p.spin_ticks, s_flag)) return;
         ++l;
+        n_l = ld_acq(&c->nl[np]);
+        e_l = ld_acq(&c->el[np]);
+        kept = ld_acq(&c->kept[np]);
     }
     if (p.parent) parent_range(p, (int64_t)blockIdx.x * kBlock + threadIdx.x, (int64_t)G * kBlock);
 }
@@ -754,11 +806,12 @@ hipError_t launch_plain_level(const Params& p, int l, const int32_t* fv, int nf,
 
 hipError_t launch_prim_compact(const int32_t* offsets, int32_t n, const int32_t* owner, const int32_t* cand,
                                const int32_t* cnt, int32_t ntiles, int32_t* out_rs, int32_t* out_ex,
-                               int32_t* out_tstart, int32_t* totals, unsigned long long* desc, Ctrl* ctrl,
-                               uint32_t* bitmap, hipStream_t s) {
+                               int32_t* out_tstart, int32_t tstart_cap, int32_t* totals, unsigned long long* desc,
+                               Ctrl* ctrl, uint32_t* bitmap, hipStream_t s) {
     Params p{};
     p.offsets = offsets;
     p.n = n;
+    p.max_tiles = tstart_cap;
     p.owner = const_cast<int32_t*>(owner);
     p.cand = const_cast<int32_t*>(cand);
     p.cnt = const_cast<int32_t*>(cnt);

@@ -165,3 +165,21 @@ def test_errors(rmat14):
     with pytest.raises(BFSError) as e:
         Graph(bad.offsets, bad.cols, validate=True)
     assert e.value.status == _lib.BFS_EBADCSR
+
+
+def test_small_stretches_handing_over_to_the_full_grid():
+    # Low-degree sources on a larger R-MAT: the lone workgroup runs one or two
+    # small levels and hands a large frontier back to the whole grid (the
+    # hand-over must not disturb workgroups still reading the entry level).
+    g = gg.rmat(18, seed=41)
+    G = Graph(g.offsets, g.cols)
+    deg = g.degrees()
+    cand = np.flatnonzero((deg > 0) & (deg <= 3))
+    rng = np.random.default_rng(5)
+    srcs = rng.choice(cand, 12, replace=False)
+    for small in (16384, 2048, 0):
+        ws = Workspace(G, small_edges=small)
+        for s in srcs:
+            lv, par = run_single(ws, s)
+            assert_same(lv, par, g, [s])
+        assert ws.stats()["status"] == 0
