@@ -66,6 +66,9 @@ typedef struct bfs_workspace_s* bfs_workspace_t;  /* scratch for one in-flight r
 #define BFS_OPT_GRID        3  /* workgroups of the persistent kernel (0 = fill the GPU) */
 #define BFS_OPT_PROFILE     4  /* 1: time the main kernel with HIP events (bfs_stats_t.kernel_ms) */
 #define BFS_OPT_BATCH_PULL  5  /* batched search: edges above which a level pulls (-1 = never) */
+#define BFS_OPT_PUSH_EDGES  6  /* levels with at most this many edges push parents (atomic
+                                  minimum per edge); larger ones pull them from sorted rows
+                                  (default m / 8) */
 
 typedef struct {
     int32_t levels;          /* frontiers processed: max level + 1 */
@@ -166,6 +169,15 @@ bfs_status_t bfs_last_level_stats(bfs_workspace_t ws, int32_t cap, int64_t* n_l,
    sets *count, and forgets them.  At most 4096 runs are remembered. */
 bfs_status_t bfs_kernel_times(bfs_workspace_t ws, int32_t cap, double* ms, int32_t* count);
 
+/* Per-level device time of the last run in BFS_MODE_AUTO or INSENSITIVE:
+   expand_us[l] from the start of level l to the end of its scan of the
+   adjacency (the whole level when it ran on one workgroup up to its own
+   de-duplication), compact_us[l] for its de-duplication and linearisation.
+   Read from the device's 100 MHz clock by workgroup 0; count = 0 for the
+   host-paced modes.  Synchronises with the run. */
+bfs_status_t bfs_last_level_times(bfs_workspace_t ws, int32_t cap, double* expand_us, double* compact_us,
+                                  int32_t* count);
+
 const char* bfs_status_str(bfs_status_t s);
 const char* bfs_last_error(void);
 
@@ -182,19 +194,20 @@ const char* bfs_last_error(void);
  *     positions in cand.
  *   owner[n]: slot id that owns each vertex.
  *   offsets[n+1]: graph CSR offsets (degree = offsets[v+1] - offsets[v]).
- *   Outputs: out_rs[i] = offsets[v_i], out_ex[i] = sum of the degrees of the
+ *   Outputs: out_v[i] = v_i, the i-th survivor; out_rs[i] = offsets[v_i];
+ *   out_ex[i] = sum of the degrees of the
  *   survivors before i (in output order), out_ex[count] = total;
  *   out_tstart[t] = index of the survivor holding edge t*grain (tstart_cap
  *   entries available; BFS_EDEVICE if the edge total needs more);
  *   totals[0] = survivor count (degree >= 1 only), totals[1] = edge total
  *   (int32 device array of 2).  Survivors of degree 0 are dropped.
- *   out_rs needs n entries and out_ex n + 1.  Output order is unspecified;
+ *   out_v and out_rs need n entries, out_ex n + 1.  Output order is unspecified;
  *   the set is exact.  Synchronises with stream.
  * grain must be the library's tile size (bfs_prim_grain()).
  */
 bfs_status_t bfs_prim_compact(const int32_t* offsets, int32_t n, const int32_t* owner,
                               const int32_t* cand, const int32_t* cnt, int32_t ntiles,
-                              int32_t* out_rs, int32_t* out_ex, int32_t* out_tstart,
+                              int32_t* out_v, int32_t* out_rs, int32_t* out_ex, int32_t* out_tstart,
                               int32_t tstart_cap, int32_t* totals, void* stream);
 
 /* Edges per share (tile) of the multi-workgroup level loop. */

@@ -15,14 +15,18 @@ import numpy as np
 from . import _lib
 from ._lib import (BFS_DEVICE_PTRS, BFS_HOST_PTRS, BFS_MODE_AUTO, BFS_MODE_INSENSITIVE, BFS_MODE_LEVEL,
                    BFS_MODE_PLAIN, BFS_OPT_BATCH_PULL, BFS_OPT_GRID, BFS_OPT_MODE, BFS_OPT_PROFILE,
-                   BFS_OPT_SMALL_EDGES, BFS_VALIDATE, BFSError, bfs_stats_t)
+                   BFS_OPT_PUSH_EDGES, BFS_OPT_SMALL_EDGES, BFS_VALIDATE, BFSError, bfs_stats_t)
 
 __all__ = [
     "bfs_init", "bfs_graph_free", "bfs_graph_info", "bfs_workspace_bytes", "bfs_workspace_create",
     "bfs_workspace_free", "bfs_workspace_set_option", "bfs_run", "bfs_run_multiroot", "bfs_run_batch",
-    "bfs_sync", "bfs_last_stats", "bfs_last_level_stats", "bfs_kernel_times", "bfs_status_str",
+    "bfs_sync", "bfs_last_stats", "bfs_last_level_stats", "bfs_last_level_times", "bfs_kernel_times", "bfs_status_str",
     "bfs_prim_compact",
     "bfs_prim_grain", "Graph", "Workspace", "BFSError",
+    "BFS_MODE_AUTO", "BFS_MODE_LEVEL", "BFS_MODE_PLAIN", "BFS_MODE_INSENSITIVE", "BFS_OPT_MODE",
+    "BFS_OPT_SMALL_EDGES", "BFS_OPT_GRID", "BFS_OPT_PROFILE", "BFS_OPT_BATCH_PULL", "BFS_OPT_PUSH_EDGES",
+    "BFS_HOST_PTRS",
+    "BFS_DEVICE_PTRS", "BFS_VALIDATE",
 ]
 
 
@@ -46,7 +50,7 @@ def _dptr(t, dtype, what):
         raise TypeError(f"{what} must be a device tensor")
     if t.dtype != dtype or not t.is_contiguous():
         raise TypeError(f"{what} must be a contiguous {dtype} tensor")
-    return t.data_ptr()
+    return t.data_ptr() if t.numel() else None
 
 
 def bfs_status_str(status: int) -> str:
@@ -150,6 +154,15 @@ def bfs_last_level_stats(ws: int, cap: int = 1 << 16):
     return n_l[:cnt.value].copy(), e_l[:cnt.value].copy()
 
 
+def bfs_last_level_times(ws: int, cap: int = 1 << 16):
+    ex = np.zeros(cap, np.float64)
+    co = np.zeros(cap, np.float64)
+    cnt = ctypes.c_int32()
+    _lib.check(_lib.load().bfs_last_level_times(ws, cap, ex.ctypes.data, co.ctypes.data, ctypes.byref(cnt)),
+               "bfs_last_level_times")
+    return ex[:cnt.value].copy(), co[:cnt.value].copy()
+
+
 def bfs_kernel_times(ws: int, cap: int = 4096) -> np.ndarray:
     ms = np.zeros(cap, np.float64)
     cnt = ctypes.c_int32()
@@ -161,12 +174,13 @@ def bfs_prim_grain() -> int:
     return int(_lib.load().bfs_prim_grain())
 
 
-def bfs_prim_compact(offsets, owner, cand, cnt, out_rs, out_ex, out_tstart, totals, stream=None) -> None:
+def bfs_prim_compact(offsets, owner, cand, cnt, out_v, out_rs, out_ex, out_tstart, totals, stream=None) -> None:
     torch = _torch()
     i32 = torch.int32
     _lib.check(_lib.load().bfs_prim_compact(
         _dptr(offsets, i32, "offsets"), offsets.numel() - 1, _dptr(owner, i32, "owner"), _dptr(cand, i32, "cand"),
-        _dptr(cnt, i32, "cnt"), cnt.numel(), _dptr(out_rs, i32, "out_rs"), _dptr(out_ex, i32, "out_ex"),
+        _dptr(cnt, i32, "cnt"), cnt.numel(), _dptr(out_v, i32, "out_v"), _dptr(out_rs, i32, "out_rs"),
+        _dptr(out_ex, i32, "out_ex"),
         _dptr(out_tstart, i32, "out_tstart"), out_tstart.numel(), _dptr(totals, i32, "totals"), _stream_ptr(stream)),
         "bfs_prim_compact")
 
@@ -207,7 +221,7 @@ class Workspace:
         if mode is not None:
             bfs_workspace_set_option(self.handle, BFS_OPT_MODE, mode)
         names = {"small_edges": BFS_OPT_SMALL_EDGES, "grid": BFS_OPT_GRID, "profile": BFS_OPT_PROFILE,
-                 "batch_pull": BFS_OPT_BATCH_PULL}
+                 "batch_pull": BFS_OPT_BATCH_PULL, "push_edges": BFS_OPT_PUSH_EDGES}
         for k, v in opts.items():
             bfs_workspace_set_option(self.handle, names[k], v)
 
@@ -253,6 +267,9 @@ class Workspace:
 
     def kernel_times(self):
         return bfs_kernel_times(self.handle)
+
+    def level_times(self, cap: int = 1 << 16):
+        return bfs_last_level_times(self.handle, cap)
 
     def free(self):
         if self.handle:

@@ -36,6 +36,7 @@ BFS_OPT_SMALL_EDGES = 2
 BFS_OPT_GRID = 3
 BFS_OPT_PROFILE = 4
 BFS_OPT_BATCH_PULL = 5
+BFS_OPT_PUSH_EDGES = 6
 
 MODE_NAMES = {BFS_MODE_AUTO: "auto", BFS_MODE_LEVEL: "level", BFS_MODE_PLAIN: "plain",
               BFS_MODE_INSENSITIVE: "insensitive"}
@@ -85,11 +86,14 @@ _SIGS = {
                                               ctypes.POINTER(ctypes.c_int32)]),
     "bfs_kernel_times": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                           ctypes.POINTER(ctypes.c_int32)]),
+    "bfs_last_level_times": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                              ctypes.POINTER(ctypes.c_int32)]),
     "bfs_status_str": (ctypes.c_char_p, [ctypes.c_int32]),
     "bfs_last_error": (ctypes.c_char_p, []),
     "bfs_prim_compact": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                           ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
-                                          ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
+                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                          ctypes.c_void_p]),
     "bfs_prim_grain": (ctypes.c_int32, []),
 }
 

@@ -64,6 +64,7 @@ struct bfs_workspace_s {
     int32_t* owner = nullptr;
     int32_t* f_rs[2] = {nullptr, nullptr};
     int32_t* f_ex[2] = {nullptr, nullptr};
+    int32_t* f_v[2] = {nullptr, nullptr};
     int32_t* tstart[2] = {nullptr, nullptr};
     int32_t* cand = nullptr;
     int32_t* cnt = nullptr;
@@ -71,6 +72,7 @@ struct bfs_workspace_s {
     Ctrl* ctrl = nullptr;
     int32_t* stat_nl = nullptr;
     int32_t* stat_el = nullptr;
+    uint64_t* stat_ts = nullptr;
     int32_t* roots = nullptr;
     int32_t* plain_fv[2] = {nullptr, nullptr};
     // batched buffers
@@ -91,6 +93,7 @@ struct bfs_workspace_s {
     bool profiled = false;
     int32_t mode = BFS_MODE_AUTO;
     int32_t small_edges = kDefaultSmallEdges;
+    int32_t push_edges = -1;  // -1: m / 8 of the workspace's graph
     int32_t grid_opt = 0;
     int32_t profile = 0;
     int32_t batch_pull = -2;  // -2: library default
@@ -139,6 +142,7 @@ Params make_params(bfs_workspace_s* ws, int32_t* level, int32_t* parent) {
     for (int i = 0; i < 2; ++i) {
         p.f_rs[i] = ws->f_rs[i];
         p.f_ex[i] = ws->f_ex[i];
+        p.f_v[i] = ws->f_v[i];
         p.tstart[i] = ws->tstart[i];
         p.desc[i] = ws->desc[i];
     }
@@ -147,7 +151,12 @@ Params make_params(bfs_workspace_s* ws, int32_t* level, int32_t* parent) {
     p.ctrl = ws->ctrl;
     p.stat_nl = ws->stat_nl;
     p.stat_el = ws->stat_el;
+    p.stat_ts = ws->stat_ts;
     p.small_edges = ws->small_edges;
+    // Pushing costs one atomic per scanned edge into an unsettled vertex; pulling
+    // costs about one row read per new vertex but long ones when the frontier is
+    // small next to what it discovers.  Levels below an eighth of the graph push.
+    p.push_edges = ws->push_edges >= 0 ? ws->push_edges : (int32_t)std::min<int64_t>(ws->g->m / 8, INT32_MAX);
     p.max_tiles = ws->max_tiles;
     p.spin_ticks = kSpinTicks;
     return p;
@@ -177,17 +186,18 @@ bfs_status_t read_ctrl(bfs_workspace_s* ws, hipStream_t s) {
 // Level loop driven from the host: one expand and one compact launch per
 // level, each with a grid sized to the level's shares.
 bfs_status_t run_level_mode(bfs_workspace_s* ws, Params& p, hipStream_t s) {
-    const int root_tiles = (p.nroots + kGrain - 1) / kGrain;
+    const int rtiles = (p.nroots + kGrain - 1) / kGrain;
     const int gmax = grid_for(ws);
-    HIP_TRY(launch_prep(p, root_tiles, s));
-    HIP_TRY(launch_level_roots(p, s));
-    HIP_TRY(launch_level_compact(p, -1, root_tiles, std::min(root_tiles, gmax), s));
+    const int pr = std::min(rtiles, gmax);
+    HIP_TRY(launch_prep(p, pr, p.parent != nullptr, s));
+    HIP_TRY(launch_level_roots(p, pr, s));
+    HIP_TRY(launch_level_compact(p, -1, rtiles, pr, s));
     ws->h_nl.clear();
     ws->h_el.clear();
     for (int l = 0;; ++l) {
         bfs_status_t st = read_ctrl(ws, s);
         if (st) return st;
-        if (ws->h_ctrl->error) return fail(BFS_EDEVICE, "device wait timed out");
+        if (ws->h_ctrl->error) return fail(BFS_EDEVICE, "device-side failure (code %d)", ws->h_ctrl->error);
         const int par = l & 1;
         const int n_l = ws->h_ctrl->nl[par], e_l = ws->h_ctrl->el[par], kept = ws->h_ctrl->kept[par];
         if (kept > 0) {
@@ -196,11 +206,10 @@ bfs_status_t run_level_mode(bfs_workspace_s* ws, Params& p, hipStream_t s) {
         }
         if (n_l == 0) break;
         const int ntiles = (int)(((int64_t)e_l + kGrain - 1) / kGrain);
-        const int grid = std::min(ntiles, gmax);
-        HIP_TRY(launch_level_expand(p, l, ntiles, grid, s));
-        HIP_TRY(launch_level_compact(p, l, ntiles, grid, s));
+        const int shares = std::min(ntiles, gmax);  // P_l = min(P, W_l)
+        HIP_TRY(launch_level_expand(p, l, ntiles, shares, s));
+        HIP_TRY(launch_level_compact(p, l, ntiles, shares, s));
     }
-    if (p.parent) HIP_TRY(launch_parent(p, s));
     ws->host_stats = true;
     ws->last_grid = gmax;
     return BFS_OK;
@@ -214,7 +223,7 @@ bfs_status_t run_plain_mode(bfs_workspace_s* ws, Params& p, hipStream_t s) {
         HIP_TRY(dalloc(&ws->plain_fv[1], (size_t)n + 1));
     }
     if (p.roots) return fail(BFS_EINVAL, "BFS_MODE_PLAIN runs single-source searches only");
-    HIP_TRY(launch_prep(p, 0, s));
+    HIP_TRY(launch_prep(p, 0, false, s));
     HIP_TRY(launch_plain_init(p, ws->plain_fv[0], s));
     ws->h_nl.clear();
     ws->h_el.clear();
@@ -282,9 +291,9 @@ bfs_status_t run_common(bfs_workspace_s* ws, const int32_t* roots_host, int32_t 
         st = run_plain_mode(ws, p, s);
     } else {
         if (mode == BFS_MODE_INSENSITIVE) p.small_edges = 0;
-        const int root_tiles = (p.nroots + kGrain - 1) / kGrain;
         const int grid = grid_for(ws);
-        HIP_TRY(launch_prep(p, root_tiles, s));
+        const int rtiles = (p.nroots + kGrain - 1) / kGrain;
+        HIP_TRY(launch_prep(p, std::min(rtiles, grid), p.parent != nullptr, s));
         std::pair<hipEvent_t, hipEvent_t>* pe = nullptr;
         if (ws->profile) {
             st = profile_slot(ws, &pe);
@@ -424,9 +433,10 @@ bfs_status_t bfs_workspace_free(bfs_workspace_t ws) {
     if (!ws) return fail(BFS_EINVAL, "null workspace");
     (void)hipSetDevice(ws->device);
     if (ws->has_run) (void)hipEventSynchronize(ws->ev_done);
-    void* ptrs[] = {ws->bitmap, ws->owner, ws->f_rs[0], ws->f_rs[1], ws->f_ex[0], ws->f_ex[1], ws->tstart[0],
+    void* ptrs[] = {ws->bitmap, ws->owner, ws->f_rs[0], ws->f_rs[1], ws->f_ex[0], ws->f_ex[1], ws->f_v[0],
+                    ws->f_v[1], ws->tstart[0],
                     ws->tstart[1], ws->cand, ws->cnt, ws->desc[0], ws->desc[1], ws->ctrl, ws->stat_nl,
-                    ws->stat_el, ws->roots, ws->plain_fv[0], ws->plain_fv[1], ws->b_fr, ws->b_nx, ws->b_vis,
+                    ws->stat_el, ws->stat_ts, ws->roots, ws->plain_fv[0], ws->plain_fv[1], ws->b_fr, ws->b_nx, ws->b_vis,
                     ws->b_act[0], ws->b_act[1], ws->b_act_ex[0], ws->b_act_ex[1], ws->b_tstart[0],
                     ws->b_tstart[1], ws->b_desc[0], ws->b_desc[1], ws->b_act_bits, ws->b_sources};
     for (void* q : ptrs)
@@ -463,6 +473,7 @@ bfs_status_t bfs_workspace_create(bfs_graph_t g, int32_t max_sources, bfs_worksp
     for (int i = 0; i < 2; ++i) {
         A(dalloc(&ws->f_rs[i], n + 2));
         A(dalloc(&ws->f_ex[i], n + 2));
+        A(dalloc(&ws->f_v[i], n + 2));
         A(dalloc(&ws->tstart[i], (size_t)T));
         A(dalloc(&ws->desc[i], (size_t)T));
     }
@@ -471,6 +482,7 @@ bfs_status_t bfs_workspace_create(bfs_graph_t g, int32_t max_sources, bfs_worksp
     A(dalloc(&ws->ctrl, 1));
     A(dalloc(&ws->stat_nl, kStatCap));
     A(dalloc(&ws->stat_el, kStatCap));
+    A(dalloc(&ws->stat_ts, 3 * (size_t)kStatCap));
     A(dalloc(&ws->roots, n));
     if (max_sources > 1) {
         A(dalloc(&ws->b_fr, n * 4));
@@ -507,6 +519,7 @@ bfs_status_t bfs_workspace_create(bfs_graph_t g, int32_t max_sources, bfs_worksp
         zok = hipMemset(ws->tstart[i], 0, sizeof(int32_t) * (size_t)T) == hipSuccess &&
               hipMemset(ws->f_rs[i], 0, sizeof(int32_t) * (n + 2)) == hipSuccess &&
               hipMemset(ws->f_ex[i], 0, sizeof(int32_t) * (n + 2)) == hipSuccess &&
+              hipMemset(ws->f_v[i], 0, sizeof(int32_t) * (n + 2)) == hipSuccess &&
               hipMemset(ws->desc[i], 0, sizeof(unsigned long long) * (size_t)T) == hipSuccess;
     if (!zok || hipMemset(ws->ctrl, 0, sizeof(Ctrl)) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
         bfs_workspace_free(ws);
@@ -533,6 +546,10 @@ bfs_status_t bfs_workspace_set_option(bfs_workspace_t ws, int32_t option, int64_
             return BFS_OK;
         case BFS_OPT_PROFILE:
             ws->profile = value != 0;
+            return BFS_OK;
+        case BFS_OPT_PUSH_EDGES:
+            if (value < 0 || value > INT32_MAX) return fail(BFS_EINVAL, "bad push threshold");
+            ws->push_edges = (int32_t)value;
             return BFS_OK;
         case BFS_OPT_BATCH_PULL:
             if (value < -1 || value > INT32_MAX) return fail(BFS_EINVAL, "bad pull threshold");
@@ -650,13 +667,34 @@ bfs_status_t bfs_kernel_times(bfs_workspace_t ws, int32_t cap, double* ms, int32
     return BFS_OK;
 }
 
+bfs_status_t bfs_last_level_times(bfs_workspace_t ws, int32_t cap, double* expand_us, double* compact_us,
+                                  int32_t* count) {
+    if (!ws || !count || cap < 0 || (cap > 0 && (!expand_us || !compact_us))) return fail(BFS_EINVAL, "bad argument");
+    bfs_stats_t s;
+    bfs_status_t st = bfs_last_stats(ws, &s);
+    if (st) return st;
+    *count = 0;
+    if (ws->host_stats) return BFS_OK;  // per-level launches are not timed on the device
+    const int c = std::min(std::min(cap, s.levels), kStatCap);
+    if (c <= 0) return BFS_OK;
+    std::vector<uint64_t> ts(3 * (size_t)c);
+    HIP_TRY(hipMemcpy(ts.data(), ws->stat_ts, sizeof(uint64_t) * ts.size(), hipMemcpyDeviceToHost));
+    for (int i = 0; i < c; ++i) {
+        const double t0 = (double)ts[3 * i], t1 = (double)ts[3 * i + 1], t2 = (double)ts[3 * i + 2];
+        expand_us[i] = (t1 - t0) * 0.01;  // s_memrealtime runs at 100 MHz
+        compact_us[i] = (t2 - t1) * 0.01;
+    }
+    *count = c;
+    return BFS_OK;
+}
+
 int32_t bfs_prim_grain(void) { return kGrain; }
 
 bfs_status_t bfs_prim_compact(const int32_t* offsets, int32_t n, const int32_t* owner, const int32_t* cand,
-                              const int32_t* cnt, int32_t ntiles, int32_t* out_rs, int32_t* out_ex,
+                              const int32_t* cnt, int32_t ntiles, int32_t* out_v, int32_t* out_rs, int32_t* out_ex,
                               int32_t* out_tstart, int32_t tstart_cap, int32_t* totals, void* stream) {
-    if (!offsets || !owner || !cand || !cnt || !out_rs || !out_ex || !out_tstart || !totals || n < 0 || ntiles < 0 ||
-        tstart_cap < 0)
+    if (!offsets || !owner || (ntiles > 0 && (!cand || !cnt)) || !out_v || !out_rs || !out_ex || !out_tstart ||
+        !totals || n < 0 || ntiles < 0 || tstart_cap < 0)
         return fail(BFS_EINVAL, "bad argument");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     unsigned long long* desc = nullptr;
@@ -667,8 +705,8 @@ bfs_status_t bfs_prim_compact(const int32_t* offsets, int32_t n, const int32_t* 
     HIP_TRY(dalloc(&bitmap, ((size_t)n + 31) / 32));
     HIP_TRY(hipMemsetAsync(ctrl, 0, sizeof(Ctrl), s));
     HIP_TRY(hipMemsetAsync(bitmap, 0, std::max<size_t>(((size_t)n + 31) / 32, 1) * 4, s));
-    hipError_t e = launch_prim_compact(offsets, n, owner, cand, cnt, ntiles, out_rs, out_ex, out_tstart, tstart_cap,
-                                       totals, desc, ctrl, bitmap, s);
+    hipError_t e = launch_prim_compact(offsets, n, owner, cand, cnt, ntiles, out_v, out_rs, out_ex, out_tstart,
+                                       tstart_cap, totals, desc, ctrl, bitmap, s);
     hipError_t e2 = hipStreamSynchronize(s);
     Ctrl hc;
     hipError_t e3 = hipMemcpy(&hc, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost);

@@ -9,24 +9,27 @@ namespace s3bfs {
 // ---- launch geometry -------------------------------------------------------------------
 constexpr int kBlock = 512;               // threads per workgroup of the level loop
 constexpr int kWaves = kBlock / 64;       // wave64
-constexpr int kVT = 4;                    // edges per thread in one share
-constexpr int kGrain = kBlock * kVT;      // edges per share ("grainsize"), 2048
+constexpr int kVT = 4;                    // edges per thread in one sub-tile
+constexpr int kGrain = kBlock * kVT;      // edges per sub-tile (the share granularity), 2048
+constexpr int kSlice = kGrain + 1;        // frontier entries a sub-tile can touch
+constexpr int kPre = (kSlice + kBlock - 1) / kBlock;  // slice entries each thread prefetches
 constexpr int kVTS = 8;                   // edges per thread per round, single-workgroup levels
 constexpr int kSmallN = 4096;             // frontier capacity of single-workgroup levels (LDS)
 constexpr int kSmallC = 4096;             // candidates held in LDS in single-workgroup levels
 constexpr int kStatCap = 1 << 16;         // per-level statistics kept
 constexpr int kDefaultSmallEdges = 4 * kBlock * kVTS;
+constexpr int kPullScan = 16;             // neighbours a lane tests before a row goes to the whole workgroup
 
-// LDS words used by the level loop (the single-workgroup layout is the larger one).
-constexpr int kLdsSmall = kSmallN + (kSmallN + 1) + kSmallC;
-constexpr int kLdsLarge = 2 * (kGrain + 1);
+// LDS words used by the level loop (the two layouts share one allocation).
+constexpr int kLdsSmall = 2 * kSmallN + 1 + kSmallC;   // frontier (rs, ex) + candidates
+constexpr int kLdsLarge = 2 * 2 * kSlice;              // double-buffered sub-tile slices (ex, rs)
 constexpr int kLdsWords = (kLdsSmall > kLdsLarge ? kLdsSmall : kLdsLarge) + 2 * kWaves + 8;
 
 // ---- device control block --------------------------------------------------------------
 // Every field is accessed with agent-scope atomics (coherent across XCDs).
 struct Ctrl {
     unsigned long long bar;   // grid-barrier arrivals, monotone within a launch
-    unsigned int ticket[2];   // compaction tile tickets, per level parity
+    unsigned int unused[2];
     int nl[2];                // next frontier size (vertices of degree >= 1), per parity
     int el[2];                // next frontier edge total, per parity
     int kept[2];              // vertices reaching that level (any degree), per parity
@@ -58,19 +61,22 @@ struct Params {
     int32_t* owner;           // owning candidate slot per vertex
     int32_t* f_rs[2];         // frontier row starts, per parity
     int32_t* f_ex[2];         // frontier exclusive degree sums (+ total), per parity
-    int32_t* tstart[2];       // share start points, per parity
-    int32_t* cand;            // candidate slots
-    int32_t* cnt;             // candidates per share
-    unsigned long long* desc[2];  // look-back descriptors, per parity
+    int32_t* f_v[2];          // frontier vertex ids, per parity (written only if non-null)
+    int32_t* tstart[2];       // sub-tile start points, per parity
+    int32_t* cand;            // private queues: share b owns cand[tb*kGrain, te*kGrain)
+    int32_t* cnt;             // queue length per share
+    unsigned long long* desc[2];  // look-back descriptors per share, per parity
     Ctrl* ctrl;
     int32_t* stat_nl;
     int32_t* stat_el;
+    uint64_t* stat_ts;        // per level: start, start of compaction, end (s_memrealtime ticks)
     // roots
     const int32_t* roots;     // device array, or null for a single root
     int32_t single_root;
     int32_t nroots;
     // tuning
     int32_t small_edges;      // 0 disables single-workgroup levels
+    int32_t push_edges;       // levels with at most this many edges push parents, larger ones pull
     int32_t max_tiles;
     uint64_t spin_ticks;      // s_memrealtime ticks a wait may last without progress
 };
@@ -98,17 +104,17 @@ struct BatchParams {
 
 // ---- host-side launchers (bfs_kernels.hip) ---------------------------------------------
 int persistent_grid_capacity(int device);   // workgroups that can be co-resident
-hipError_t launch_prep(const Params& p, int prep_tiles, hipStream_t s);
+hipError_t launch_prep(const Params& p, int prep_shares, bool fill_parent, hipStream_t s);
 hipError_t launch_persistent(const Params& p, int grid, hipStream_t s);
-hipError_t launch_level_roots(const Params& p, hipStream_t s);
-hipError_t launch_level_compact(const Params& p, int l, int ntiles, int grid, hipStream_t s);
-hipError_t launch_level_expand(const Params& p, int l, int ntiles, int grid, hipStream_t s);
+hipError_t launch_level_roots(const Params& p, int shares, hipStream_t s);
+hipError_t launch_level_compact(const Params& p, int l, int ntiles, int shares, hipStream_t s);
+hipError_t launch_level_expand(const Params& p, int l, int ntiles, int shares, hipStream_t s);
 hipError_t launch_parent(const Params& p, hipStream_t s);
 hipError_t launch_plain_init(const Params& p, int32_t* fv0, hipStream_t s);
 hipError_t launch_plain_level(const Params& p, int l, const int32_t* fv, int nf, int32_t* fv_next,
                               hipStream_t s);
 hipError_t launch_prim_compact(const int32_t* offsets, int32_t n, const int32_t* owner,
-                               const int32_t* cand, const int32_t* cnt, int32_t ntiles,
+                               const int32_t* cand, const int32_t* cnt, int32_t ntiles, int32_t* out_v,
                                int32_t* out_rs, int32_t* out_ex, int32_t* out_tstart, int32_t tstart_cap,
                                int32_t* totals, unsigned long long* desc, Ctrl* ctrl, uint32_t* bitmap,
                                hipStream_t s);

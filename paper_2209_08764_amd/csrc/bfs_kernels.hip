@@ -148,32 +148,55 @@ __device__ __forceinline__ unsigned desc_st(unsigned long long d) { return (unsi
 __device__ __forceinline__ unsigned desc_cnt(unsigned long long d) { return (unsigned)(d >> 31) & 0x7fffffffu; }
 __device__ __forceinline__ unsigned desc_sum(unsigned long long d) { return (unsigned)d & 0x7fffffffu; }
 
-// Thread 0 publishes tile k's aggregate and looks back for its exclusive
-// prefix.  Returns false on a failed wait.
-__device__ bool lookback(unsigned long long* desc, int k, int agg_c, int agg_s, Ctrl* c, uint64_t spin_ticks,
-                         int* pre_c, int* pre_s) {
+// Wave 0 publishes tile k's aggregate and looks back for its exclusive
+// prefix, 64 predecessors per step: every lane loads one descriptor, the
+// closest inclusive prefix is found with a ballot, and the aggregates in
+// between are summed across the wave.  Must be called by all 64 lanes of one
+// wave.  Returns false on a failed wait.
+__device__ bool lookback_wave(unsigned long long* desc, int k, int agg_c, int agg_s, Ctrl* c,
+                              uint64_t spin_ticks, int* pre_c, int* pre_s) {
+    const int lane = lane_id();
     if (k == 0) {
-        st_rel(&desc[0], pack_desc(2, agg_c, agg_s));
+        if (lane == 0) st_rel(&desc[0], pack_desc(2, agg_c, agg_s));
         *pre_c = 0;
         *pre_s = 0;
         return true;
     }
-    st_rel(&desc[k], pack_desc(1, agg_c, agg_s));
-    unsigned ac = 0, as = 0;
-    int j = k - 1;
+    if (lane == 0) st_rel(&desc[k], pack_desc(1, agg_c, agg_s));
+    int acc_c = 0, acc_s = 0;
+    int base = k - 1;
+    uint64_t t0 = now_ticks();
     for (;;) {
-        unsigned long long d = ld_acq(&desc[j]);
-        if (desc_st(d) == 0) {
-            if (!spin_until(c, spin_ticks, [&] { return desc_st(d = ld_acq(&desc[j])) != 0; })) return false;
+        const int j = base - lane;
+        const unsigned long long d = j >= 0 ? ld_acq(&desc[j]) : pack_desc(2, 0, 0);
+        const unsigned st = desc_st(d);
+        const uint64_t b0 = ballot(st == 0);
+        const uint64_t b2 = ballot(st == 2);
+        // lanes up to and including the closest inclusive prefix (or all 64)
+        const int last = b2 ? __builtin_ctzll(b2) : 63;
+        const uint64_t need = last == 63 ? ~0ull : ((1ull << (last + 1)) - 1);
+        if (b0 & need) {
+            // a closer predecessor has not published yet: wait and reload
+            __builtin_amdgcn_s_sleep(1);
+            if (now_ticks() - t0 > spin_ticks || ld_acq(&c->error) != 0) {
+                if (lane == 0)
+                    __hip_atomic_store(&c->error, BFS_EDEVICE_CODE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                return false;
+            }
+            continue;
         }
-        ac += desc_cnt(d);
-        as += desc_sum(d);
-        if (desc_st(d) == 2) break;
-        --j;
+        const bool take = lane <= last;
+        const int vc = take ? (int)desc_cnt(d) : 0;
+        const int vs = take ? (int)desc_sum(d) : 0;
+        acc_c += __builtin_amdgcn_readlane(wave_incl_scan(vc), 63);
+        acc_s += __builtin_amdgcn_readlane(wave_incl_scan(vs), 63);
+        if (b2) break;
+        base -= 64;
+        t0 = now_ticks();
     }
-    st_rel(&desc[k], pack_desc(2, ac + agg_c, as + agg_s));
-    *pre_c = (int)ac;
-    *pre_s = (int)as;
+    if (lane == 0) st_rel(&desc[k], pack_desc(2, acc_c + agg_c, acc_s + agg_s));
+    *pre_c = acc_c;
+    *pre_s = acc_s;
     return true;
 }
 
@@ -192,137 +215,84 @@ struct Lds {
     int w[kLdsWords];
 };
 
-// ---- compaction of one tile's private queue ----------------------------------------------
-// l is the level whose candidates are compacted (-1 for the roots); the
-// survivors form the frontier of level l + 1.
-__device__ bool compact_tile(const Params& p, int l, int k, int ntiles, int* lds) {
-    int* s_wave = lds + kLdsWords - 2 * kWaves - 8;
-    int* s_wave2 = s_wave + kWaves;
-    int* s_b = s_wave2 + kWaves;
-    const int par = l & 1;
-    const int np = (l + 1) & 1;
-    int c = p.cnt[k];
-    if (c < 0 || c > kGrain) {
-        if (threadIdx.x == 0) flag_internal(p.ctrl);
-        c = 0;
-    }
-    int v[kVT], rs[kVT], d[kVT];
-    int tc = 0, ts = 0, traw = 0;
-#pragma unroll
-    for (int i = 0; i < kVT; ++i) {
-        const int idx = i * kBlock + threadIdx.x;
-        v[i] = -1;
-        if (idx < c) {
-            const int slot = k * kGrain + idx;
-            const int vv = p.cand[slot];
-            if ((unsigned)vv >= (unsigned)p.n) flag_internal(p.ctrl);
-            else if (p.owner[vv] == slot) v[i] = vv;
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < kVT; ++i) {
-        d[i] = 0;
-        rs[i] = 0;
-        if (v[i] >= 0) {
-            rs[i] = p.offsets[v[i]];
-            d[i] = p.offsets[v[i] + 1] - rs[i];
-            ++traw;
-            if (d[i] > 0) { ++tc; ts += d[i]; }
-        }
-    }
-    int C, S, R;
-    const int c_ex = block_excl_scan(tc, s_wave, &C);
-    const int s_ex = block_excl_scan(ts, s_wave2, &S);
-    block_excl_scan(traw, s_wave, &R);  // survivors of any degree: only the total is used
-    if (threadIdx.x == 0) {
-        int pc = 0, ps = 0;
-        bool ok = lookback(p.desc[par], k, C, S, p.ctrl, p.spin_ticks, &pc, &ps);
-        s_b[0] = pc;
-        s_b[1] = ps;
-        s_b[2] = ok;
-        if (R) __hip_atomic_fetch_add(&p.ctrl->kept[np], R, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (ok && k == ntiles - 1) {
-            st_rel(&p.ctrl->nl[np], pc + C);
-            st_rel(&p.ctrl->el[np], ps + S);
-            if (pc + C <= p.n) p.f_ex[np][pc + C] = ps + S;
-            else flag_internal(p.ctrl);
-        }
-    }
-    __syncthreads();
-    const int pc = s_b[0], ps = s_b[1];
-    const bool ok = s_b[2] != 0;
-    __syncthreads();
-    if (!ok) return false;
-    int pos = pc + c_ex, e = ps + s_ex;
-    int32_t* frs = p.f_rs[np];
-    int32_t* fex = p.f_ex[np];
-    int32_t* tst = p.tstart[np];
-#pragma unroll
-    for (int i = 0; i < kVT; ++i) {
-        if (v[i] >= 0) {
-            __hip_atomic_fetch_or(&p.bitmap[v[i] >> 5], 1u << (v[i] & 31), __ATOMIC_RELAXED,
-                                  __HIP_MEMORY_SCOPE_AGENT);
-            if (d[i] > 0) {
-                if ((unsigned)pos < (unsigned)p.n) {
-                    frs[pos] = rs[i];
-                    fex[pos] = e;
-                    scatter_starts(p, tst, pos, e, d[i]);
-                } else {
-                    flag_internal(p.ctrl);
-                }
-                ++pos;
-                e += d[i];
-            }
-        }
-    }
-    return true;
+__device__ __forceinline__ int* lds_wave(int* lds) { return lds + kLdsWords - 2 * kWaves - 8; }
+__device__ __forceinline__ int* lds_wave2(int* lds) { return lds + kLdsWords - kWaves - 8; }
+__device__ __forceinline__ int* lds_misc(int* lds) { return lds + kLdsWords - 8; }
+
+// Share b of P: the contiguous run of sub-tiles [tb, te) of the level's
+// ntiles (the paper's (almost) equal division of e_l among P_l threads,
+// rounded to whole sub-tiles; shares differ by at most one sub-tile).  Its
+// private queue is cand[tb * kGrain, te * kGrain).
+__device__ __forceinline__ void share_range(int b, int P, int ntiles, int* tb, int* te) {
+    *tb = (int)(((int64_t)b * ntiles) / P);
+    *te = (int)(((int64_t)(b + 1) * ntiles) / P);
 }
 
-// Ticket-ordered loop over the compaction tiles of level l.
-__device__ bool compact_phase(const Params& p, int l, int ntiles, int* lds) {
-    int* s_b = lds + kLdsWords - 8;
-    const int par = l & 1;
-    for (;;) {
-        if (threadIdx.x == 0)
-            s_b[4] = (int)__hip_atomic_fetch_add(&p.ctrl->ticket[par], 1u, __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_AGENT);
-        __syncthreads();
-        const int k = s_b[4];
-        __syncthreads();
-        if (k >= ntiles) return true;
-        if (!compact_tile(p, l, k, ntiles, lds)) return false;
-    }
+// Parent of a vertex v reached at level l + 1 is its smallest-id neighbour
+// at level l.  Two equivalent ways to get it, chosen per level:
+//  push  (levels with few edges) every scanned edge (u, v) whose target is
+//        unsettled does an atomic minimum parent[v] = min(parent[v], u); all
+//        level-l neighbours of v are scanned in this level, and the order of
+//        the minima does not matter;
+//  pull  (large levels, where new vertices have many level-l neighbours)
+//        once level l + 1 is final, v's sorted row is read until the first
+//        neighbour at level l.  A lane tests kPullScan neighbours; longer
+//        rows go to the whole workgroup (first_parent_wg).
+__device__ __forceinline__ void parent_push(const Params& p, int v, int u) {
+    __hip_atomic_fetch_min(reinterpret_cast<unsigned*>(p.parent) + v, (unsigned)u, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// ---- expansion of one share ---------------------------------------------------------------
-__device__ void expand_tile(const Params& p, int l, int k, int ntiles, int n_l, int e_l, int* lds) {
-    int* s_ex = lds;
-    int* s_rs = lds + kGrain + 1;
-    int* s_wave = lds + kLdsWords - 2 * kWaves - 8;
-    const int par = l & 1;
-    const int g0 = k * kGrain;
-    const int g1 = min(g0 + kGrain, e_l);
-    const int32_t* tst = p.tstart[par];
-    const int j0 = tst[k];
-    const int j1 = (k + 1 < ntiles) ? tst[k + 1] : n_l - 1;
-    const int nv = j1 - j0 + 1;  // <= kGrain + 1: every frontier vertex has degree >= 1
-    if (j0 < 0 || j1 >= n_l || nv < 1 || nv > kGrain + 1 || k >= p.max_tiles) {
-        // cannot happen for a well-formed frontier; refuse rather than overrun LDS
-        if (threadIdx.x == 0) {
-            flag_internal(p.ctrl);
-            p.cnt[k < p.max_tiles ? k : 0] = 0;
+// First neighbour at level l among the first kPullScan of the row, -2 if
+// none there but the row is longer, -1 if the row has none at all.
+__device__ __forceinline__ int first_parent_lane(const Params& p, int rs, int d, int l) {
+    const int end = rs + min(d, kPullScan);
+    for (int e = rs; e < end; e += 4) {
+        int c[4], lv[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) c[q] = e + q < end ? p.cols[e + q] : -1;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) lv[q] = (unsigned)c[q] < (unsigned)p.n ? p.level[c[q]] : -2;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (lv[q] == l) return c[q];
+    }
+    return d > kPullScan ? -2 : -1;
+}
+
+// The whole workgroup reads the rest of a long row, kBlock neighbours per
+// step, and keeps the first position holding a level-l neighbour.  Uniform
+// arguments; s_red holds kWaves + 1 ints.
+__device__ int first_parent_wg(const Params& p, int rs, int d, int l, int* s_red) {
+    for (int base = kPullScan; base < d; base += kBlock) {
+        const int e = rs + base + threadIdx.x;
+        int c = -1;
+        bool hit = false;
+        if (base + threadIdx.x < d) {
+            c = p.cols[e];
+            hit = (unsigned)c < (unsigned)p.n && p.level[c] == l;
         }
+        const uint64_t bb = ballot(hit);
+        if (lane_id() == 0) s_red[wave_id()] = bb ? wave_id() * 64 + __builtin_ctzll(bb) : INT32_MAX;
         __syncthreads();
-        return;
+        int first = INT32_MAX;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) first = min(first, s_red[w]);
+        if (first != INT32_MAX && threadIdx.x == first) s_red[kWaves] = c;
+        __syncthreads();
+        const int found = s_red[kWaves];
+        __syncthreads();
+        if (first != INT32_MAX) return found;
     }
-    const int32_t* fex = p.f_ex[par];
-    const int32_t* frs = p.f_rs[par];
-    for (int i = threadIdx.x; i < nv; i += kBlock) {
-        s_ex[i] = fex[j0 + i];
-        s_rs[i] = frs[j0 + i];
-    }
-    __syncthreads();
-    int v[kVT];
+    return -1;
+}
+
+// Reads the neighbours of this lane's kVT edges among [g0, g1) of the
+// current frontier, whose entries [j0, j0 + nv) are staged in `sl`
+// (ex | rs); -1 where there is no edge.  With `fv` also the frontier vertex
+// each edge comes from (for pushed parents).
+__device__ __forceinline__ void gather_tile(const Params& p, const int* sl, int nv, int g0, int g1, int* v,
+                                            const int32_t* fv, int j0, int* u) {
 #pragma unroll
     for (int i = 0; i < kVT; ++i) {
         const int g = g0 + i * kBlock + threadIdx.x;
@@ -331,9 +301,10 @@ __device__ void expand_tile(const Params& p, int l, int k, int ntiles, int n_l, 
             int lo = 0, hi = nv;
             while (hi - lo > 1) {
                 const int mid = (lo + hi) >> 1;
-                if (s_ex[mid] <= g) lo = mid; else hi = mid;
+                if (sl[mid] <= g) lo = mid; else hi = mid;
             }
-            const int idx = s_rs[lo] + (g - s_ex[lo]);
+            if (fv) u[i] = fv[j0 + lo];
+            const int idx = sl[kSlice + lo] + (g - sl[lo]);
             if ((unsigned)idx < (unsigned)p.m) {
                 v[i] = __builtin_nontemporal_load(p.cols + idx);
                 if ((unsigned)v[i] >= (unsigned)p.n) v[i] = -1;
@@ -342,53 +313,339 @@ __device__ void expand_tile(const Params& p, int l, int k, int ntiles, int n_l, 
             }
         }
     }
-#pragma unroll
-    for (int i = 0; i < kVT; ++i)
-        if (v[i] >= 0 && ((p.bitmap[v[i] >> 5] >> (v[i] & 31)) & 1u)) v[i] = -1;
-#pragma unroll
-    for (int i = 0; i < kVT; ++i)
-        if (v[i] >= 0 && p.level[v[i]] != -1) v[i] = -1;
-#pragma unroll
-    for (int i = 0; i < kVT; ++i)
-        if (v[i] >= 0) p.level[v[i]] = l + 1;
-    int slot[kVT];
-    int wt = 0;
-#pragma unroll
-    for (int i = 0; i < kVT; ++i) {
-        const uint64_t b = ballot(v[i] >= 0);
-        slot[i] = wt + mbcnt(b);
-        wt += __popcll(b);
+}
+
+// ---- EXPLORE-VERTEX over one share ---------------------------------------------------------
+// The share's sub-tiles are scanned in order, software-pipelined: while the
+// neighbours of sub-tile t are filtered (visited bitmap, then level array)
+// and the new ones appended to the share's private queue, the neighbour
+// reads of sub-tile t + 1 are already in flight and the frontier entries of
+// sub-tile t + 2 are being fetched into registers.  Sub-tile t needs the
+// frontier entries [tstart[t], tstart[t+1]] (at most kSlice of them, since
+// every frontier vertex has an edge), staged in one of two LDS buffers; each
+// lane maps its edge to an entry by binary search there.  A new vertex gets
+// level = l + 1, its visited bit, owner = its queue slot and a place in the
+// queue (the benign race: several lanes may append the same vertex).
+__device__ void expand_share(const Params& p, int l, int b, int P, int ntiles, int n_l, int e_l, int* lds) {
+    int* s_wave = lds_wave(lds);
+    int tb, te;
+    share_range(b, P, ntiles, &tb, &te);
+    if (tb >= te) {
+        if (threadIdx.x == 0) p.cnt[b] = 0;
+        return;
     }
-    if (lane_id() == 0) s_wave[wave_id()] = wt;
+    const int par = l & 1;
+    const int32_t* tst = p.tstart[par];
+    const int32_t* fex = p.f_ex[par];
+    const int32_t* frs = p.f_rs[par];
+    const int32_t* fvp = (p.parent && e_l <= p.push_edges) ? p.f_v[par] : nullptr;  // push level
+    const int qbase = tb * kGrain;
+    int qn = 0;
+    auto slice_end = [&](int t) { return t + 1 < ntiles ? tst[t + 1] : n_l - 1; };
+    auto slice_ok = [&](int a, int z) { return a >= 0 && z < n_l && z >= a && z - a + 1 <= kSlice; };
+    auto stage_slice = [&](int* buf, int a, int z) {
+        for (int i = threadIdx.x; i <= z - a; i += kBlock) {
+            buf[i] = fex[a + i];
+            buf[kSlice + i] = frs[a + i];
+        }
+    };
+    int* buf0 = lds;
+    int* buf1 = lds + 2 * kSlice;
+    // prologue: slices of sub-tiles tb and tb + 1 in LDS, neighbours of tb in flight
+    const int a0 = tst[tb], z0 = slice_end(tb);
+    int a1 = z0, z1 = (tb + 1 < te) ? slice_end(tb + 1) : z0;
+    bool bad = !slice_ok(a0, z0) || (tb + 1 < te && !slice_ok(a1, z1));
+    if (!bad) {
+        stage_slice(buf0, a0, z0);
+        if (tb + 1 < te) stage_slice(buf1, a1, z1);
+    }
     __syncthreads();
-    int base = 0, tot = 0;
+    int vc[kVT], uc[kVT];
 #pragma unroll
-    for (int w = 0; w < kWaves; ++w) {
-        const int t = s_wave[w];
-        base += (w < wave_id()) ? t : 0;
-        tot += t;
+    for (int i = 0; i < kVT; ++i) vc[i] = uc[i] = -1;
+    if (!bad) gather_tile(p, buf0, z0 - a0 + 1, tb * kGrain, min(tb * kGrain + kGrain, e_l), vc, fvp, a0, uc);
+    for (int t = tb; t < te && !bad; ++t) {
+        int* cur1 = ((t + 1 - tb) & 1) ? buf1 : buf0;   // slice of sub-tile t + 1
+        int* free2 = ((t - tb) & 1) ? buf1 : buf0;      // receives the slice of sub-tile t + 2
+        // fetch the slice of sub-tile t + 2 into registers
+        const bool has2 = t + 2 < te;
+        const int a2 = z1, z2 = has2 ? slice_end(t + 2) : z1;
+        const bool ok2 = !has2 || slice_ok(a2, z2);
+        int pe[kPre], pr[kPre];
+#pragma unroll
+        for (int r = 0; r < kPre; ++r) {
+            const int i = threadIdx.x + r * kBlock;
+            if (has2 && ok2 && i <= z2 - a2) {
+                pe[r] = fex[a2 + i];
+                pr[r] = frs[a2 + i];
+            }
+        }
+        // issue the neighbour reads of sub-tile t + 1
+        int vn[kVT], un[kVT];
+#pragma unroll
+        for (int i = 0; i < kVT; ++i) vn[i] = un[i] = -1;
+        if (t + 1 < te)
+            gather_tile(p, cur1, z1 - a1 + 1, (t + 1) * kGrain, min((t + 1) * kGrain + kGrain, e_l), vn, fvp, a1,
+                        un);
+        // filter and append the neighbours of sub-tile t
+        bool fresh[kVT];
+#pragma unroll
+        for (int i = 0; i < kVT; ++i)
+            if (vc[i] >= 0 && ((p.bitmap[vc[i] >> 5] >> (vc[i] & 31)) & 1u)) vc[i] = -1;
+        if (fvp) {
+            // push level: every edge into an unsettled vertex offers its source as parent
+#pragma unroll
+            for (int i = 0; i < kVT; ++i) {
+                fresh[i] = false;
+                if (vc[i] >= 0) {
+                    const int lv = p.level[vc[i]];
+                    if (lv == -1) fresh[i] = true;
+                    else if (lv != l + 1) vc[i] = -1;
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < kVT; ++i)
+                if (vc[i] >= 0) parent_push(p, vc[i], uc[i]);
+        } else {
+#pragma unroll
+            for (int i = 0; i < kVT; ++i) fresh[i] = vc[i] >= 0 && p.level[vc[i]] == -1;
+        }
+        // A pull level sets the visited bit at discovery, so later edges into
+        // the vertex stop at the bitmap; a push level must let every such edge
+        // offer its source, so its bits are set at de-duplication instead.
+#pragma unroll
+        for (int i = 0; i < kVT; ++i) {
+            if (fresh[i]) {
+                p.level[vc[i]] = l + 1;
+                if (!fvp)
+                    __hip_atomic_fetch_or(&p.bitmap[vc[i] >> 5], 1u << (vc[i] & 31), __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+        int slot[kVT];
+        int wt = 0;
+#pragma unroll
+        for (int i = 0; i < kVT; ++i) {
+            const uint64_t bb = ballot(fresh[i]);
+            slot[i] = wt + mbcnt(bb);
+            wt += __popcll(bb);
+        }
+        if (lane_id() == 0) s_wave[wave_id()] = wt;
+        __syncthreads();
+        int wbase = 0, tot = 0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) {
+            const int x = s_wave[w];
+            wbase += (w < wave_id()) ? x : 0;
+            tot += x;
+        }
+#pragma unroll
+        for (int i = 0; i < kVT; ++i) {
+            if (fresh[i]) {
+                const int s = qbase + qn + wbase + slot[i];
+                p.owner[vc[i]] = s;
+                p.cand[s] = vc[i];
+            }
+        }
+        qn += tot;
+        // publish the slice of sub-tile t + 2 (the buffer of sub-tile t is free)
+        if (has2) {
+            if (!ok2) {
+                bad = true;
+            } else {
+#pragma unroll
+                for (int r = 0; r < kPre; ++r) {
+                    const int i = threadIdx.x + r * kBlock;
+                    if (i <= z2 - a2) {
+                        free2[i] = pe[r];
+                        free2[kSlice + i] = pr[r];
+                    }
+                }
+            }
+        }
+        a1 = a2;
+        z1 = z2;
+#pragma unroll
+        for (int i = 0; i < kVT; ++i) {
+            vc[i] = vn[i];
+            uc[i] = un[i];
+        }
+        __syncthreads();
     }
+    if (threadIdx.x == 0) {
+        if (bad) flag_internal(p.ctrl);
+        p.cnt[b] = qn;
+    }
+    __syncthreads();
+}
+
+// ---- de-duplication and linearisation of one share's queue -----------------------------------
+// Pass 1 keeps queue entries whose slot still owns the vertex (Owner[v] = i),
+// sets their visited bits, and compacts the survivors of degree >= 1 in
+// place; the share's (count, edge total) then gets its exclusive prefix by
+// decoupled look-back over the shares (the Sizes prefix sum).  Pass 2 writes
+// the survivors to the next frontier with their exclusive degree sums and
+// the start points of the next level's sub-tiles.  l = -1 compacts the roots.
+__device__ bool compact_share(const Params& p, int l, int b, int P, int ntiles, bool pull_parents, bool set_bits,
+                              int* lds) {
+    int* s_wave = lds_wave(lds);
+    int* s_wave2 = lds_wave2(lds);
+    int* s_b = lds_misc(lds);
+    const int par = l & 1;
+    const int np = (l + 1) & 1;
+    int tb, te;
+    share_range(b, P, ntiles, &tb, &te);
+    const int qbase = tb * kGrain;
+    int qn = tb < te ? p.cnt[b] : 0;
+    if (qn < 0 || qn > (te - tb) * kGrain) {
+        if (threadIdx.x == 0) flag_internal(p.ctrl);
+        qn = 0;
+    }
+    // pass 1
+    int surv = 0, degsum = 0, raw = 0;
+    for (int c0 = 0; c0 < qn; c0 += kGrain) {
+        int v[kVT], d[kVT];
+        int tc = 0, ts = 0, tr = 0;
 #pragma unroll
-    for (int i = 0; i < kVT; ++i) {
-        if (v[i] >= 0) {
-            const int s = k * kGrain + base + slot[i];
-            p.owner[v[i]] = s;
-            p.cand[s] = v[i];
+        for (int i = 0; i < kVT; ++i) {
+            const int idx = c0 + threadIdx.x * kVT + i;
+            v[i] = -1;
+            if (idx < qn) {
+                const int vv = p.cand[qbase + idx];
+                if ((unsigned)vv >= (unsigned)p.n) flag_internal(p.ctrl);
+                else if (p.owner[vv] == qbase + idx) v[i] = vv;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < kVT; ++i) {
+            d[i] = 0;
+            if (v[i] >= 0) {
+                d[i] = p.offsets[v[i] + 1] - p.offsets[v[i]];
+                ++tr;
+                if (set_bits)  // roots and push levels; pull levels set bits at discovery
+                    __hip_atomic_fetch_or(&p.bitmap[v[i] >> 5], 1u << (v[i] & 31), __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
+                if (d[i] > 0) { ++tc; ts += d[i]; }
+            }
+        }
+        int C, S, R;
+        const int pos0 = block_excl_scan(tc, s_wave, &C);
+        block_excl_scan(ts, s_wave2, &S);
+        block_excl_scan(tr, s_wave, &R);
+        // in place: every read of this chunk happened before the scans' barriers
+        int pos = surv + pos0;
+#pragma unroll
+        for (int i = 0; i < kVT; ++i)
+            if (v[i] >= 0 && d[i] > 0) p.cand[qbase + pos++] = v[i];
+        surv += C;
+        degsum += S;
+        raw += R;
+        __syncthreads();
+    }
+    // Sizes prefix sum over the shares
+    if (wave_id() == 0) {
+        int pc = 0, ps = 0;
+        const bool okw = lookback_wave(p.desc[par], b, surv, degsum, p.ctrl, p.spin_ticks, &pc, &ps);
+        if (threadIdx.x == 0) {
+            s_b[0] = pc;
+            s_b[1] = ps;
+            s_b[2] = okw;
+            if (raw) __hip_atomic_fetch_add(&p.ctrl->kept[np], raw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (okw && b == P - 1) {
+                st_rel(&p.ctrl->nl[np], pc + surv);
+                st_rel(&p.ctrl->el[np], ps + degsum);
+                if (pc + surv <= p.n) p.f_ex[np][pc + surv] = ps + degsum;
+                else flag_internal(p.ctrl);
+            }
         }
     }
-    if (threadIdx.x == 0) p.cnt[k] = tot;
     __syncthreads();
+    const int pc = s_b[0], ps = s_b[1];
+    const bool ok = s_b[2] != 0;
+    __syncthreads();
+    if (!ok) return false;
+    // pass 2
+    const bool pull = p.parent && l >= 0 && pull_parents;
+    int run_e = 0;
+    for (int c0 = 0; c0 < surv; c0 += kGrain) {
+        int v[kVT], rs[kVT], d[kVT];
+        int ts = 0;
+#pragma unroll
+        for (int i = 0; i < kVT; ++i) {
+            const int idx = c0 + threadIdx.x * kVT + i;
+            v[i] = -1;
+            d[i] = 0;
+            rs[i] = 0;
+            if (idx < surv) {
+                v[i] = p.cand[qbase + idx];
+                rs[i] = p.offsets[v[i]];
+                d[i] = p.offsets[v[i] + 1] - rs[i];
+                ts += d[i];
+            }
+        }
+        int S;
+        int e = ps + run_e + block_excl_scan(ts, s_wave, &S);
+        int pos = pc + c0 + threadIdx.x * kVT;
+        if (pull) {
+            // rows whose first kPullScan neighbours hold no parent go to the whole workgroup
+            int* s_hard = lds;                // (v, rs, d) triples: the slice buffers are free now
+            int* s_red = lds + 3 * kGrain;    // kWaves + 1 ints
+            int* s_nh = s_red + kWaves + 1;
+            if (threadIdx.x == 0) *s_nh = 0;
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < kVT; ++i) {
+                if (v[i] >= 0) {
+                    const int f = first_parent_lane(p, rs[i], d[i], l);
+                    if (f == -2) {
+                        const int h = atomicAdd(s_nh, 1);
+                        s_hard[3 * h] = v[i];
+                        s_hard[3 * h + 1] = rs[i];
+                        s_hard[3 * h + 2] = d[i];
+                    } else {
+                        p.parent[v[i]] = f;
+                    }
+                }
+            }
+            __syncthreads();
+            const int nh = *s_nh;
+            for (int h = 0; h < nh; ++h) {
+                const int hv = s_hard[3 * h], hrs = s_hard[3 * h + 1], hd = s_hard[3 * h + 2];
+                const int f = first_parent_wg(p, hrs, hd, l, s_red);
+                if (threadIdx.x == 0) p.parent[hv] = f;
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int i = 0; i < kVT; ++i) {
+            if (v[i] >= 0) {
+                if ((unsigned)pos < (unsigned)p.n) {
+                    p.f_v[np][pos] = v[i];
+                    p.f_rs[np][pos] = rs[i];
+                    p.f_ex[np][pos] = e;
+                    scatter_starts(p, p.tstart[np], pos, e, d[i]);
+                } else {
+                    flag_internal(p.ctrl);
+                }
+                e += d[i];
+            }
+            ++pos;
+        }
+        run_e += S;
+    }
+    return true;
 }
 
 // ---- a stretch of small levels run by one workgroup out of LDS -----------------------------
 // Entered at level l with the frontier in global memory (parity l & 1).
-// Leaves with the frontier of level ctrl->resume in global memory.
+// Leaves with the frontier of level ctrl->resume in global memory and its
+// size in the resume slot.
 __device__ void small_levels(const Params& p, int l, int n_l, int e_l, int* lds) {
     int* s_rs = lds;
     int* s_ex = lds + kSmallN;
     int* s_cand = s_ex + kSmallN + 1;
-    int* s_wave = lds + kLdsWords - 2 * kWaves - 8;
-    int* s_wave2 = s_wave + kWaves;
+    int* s_wave = lds_wave(lds);
+    int* s_wave2 = lds_wave2(lds);
     {
         const int par = l & 1;
         for (int i = threadIdx.x; i < n_l; i += kBlock) {
@@ -401,20 +658,25 @@ __device__ void small_levels(const Params& p, int l, int n_l, int e_l, int* lds)
     int done_levels = 0;
     for (;;) {
         const int np = (l + 1) & 1;
+        const int32_t* fvc = p.f_v[l & 1];  // this level's frontier ids (global copy)
+        if (threadIdx.x == 0 && l < kStatCap) p.stat_ts[3 * l] = now_ticks();
         // expand level l: every frontier edge, kBlock * kVTS per round
         int ncand = 0;
         for (int base0 = 0; base0 < e_l; base0 += kBlock * kVTS) {
-            int v[kVTS];
+            int v[kVTS], u[kVTS];
+            bool fresh[kVTS];
 #pragma unroll
             for (int i = 0; i < kVTS; ++i) {
                 const int g = base0 + i * kBlock + threadIdx.x;
                 v[i] = -1;
+                u[i] = -1;
                 if (g < e_l) {
                     int lo = 0, hi = n_l;
                     while (hi - lo > 1) {
                         const int mid = (lo + hi) >> 1;
                         if (s_ex[mid] <= g) lo = mid; else hi = mid;
                     }
+                    if (p.parent) u[i] = fvc[lo];
                     const int idx = s_rs[lo] + (g - s_ex[lo]);
                     if ((unsigned)idx < (unsigned)p.m) {
                         v[i] = p.cols[idx];
@@ -424,19 +686,32 @@ __device__ void small_levels(const Params& p, int l, int n_l, int e_l, int* lds)
                     }
                 }
             }
+            // parents are pushed: every edge into an unsettled vertex offers its source
 #pragma unroll
-            for (int i = 0; i < kVTS; ++i)
-                if (v[i] >= 0 && p.level[v[i]] != -1) v[i] = -1;
+            for (int i = 0; i < kVTS; ++i) {
+                fresh[i] = false;
+                if (v[i] >= 0) {
+                    const int lv = p.level[v[i]];
+                    if (lv == -1) fresh[i] = true;
+                    else if (lv != l + 1) v[i] = -1;
+                }
+            }
 #pragma unroll
-            for (int i = 0; i < kVTS; ++i)
-                if (v[i] >= 0) p.level[v[i]] = l + 1;
+            for (int i = 0; i < kVTS; ++i) {
+                if (v[i] >= 0 && p.parent) parent_push(p, v[i], u[i]);
+                if (fresh[i]) {
+                    p.level[v[i]] = l + 1;
+                    __hip_atomic_fetch_or(&p.bitmap[v[i] >> 5], 1u << (v[i] & 31), __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
+                }
+            }
             int slot[kVTS];
             int wt = 0;
 #pragma unroll
             for (int i = 0; i < kVTS; ++i) {
-                const uint64_t b = ballot(v[i] >= 0);
-                slot[i] = wt + mbcnt(b);
-                wt += __popcll(b);
+                const uint64_t bb = ballot(fresh[i]);
+                slot[i] = wt + mbcnt(bb);
+                wt += __popcll(bb);
             }
             if (lane_id() == 0) s_wave[wave_id()] = wt;
             __syncthreads();
@@ -449,7 +724,7 @@ __device__ void small_levels(const Params& p, int l, int n_l, int e_l, int* lds)
             }
 #pragma unroll
             for (int i = 0; i < kVTS; ++i) {
-                if (v[i] >= 0) {
+                if (fresh[i]) {
                     const int s = ncand + wb + slot[i];
                     p.owner[v[i]] = s;
                     if (s < kSmallC) s_cand[s] = v[i]; else p.cand[s] = v[i];
@@ -458,6 +733,7 @@ __device__ void small_levels(const Params& p, int l, int n_l, int e_l, int* lds)
             ncand += tot;
             __syncthreads();
         }
+        if (threadIdx.x == 0 && l < kStatCap) p.stat_ts[3 * l + 1] = now_ticks();
         // de-duplicate and build the next frontier (LDS and global copies)
         int outc = 0, outs = 0, outr = 0;
         for (int base0 = 0; base0 < ncand; base0 += kBlock * kVTS) {
@@ -492,10 +768,9 @@ __device__ void small_levels(const Params& p, int l, int n_l, int e_l, int* lds)
 #pragma unroll
             for (int i = 0; i < kVTS; ++i) {
                 if (v[i] >= 0) {
-                    __hip_atomic_fetch_or(&p.bitmap[v[i] >> 5], 1u << (v[i] & 31), __ATOMIC_RELAXED,
-                                          __HIP_MEMORY_SCOPE_AGENT);
                     if (d[i] > 0) {
                         if ((unsigned)pos < (unsigned)p.n) {
+                            p.f_v[np][pos] = v[i];
                             p.f_rs[np][pos] = rs[i];
                             p.f_ex[np][pos] = e;
                             scatter_starts(p, p.tstart[np], pos, e, d[i]);
@@ -516,6 +791,7 @@ __device__ void small_levels(const Params& p, int l, int n_l, int e_l, int* lds)
             outr += R;
             __syncthreads();
         }
+        if (threadIdx.x == 0 && l < kStatCap) p.stat_ts[3 * l + 2] = now_ticks();
         ++l;
         ++done_levels;
         if (threadIdx.x == 0) {
@@ -549,7 +825,7 @@ __device__ void small_levels(const Params& p, int l, int n_l, int e_l, int* lds)
     }
 }
 
-// ---- parent pass ------------------------------------------------------------------------------
+// ---- parent pass (plain per-level comparator only) -------------------------------------------
 // parent[v] = smallest-id neighbour one level closer (rows are sorted, so the
 // first such neighbour in the row), parent[root] = root, -1 if unreached.
 __device__ void parent_range(const Params& p, int64_t first, int64_t stride) {
@@ -571,19 +847,22 @@ __device__ void parent_range(const Params& p, int64_t first, int64_t stride) {
 
 // ---- kernels ---------------------------------------------------------------------------------
 
-// Resets the control block and the per-run arrays: level = -1, bitmap = 0,
-// and the descriptors of the roots' compaction.
-__global__ void __launch_bounds__(kBlock) k_prep(Params p, int prep_tiles) {
+// Resets the control block and the per-run arrays: level = -1, parent = -1
+// (all bits set, so unsigned minima replace it), bitmap = 0, and the
+// descriptors of the roots' compaction.
+__global__ void __launch_bounds__(kBlock) k_prep(Params p, int prep_shares, int fill_parent) {
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t v = tid; v < p.n; v += stride) p.level[v] = -1;
+    for (int64_t v = tid; v < p.n; v += stride) {
+        p.level[v] = -1;
+        if (fill_parent) p.parent[v] = -1;
+    }
     const int64_t words = ((int64_t)p.n + 31) >> 5;
     for (int64_t w = tid; w < words; w += stride) p.bitmap[w] = 0u;
-    for (int64_t t = tid; t < prep_tiles; t += stride) p.desc[1][t] = 0ull;
+    for (int64_t t = tid; t < prep_shares; t += stride) p.desc[1][t] = 0ull;
     if (tid == 0) {
         Ctrl* c = p.ctrl;
         c->bar = 0;
-        c->ticket[0] = c->ticket[1] = 0;
         c->nl[0] = c->nl[1] = 0;
         c->el[0] = c->el[1] = 0;
         c->kept[0] = c->kept[1] = 0;
@@ -593,31 +872,48 @@ __global__ void __launch_bounds__(kBlock) k_prep(Params p, int prep_tiles) {
         c->resume = 0;
         c->heartbeat = 0;
         c->plain_next = 0;
+        c->r_nl = c->r_el = c->r_kept = 0;
     }
 }
 
-// Roots become the private queues of level -1: root i sits in slot i.
-__device__ void roots_range(const Params& p, int64_t first, int64_t stride) {
+// Roots become the private queues of level -1: root i sits in slot i, and
+// share b of the roots' P_r shares owns slots [tb * kGrain, te * kGrain).
+__device__ void roots_range(const Params& p, int P, int64_t first, int64_t stride) {
+    const int rtiles = (p.nroots + kGrain - 1) / kGrain;
     for (int64_t i = first; i < p.nroots; i += stride) {
         const int r = p.roots ? p.roots[i] : p.single_root;
         p.level[r] = 0;
+        if (p.parent) p.parent[r] = r;
         p.owner[r] = (int)i;
         p.cand[i] = r;
-        if ((i % kGrain) == 0) p.cnt[i / kGrain] = (int)min((int64_t)kGrain, (int64_t)p.nroots - i);
+    }
+    for (int64_t b = first; b < P; b += stride) {
+        int tb, te;
+        share_range((int)b, P, rtiles, &tb, &te);
+        p.cnt[b] = (int)max((int64_t)0, min((int64_t)te * kGrain, (int64_t)p.nroots) - (int64_t)tb * kGrain);
     }
 }
 
-__global__ void __launch_bounds__(kBlock) k_persistent(Params p) {
+__device__ __forceinline__ int shares_for(int ntiles, int G) { return ntiles < G ? ntiles : G; }
+
+// Register budget of the persistent kernel: its occupancy (workgroups per
+// CU) is what hides the memory latency of the level loop.
+#ifndef BFS_PERSISTENT_WAVES_PER_EU
+#define BFS_PERSISTENT_WAVES_PER_EU 4
+#endif
+__global__ void __attribute__((amdgpu_waves_per_eu(BFS_PERSISTENT_WAVES_PER_EU))) __launch_bounds__(kBlock)
+k_persistent(Params p) {
     __shared__ Lds lds_s;
     int* lds = lds_s.w;
     int* s_flag = lds + kLdsWords - 1;
     const int G = gridDim.x;
     Ctrl* c = p.ctrl;
 
-    roots_range(p, (int64_t)blockIdx.x * kBlock + threadIdx.x, (int64_t)G * kBlock);
+    const int rtiles = (p.nroots + kGrain - 1) / kGrain;
+    const int Pr = shares_for(rtiles, G);
+    roots_range(p, Pr, (int64_t)blockIdx.x * kBlock + threadIdx.x, (int64_t)G * kBlock);
     if (!grid_barrier(c, p.spin_ticks, s_flag)) return;
-    const int root_tiles = (p.nroots + kGrain - 1) / kGrain;
-    if (!compact_phase(p, -1, root_tiles, lds)) return;
+    if (blockIdx.x < Pr && !compact_share(p, -1, blockIdx.x, Pr, rtiles, false, true, lds)) return;
     if (!grid_barrier(c, p.spin_ticks, s_flag)) return;
 
     // The size of each level is read once, right after the barrier that
@@ -629,6 +925,8 @@ __global__ void __launch_bounds__(kBlock) k_persistent(Params p) {
     int kept = ld_acq(&c->kept[0]);
     for (;;) {
         const int par = l & 1;
+        const bool rec = blockIdx.x == 0 && threadIdx.x == 0 && l < kStatCap;
+        if (rec) p.stat_ts[3 * l] = now_ticks();
         if (blockIdx.x == 0 && threadIdx.x == 0 && kept > 0) {
             if (l < kStatCap) { p.stat_nl[l] = kept; p.stat_el[l] = e_l; }
             st_rel(&c->levels, l + 1);
@@ -644,35 +942,36 @@ __global__ void __launch_bounds__(kBlock) k_persistent(Params p) {
             continue;
         }
         const int ntiles = (int)(((int64_t)e_l + kGrain - 1) / kGrain);
+        const int P = shares_for(ntiles, G);  // P_l = min(P, W_l)
         const int np = (l + 1) & 1;
         // reset this level's compaction state (last used two levels ago)
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-            st_rel(&c->ticket[par], 0u);
-            st_rel(&c->kept[np], 0);
-        }
-        for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < ntiles; t += (int64_t)G * kBlock)
-            p.desc[par][t] = 0ull;
-        for (int k = blockIdx.x; k < ntiles; k += G) expand_tile(p, l, k, ntiles, n_l, e_l, lds);
+        if (blockIdx.x == 0 && threadIdx.x == 0) st_rel(&c->kept[np], 0);
+        for (int t = blockIdx.x * kBlock + threadIdx.x; t < P; t += G * kBlock) p.desc[par][t] = 0ull;
+        if (blockIdx.x < P) expand_share(p, l, blockIdx.x, P, ntiles, n_l, e_l, lds);
         if (!grid_barrier(c, p.spin_ticks, s_flag)) return;
-        if (!compact_phase(p, l, ntiles, lds)) return;
+        if (rec) p.stat_ts[3 * l + 1] = now_ticks();
+        const bool push = p.parent && e_l <= p.push_edges;
+        if (blockIdx.x < P && !compact_share(p, l, blockIdx.x, P, ntiles, !push, push, lds)) return;
         if (!grid_barrier(c, p.spin_ticks, s_flag)) return;
+        if (rec) p.stat_ts[3 * l + 2] = now_ticks();
         ++l;
         n_l = ld_acq(&c->nl[np]);
         e_l = ld_acq(&c->el[np]);
         kept = ld_acq(&c->kept[np]);
     }
-    if (p.parent) parent_range(p, (int64_t)blockIdx.x * kBlock + threadIdx.x, (int64_t)G * kBlock);
 }
 
 // ---- per-level launches (BFS_MODE_LEVEL) ---------------------------------------------------
 
-__global__ void __launch_bounds__(kBlock) k_level_roots(Params p) {
-    roots_range(p, (int64_t)blockIdx.x * kBlock + threadIdx.x, (int64_t)gridDim.x * kBlock);
+__global__ void __launch_bounds__(kBlock) k_level_roots(Params p, int P) {
+    roots_range(p, P, (int64_t)blockIdx.x * kBlock + threadIdx.x, (int64_t)gridDim.x * kBlock);
 }
 
+// One workgroup per share (grid = P).
 __global__ void __launch_bounds__(kBlock) k_level_compact(Params p, int l, int ntiles) {
     __shared__ Lds lds_s;
-    compact_phase(p, l, ntiles, lds_s.w);
+    const bool push = l < 0 || (p.parent && ld_acq(&p.ctrl->el[l & 1]) <= p.push_edges);
+    compact_share(p, l, blockIdx.x, gridDim.x, ntiles, !push, push, lds_s.w);
 }
 
 __global__ void __launch_bounds__(kBlock) k_level_expand(Params p, int l, int ntiles) {
@@ -680,13 +979,9 @@ __global__ void __launch_bounds__(kBlock) k_level_expand(Params p, int l, int nt
     const int n_l = ld_acq(&p.ctrl->nl[l & 1]);
     const int e_l = ld_acq(&p.ctrl->el[l & 1]);
     const int par = l & 1, np = (l + 1) & 1;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        st_rel(&p.ctrl->ticket[par], 0u);
-        st_rel(&p.ctrl->kept[np], 0);
-    }
-    for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < ntiles; t += (int64_t)gridDim.x * kBlock)
-        p.desc[par][t] = 0ull;
-    for (int k = blockIdx.x; k < ntiles; k += gridDim.x) expand_tile(p, l, k, ntiles, n_l, e_l, lds_s.w);
+    if (blockIdx.x == 0 && threadIdx.x == 0) st_rel(&p.ctrl->kept[np], 0);
+    if (threadIdx.x == 0) p.desc[par][blockIdx.x] = 0ull;
+    expand_share(p, l, blockIdx.x, gridDim.x, ntiles, n_l, e_l, lds_s.w);
 }
 
 __global__ void __launch_bounds__(kBlock) k_parent(Params p) {
@@ -715,20 +1010,17 @@ __global__ void __launch_bounds__(256) k_plain_level(Params p, int l, const int3
     }
 }
 
-// ---- primitive test kernel ---------------------------------------------------------------------
+// ---- primitive test kernel: compaction of given private queues ------------------------------
 
-__global__ void __launch_bounds__(kBlock) k_prim_compact(Params p, int ntiles, int32_t* totals) {
+__global__ void __launch_bounds__(kBlock) k_prim_compact(Params p, int ntiles) {
     __shared__ Lds lds_s;
-    compact_phase(p, 0, ntiles, lds_s.w);
-    __syncthreads();
-    (void)totals;
+    compact_share(p, 0, blockIdx.x, gridDim.x, ntiles, false, true, lds_s.w);
 }
 
-__global__ void k_prim_reset(Params p, int ntiles) {
+__global__ void k_prim_reset(Params p, int P) {
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    for (int64_t t = tid; t < ntiles; t += (int64_t)gridDim.x * blockDim.x) p.desc[0][t] = 0ull;
+    for (int64_t t = tid; t < P; t += (int64_t)gridDim.x * blockDim.x) p.desc[0][t] = 0ull;
     if (tid == 0) {
-        p.ctrl->ticket[0] = 0;
         p.ctrl->kept[1] = 0;
         p.ctrl->nl[1] = 0;
         p.ctrl->el[1] = 0;
@@ -738,8 +1030,10 @@ __global__ void k_prim_reset(Params p, int ntiles) {
 
 __global__ void k_prim_totals(Params p, int32_t* totals) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
-        totals[0] = p.ctrl->nl[1];
-        totals[1] = p.ctrl->el[1];
+        const int nl = p.ctrl->nl[1], el = p.ctrl->el[1];
+        totals[0] = nl;
+        totals[1] = el;
+        if (nl >= 0 && nl <= p.n) p.f_ex[1][nl] = el;  // the total after the last entry, also for no entries
     }
 }
 
@@ -762,8 +1056,8 @@ static int fill_grid(int64_t items) {
     return (int)g;
 }
 
-hipError_t launch_prep(const Params& p, int prep_tiles, hipStream_t s) {
-    hipLaunchKernelGGL(k_prep, dim3(fill_grid(p.n)), dim3(kBlock), 0, s, p, prep_tiles);
+hipError_t launch_prep(const Params& p, int prep_shares, bool fill_parent, hipStream_t s) {
+    hipLaunchKernelGGL(k_prep, dim3(fill_grid(p.n)), dim3(kBlock), 0, s, p, prep_shares, fill_parent ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -772,18 +1066,19 @@ hipError_t launch_persistent(const Params& p, int grid, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_level_roots(const Params& p, hipStream_t s) {
-    hipLaunchKernelGGL(k_level_roots, dim3(fill_grid(p.nroots)), dim3(kBlock), 0, s, p);
+hipError_t launch_level_roots(const Params& p, int shares, hipStream_t s) {
+    hipLaunchKernelGGL(k_level_roots, dim3(fill_grid(p.nroots > shares ? p.nroots : shares)), dim3(kBlock), 0, s, p,
+                       shares);
     return hipGetLastError();
 }
 
-hipError_t launch_level_compact(const Params& p, int l, int ntiles, int grid, hipStream_t s) {
-    hipLaunchKernelGGL(k_level_compact, dim3(grid), dim3(kBlock), 0, s, p, l, ntiles);
+hipError_t launch_level_compact(const Params& p, int l, int ntiles, int shares, hipStream_t s) {
+    hipLaunchKernelGGL(k_level_compact, dim3(shares), dim3(kBlock), 0, s, p, l, ntiles);
     return hipGetLastError();
 }
 
-hipError_t launch_level_expand(const Params& p, int l, int ntiles, int grid, hipStream_t s) {
-    hipLaunchKernelGGL(k_level_expand, dim3(grid), dim3(kBlock), 0, s, p, l, ntiles);
+hipError_t launch_level_expand(const Params& p, int l, int ntiles, int shares, hipStream_t s) {
+    hipLaunchKernelGGL(k_level_expand, dim3(shares), dim3(kBlock), 0, s, p, l, ntiles);
     return hipGetLastError();
 }
 
@@ -805,9 +1100,10 @@ hipError_t launch_plain_level(const Params& p, int l, const int32_t* fv, int nf,
 }
 
 hipError_t launch_prim_compact(const int32_t* offsets, int32_t n, const int32_t* owner, const int32_t* cand,
-                               const int32_t* cnt, int32_t ntiles, int32_t* out_rs, int32_t* out_ex,
+                               const int32_t* cnt, int32_t ntiles, int32_t* out_v, int32_t* out_rs, int32_t* out_ex,
                                int32_t* out_tstart, int32_t tstart_cap, int32_t* totals, unsigned long long* desc,
                                Ctrl* ctrl, uint32_t* bitmap, hipStream_t s) {
+    // one share per tile: share t's private queue is tile t's
     Params p{};
     p.offsets = offsets;
     p.n = n;
@@ -815,6 +1111,7 @@ hipError_t launch_prim_compact(const int32_t* offsets, int32_t n, const int32_t*
     p.owner = const_cast<int32_t*>(owner);
     p.cand = const_cast<int32_t*>(cand);
     p.cnt = const_cast<int32_t*>(cnt);
+    p.f_v[1] = out_v;
     p.f_rs[1] = out_rs;
     p.f_ex[1] = out_ex;
     p.tstart[1] = out_tstart;
@@ -823,8 +1120,7 @@ hipError_t launch_prim_compact(const int32_t* offsets, int32_t n, const int32_t*
     p.bitmap = bitmap;
     p.spin_ticks = 300000000ull;
     hipLaunchKernelGGL(k_prim_reset, dim3(fill_grid(ntiles)), dim3(kBlock), 0, s, p, ntiles);
-    int g = ntiles < 1024 ? (ntiles > 0 ? ntiles : 1) : 1024;
-    hipLaunchKernelGGL(k_prim_compact, dim3(g), dim3(kBlock), 0, s, p, ntiles, totals);
+    if (ntiles > 0) hipLaunchKernelGGL(k_prim_compact, dim3(ntiles), dim3(kBlock), 0, s, p, ntiles);
     hipLaunchKernelGGL(k_prim_totals, dim3(1), dim3(64), 0, s, p, totals);
     return hipGetLastError();
 }

@@ -183,3 +183,21 @@ def test_small_stretches_handing_over_to_the_full_grid():
             lv, par = run_single(ws, s)
             assert_same(lv, par, g, [s])
         assert ws.stats()["status"] == 0
+
+
+@pytest.mark.parametrize("push_edges", [0, 64, 1 << 20, 1 << 30])
+@pytest.mark.parametrize("small_edges", [0, 16384])
+def test_parent_rules_agree(push_edges, small_edges):
+    # pushed (atomic minimum per edge) and pulled (first level-l entry of a
+    # sorted row) parents must agree; the hub's parent is the last entry of
+    # its 5000-long row, so the pull falls back to the whole-workgroup scan
+    n = 5002
+    edges = [(0, i) for i in range(1, 5001)] + [(5001, 5000)] + [(i, i + 1) for i in range(1, 60)]
+    star = gg.from_edges(n, edges)
+    g14 = gg.rmat(14, seed=23)
+    for g, srcs in [(star, [5001, 0, 30]), (g14, list(gg.pick_sources(g14, 3, seed=4)))]:
+        G = Graph(g.offsets, g.cols)
+        ws = Workspace(G, small_edges=small_edges, push_edges=push_edges)
+        for s in srcs:
+            lv, par = run_single(ws, s)
+            assert_same(lv, par, g, [s])
