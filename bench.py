@@ -142,6 +142,42 @@ def host_cores() -> int:
     return max(1, min(n, 16))
 
 
+def rocpd_summary(paths):
+    """Per-kernel summary of rocprofv3 databases (kernel trace and/or counters), as text."""
+    import sqlite3
+    for path in paths:
+        con = sqlite3.connect(path)
+        print(f"# {path}")
+        tabs = {r[0] for r in con.execute("select name from sqlite_master where type in ('table','view')")}
+        if "top_kernels" in tabs:
+            rows = con.execute("select name, total_calls, total_duration, average, percentage from top_kernels "
+                               "order by total_duration desc limit 10").fetchall()
+            if rows:
+                print("kernel | calls | total_us | avg_us | percent")
+                for r in rows:
+                    print(f"{r[0]} | {r[1]} | {r[2]:.1f} | {r[3]:.1f} | {r[4]:.2f}")
+        if "counters_collection" in tabs:
+            rows = con.execute("select kernel_name, counter_name, count(*), avg(value), min(value), max(value) "
+                               "from counters_collection group by kernel_name, counter_name "
+                               "order by avg(value) desc limit 12").fetchall()
+            if rows:
+                print("kernel | counter | dispatches | avg | min | max")
+                for r in rows:
+                    print(f"{r[0]} | {r[1]} | {r[2]} | {r[3]:.1f} | {r[4]:.1f} | {r[5]:.1f}")
+
+
+def calib_copy(args):
+    """A plain device copy of known size: the reference for scaling rocprofv3's HBM counters."""
+    import torch
+    nbytes = 1 << 30
+    x = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(4):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"calib_copy_bytes": nbytes, "launches": 4}), flush=True)
+
+
 def run(args):
     import torch
 
@@ -250,11 +286,19 @@ def main():
     ap.add_argument("--scale", type=int, default=24)
     ap.add_argument("--quick", action="store_true", help="headline workload only")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--calib-copy", action="store_true", help="only run a 1 GiB device copy (counter calibration)")
+    ap.add_argument("--rocpd-summary", nargs="+", metavar="DB", help="summarise rocprofv3 result databases and exit")
     args = ap.parse_args()
+    if args.rocpd_summary:
+        rocpd_summary(args.rocpd_summary)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build runs the search on a single MI355X "
               "(sharding across GPUs is not implemented)", file=sys.stderr)
         sys.exit(2)
+    if args.calib_copy:
+        calib_copy(args)
+        return
     run(args)
 
 
