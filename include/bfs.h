@@ -65,7 +65,9 @@ typedef struct bfs_workspace_s* bfs_workspace_t;  /* scratch for one in-flight r
 #define BFS_OPT_SMALL_EDGES 2  /* largest e_l run by a single workgroup (0 disables) */
 #define BFS_OPT_GRID        3  /* workgroups of the persistent kernel (0 = fill the GPU) */
 #define BFS_OPT_PROFILE     4  /* 1: time the main kernel with HIP events (bfs_stats_t.kernel_ms) */
-#define BFS_OPT_BATCH_PULL  5  /* batched search: edges above which a level pulls (-1 = never) */
+#define BFS_OPT_BATCH_PULL  5  /* batched search: active edges above which a level pulls instead
+                                  of pushing (-1 = never pull; default m / 8) */
+#define BFS_OPT_BATCH_LEVELS 7 /* batched search: levels per replay of the captured loop (default 8) */
 #define BFS_OPT_PUSH_EDGES  6  /* levels with at most this many edges push parents (atomic
                                   minimum per edge); larger ones pull them from sorted rows
                                   (default m / 8) */

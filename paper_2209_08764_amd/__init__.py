@@ -15,7 +15,7 @@ import numpy as np
 from . import _lib
 from ._lib import (BFS_DEVICE_PTRS, BFS_HOST_PTRS, BFS_MODE_AUTO, BFS_MODE_INSENSITIVE, BFS_MODE_LEVEL,
                    BFS_MODE_PLAIN, BFS_OPT_BATCH_PULL, BFS_OPT_GRID, BFS_OPT_MODE, BFS_OPT_PROFILE,
-                   BFS_OPT_PUSH_EDGES, BFS_OPT_SMALL_EDGES, BFS_VALIDATE, BFSError, bfs_stats_t)
+                   BFS_OPT_BATCH_LEVELS, BFS_OPT_PUSH_EDGES, BFS_OPT_SMALL_EDGES, BFS_VALIDATE, BFSError, bfs_stats_t)
 
 __all__ = [
     "bfs_init", "bfs_graph_free", "bfs_graph_info", "bfs_workspace_bytes", "bfs_workspace_create",
@@ -24,7 +24,7 @@ __all__ = [
     "bfs_prim_compact",
     "bfs_prim_grain", "Graph", "Workspace", "BFSError",
     "BFS_MODE_AUTO", "BFS_MODE_LEVEL", "BFS_MODE_PLAIN", "BFS_MODE_INSENSITIVE", "BFS_OPT_MODE",
-    "BFS_OPT_SMALL_EDGES", "BFS_OPT_GRID", "BFS_OPT_PROFILE", "BFS_OPT_BATCH_PULL", "BFS_OPT_PUSH_EDGES",
+    "BFS_OPT_SMALL_EDGES", "BFS_OPT_GRID", "BFS_OPT_PROFILE", "BFS_OPT_BATCH_PULL", "BFS_OPT_PUSH_EDGES", "BFS_OPT_BATCH_LEVELS",
     "BFS_HOST_PTRS",
     "BFS_DEVICE_PTRS", "BFS_VALIDATE",
 ]
@@ -221,7 +221,8 @@ class Workspace:
         if mode is not None:
             bfs_workspace_set_option(self.handle, BFS_OPT_MODE, mode)
         names = {"small_edges": BFS_OPT_SMALL_EDGES, "grid": BFS_OPT_GRID, "profile": BFS_OPT_PROFILE,
-                 "batch_pull": BFS_OPT_BATCH_PULL, "push_edges": BFS_OPT_PUSH_EDGES}
+                 "batch_pull": BFS_OPT_BATCH_PULL, "push_edges": BFS_OPT_PUSH_EDGES,
+                 "batch_levels": BFS_OPT_BATCH_LEVELS}
         for k, v in opts.items():
             bfs_workspace_set_option(self.handle, names[k], v)
 

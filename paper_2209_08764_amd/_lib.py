@@ -37,6 +37,7 @@ BFS_OPT_GRID = 3
 BFS_OPT_PROFILE = 4
 BFS_OPT_BATCH_PULL = 5
 BFS_OPT_PUSH_EDGES = 6
+BFS_OPT_BATCH_LEVELS = 7
 
 MODE_NAMES = {BFS_MODE_AUTO: "auto", BFS_MODE_LEVEL: "level", BFS_MODE_PLAIN: "plain",
               BFS_MODE_INSENSITIVE: "insensitive"}

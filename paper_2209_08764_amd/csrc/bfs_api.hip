@@ -80,11 +80,26 @@ struct bfs_workspace_s {
     unsigned long long* b_nx = nullptr;
     unsigned long long* b_vis = nullptr;
     int32_t* b_act[2] = {nullptr, nullptr};
+    int32_t* b_act_rs[2] = {nullptr, nullptr};
     int32_t* b_act_ex[2] = {nullptr, nullptr};
     int32_t* b_tstart[2] = {nullptr, nullptr};
     unsigned long long* b_desc[2] = {nullptr, nullptr};
     uint32_t* b_act_bits = nullptr;
+    int32_t* b_nz_v = nullptr;
+    int32_t* b_nz_ts = nullptr;
     int32_t* b_sources = nullptr;
+    int32_t b_max_tiles = 0;
+    int32_t b_utiles = 0;
+    int32_t b_grid_cap = 0;
+    int32_t batch_levels = 8;            // levels per replay of the captured loop
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t b_exec = nullptr;
+    hipGraph_t b_graph = nullptr;
+    uint8_t* b_exec_level = nullptr;     // the graph's baked-in arguments
+    int32_t b_exec_k = 0;
+    int32_t b_exec_grid = 0;
+    int32_t b_exec_pull = 0;
+    int32_t b_exec_levels = 0;
     // host side
     Ctrl* h_ctrl = nullptr;  // pinned
     hipEvent_t ev_done = nullptr, ev0 = nullptr, ev1 = nullptr;
@@ -315,6 +330,41 @@ bfs_status_t run_common(bfs_workspace_s* ws, const int32_t* roots_host, int32_t 
     return st;
 }
 
+BatchParams make_batch_params(bfs_workspace_s* ws, uint8_t* level, int32_t k, const int32_t* sources_dev) {
+    BatchParams bp{};
+    bp.offsets = ws->g->offsets;
+    bp.cols = ws->g->cols;
+    bp.n = ws->g->n;
+    bp.m = ws->g->m;
+    bp.k = k;
+    bp.words = (k + 63) / 64;
+    bp.level = level;
+    bp.fr = ws->b_fr;
+    bp.nx = ws->b_nx;
+    bp.vis = ws->b_vis;
+    for (int i = 0; i < 2; ++i) {
+        bp.act[i] = ws->b_act[i];
+        bp.act_rs[i] = ws->b_act_rs[i];
+        bp.act_ex[i] = ws->b_act_ex[i];
+        bp.act_ts[i] = ws->b_tstart[i];
+        bp.desc[i] = ws->b_desc[i];
+    }
+    bp.act_bits = ws->b_act_bits;
+    bp.nz_v = ws->b_nz_v;
+    bp.nz_ts = ws->b_nz_ts;
+    bp.sources = sources_dev;
+    bp.ctrl = ws->ctrl;
+    bp.stat_nl = ws->stat_nl;
+    bp.stat_el = ws->stat_el;
+    bp.max_tiles = ws->b_max_tiles;
+    bp.utiles = ws->b_utiles;
+    // pulling reads every row once; pushing costs up to four atomics per active edge
+    bp.pull_edges = ws->batch_pull >= -1 ? (ws->batch_pull < 0 ? INT32_MAX : ws->batch_pull)
+                                         : (int32_t)std::min<int64_t>(ws->g->m / 8, INT32_MAX);
+    bp.spin_ticks = kSpinTicks;
+    return bp;
+}
+
 }  // namespace
 
 extern "C" {
@@ -438,7 +488,11 @@ bfs_status_t bfs_workspace_free(bfs_workspace_t ws) {
                     ws->tstart[1], ws->cand, ws->cnt, ws->desc[0], ws->desc[1], ws->ctrl, ws->stat_nl,
                     ws->stat_el, ws->stat_ts, ws->roots, ws->plain_fv[0], ws->plain_fv[1], ws->b_fr, ws->b_nx, ws->b_vis,
                     ws->b_act[0], ws->b_act[1], ws->b_act_ex[0], ws->b_act_ex[1], ws->b_tstart[0],
-                    ws->b_tstart[1], ws->b_desc[0], ws->b_desc[1], ws->b_act_bits, ws->b_sources};
+                    ws->b_tstart[1], ws->b_desc[0], ws->b_desc[1], ws->b_act_bits, ws->b_sources,
+                    ws->b_act_rs[0], ws->b_act_rs[1], ws->b_nz_v, ws->b_nz_ts};
+    if (ws->b_exec) (void)hipGraphExecDestroy(ws->b_exec);
+    if (ws->b_graph) (void)hipGraphDestroy(ws->b_graph);
+    if (ws->cap_stream) (void)hipStreamDestroy(ws->cap_stream);
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     if (ws->h_ctrl) (void)hipHostFree(ws->h_ctrl);
@@ -485,16 +539,21 @@ bfs_status_t bfs_workspace_create(bfs_graph_t g, int32_t max_sources, bfs_worksp
     A(dalloc(&ws->stat_ts, 3 * (size_t)kStatCap));
     A(dalloc(&ws->roots, n));
     if (max_sources > 1) {
+        ws->b_max_tiles = (int32_t)((g->m + kGrainB - 1) / kGrainB + 2);
+        ws->b_utiles = (int32_t)((n + kUTile - 1) / kUTile);
         A(dalloc(&ws->b_fr, n * 4));
         A(dalloc(&ws->b_nx, n * 4));
         A(dalloc(&ws->b_vis, n * 4));
         for (int i = 0; i < 2; ++i) {
             A(dalloc(&ws->b_act[i], n + 2));
+            A(dalloc(&ws->b_act_rs[i], n + 2));
             A(dalloc(&ws->b_act_ex[i], n + 2));
-            A(dalloc(&ws->b_tstart[i], (size_t)T));
-            A(dalloc(&ws->b_desc[i], (size_t)T));
+            A(dalloc(&ws->b_tstart[i], (size_t)ws->b_max_tiles));
+            A(dalloc(&ws->b_desc[i], (size_t)std::max(ws->b_utiles, 1)));
         }
-        A(dalloc(&ws->b_act_bits, (n + 31) / 32));
+        A(dalloc(&ws->b_act_bits, (n + 31) / 32 + 1));
+        A(dalloc(&ws->b_nz_v, n + 1));
+        A(dalloc(&ws->b_nz_ts, (size_t)ws->b_max_tiles));
         A(dalloc(&ws->b_sources, 256));
     }
     if (okk && hipHostMalloc(reinterpret_cast<void**>(&ws->h_ctrl), sizeof(Ctrl), hipHostMallocDefault) != hipSuccess)
@@ -525,6 +584,18 @@ bfs_status_t bfs_workspace_create(bfs_graph_t g, int32_t max_sources, bfs_worksp
         bfs_workspace_free(ws);
         return fail(BFS_EHIP, "hipMemset failed");
     }
+    if (max_sources > 1) {
+        ws->b_grid_cap = batch_grid_capacity(ws->device);
+        if (ws->b_grid_cap <= 0 || hipStreamCreateWithFlags(&ws->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+            bfs_workspace_free(ws);
+            return fail(BFS_EHIP, "could not prepare the batched search");
+        }
+        BatchParams bp = make_batch_params(ws, nullptr, 0, nullptr);
+        if (launch_batch_setup(bp, ws->b_grid_cap, nullptr) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+            bfs_workspace_free(ws);
+            return fail(BFS_EHIP, "batched set-up kernels failed");
+        }
+    }
     *out = ws;
     return BFS_OK;
 }
@@ -550,6 +621,10 @@ bfs_status_t bfs_workspace_set_option(bfs_workspace_t ws, int32_t option, int64_
         case BFS_OPT_PUSH_EDGES:
             if (value < 0 || value > INT32_MAX) return fail(BFS_EINVAL, "bad push threshold");
             ws->push_edges = (int32_t)value;
+            return BFS_OK;
+        case BFS_OPT_BATCH_LEVELS:
+            if (value < 1 || value > 256) return fail(BFS_EINVAL, "levels per replay must be in [1, 256]");
+            ws->batch_levels = (int32_t)value;
             return BFS_OK;
         case BFS_OPT_BATCH_PULL:
             if (value < -1 || value > INT32_MAX) return fail(BFS_EINVAL, "bad pull threshold");
@@ -721,8 +796,78 @@ bfs_status_t bfs_prim_compact(const int32_t* offsets, int32_t n, const int32_t* 
 }
 
 bfs_status_t bfs_run_batch(bfs_workspace_t ws, const int32_t* sources, int32_t k, uint8_t* level, void* stream) {
-    (void)ws; (void)sources; (void)k; (void)level; (void)stream;
-    return fail(BFS_EINVAL, "batched search not built yet");
+    if (!ws) return fail(BFS_EINVAL, "null workspace");
+    if (!sources || !level) return fail(BFS_EINVAL, "null sources or level array");
+    if (k < 1 || k > ws->max_sources)
+        return fail(BFS_EINVAL, "k = %d outside [1, %d] (the workspace's max_sources)", k, ws->max_sources);
+    if (!ws->b_fr) return fail(BFS_EINVAL, "workspace was created for single-source runs (max_sources = 1)");
+    if (reinterpret_cast<uintptr_t>(level) % 4 != 0) return fail(BFS_EINVAL, "level array must be 4-byte aligned");
+    for (int32_t j = 0; j < k; ++j)
+        if (sources[j] < 0 || sources[j] >= ws->g->n)
+            return fail(BFS_ERANGE, "source %d = %d outside [0, %d)", j, sources[j], ws->g->n);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    bfs_status_t st = check_busy(ws, s);
+    if (st) return st;
+    HIP_TRY(hipSetDevice(ws->device));
+    ws->host_stats = false;
+    ws->profiled = false;
+    ws->last_mode = BFS_MODE_AUTO;
+    ws->host_status = BFS_OK;
+    HIP_TRY(hipMemcpyAsync(ws->b_sources, sources, sizeof(int32_t) * (size_t)k, hipMemcpyHostToDevice, s));
+    BatchParams bp = make_batch_params(ws, level, k, ws->b_sources);
+    const int grid = ws->grid_opt > 0 ? std::min(ws->grid_opt, ws->b_grid_cap) : ws->b_grid_cap;
+    // the captured level loop bakes in its arguments: recapture when they change
+    if (!ws->b_exec || ws->b_exec_level != level || ws->b_exec_k != k || ws->b_exec_grid != grid ||
+        ws->b_exec_pull != bp.pull_edges || ws->b_exec_levels != ws->batch_levels) {
+        if (ws->b_exec) (void)hipGraphExecDestroy(ws->b_exec);
+        if (ws->b_graph) (void)hipGraphDestroy(ws->b_graph);
+        ws->b_exec = nullptr;
+        ws->b_graph = nullptr;
+        HIP_TRY(hipStreamBeginCapture(ws->cap_stream, hipStreamCaptureModeThreadLocal));
+        for (int i = 0; i < ws->batch_levels; ++i) {
+            hipError_t e = launch_batch_level(bp, grid, ws->cap_stream);
+            if (e != hipSuccess) {
+                hipGraph_t gdead = nullptr;
+                (void)hipStreamEndCapture(ws->cap_stream, &gdead);
+                if (gdead) (void)hipGraphDestroy(gdead);
+                return fail(BFS_EHIP, "capturing the batched level loop: %s", hipGetErrorString(e));
+            }
+        }
+        HIP_TRY(hipStreamEndCapture(ws->cap_stream, &ws->b_graph));
+        HIP_TRY(hipGraphInstantiate(&ws->b_exec, ws->b_graph, nullptr, nullptr, 0));
+        ws->b_exec_level = level;
+        ws->b_exec_k = k;
+        ws->b_exec_grid = grid;
+        ws->b_exec_pull = bp.pull_edges;
+        ws->b_exec_levels = ws->batch_levels;
+    }
+    std::pair<hipEvent_t, hipEvent_t>* pe = nullptr;
+    if (ws->profile) {
+        st = profile_slot(ws, &pe);
+        if (st) return st;
+        HIP_TRY(hipEventRecord(pe->first, s));
+    }
+    HIP_TRY(launch_batch_start(bp, s));
+    // replay the captured levels until the device reports that nothing is active
+    const int64_t max_replays = (int64_t)ws->g->n / std::max(ws->batch_levels, 1) + 2;
+    for (int64_t r = 0;; ++r) {
+        HIP_TRY(hipGraphLaunch(ws->b_exec, s));
+        HIP_TRY(hipMemcpyAsync(ws->h_ctrl, ws->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (ws->h_ctrl->bdone || ws->h_ctrl->error) break;
+        if (r > max_replays) return fail(BFS_EDEVICE, "batched level loop did not finish");
+    }
+    if (pe) {
+        HIP_TRY(hipEventRecord(pe->second, s));
+        ws->profiled = true;
+    }
+    ws->last_grid = grid;
+    HIP_TRY(hipEventRecord(ws->ev_done, s));
+    ws->last_stream = s;
+    ws->has_run = true;
+    if (ws->h_ctrl->error) return fail(BFS_EDEVICE, "device-side failure in the batched search (code %d)", ws->h_ctrl->error);
+    if (ws->h_ctrl->batch_overflow) return fail(BFS_EOVERFLOW, "a batched level reached 255");
+    return BFS_OK;
 }
 
 }  // extern "C"

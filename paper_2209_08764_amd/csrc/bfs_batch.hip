@@ -1,0 +1,477 @@
+// Batched multi-source search: k <= 256 searches in one level loop, each
+// vertex carrying 4 x 64-bit masks (bit j = source j): frontier F, next N
+// and visited V.  Per level l:
+//
+//   expand  push (few active edges): every edge (u, v) of an active vertex u
+//           ORs F[u] into N[v] with 64-bit atomics, load-balanced over the
+//           active list with the same share / sub-tile split as the
+//           single-source loop (the paper's equal division of e_l);
+//           pull (many active edges): every vertex of degree >= 1 that still
+//           misses some source ORs F[u] over its active neighbours u (active
+//           bitmap in L2) into an LDS accumulator; only rows cut by a
+//           sub-tile boundary go to N[v] atomically.
+//   update  a dense pass over the vertices: new = N & ~V, V |= new, F = new,
+//           level byte l + 1 for every new bit (byte-masked wave stores of
+//           the vertex's row), N = 0, and the next active list with its
+//           degree prefix sums and sub-tile start points by decoupled
+//           look-back over update tiles (the Sizes prefix sum again).
+//   next    one lane advances the level and stops the loop when no vertex is
+//           active or a level would not fit in a byte.
+//
+// OR is commutative and idempotent, so the result does not depend on the
+// order of the atomics or on push versus pull.  The level loop is replayed
+// from a captured hipGraph; every kernel returns at once after the stop.
+#include "bfs_device.h"
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace s3bfs {
+
+namespace {
+
+__device__ __forceinline__ void bshare_range(int b, int P, int ntiles, int* tb, int* te) {
+    *tb = (int)(((int64_t)b * ntiles) / P);
+    *te = (int)(((int64_t)(b + 1) * ntiles) / P);
+}
+
+__device__ __forceinline__ void bflag(Ctrl* c) {
+    __hip_atomic_store(&c->error, BFS_EINTERNAL_CODE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void bscatter(const BatchParams& p, int32_t* ts, int pos, int64_t e, int d) {
+    int64_t t = (e + kGrainB - 1) / kGrainB;
+    const int64_t tend = (e + d + kGrainB - 1) / kGrainB;
+    if (t < 0 || tend > p.max_tiles) {
+        bflag(p.ctrl);
+        return;
+    }
+    for (; t < tend; ++t) ts[t] = pos;
+}
+
+struct BLds {
+    unsigned long long acc[kSliceB * 4];   // pull accumulators (8 B aligned first)
+    int sl[3 * kSliceB];                   // sub-tile slice: ex | rs | v
+    int misc[2 * kWaves + 16 + kUTile / 32];
+};
+
+}  // namespace
+
+// ---- one-off set-up: the vertices of degree >= 1 and the sub-tiles over all edges ----------
+// nz_v lists them in ascending order; since isolated vertices own no edge,
+// the edges before nz_v[j] are exactly offsets[nz_v[j]].
+__global__ void __launch_bounds__(kBlock) k_batch_nz(BatchParams p) {
+    __shared__ BLds lds;
+    int* s_wave = lds.misc;
+    const int tile = blockIdx.x;
+    const int v0 = tile * kUTile + threadIdx.x * kUV;
+    int keep[kUV], tc = 0;
+#pragma unroll
+    for (int i = 0; i < kUV; ++i) {
+        const int v = v0 + i;
+        keep[i] = v < p.n && p.offsets[v + 1] > p.offsets[v];
+        tc += keep[i];
+    }
+    int C;
+    const int pre = block_excl_scan(tc, s_wave, &C);
+    int* s_b = lds.misc + 2 * kWaves;
+    if (wave_id() == 0) {
+        int pc = 0, ps = 0;
+        const bool ok = lookback_wave(p.desc[0], tile, C, 0, p.ctrl, p.spin_ticks, &pc, &ps);
+        if (threadIdx.x == 0) {
+            s_b[0] = pc;
+            s_b[1] = ok;
+            if (ok && tile == (int)gridDim.x - 1) st_rel(&p.ctrl->nz_count, pc + C);
+        }
+    }
+    __syncthreads();
+    if (!s_b[1]) return;
+    int pos = s_b[0] + pre;
+#pragma unroll
+    for (int i = 0; i < kUV; ++i) {
+        if (keep[i]) {
+            const int v = v0 + i;
+            p.nz_v[pos] = v;
+            bscatter(p, p.nz_ts, pos, p.offsets[v], p.offsets[v + 1] - p.offsets[v]);
+            ++pos;
+        }
+    }
+}
+
+// ---- per run ---------------------------------------------------------------------------------
+
+// level bytes = 255, V = N = 0, active bitmap = 0, control block reset.
+__global__ void __launch_bounds__(kBlock) k_batch_prep(BatchParams p) {
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t nbytes = (int64_t)p.n * p.k;
+    uint32_t* l32 = reinterpret_cast<uint32_t*>(p.level);  // the caller's array is 4-byte aligned
+    for (int64_t i = tid; i < nbytes / 4; i += stride) l32[i] = 0xffffffffu;
+    for (int64_t i = (nbytes / 4) * 4 + tid; i < nbytes; i += stride) p.level[i] = 255;
+    for (int64_t i = tid; i < (int64_t)p.n * 4; i += stride) {
+        p.vis[i] = 0ull;
+        p.nx[i] = 0ull;
+    }
+    for (int64_t i = tid; i < ((int64_t)p.n + 31) / 32; i += stride) p.act_bits[i] = 0u;
+    for (int64_t i = tid; i < p.utiles; i += stride) p.desc[0][i] = 0ull;
+    if (tid == 0) {
+        Ctrl* c = p.ctrl;
+        c->b_nact[0] = c->b_nact[1] = 0;
+        c->b_eact[0] = c->b_eact[1] = 0;
+        c->blevel = -1;
+        c->bdone = 0;
+        c->batch_overflow = 0;
+        c->error = 0;
+        c->levels = 0;
+    }
+}
+
+// Bit j of N[sources[j]]: the sources become the "next" set of level -1.
+__global__ void k_batch_seed(BatchParams p) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        for (int j = 0; j < p.k; ++j) {
+            const int s = p.sources[j];
+            p.nx[(int64_t)s * 4 + (j >> 6)] |= 1ull << (j & 63);
+        }
+    }
+}
+
+// Dense update after the expansion of level l (l = -1: the seeds).
+__global__ void __launch_bounds__(kBlock) k_batch_update(BatchParams p) {
+    __shared__ BLds lds;
+    Ctrl* c = p.ctrl;
+    if (ld_acq(&c->bdone)) return;
+    const int l = ld_acq(&c->blevel);
+    const int np = (l + 1) & 1;
+    int* s_wave = lds.misc;
+    int* s_wave2 = lds.misc + kWaves;
+    int* s_b = lds.misc + 2 * kWaves;
+    uint32_t* s_bits = reinterpret_cast<uint32_t*>(lds.misc + 2 * kWaves + 16);
+    const int tile = blockIdx.x;
+    const int v0 = tile * kUTile + threadIdx.x * kUV;
+    const int W = p.words;
+    const uint8_t lv = (uint8_t)(l + 1);
+    const bool fits = l + 1 < 255;
+    if (threadIdx.x < kUTile / 32) s_bits[threadIdx.x] = 0u;
+    __syncthreads();
+    int tc = 0, ts = 0;
+    int act[kUV], deg[kUV], rs[kUV];
+    unsigned long long nw[kUV][4];
+#pragma unroll
+    for (int i = 0; i < kUV; ++i) {
+        const int v = v0 + i;
+        act[i] = 0;
+        deg[i] = 0;
+        rs[i] = 0;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) nw[i][w] = 0ull;
+        if (v < p.n) {
+            unsigned long long any = 0ull;
+            unsigned long long nn[4];
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                nn[w] = w < W ? p.nx[(int64_t)v * 4 + w] : 0ull;
+                any |= nn[w];
+            }
+            if (any) {
+                unsigned long long fresh = 0ull;
+#pragma unroll
+                for (int w = 0; w < 4; ++w) {
+                    if (w < W) {
+                        const unsigned long long vw = p.vis[(int64_t)v * 4 + w];
+                        nw[i][w] = nn[w] & ~vw;
+                        fresh |= nw[i][w];
+                        p.nx[(int64_t)v * 4 + w] = 0ull;
+                        if (nw[i][w]) p.vis[(int64_t)v * 4 + w] = vw | nw[i][w];
+                        p.fr[(int64_t)v * 4 + w] = nw[i][w];
+                    }
+                }
+                if (fresh) {
+                    if (!fits) {
+                        __hip_atomic_store(&c->batch_overflow, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    } else {
+                        act[i] = 1;
+                        rs[i] = p.offsets[v];
+                        deg[i] = p.offsets[v + 1] - rs[i];
+                        atomicOr(&s_bits[(threadIdx.x * kUV + i) >> 5], 1u << ((threadIdx.x * kUV + i) & 31));
+                        if (deg[i] > 0) {
+                            ++tc;
+                            ts += deg[i];
+                        }
+                    }
+                }
+            }
+        }
+    }
+    // level bytes: the wave writes each new vertex's row, lane q covering sources 4q..4q+3
+#pragma unroll
+    for (int i = 0; i < kUV; ++i) {
+        uint64_t todo = ballot(act[i] != 0);
+        while (todo) {
+            const int src_lane = __builtin_ctzll(todo);
+            todo &= todo - 1;
+            const int v = __builtin_amdgcn_readfirstlane(__shfl(v0 + i, src_lane));
+            unsigned long long m4[4];
+#pragma unroll
+            for (int w = 0; w < 4; ++w) m4[w] = __shfl(nw[i][w], src_lane);
+            const int q = lane_id();
+            uint8_t* row = p.level + (int64_t)v * p.k;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int j = 4 * q + b;
+                if (j < p.k && ((m4[j >> 6] >> (j & 63)) & 1ull)) row[j] = lv;
+            }
+        }
+    }
+    int C, S;
+    const int pre_c = block_excl_scan(tc, s_wave, &C);
+    const int pre_s = block_excl_scan(ts, s_wave2, &S);
+    if (wave_id() == 0) {
+        int pc = 0, ps = 0;
+        const bool ok = lookback_wave(p.desc[np], tile, C, S, c, p.spin_ticks, &pc, &ps);
+        if (threadIdx.x == 0) {
+            s_b[0] = pc;
+            s_b[1] = ps;
+            s_b[2] = ok;
+            if (ok && tile == (int)gridDim.x - 1) {
+                st_rel(&c->b_nact[np], pc + C);
+                st_rel(&c->b_eact[np], ps + S);
+                p.act_ex[np][pc + C] = ps + S;
+            }
+        }
+    }
+    __syncthreads();
+    // active bitmap of the next level (this tile's 2048 vertices are 64 whole words)
+    if (threadIdx.x < kUTile / 32) {
+        const int64_t wi = ((int64_t)tile * kUTile) / 32 + threadIdx.x;
+        if (wi < ((int64_t)p.n + 31) / 32) p.act_bits[wi] = s_bits[threadIdx.x];
+    }
+    if (!s_b[2]) return;
+    int pos = s_b[0] + pre_c;
+    int64_t e = (int64_t)s_b[1] + pre_s;
+#pragma unroll
+    for (int i = 0; i < kUV; ++i) {
+        if (act[i] && deg[i] > 0) {
+            if ((unsigned)pos < (unsigned)p.n) {
+                p.act[np][pos] = v0 + i;
+                p.act_rs[np][pos] = rs[i];
+                p.act_ex[np][pos] = (int)e;
+                bscatter(p, p.act_ts[np], pos, e, deg[i]);
+            } else {
+                bflag(c);
+            }
+            ++pos;
+            e += deg[i];
+        }
+    }
+}
+
+// Expansion of level l: push over the active edges or pull over all rows.
+__global__ void __launch_bounds__(kBlock) k_batch_expand(BatchParams p) {
+    __shared__ BLds lds;
+    Ctrl* c = p.ctrl;
+    if (ld_acq(&c->bdone)) return;
+    const int l = ld_acq(&c->blevel);
+    const int par = l & 1;
+    const int n_a = ld_acq(&c->b_nact[par]);
+    const int e_a = ld_acq(&c->b_eact[par]);
+    const int W = p.words;
+    // descriptors of this level's update (last used two levels ago)
+    for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < p.utiles; t += (int64_t)gridDim.x * kBlock)
+        p.desc[(l + 1) & 1][t] = 0ull;
+    int* sl = lds.sl;
+    if (e_a <= p.pull_edges) {
+        // ---- push over the active list ----
+        const int ntiles = (int)(((int64_t)e_a + kGrainB - 1) / kGrainB);
+        const int P = ntiles < (int)gridDim.x ? ntiles : (int)gridDim.x;
+        if ((int)blockIdx.x >= P) return;
+        int tb, te;
+        bshare_range(blockIdx.x, P, ntiles, &tb, &te);
+        const int32_t* ts = p.act_ts[par];
+        for (int t = tb; t < te; ++t) {
+            const int j0 = ts[t];
+            const int j1 = t + 1 < ntiles ? ts[t + 1] : n_a - 1;
+            const int nv = j1 - j0 + 1;
+            if (j0 < 0 || j1 >= n_a || nv < 1 || nv > kSliceB) {
+                if (threadIdx.x == 0) bflag(c);
+                return;
+            }
+            __syncthreads();
+            for (int i = threadIdx.x; i < nv; i += kBlock) {
+                sl[i] = p.act_ex[par][j0 + i];
+                sl[kSliceB + i] = p.act_rs[par][j0 + i];
+                sl[2 * kSliceB + i] = p.act[par][j0 + i];
+            }
+            __syncthreads();
+            const int g0 = t * kGrainB, g1 = min(g0 + kGrainB, e_a);
+#pragma unroll
+            for (int r = 0; r < kBVT; ++r) {
+                const int g = g0 + r * kBlock + threadIdx.x;
+                if (g < g1) {
+                    int lo = 0, hi = nv;
+                    while (hi - lo > 1) {
+                        const int mid = (lo + hi) >> 1;
+                        if (sl[mid] <= g) lo = mid; else hi = mid;
+                    }
+                    const int idx = sl[kSliceB + lo] + (g - sl[lo]);
+                    const int u = sl[2 * kSliceB + lo];
+                    if ((unsigned)idx >= (unsigned)p.m) {
+                        bflag(c);
+                        continue;
+                    }
+                    const int v = p.cols[idx];
+                    if ((unsigned)v >= (unsigned)p.n) continue;
+#pragma unroll
+                    for (int w = 0; w < 4; ++w) {
+                        if (w < W) {
+                            const unsigned long long f = p.fr[(int64_t)u * 4 + w];
+                            if (f) atomicOr(&p.nx[(int64_t)v * 4 + w], f);
+                        }
+                    }
+                }
+            }
+        }
+        return;
+    }
+    // ---- pull over every row that still misses a source ----
+    const int nz = ld_acq(&c->nz_count);
+    const int ntiles = (int)((p.m + kGrainB - 1) / kGrainB);
+    const int P = ntiles < (int)gridDim.x ? ntiles : (int)gridDim.x;
+    if ((int)blockIdx.x >= P) return;
+    int tb, te;
+    bshare_range(blockIdx.x, P, ntiles, &tb, &te);
+    unsigned long long full[4];
+#pragma unroll
+    for (int w = 0; w < 4; ++w)
+        full[w] = w < W ? ((w + 1) * 64 <= p.k ? ~0ull : ((1ull << (p.k - w * 64)) - 1ull)) : 0ull;
+    for (int t = tb; t < te; ++t) {
+        const int j0 = p.nz_ts[t];
+        const int j1 = t + 1 < ntiles ? p.nz_ts[t + 1] : nz - 1;
+        const int nv = j1 - j0 + 1;
+        if (j0 < 0 || j1 >= nz || nv < 1 || nv > kSliceB) {
+            if (threadIdx.x == 0) bflag(c);
+            return;
+        }
+        const int64_t g0 = (int64_t)t * kGrainB, g1 = min(g0 + kGrainB, p.m);
+        __syncthreads();
+        // slice: row start | vertex | 1 if the vertex still misses a source
+        for (int i = threadIdx.x; i < nv; i += kBlock) {
+            const int v = p.nz_v[j0 + i];
+            sl[i] = p.offsets[v];
+            sl[kSliceB + i] = v;
+            bool need = false;
+#pragma unroll
+            for (int w = 0; w < 4; ++w)
+                if (w < W) need |= p.vis[(int64_t)v * 4 + w] != full[w];
+            sl[2 * kSliceB + i] = need;
+#pragma unroll
+            for (int w = 0; w < 4; ++w) lds.acc[i * 4 + w] = 0ull;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kBVT; ++r) {
+            const int64_t g = g0 + r * kBlock + threadIdx.x;
+            if (g < g1) {
+                int lo = 0, hi = nv;
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (sl[mid] <= g) lo = mid; else hi = mid;
+                }
+                if (sl[2 * kSliceB + lo]) {
+                    const int u = p.cols[g];
+                    if ((unsigned)u < (unsigned)p.n && ((p.act_bits[u >> 5] >> (u & 31)) & 1u)) {
+#pragma unroll
+                        for (int w = 0; w < 4; ++w) {
+                            if (w < W) {
+                                const unsigned long long f = p.fr[(int64_t)u * 4 + w];
+                                if (f) atomicOr(&lds.acc[lo * 4 + w], f);
+                            }
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        // hand the accumulated masks to N: rows cut by the sub-tile's ends may also be
+        // accumulated by a neighbouring sub-tile, so those use atomics
+        for (int i = threadIdx.x; i < nv; i += kBlock) {
+            const int v = sl[kSliceB + i];
+            const int64_t r0 = sl[i], r1 = p.offsets[v + 1];
+            const bool cut = r0 < g0 || r1 > g1;
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                if (w < W) {
+                    const unsigned long long a = lds.acc[i * 4 + w];
+                    if (a) {
+                        if (cut) atomicOr(&p.nx[(int64_t)v * 4 + w], a);
+                        else p.nx[(int64_t)v * 4 + w] = a;
+                    }
+                }
+            }
+        }
+    }
+}
+
+// Advances the level; stops the loop when nothing is active or a level overflowed.
+__global__ void k_batch_next(BatchParams p) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    Ctrl* c = p.ctrl;
+    if (c->bdone) return;
+    const int l = c->blevel + 1;
+    c->blevel = l;
+    const int na = c->b_nact[l & 1];
+    if (na > 0) {
+        if (l < kStatCap) {
+            p.stat_nl[l] = na;
+            p.stat_el[l] = c->b_eact[l & 1];
+        }
+        c->levels = l + 1;
+    }
+    if (na == 0 || c->batch_overflow || c->error) c->bdone = 1;
+}
+
+// ---- host launchers ----------------------------------------------------------------------------
+
+int batch_grid_capacity(int device) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k_batch_expand), kBlock,
+                                                     0) != hipSuccess)
+        return 0;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
+    return per_cu * cus;
+}
+
+static int bfill_grid(int64_t items) {
+    int64_t g = (items + kBlock - 1) / kBlock;
+    if (g < 1) g = 1;
+    if (g > 4096) g = 4096;
+    return (int)g;
+}
+
+// Once per workspace: the list of vertices of degree >= 1 and its sub-tile starts.
+hipError_t launch_batch_setup(const BatchParams& p, int grid, hipStream_t s) {
+    (void)grid;
+    hipLaunchKernelGGL(k_batch_prep, dim3(bfill_grid(p.n)), dim3(kBlock), 0, s, p);
+    hipLaunchKernelGGL(k_batch_nz, dim3(p.utiles), dim3(kBlock), 0, s, p);
+    return hipGetLastError();
+}
+
+// Per run: reset, seed, and the update that turns the seeds into level 0.
+hipError_t launch_batch_start(const BatchParams& p, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_prep, dim3(bfill_grid((int64_t)p.n * 4)), dim3(kBlock), 0, s, p);
+    hipLaunchKernelGGL(k_batch_seed, dim3(1), dim3(64), 0, s, p);
+    hipLaunchKernelGGL(k_batch_update, dim3(p.utiles), dim3(kBlock), 0, s, p);
+    hipLaunchKernelGGL(k_batch_next, dim3(1), dim3(64), 0, s, p);
+    return hipGetLastError();
+}
+
+// One level: expand, update, next (captured into a graph by the caller).
+hipError_t launch_batch_level(const BatchParams& p, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_expand, dim3(grid), dim3(kBlock), 0, s, p);
+    hipLaunchKernelGGL(k_batch_update, dim3(p.utiles), dim3(kBlock), 0, s, p);
+    hipLaunchKernelGGL(k_batch_next, dim3(1), dim3(64), 0, s, p);
+    return hipGetLastError();
+}
+
+}  // namespace s3bfs

@@ -39,12 +39,14 @@ struct Ctrl {
     int resume;               // level at which the full grid resumes
     int heartbeat;            // bumped by a lone workgroup so waiting ones keep waiting
     int plain_next;           // PLAIN mode: next-frontier counter
-    int batch_active;         // batched: active vertices of the next level
-    int batch_edges;          // batched: their edge total
-    int batch_new;            // batched: vertices with new bits
+    int b_nact[2];            // batched: active vertices of a level, per parity
+    int b_eact[2];            // batched: their edge total, per parity
+    int blevel;               // batched: level whose expansion runs next
+    int bdone;                // batched: no active vertex left (or overflow)
     int batch_overflow;       // batched: a level reached 255
     int r_nl, r_el, r_kept;   // frontier handed back by a lone workgroup (level = resume)
-    int pad[9];
+    int nz_count;             // batched: vertices of degree >= 1
+    int pad[5];
 };
 
 struct Params {
@@ -82,23 +84,38 @@ struct Params {
 };
 
 // Batched multi-source search (up to 256 sources, 4 x 64-bit masks per vertex).
+constexpr int kBVT = 2;                   // edges per thread in one batched sub-tile
+constexpr int kGrainB = kBlock * kBVT;    // edges per batched sub-tile, 1024
+constexpr int kSliceB = kGrainB + 1;
+constexpr int kUV = 4;                    // vertices per thread in the dense update pass
+constexpr int kUTile = kBlock * kUV;      // vertices per update tile, 2048
+
 struct BatchParams {
     const int32_t* offsets;
     const int32_t* cols;
     int32_t n;
-    int32_t k;                // sources in this batch
-    uint8_t* level;           // [n][k]
+    int64_t m;
+    int32_t k;                // sources in this batch (1..256)
+    int32_t words;            // mask words in use, ceil(k / 64)
+    uint8_t* level;           // [n][k], 255 = unreached
     unsigned long long* fr;   // frontier masks [n][4]
-    unsigned long long* nx;   // next masks [n][4]
+    unsigned long long* nx;   // next masks [n][4] (all zero between levels)
     unsigned long long* vis;  // visited masks [n][4]
-    int32_t* act[2];          // active vertex lists per parity
+    int32_t* act[2];          // active vertices, per level parity
+    int32_t* act_rs[2];       // their row starts
     int32_t* act_ex[2];       // their exclusive degree sums (+ total)
-    int32_t* tstart[2];       // share start points per parity
-    unsigned long long* desc[2];
-    uint32_t* act_bits;       // active bitmap of the current level
+    int32_t* act_ts[2];       // sub-tile start points over the active edges
+    uint32_t* act_bits;       // active bitmap of the level being expanded
+    int32_t* nz_v;            // vertices of degree >= 1, ascending (static per graph)
+    int32_t* nz_ts;           // sub-tile start points over all edges [0, m) in nz_v
+    unsigned long long* desc[2];  // look-back descriptors of the update tiles, per parity
+    const int32_t* sources;   // the k sources (device)
     Ctrl* ctrl;
-    int32_t max_tiles;
-    int32_t pull_edges;       // edges above which a level pulls instead of pushing
+    int32_t* stat_nl;
+    int32_t* stat_el;
+    int32_t max_tiles;        // entries of act_ts / nz_ts
+    int32_t utiles;           // update tiles, ceil(n / kUTile)
+    int32_t pull_edges;       // levels with more active edges pull instead of pushing
     uint64_t spin_ticks;
 };
 
@@ -119,7 +136,9 @@ hipError_t launch_prim_compact(const int32_t* offsets, int32_t n, const int32_t*
                                int32_t* totals, unsigned long long* desc, Ctrl* ctrl, uint32_t* bitmap,
                                hipStream_t s);
 
-hipError_t launch_batch_init(const BatchParams& p, const int32_t* sources_dev, hipStream_t s);
-hipError_t launch_batch_level(const BatchParams& p, int l, int grid, hipStream_t s);
+hipError_t launch_batch_setup(const BatchParams& p, int grid, hipStream_t s);
+hipError_t launch_batch_start(const BatchParams& p, hipStream_t s);
+hipError_t launch_batch_level(const BatchParams& p, int grid, hipStream_t s);
+int batch_grid_capacity(int device);
 
 }  // namespace s3bfs

@@ -1,0 +1,93 @@
+"""GPU parity of the batched multi-source search against the oracle (bit-exact uint8 levels).
+
+Column j of the [n][k] output must equal the single-source oracle's levels
+from sources[j] mapped to uint8 (255 = unreached), for any mix of pushed and
+pulled levels and any number of levels per graph replay.
+"""
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2209_08764_amd import BFSError, Graph, Workspace, _lib  # noqa: E402
+
+
+def _check(ws, g, srcs):
+    out = ws.run_batch(srcs)
+    ws.sync()
+    got = out.cpu().numpy().reshape(g.n, len(srcs))
+    want, ovf = oracle.bfs_batch_u8(g.offsets, g.cols, srcs)
+    assert not ovf
+    bad = np.argwhere(got != want)
+    assert bad.size == 0, f"{len(bad)} entries differ, first (v, j) {bad[:5].tolist()}: " \
+                          f"got {got[tuple(bad[0])]} want {want[tuple(bad[0])]}"
+
+
+@pytest.fixture(scope="module")
+def rmat13():
+    g = gg.rmat(13, seed=31)
+    return g, Graph(g.offsets, g.cols)
+
+
+@pytest.mark.parametrize("k", [1, 7, 63, 64, 65, 130, 200, 256])
+def test_batch_matches_oracle(rmat13, k):
+    g, G = rmat13
+    ws = Workspace(G, max_sources=256)
+    _check(ws, g, gg.pick_sources(g, k, seed=k))
+
+
+@pytest.mark.parametrize("pull", [-1, 0, 1000, 100000])
+@pytest.mark.parametrize("levels", [1, 3, 8])
+def test_push_pull_and_replay_length_do_not_change_results(rmat13, pull, levels):
+    g, G = rmat13
+    ws = Workspace(G, max_sources=256, batch_pull=pull, batch_levels=levels)
+    _check(ws, g, gg.pick_sources(g, 96, seed=7))
+
+
+@pytest.mark.parametrize("make", [lambda: gg.grid(40, 30), lambda: gg.powerlaw_forest(3000, seed=5),
+                                  lambda: gg.erdos_renyi(5000, 3.0, seed=2), lambda: gg.rmat(11, seed=2, permute=False)])
+def test_structured_graphs(make):
+    g = make()
+    G = Graph(g.offsets, g.cols)
+    ws = Workspace(G, max_sources=256)
+    _check(ws, g, gg.pick_sources(g, 77, seed=3))
+
+
+def test_duplicate_sources_and_reuse(rmat13):
+    g, G = rmat13
+    ws = Workspace(G, max_sources=128)
+    s = gg.pick_sources(g, 20, seed=9)
+    srcs = np.concatenate([s, s[:5], s[3:4]])
+    _check(ws, g, srcs)
+    _check(ws, g, s[:3])          # a different k: the captured loop is rebuilt
+    _check(ws, g, srcs)
+
+
+def test_overflow_on_long_paths():
+    n = 300
+    path = gg.from_edges(n, [(i, i + 1) for i in range(n - 1)])
+    G = Graph(path.offsets, path.cols)
+    ws = Workspace(G, max_sources=4)
+    with pytest.raises(BFSError) as e:
+        ws.run_batch([0, 10])
+    assert e.value.status == _lib.BFS_EOVERFLOW
+    # sources whose eccentricity fits are fine
+    _check(ws, path, [150, 140])
+
+
+def test_batch_errors(rmat13):
+    g, G = rmat13
+    ws = Workspace(G, max_sources=8)
+    with pytest.raises(BFSError) as e:
+        ws.run_batch(list(range(9)))
+    assert e.value.status == _lib.BFS_EINVAL
+    with pytest.raises(BFSError) as e:
+        ws.run_batch([0, g.n])
+    assert e.value.status == _lib.BFS_ERANGE
+    single = Workspace(G)          # max_sources = 1 has no batched buffers
+    with pytest.raises(BFSError):
+        single.run_batch([1, 2])
