@@ -178,6 +178,120 @@ def calib_copy(args):
     print(json.dumps({"calib_copy_bytes": nbytes, "launches": 4}), flush=True)
 
 
+def bench_c1(torch, W, Graph, Workspace):
+    """R-MAT scale 16, one seeded source: microseconds per search."""
+    g, srcs = W.c1_rmat16()
+    G = Graph(g.offsets, g.cols)
+    ws = Workspace(G, profile=1)
+    lv = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    pa = torch.empty_like(lv)
+    s = int(srcs[0])
+    ws.run(s, lv, pa)
+    st = ws.stats()
+    mc_half = st["edges"] / 2
+    step_ms, _, kms = time_single_source(ws, lv, pa, [s], 200, torch, [mc_half])
+    t = float(np.median(step_ms))
+    return {"workload": "rmat16 (scale 16, EF 16), 1 source", "us_per_search": round(t * 1e3, 1),
+            "kernel_us": round(float(np.median(kms)) * 1e3, 1), "gteps": round(mc_half / (t * 1e-3) / 1e9, 3),
+            "levels": st["levels"], "small_levels": st["small_levels"]}
+
+
+def bench_c2(torch, W, Graph, Workspace):
+    """4096 x 4096 grid from corner 0: a high-diameter search (8191 levels)."""
+    g, srcs = W.c2_grid4096()
+    G = Graph(g.offsets, g.cols)
+    ws = Workspace(G, profile=1)
+    lv = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    pa = torch.empty_like(lv)
+    ws.run(0, lv, pa)
+    st = ws.stats()
+    step_ms, _, kms = time_single_source(ws, lv, pa, [0], 3, torch, [st["edges"] / 2])
+    t = float(np.median(step_ms))
+    W_ = 4096
+    r, c = np.divmod(np.arange(g.n), W_)
+    closed = bool(np.array_equal(lv.cpu().numpy(), r + c))
+    return {"workload": "grid 4096x4096 from vertex 0", "ms_per_search": round(t, 2),
+            "us_per_level": round(t * 1e3 / st["levels"], 2), "levels": st["levels"],
+            "small_levels": st["small_levels"], "gteps": round(st["edges"] / 2 / (t * 1e-3) / 1e9, 3),
+            "closed_form_levels_ok": closed}
+
+
+def bench_c4(torch, W, Graph, Workspace, g=None, srcs=None):
+    """R-MAT scale 22, 256 sources in one batched run; versus single-source and plain runs."""
+    from paper_2209_08764_amd import BFS_MODE_PLAIN, BFS_OPT_MODE
+    if g is None:
+        g, srcs = W.c4_rmat22()
+    G = Graph(g.offsets, g.cols)
+    ws = Workspace(G, max_sources=256, profile=1)
+    out = torch.empty(g.n * 256, dtype=torch.uint8, device="cuda")
+    ws.run_batch(srcs, out)
+    ws.sync()
+    ws.kernel_times()
+    times = []
+    for _ in range(5):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ws.run_batch(srcs, out)
+        torch.cuda.synchronize()
+        times.append((time.perf_counter() - t0) * 1e3)
+    kt = ws.kernel_times()
+    tb = float(np.median(times))
+    lev = out.view(g.n, 256)
+    deg = torch.from_numpy(np.diff(g.offsets.astype(np.int64))).cuda()
+    edges = float(sum(int(deg[lev[:, j] != 255].sum()) for j in range(256))) / 2
+    n_l, e_l = ws.level_stats()
+    # 16 of the sources one at a time (single-source path), and the plain kernel on 4
+    ss = Workspace(G, profile=1)
+    lv = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    pa = torch.empty_like(lv)
+    mc = []
+    for s in srcs[:16]:
+        ss.run(int(s), lv, pa)
+        mc.append(ss.stats()["edges"] / 2)
+    sm, _, _ = time_single_source(ss, lv, pa, srcs[:16], 16, torch, mc)
+    single_ms = float(np.mean(sm))
+    ss.set(BFS_OPT_MODE, BFS_MODE_PLAIN)
+    pm, _, _ = time_single_source(ss, lv, pa, srcs[:4], 4, torch, mc[:4])
+    plain_ms = float(np.mean(pm))
+    gteps = edges / (tb * 1e-3) / 1e9
+    return {"workload": "rmat22 (scale 22, EF 16), 256 sources in one batched run",
+            "ms_per_batch": round(tb, 3), "loop_ms": round(float(np.median(kt)), 3),
+            "gteps_aggregate": round(gteps, 1), "levels": len(n_l),
+            "active_per_level": n_l.tolist(), "active_edges_per_level": e_l.tolist(),
+            "single_source_ms_mean": round(single_ms, 3),
+            "speedup_vs_256_single_source": round(256 * single_ms / tb, 2),
+            "plain_ms_mean": round(plain_ms, 2), "speedup_vs_256_plain": round(256 * plain_ms / tb, 1)}
+
+
+def bench_c5(torch, W, count: int, rmat22=None):
+    """Serving: 8 resident graphs, Poisson queries at 0.7x the closed-loop rate."""
+    from paper_2209_08764_amd.serve import GpuExecutor, Scheduler, latency_summary, poisson_queries
+    graphs = W.c5_graphs() if rmat22 is None else None
+    if graphs is None:
+        graphs = W.c5_graphs_with(rmat22)
+    ex = GpuExecutor(graphs, max_inflight=4)
+    noniso = {k: np.flatnonzero(np.diff(g.offsets)) for k, g in graphs.items()}
+    budget = 16 << 30
+    # closed loop: all queries at t = 0, the saturated rate
+    sch = Scheduler(ex, budget_bytes=budget, max_inflight=4)
+    warm = poisson_queries(graphs, noniso, rate=0, count=min(200, count), seed=5)
+    sch.run(warm)
+    closed = poisson_queries(graphs, noniso, rate=0, count=count, seed=6)
+    sch.run(closed)
+    sat = latency_summary(closed)["qps"]
+    rate = 0.7 * sat
+    qs = poisson_queries(graphs, noniso, rate=rate, count=count, seed=7)
+    sch.run(qs)
+    summ = latency_summary(qs)
+    sch.close()
+    return {"workload": "8 resident graphs (rmat18/20/22/23, G(2^20, 8), grids 1024^2 and 2048^2, "
+                        "power-law forest 2^20), Poisson arrivals",
+            "closed_loop_qps": round(sat, 1), "rate_qps": round(rate, 1), "queries": count,
+            "p50_ms": round(summ["p50_ms"], 3), "p99_ms": round(summ["p99_ms"], 3),
+            "mean_ms": round(summ["mean_ms"], 3), "qps": round(summ["qps"], 1),
+            "batched_fraction": round(summ["batched_fraction"], 3), "budget_bytes": budget}
+
+
 def run(args):
     import torch
 
@@ -254,6 +368,28 @@ def run(args):
         log(f"CPU oracle baseline on {threads} host threads")
         cpu = cpu_baseline(g, sources, threads)
         log(f"  oracle {cpu['value']} GTEPS on {threads} threads")
+    ws.free()
+    G.free()
+    del level, parent, ws, G, g
+    torch.cuda.empty_cache()
+
+    if not args.quick:
+        log("C1: R-MAT 16")
+        extras["c1"] = bench_c1(torch, W, Graph, Workspace)
+        log(f"  {extras['c1']}")
+        log("C2: grid 4096x4096")
+        extras["c2"] = bench_c2(torch, W, Graph, Workspace)
+        log(f"  {extras['c2']}")
+        torch.cuda.empty_cache()
+        log("C4: R-MAT 22, 256 sources batched")
+        g22, s22 = W.c4_rmat22()
+        extras["c4"] = bench_c4(torch, W, Graph, Workspace, g22, s22)
+        log(f"  {extras['c4']}")
+        torch.cuda.empty_cache()
+        if args.serve_queries > 0:
+            log(f"C5: serving, {args.serve_queries} queries")
+            extras["c5"] = bench_c5(torch, W, args.serve_queries, rmat22=g22)
+            log(f"  {extras['c5']}")
 
     out = {
         "metric": METRIC,
@@ -286,6 +422,7 @@ def main():
     ap.add_argument("--scale", type=int, default=24)
     ap.add_argument("--quick", action="store_true", help="headline workload only")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--serve-queries", type=int, default=2000, help="queries in the serving run (0 skips it)")
     ap.add_argument("--calib-copy", action="store_true", help="only run a 1 GiB device copy (counter calibration)")
     ap.add_argument("--rocpd-summary", nargs="+", metavar="DB", help="summarise rocprofv3 result databases and exit")
     args = ap.parse_args()

@@ -48,6 +48,20 @@ def c4_rmat22(scale: int = 22, nsrc: int = 256):
     return g, pick_sources(g, nsrc, seed=SEEDS["rmat22"][1])
 
 
+def c5_graphs_with(rmat22):
+    """The serving set reusing an already generated R-MAT 22 (same seed as C4)."""
+    return {
+        "rmat18": rmat(18, 16, seed=SEEDS["rmat18"][0]),
+        "rmat20": rmat(20, 16, seed=SEEDS["rmat20"][0]),
+        "rmat22": rmat22,
+        "rmat23": rmat(23, 16, seed=SEEDS["rmat23"][0]),
+        "er20": erdos_renyi(1 << 20, 8.0, seed=SEEDS["er20"][0]),
+        "grid1024": grid(1024, 1024),
+        "grid2048": grid(2048, 2048),
+        "forest20": powerlaw_forest(1 << 20, seed=SEEDS["forest20"][0]),
+    }
+
+
 def c5_graphs(small: bool = False):
     """The serving set: name -> graph.  small=True shrinks every graph (tests)."""
     if small:

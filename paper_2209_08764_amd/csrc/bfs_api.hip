@@ -92,14 +92,11 @@ struct bfs_workspace_s {
     int32_t b_utiles = 0;
     int32_t b_grid_cap = 0;
     int32_t batch_levels = 8;            // levels per replay of the captured loop
-    hipStream_t cap_stream = nullptr;
+    hipStream_t own_stream = nullptr;    // the workspace's private stream (set-up and capture)
     hipGraphExec_t b_exec = nullptr;
     hipGraph_t b_graph = nullptr;
-    uint8_t* b_exec_level = nullptr;     // the graph's baked-in arguments
-    int32_t b_exec_k = 0;
-    int32_t b_exec_grid = 0;
-    int32_t b_exec_pull = 0;
-    int32_t b_exec_levels = 0;
+    BatchArgs* b_args = nullptr;         // per-run arguments the captured kernels read
+    BatchArgs* h_args = nullptr;         // pinned staging copy
     // host side
     Ctrl* h_ctrl = nullptr;  // pinned
     hipEvent_t ev_done = nullptr, ev0 = nullptr, ev1 = nullptr;
@@ -330,15 +327,13 @@ bfs_status_t run_common(bfs_workspace_s* ws, const int32_t* roots_host, int32_t 
     return st;
 }
 
-BatchParams make_batch_params(bfs_workspace_s* ws, uint8_t* level, int32_t k, const int32_t* sources_dev) {
+BatchParams make_batch_params(bfs_workspace_s* ws) {
     BatchParams bp{};
     bp.offsets = ws->g->offsets;
     bp.cols = ws->g->cols;
     bp.n = ws->g->n;
     bp.m = ws->g->m;
-    bp.k = k;
-    bp.words = (k + 63) / 64;
-    bp.level = level;
+    bp.args = ws->b_args;
     bp.fr = ws->b_fr;
     bp.nx = ws->b_nx;
     bp.vis = ws->b_vis;
@@ -352,17 +347,49 @@ BatchParams make_batch_params(bfs_workspace_s* ws, uint8_t* level, int32_t k, co
     bp.act_bits = ws->b_act_bits;
     bp.nz_v = ws->b_nz_v;
     bp.nz_ts = ws->b_nz_ts;
-    bp.sources = sources_dev;
+    bp.sources = ws->b_sources;
     bp.ctrl = ws->ctrl;
     bp.stat_nl = ws->stat_nl;
     bp.stat_el = ws->stat_el;
     bp.max_tiles = ws->b_max_tiles;
     bp.utiles = ws->b_utiles;
-    // pulling reads every row once; pushing costs up to four atomics per active edge
-    bp.pull_edges = ws->batch_pull >= -1 ? (ws->batch_pull < 0 ? INT32_MAX : ws->batch_pull)
-                                         : (int32_t)std::min<int64_t>(ws->g->m / 8, INT32_MAX);
     bp.spin_ticks = kSpinTicks;
     return bp;
+}
+
+int32_t batch_pull_edges(const bfs_workspace_s* ws) {
+    // pulling reads every row once; pushing costs up to four atomics per active edge
+    return ws->batch_pull >= -1 ? (ws->batch_pull < 0 ? INT32_MAX : ws->batch_pull)
+                                : (int32_t)std::min<int64_t>(ws->g->m / 8, INT32_MAX);
+}
+
+int batch_grid(const bfs_workspace_s* ws) {
+    return ws->grid_opt > 0 ? std::min(ws->grid_opt, ws->b_grid_cap) : ws->b_grid_cap;
+}
+
+// Captures batch_levels levels of the batched loop on the workspace's own
+// stream.  Done when the workspace is made or its launch shape changes,
+// never while a run is in progress.
+bfs_status_t capture_batch(bfs_workspace_s* ws) {
+    if (ws->b_exec) (void)hipGraphExecDestroy(ws->b_exec);
+    if (ws->b_graph) (void)hipGraphDestroy(ws->b_graph);
+    ws->b_exec = nullptr;
+    ws->b_graph = nullptr;
+    const BatchParams bp = make_batch_params(ws);
+    const int grid = batch_grid(ws);
+    HIP_TRY(hipStreamBeginCapture(ws->own_stream, hipStreamCaptureModeThreadLocal));
+    for (int i = 0; i < ws->batch_levels; ++i) {
+        hipError_t e = launch_batch_level(bp, grid, ws->own_stream);
+        if (e != hipSuccess) {
+            hipGraph_t gdead = nullptr;
+            (void)hipStreamEndCapture(ws->own_stream, &gdead);
+            if (gdead) (void)hipGraphDestroy(gdead);
+            return fail(BFS_EHIP, "capturing the batched level loop: %s", hipGetErrorString(e));
+        }
+    }
+    HIP_TRY(hipStreamEndCapture(ws->own_stream, &ws->b_graph));
+    HIP_TRY(hipGraphInstantiate(&ws->b_exec, ws->b_graph, nullptr, nullptr, 0));
+    return BFS_OK;
 }
 
 }  // namespace
@@ -492,7 +519,9 @@ bfs_status_t bfs_workspace_free(bfs_workspace_t ws) {
                     ws->b_act_rs[0], ws->b_act_rs[1], ws->b_nz_v, ws->b_nz_ts};
     if (ws->b_exec) (void)hipGraphExecDestroy(ws->b_exec);
     if (ws->b_graph) (void)hipGraphDestroy(ws->b_graph);
-    if (ws->cap_stream) (void)hipStreamDestroy(ws->cap_stream);
+    if (ws->b_args) (void)hipFree(ws->b_args);
+    if (ws->h_args) (void)hipHostFree(ws->h_args);
+    if (ws->own_stream) (void)hipStreamDestroy(ws->own_stream);
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     if (ws->h_ctrl) (void)hipHostFree(ws->h_ctrl);
@@ -570,30 +599,44 @@ bfs_status_t bfs_workspace_create(bfs_graph_t g, int32_t max_sources, bfs_worksp
         bfs_workspace_free(ws);
         return fail(BFS_EHIP, "could not size the persistent grid");
     }
-    // defined contents everywhere, so no stale or never-written entry can hold an out-of-range index
-    bool zok = hipMemset(ws->cnt, 0, sizeof(int32_t) * (size_t)T) == hipSuccess &&
-               hipMemset(ws->cand, 0, sizeof(int32_t) * (size_t)T * kGrain) == hipSuccess &&
-               hipMemset(ws->owner, 0xff, sizeof(int32_t) * n) == hipSuccess;
+    // defined contents everywhere, so no stale or never-written entry can hold an out-of-range
+    // index; everything is set up on the workspace's own stream (no device-wide synchronisation)
+    if (hipStreamCreateWithFlags(&ws->own_stream, hipStreamNonBlocking) != hipSuccess) {
+        bfs_workspace_free(ws);
+        return fail(BFS_EHIP, "could not create the workspace stream");
+    }
+    hipStream_t os = ws->own_stream;
+    bool zok = hipMemsetAsync(ws->cnt, 0, sizeof(int32_t) * (size_t)T, os) == hipSuccess &&
+               hipMemsetAsync(ws->cand, 0, sizeof(int32_t) * (size_t)T * kGrain, os) == hipSuccess &&
+               hipMemsetAsync(ws->owner, 0xff, sizeof(int32_t) * n, os) == hipSuccess;
     for (int i = 0; i < 2 && zok; ++i)
-        zok = hipMemset(ws->tstart[i], 0, sizeof(int32_t) * (size_t)T) == hipSuccess &&
-              hipMemset(ws->f_rs[i], 0, sizeof(int32_t) * (n + 2)) == hipSuccess &&
-              hipMemset(ws->f_ex[i], 0, sizeof(int32_t) * (n + 2)) == hipSuccess &&
-              hipMemset(ws->f_v[i], 0, sizeof(int32_t) * (n + 2)) == hipSuccess &&
-              hipMemset(ws->desc[i], 0, sizeof(unsigned long long) * (size_t)T) == hipSuccess;
-    if (!zok || hipMemset(ws->ctrl, 0, sizeof(Ctrl)) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+        zok = hipMemsetAsync(ws->tstart[i], 0, sizeof(int32_t) * (size_t)T, os) == hipSuccess &&
+              hipMemsetAsync(ws->f_rs[i], 0, sizeof(int32_t) * (n + 2), os) == hipSuccess &&
+              hipMemsetAsync(ws->f_ex[i], 0, sizeof(int32_t) * (n + 2), os) == hipSuccess &&
+              hipMemsetAsync(ws->f_v[i], 0, sizeof(int32_t) * (n + 2), os) == hipSuccess &&
+              hipMemsetAsync(ws->desc[i], 0, sizeof(unsigned long long) * (size_t)T, os) == hipSuccess;
+    if (!zok || hipMemsetAsync(ws->ctrl, 0, sizeof(Ctrl), os) != hipSuccess || hipStreamSynchronize(os) != hipSuccess) {
         bfs_workspace_free(ws);
         return fail(BFS_EHIP, "hipMemset failed");
     }
     if (max_sources > 1) {
         ws->b_grid_cap = batch_grid_capacity(ws->device);
-        if (ws->b_grid_cap <= 0 || hipStreamCreateWithFlags(&ws->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        if (ws->b_grid_cap <= 0 || dalloc(&ws->b_args, 1) != hipSuccess ||
+            hipHostMalloc(reinterpret_cast<void**>(&ws->h_args), sizeof(BatchArgs), hipHostMallocDefault) != hipSuccess) {
             bfs_workspace_free(ws);
             return fail(BFS_EHIP, "could not prepare the batched search");
         }
-        BatchParams bp = make_batch_params(ws, nullptr, 0, nullptr);
-        if (launch_batch_setup(bp, ws->b_grid_cap, nullptr) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+        *ws->h_args = BatchArgs{nullptr, 0, 0, batch_pull_edges(ws), 0};
+        const BatchParams bp = make_batch_params(ws);
+        if (hipMemcpyAsync(ws->b_args, ws->h_args, sizeof(BatchArgs), hipMemcpyHostToDevice, os) != hipSuccess ||
+            launch_batch_setup(bp, ws->b_grid_cap, os) != hipSuccess || hipStreamSynchronize(os) != hipSuccess) {
             bfs_workspace_free(ws);
             return fail(BFS_EHIP, "batched set-up kernels failed");
+        }
+        bfs_status_t cst = capture_batch(ws);
+        if (cst) {
+            bfs_workspace_free(ws);
+            return cst;
         }
     }
     *out = ws;
@@ -614,7 +657,7 @@ bfs_status_t bfs_workspace_set_option(bfs_workspace_t ws, int32_t option, int64_
         case BFS_OPT_GRID:
             if (value < 0 || value > INT32_MAX) return fail(BFS_EINVAL, "bad grid");
             ws->grid_opt = (int32_t)value;
-            return BFS_OK;
+            return ws->b_exec ? capture_batch(ws) : BFS_OK;
         case BFS_OPT_PROFILE:
             ws->profile = value != 0;
             return BFS_OK;
@@ -625,7 +668,7 @@ bfs_status_t bfs_workspace_set_option(bfs_workspace_t ws, int32_t option, int64_
         case BFS_OPT_BATCH_LEVELS:
             if (value < 1 || value > 256) return fail(BFS_EINVAL, "levels per replay must be in [1, 256]");
             ws->batch_levels = (int32_t)value;
-            return BFS_OK;
+            return ws->b_exec ? capture_batch(ws) : BFS_OK;
         case BFS_OPT_BATCH_PULL:
             if (value < -1 || value > INT32_MAX) return fail(BFS_EINVAL, "bad pull threshold");
             ws->batch_pull = (int32_t)value;
@@ -814,33 +857,10 @@ bfs_status_t bfs_run_batch(bfs_workspace_t ws, const int32_t* sources, int32_t k
     ws->last_mode = BFS_MODE_AUTO;
     ws->host_status = BFS_OK;
     HIP_TRY(hipMemcpyAsync(ws->b_sources, sources, sizeof(int32_t) * (size_t)k, hipMemcpyHostToDevice, s));
-    BatchParams bp = make_batch_params(ws, level, k, ws->b_sources);
-    const int grid = ws->grid_opt > 0 ? std::min(ws->grid_opt, ws->b_grid_cap) : ws->b_grid_cap;
-    // the captured level loop bakes in its arguments: recapture when they change
-    if (!ws->b_exec || ws->b_exec_level != level || ws->b_exec_k != k || ws->b_exec_grid != grid ||
-        ws->b_exec_pull != bp.pull_edges || ws->b_exec_levels != ws->batch_levels) {
-        if (ws->b_exec) (void)hipGraphExecDestroy(ws->b_exec);
-        if (ws->b_graph) (void)hipGraphDestroy(ws->b_graph);
-        ws->b_exec = nullptr;
-        ws->b_graph = nullptr;
-        HIP_TRY(hipStreamBeginCapture(ws->cap_stream, hipStreamCaptureModeThreadLocal));
-        for (int i = 0; i < ws->batch_levels; ++i) {
-            hipError_t e = launch_batch_level(bp, grid, ws->cap_stream);
-            if (e != hipSuccess) {
-                hipGraph_t gdead = nullptr;
-                (void)hipStreamEndCapture(ws->cap_stream, &gdead);
-                if (gdead) (void)hipGraphDestroy(gdead);
-                return fail(BFS_EHIP, "capturing the batched level loop: %s", hipGetErrorString(e));
-            }
-        }
-        HIP_TRY(hipStreamEndCapture(ws->cap_stream, &ws->b_graph));
-        HIP_TRY(hipGraphInstantiate(&ws->b_exec, ws->b_graph, nullptr, nullptr, 0));
-        ws->b_exec_level = level;
-        ws->b_exec_k = k;
-        ws->b_exec_grid = grid;
-        ws->b_exec_pull = bp.pull_edges;
-        ws->b_exec_levels = ws->batch_levels;
-    }
+    *ws->h_args = BatchArgs{level, k, (k + 63) / 64, batch_pull_edges(ws), 0};
+    HIP_TRY(hipMemcpyAsync(ws->b_args, ws->h_args, sizeof(BatchArgs), hipMemcpyHostToDevice, s));
+    const BatchParams bp = make_batch_params(ws);
+    const int grid = batch_grid(ws);
     std::pair<hipEvent_t, hipEvent_t>* pe = nullptr;
     if (ws->profile) {
         st = profile_slot(ws, &pe);

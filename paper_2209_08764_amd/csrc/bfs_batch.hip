@@ -104,10 +104,11 @@ __global__ void __launch_bounds__(kBlock) k_batch_nz(BatchParams p) {
 __global__ void __launch_bounds__(kBlock) k_batch_prep(BatchParams p) {
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    const int64_t nbytes = (int64_t)p.n * p.k;
-    uint32_t* l32 = reinterpret_cast<uint32_t*>(p.level);  // the caller's array is 4-byte aligned
+    uint8_t* level = p.args->level;
+    const int64_t nbytes = level ? (int64_t)p.n * p.args->k : 0;
+    uint32_t* l32 = reinterpret_cast<uint32_t*>(level);  // the caller's array is 4-byte aligned
     for (int64_t i = tid; i < nbytes / 4; i += stride) l32[i] = 0xffffffffu;
-    for (int64_t i = (nbytes / 4) * 4 + tid; i < nbytes; i += stride) p.level[i] = 255;
+    for (int64_t i = (nbytes / 4) * 4 + tid; i < nbytes; i += stride) level[i] = 255;
     for (int64_t i = tid; i < (int64_t)p.n * 4; i += stride) {
         p.vis[i] = 0ull;
         p.nx[i] = 0ull;
@@ -129,7 +130,7 @@ __global__ void __launch_bounds__(kBlock) k_batch_prep(BatchParams p) {
 // Bit j of N[sources[j]]: the sources become the "next" set of level -1.
 __global__ void k_batch_seed(BatchParams p) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        for (int j = 0; j < p.k; ++j) {
+        for (int j = 0; j < p.args->k; ++j) {
             const int s = p.sources[j];
             p.nx[(int64_t)s * 4 + (j >> 6)] |= 1ull << (j & 63);
         }
@@ -149,7 +150,9 @@ __global__ void __launch_bounds__(kBlock) k_batch_update(BatchParams p) {
     uint32_t* s_bits = reinterpret_cast<uint32_t*>(lds.misc + 2 * kWaves + 16);
     const int tile = blockIdx.x;
     const int v0 = tile * kUTile + threadIdx.x * kUV;
-    const int W = p.words;
+    const int W = p.args->words;
+    const int K = p.args->k;
+    uint8_t* level = p.args->level;
     const uint8_t lv = (uint8_t)(l + 1);
     const bool fits = l + 1 < 255;
     if (threadIdx.x < kUTile / 32) s_bits[threadIdx.x] = 0u;
@@ -215,11 +218,11 @@ __global__ void __launch_bounds__(kBlock) k_batch_update(BatchParams p) {
 #pragma unroll
             for (int w = 0; w < 4; ++w) m4[w] = __shfl(nw[i][w], src_lane);
             const int q = lane_id();
-            uint8_t* row = p.level + (int64_t)v * p.k;
+            uint8_t* row = level + (int64_t)v * K;
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
                 const int j = 4 * q + b;
-                if (j < p.k && ((m4[j >> 6] >> (j & 63)) & 1ull)) row[j] = lv;
+                if (j < K && ((m4[j >> 6] >> (j & 63)) & 1ull)) row[j] = lv;
             }
         }
     }
@@ -275,12 +278,13 @@ __global__ void __launch_bounds__(kBlock) k_batch_expand(BatchParams p) {
     const int par = l & 1;
     const int n_a = ld_acq(&c->b_nact[par]);
     const int e_a = ld_acq(&c->b_eact[par]);
-    const int W = p.words;
+    const int W = p.args->words;
+    const int K = p.args->k;
     // descriptors of this level's update (last used two levels ago)
     for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < p.utiles; t += (int64_t)gridDim.x * kBlock)
         p.desc[(l + 1) & 1][t] = 0ull;
     int* sl = lds.sl;
-    if (e_a <= p.pull_edges) {
+    if (e_a <= p.args->pull_edges) {
         // ---- push over the active list ----
         const int ntiles = (int)(((int64_t)e_a + kGrainB - 1) / kGrainB);
         const int P = ntiles < (int)gridDim.x ? ntiles : (int)gridDim.x;
@@ -343,7 +347,7 @@ __global__ void __launch_bounds__(kBlock) k_batch_expand(BatchParams p) {
     unsigned long long full[4];
 #pragma unroll
     for (int w = 0; w < 4; ++w)
-        full[w] = w < W ? ((w + 1) * 64 <= p.k ? ~0ull : ((1ull << (p.k - w * 64)) - 1ull)) : 0ull;
+        full[w] = w < W ? ((w + 1) * 64 <= K ? ~0ull : ((1ull << (K - w * 64)) - 1ull)) : 0ull;
     for (int t = tb; t < te; ++t) {
         const int j0 = p.nz_ts[t];
         const int j1 = t + 1 < ntiles ? p.nz_ts[t + 1] : nz - 1;

@@ -90,14 +90,22 @@ constexpr int kSliceB = kGrainB + 1;
 constexpr int kUV = 4;                    // vertices per thread in the dense update pass
 constexpr int kUTile = kBlock * kUV;      // vertices per update tile, 2048
 
+// Per-run arguments of a batched search, read by the kernels from device
+// memory so that one captured level loop serves every run of a workspace.
+struct BatchArgs {
+    uint8_t* level;           // [n][k], 255 = unreached
+    int32_t k;                // sources in this batch (1..256)
+    int32_t words;            // mask words in use, ceil(k / 64)
+    int32_t pull_edges;       // levels with more active edges pull instead of pushing
+    int32_t pad;
+};
+
 struct BatchParams {
     const int32_t* offsets;
     const int32_t* cols;
     int32_t n;
     int64_t m;
-    int32_t k;                // sources in this batch (1..256)
-    int32_t words;            // mask words in use, ceil(k / 64)
-    uint8_t* level;           // [n][k], 255 = unreached
+    const BatchArgs* args;    // this run's output, k and thresholds
     unsigned long long* fr;   // frontier masks [n][4]
     unsigned long long* nx;   // next masks [n][4] (all zero between levels)
     unsigned long long* vis;  // visited masks [n][4]
@@ -115,7 +123,6 @@ struct BatchParams {
     int32_t* stat_el;
     int32_t max_tiles;        // entries of act_ts / nz_ts
     int32_t utiles;           // update tiles, ceil(n / kUTile)
-    int32_t pull_edges;       // levels with more active edges pull instead of pushing
     uint64_t spin_ticks;
 };
 

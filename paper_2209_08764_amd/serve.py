@@ -1,0 +1,325 @@
+"""Serving loop: resident graphs, admission by memory, continuous batching.
+
+Queries (graph, source) arrive over time.  The scheduler admits them as
+execution slots and device memory allow: every in-flight run holds a
+workspace (plus its output arrays) charged against a byte budget, and
+workspaces are pooled per graph.  Queued queries for the same low-diameter
+graph are merged into one batched multi-source run (up to 256 sources,
+uint8 levels); other queries run single-source on their own stream.
+Queries that arrive while others are on the GPU are admitted as soon as a
+slot and memory free up, so their work overlaps on the device.
+
+Every answer is the level array of its query (int32, -1 unreached), the
+same whether it ran alone, in a batch or next to other queries.
+
+The scheduler talks to an executor (``GpuExecutor`` runs the HIP library;
+tests substitute a CPU executor) and to a clock, so its admission and
+batching logic is testable without a GPU.
+"""
+from __future__ import annotations
+
+import collections
+import concurrent.futures
+import dataclasses
+import time
+from typing import Callable
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Query:
+    qid: int
+    graph: str
+    source: int
+    arrival: float                  # seconds on the scheduler's clock
+    admitted: float | None = None
+    finished: float | None = None
+    batched: bool = False
+    result: object = None           # int32 levels (executor-specific array type)
+
+    @property
+    def latency(self) -> float:
+        return self.finished - self.arrival
+
+
+@dataclasses.dataclass
+class GraphInfo:
+    name: str
+    n: int
+    m: int
+    batchable: bool                 # low diameter: levels fit in a byte for every source
+    ws_bytes_single: int
+    ws_bytes_batch: int
+
+
+class Scheduler:
+    """Continuous-batching request loop over an executor."""
+
+    def __init__(self, executor, budget_bytes: int, max_inflight: int = 4, batch_max: int = 256,
+                 batch_min: int = 2, clock: Callable[[], float] = time.perf_counter):
+        self.ex = executor
+        self.budget = int(budget_bytes)
+        self.max_inflight = max_inflight
+        self.batch_max = batch_max
+        self.batch_min = batch_min
+        self.clock = clock
+        self.used = 0
+        self.pool: dict[tuple[str, int], list] = collections.defaultdict(list)  # idle workspaces
+        self.pool_bytes: dict[int, int] = {}
+        self.inflight: list = []
+        self.pending: collections.deque[Query] = collections.deque()
+        self.done: list[Query] = []
+        self.stats = collections.Counter()
+
+    # ---- memory ---------------------------------------------------------------------------
+    def _cost(self, info: GraphInfo, k: int) -> int:
+        out = info.n * k if k > 1 else 8 * info.n
+        return (info.ws_bytes_batch if k > 1 else info.ws_bytes_single) + out
+
+    def _acquire(self, name: str, k: int):
+        """An idle workspace for (graph, k-class), or a new one if the budget allows."""
+        info = self.ex.info[name]
+        kind = 256 if k > 1 else 1
+        if self.pool[(name, kind)]:
+            return self.pool[(name, kind)].pop()
+        cost = self._cost(info, kind)
+        while self.used + cost > self.budget and self._evict_one(exclude=(name, kind)):
+            pass
+        if self.used + cost > self.budget:
+            return None
+        ws = self.ex.create(name, kind)
+        self.used += cost
+        self.pool_bytes[id(ws)] = cost
+        self.stats["workspaces_created"] += 1
+        return ws
+
+    def _evict_one(self, exclude) -> bool:
+        for key, lst in self.pool.items():
+            if key != exclude and lst:
+                ws = lst.pop()
+                self.used -= self.pool_bytes.pop(id(ws))
+                self.ex.destroy(ws)
+                self.stats["workspaces_evicted"] += 1
+                return True
+        return False
+
+    def _release(self, name: str, kind: int, ws):
+        self.pool[(name, kind)].append(ws)
+
+    # ---- scheduling -------------------------------------------------------------------------
+    def _admit(self):
+        skipped = collections.deque()
+        while self.pending and len(self.inflight) < self.max_inflight:
+            q = self.pending.popleft()
+            info = self.ex.info[q.graph]
+            group = [q]
+            if info.batchable:
+                same = [p for p in self.pending if p.graph == q.graph][: self.batch_max - 1]
+                if len(same) + 1 >= self.batch_min:
+                    group += same
+            k = len(group)
+            ws = self._acquire(q.graph, k)
+            if ws is None and k > 1:
+                group, k = [q], 1      # no room for a batch: try the query on its own
+                ws = self._acquire(q.graph, 1)
+            if ws is None:
+                if not self.inflight and not any(self.pool.values()):
+                    need = self._cost(info, 1)
+                    raise RuntimeError(f"query on {q.graph} needs {need} bytes; the budget is {self.budget}")
+                skipped.append(q)      # memory is short for this graph: let other queries through
+                continue
+            for p in group[1:]:
+                self.pending.remove(p)
+            now = self.clock()
+            for p in group:
+                p.admitted = now
+                p.batched = k > 1
+            handle = self.ex.launch(ws, q.graph, [p.source for p in group])
+            self.inflight.append((handle, ws, q.graph, 256 if k > 1 else 1, group))
+            self.stats["batches" if k > 1 else "singles"] += 1
+        while skipped:
+            self.pending.appendleft(skipped.pop())
+
+    def _reap(self):
+        still = []
+        for item in self.inflight:
+            handle, ws, name, kind, group = item
+            if not self.ex.ready(handle):
+                still.append(item)
+                continue
+            results = self.ex.collect(handle)
+            self._release(name, kind, ws)
+            if results is None:
+                # the batch overflowed: answer its queries one by one
+                self.ex.info[name].batchable = False
+                for p in reversed(group):
+                    self.pending.appendleft(p)
+                self.stats["batch_overflows"] += 1
+                continue
+            now = self.clock()
+            for p, r in zip(group, results):
+                p.finished = now
+                p.result = r
+                self.done.append(p)
+        self.inflight = still
+
+    def run(self, queries: list[Query], idle_sleep: float = 0.0002) -> list[Query]:
+        """Serve queries in arrival order; returns them with timings and results."""
+        arrivals = collections.deque(sorted(queries, key=lambda q: q.arrival))
+        t0 = self.clock()
+        for q in arrivals:
+            q.arrival += t0
+        while arrivals or self.pending or self.inflight:
+            now = self.clock()
+            while arrivals and arrivals[0].arrival <= now:
+                self.pending.append(arrivals.popleft())
+            self._reap()
+            self._admit()
+            if not (arrivals and arrivals[0].arrival <= self.clock()):
+                self.ex.idle(idle_sleep)
+        for q in queries:
+            q.arrival -= t0
+            q.admitted -= t0
+            q.finished -= t0
+        return queries
+
+    def close(self):
+        for lst in self.pool.values():
+            for ws in lst:
+                self.ex.destroy(ws)
+        self.pool.clear()
+        self.used = 0
+
+
+def poisson_queries(graph_names, nonisolated: dict, rate: float, count: int, seed: int = 1) -> list[Query]:
+    """count queries with exponential inter-arrival times (mean 1/rate), graph uniform,
+    source uniform among the graph's vertices of degree >= 1."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    names = list(graph_names)
+    for i in range(count):
+        t += rng.exponential(1.0 / rate) if rate > 0 else 0.0
+        g = names[rng.integers(len(names))]
+        cand = nonisolated[g]
+        out.append(Query(i, g, int(cand[rng.integers(len(cand))]), t))
+    return out
+
+
+def latency_summary(queries: list[Query]) -> dict:
+    lat = np.array([q.latency for q in queries]) * 1e3
+    span = max(q.finished for q in queries) - min(q.arrival for q in queries)
+    return {"queries": len(queries), "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "mean_ms": float(lat.mean()), "qps": len(queries) / span if span > 0 else float("inf"),
+            "batched_fraction": float(np.mean([q.batched for q in queries]))}
+
+
+# ---- GPU executor --------------------------------------------------------------------------------
+
+class GpuExecutor:
+    """Runs queries with libbfs on the current device, one stream per in-flight run."""
+
+    def __init__(self, graphs: dict, max_inflight: int = 4):
+        import torch
+
+        from . import BFS_MODE_AUTO, Graph, Workspace, bfs_workspace_bytes
+
+        self.torch = torch
+        self.Workspace = Workspace
+        self.mode = BFS_MODE_AUTO
+        self.graphs = {}
+        self.info = {}
+        self.max_inflight = max_inflight
+        self.streams = [torch.cuda.Stream() for _ in range(max_inflight)]
+        self.free_streams = list(range(max_inflight))
+        self.pool = concurrent.futures.ThreadPoolExecutor(max_workers=max_inflight)
+        self.grid = None
+        for name, g in graphs.items():
+            G = Graph(g.offsets, g.cols)
+            self.graphs[name] = G
+            probe = Workspace(G)
+            if self.grid is None:
+                # concurrent persistent runs must fit on the GPU together
+                probe.run(int(np.flatnonzero(np.diff(g.offsets))[0]) if g.m else 0, want_parent=False)
+                probe.sync()
+                cap = probe.stats()["grid"]
+                self.grid = max(1, cap // max_inflight)
+            nz = np.flatnonzero(np.diff(g.offsets))
+            probe.run(int(nz[0]) if nz.size else 0, want_parent=False)
+            probe.sync()
+            ecc = probe.stats()["levels"] - 1
+            probe.free()
+            # a component's diameter is at most twice one vertex's eccentricity, and only
+            # components of the probed vertex are bounded this way: batch graphs whose bound
+            # fits a byte with a wide margin
+            self.info[name] = GraphInfo(name, g.n, g.m, batchable=4 * ecc < 255,
+                                        ws_bytes_single=bfs_workspace_bytes(G.handle, 1),
+                                        ws_bytes_batch=bfs_workspace_bytes(G.handle, 256))
+
+    def create(self, name, kind):
+        from . import BFS_OPT_GRID
+        ws = self.Workspace(self.graphs[name], max_sources=kind)
+        ws.set(BFS_OPT_GRID, self.grid)
+        ws.name = name
+        return ws
+
+    def destroy(self, ws):
+        ws.free()
+
+    def launch(self, ws, name, sources):
+        torch = self.torch
+        si = self.free_streams.pop()
+        stream = self.streams[si]
+        n = self.graphs[name].n
+        if len(sources) == 1:
+            level = torch.empty(n, dtype=torch.int32, device="cuda")
+            with torch.cuda.stream(stream):
+                ws.run(sources[0], level=level, stream=stream, want_parent=False)
+                ev = torch.cuda.Event()
+                ev.record(stream)
+            return ("single", si, ev, level, None)
+        out = torch.empty(n * len(sources), dtype=torch.uint8, device="cuda")
+
+        def work():
+            from . import BFSError, _lib
+            with torch.cuda.stream(stream):
+                try:
+                    ws.run_batch(sources, out, stream=stream)
+                except BFSError as e:
+                    if e.status != _lib.BFS_EOVERFLOW:
+                        raise
+                    return ("overflow", None)
+                ev = torch.cuda.Event()
+                ev.record(stream)
+            return ("ok", ev)
+
+        return ("batch", si, self.pool.submit(work), out, len(sources))
+
+    def ready(self, h):
+        kind, si, ev, out, k = h
+        if kind == "batch":
+            if not ev.done():
+                return False
+            status, ev = ev.result()
+            if status == "overflow":
+                return True
+        return ev.query()
+
+    def collect(self, h):
+        torch = self.torch
+        kind, si, ev, out, k = h
+        self.free_streams.append(si)
+        if kind == "single":
+            return [out]
+        if ev.result()[0] == "overflow":
+            return None          # a level did not fit in a byte: the scheduler re-queues the sources
+        cols = out.view(-1, k)
+        res = []
+        for j in range(k):
+            c = cols[:, j].to(torch.int32)
+            res.append(torch.where(c == 255, torch.full_like(c, -1), c))
+        return res
+
+    def idle(self, s):
+        time.sleep(s)

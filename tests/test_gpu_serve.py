@@ -1,0 +1,70 @@
+"""Serving on the GPU: every query's answer in the mix (concurrent streams,
+continuous batching, memory admission) equals its answer alone and the
+oracle's, with tolerance 0."""
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+from graphgen import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2209_08764_amd import Graph, Workspace  # noqa: E402
+from paper_2209_08764_amd.serve import GpuExecutor, Scheduler, latency_summary, poisson_queries  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def setup():
+    graphs = W.c5_graphs(small=True)
+    ex = GpuExecutor(graphs, max_inflight=4)
+    nonisolated = {k: np.flatnonzero(np.diff(g.offsets)) for k, g in graphs.items()}
+    return graphs, ex, nonisolated
+
+
+def _alone(graphs, qs):
+    out = {}
+    wss = {}
+    for q in qs:
+        if q.graph not in wss:
+            g = graphs[q.graph]
+            wss[q.graph] = Workspace(Graph(g.offsets, g.cols))
+        lv, _ = wss[q.graph].run(q.source, want_parent=False)
+        wss[q.graph].sync()
+        out[q.qid] = lv.cpu().numpy()
+    return out
+
+
+def test_mix_equals_alone_and_oracle(setup):
+    graphs, ex, nonisolated = setup
+    qs = poisson_queries(graphs, nonisolated, rate=20000.0, count=300, seed=11)
+    sch = Scheduler(ex, budget_bytes=4 << 30, max_inflight=4)
+    sch.run(qs)
+    torch.cuda.synchronize()
+    alone = _alone(graphs, qs)
+    for q in qs:
+        got = q.result.cpu().numpy()
+        assert np.array_equal(got, alone[q.qid]), (q.qid, q.graph, q.source, q.batched)
+    for q in qs[::25]:
+        g = graphs[q.graph]
+        assert np.array_equal(alone[q.qid], oracle.bfs_levels(g.offsets, g.cols, q.source))
+    s = latency_summary(qs)
+    assert s["batched_fraction"] > 0 and sch.stats["singles"] > 0
+    print("serving (small graphs):", s, dict(sch.stats))
+    sch.close()
+
+
+def test_budget_below_two_workspaces(setup):
+    graphs, ex, nonisolated = setup
+    big = max(ex.info.values(), key=lambda i: i.ws_bytes_batch)
+    budget = big.ws_bytes_batch + 256 * big.n + big.ws_bytes_single // 2
+    qs = poisson_queries(graphs, nonisolated, rate=0, count=60, seed=3)
+    sch = Scheduler(ex, budget_bytes=budget, max_inflight=4)
+    sch.run(qs)
+    torch.cuda.synchronize()
+    for q in qs:
+        g = graphs[q.graph]
+        assert np.array_equal(q.result.cpu().numpy(), oracle.bfs_levels(g.offsets, g.cols, q.source))
+    assert sch.used <= budget
+    sch.close()

@@ -1,0 +1,115 @@
+"""Scheduler logic of the serving loop on the CPU: a fake executor answers with the
+oracle on a simulated clock (no GPU).  Checks admission by memory, continuous
+batching, eviction and that every answer equals the oracle's."""
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+from paper_2209_08764_amd.serve import GraphInfo, Query, Scheduler, latency_summary, poisson_queries
+
+
+class FakeExecutor:
+    """Runs queries with the CPU oracle; a run of e edges takes e * 1 ns of simulated time."""
+
+    def __init__(self, graphs, slots=4, batchable=None):
+        self.now = 0.0
+        self.graphs = graphs
+        self.info = {}
+        for name, g in graphs.items():
+            b = batchable[name] if batchable else True
+            self.info[name] = GraphInfo(name, g.n, g.m, b, ws_bytes_single=1000 + 20 * g.n,
+                                        ws_bytes_batch=5000 + 100 * g.n)
+        self.live = set()
+        self.max_live = 0
+        self.launched = []
+
+    def clock(self):
+        return self.now
+
+    def idle(self, s):
+        self.now += max(s, 1e-5)
+
+    def create(self, name, kind):
+        ws = (name, kind, object())
+        self.live.add(ws)
+        self.max_live = max(self.max_live, len(self.live))
+        return ws
+
+    def destroy(self, ws):
+        self.live.remove(ws)
+
+    def launch(self, ws, name, sources):
+        g = self.graphs[name]
+        res = [oracle.bfs_levels(g.offsets, g.cols, s) for s in sources]
+        cost = 1e-9 * g.m * (1 + 0.1 * len(sources)) + 1e-5
+        self.launched.append((name, len(sources)))
+        return (self.now + cost, res)
+
+    def ready(self, h):
+        return self.now >= h[0]
+
+    def collect(self, h):
+        return h[1]
+
+
+@pytest.fixture(scope="module")
+def graphs():
+    return {"a": gg.rmat(10, seed=1), "b": gg.grid(30, 20), "c": gg.powerlaw_forest(2000, seed=2)}
+
+
+def _nonisolated(graphs):
+    return {k: np.flatnonzero(np.diff(g.offsets)) for k, g in graphs.items()}
+
+
+def test_every_answer_matches_the_oracle(graphs):
+    ex = FakeExecutor(graphs, batchable={"a": True, "b": False, "c": True})
+    sch = Scheduler(ex, budget_bytes=10 ** 9, max_inflight=3, clock=ex.clock)
+    qs = poisson_queries(graphs, _nonisolated(graphs), rate=2e5, count=300, seed=4)
+    sch.run(qs)
+    for q in qs:
+        g = graphs[q.graph]
+        assert np.array_equal(q.result, oracle.bfs_levels(g.offsets, g.cols, q.source))
+        assert q.arrival <= q.admitted <= q.finished
+    s = latency_summary(qs)
+    assert s["queries"] == 300 and s["p99_ms"] >= s["p50_ms"] >= 0
+    # the non-batchable graph never runs in a batch; the others do once queries pile up
+    assert all(k == 1 for name, k in ex.launched if name == "b")
+    assert any(k > 1 for name, k in ex.launched if name != "b")
+    assert sch.stats["batches"] > 0
+
+
+def test_budget_is_never_exceeded_and_small_budgets_serialise(graphs):
+    ex = FakeExecutor(graphs)
+    one = max(i.ws_bytes_batch + 256 * i.n for i in ex.info.values())
+    sch = Scheduler(ex, budget_bytes=one + 10, max_inflight=4, clock=ex.clock)
+    qs = poisson_queries(graphs, _nonisolated(graphs), rate=0, count=60, seed=2)   # all at once
+    orig_acquire = sch._acquire
+
+    def checked(name, k):
+        ws = orig_acquire(name, k)
+        assert sch.used <= sch.budget
+        return ws
+
+    sch._acquire = checked
+    sch.run(qs)
+    assert all(q.result is not None for q in qs)
+    assert sch.stats["workspaces_evicted"] > 0        # graphs took turns in the budget
+
+
+def test_batch_size_is_capped(graphs):
+    ex = FakeExecutor({"a": graphs["a"]})
+    sch = Scheduler(ex, budget_bytes=10 ** 9, max_inflight=2, batch_max=16, clock=ex.clock)
+    qs = poisson_queries({"a": 0}, _nonisolated(graphs), rate=0, count=100, seed=1)
+    sch.run(qs)
+    assert max(k for _, k in ex.launched) == 16
+    assert sum(k for _, k in ex.launched) == 100
+
+
+def test_queries_keep_arrival_order_within_a_graph(graphs):
+    ex = FakeExecutor({"b": graphs["b"]}, batchable={"b": False})
+    sch = Scheduler(ex, budget_bytes=10 ** 9, max_inflight=1, clock=ex.clock)
+    qs = [Query(i, "b", i, 0.0) for i in range(20)]
+    sch.run(qs)
+    adm = [q.admitted for q in qs]
+    assert adm == sorted(adm)
