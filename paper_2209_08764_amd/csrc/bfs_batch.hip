@@ -84,7 +84,7 @@ __global__ void __launch_bounds__(kBlock) k_batch_nz(BatchParams p) {
             if (ok && tile == (int)gridDim.x - 1) st_rel(&p.ctrl->nz_count, pc + C);
         }
     }
-    __syncthreads();
+    lds_barrier();
     if (!s_b[1]) return;
     int pos = s_b[0] + pre;
 #pragma unroll
@@ -156,7 +156,7 @@ __global__ void __launch_bounds__(kBlock) k_batch_update(BatchParams p) {
     const uint8_t lv = (uint8_t)(l + 1);
     const bool fits = l + 1 < 255;
     if (threadIdx.x < kUTile / 32) s_bits[threadIdx.x] = 0u;
-    __syncthreads();
+    lds_barrier();
     int tc = 0, ts = 0;
     int act[kUV], deg[kUV], rs[kUV];
     unsigned long long nw[kUV][4];
@@ -243,7 +243,7 @@ __global__ void __launch_bounds__(kBlock) k_batch_update(BatchParams p) {
             }
         }
     }
-    __syncthreads();
+    lds_barrier();
     // active bitmap of the next level (this tile's 2048 vertices are 64 whole words)
     if (threadIdx.x < kUTile / 32) {
         const int64_t wi = ((int64_t)tile * kUTile) / 32 + threadIdx.x;
@@ -300,13 +300,13 @@ __global__ void __launch_bounds__(kBlock) k_batch_expand(BatchParams p) {
                 if (threadIdx.x == 0) bflag(c);
                 return;
             }
-            __syncthreads();
+            lds_barrier();
             for (int i = threadIdx.x; i < nv; i += kBlock) {
                 sl[i] = p.act_ex[par][j0 + i];
                 sl[kSliceB + i] = p.act_rs[par][j0 + i];
                 sl[2 * kSliceB + i] = p.act[par][j0 + i];
             }
-            __syncthreads();
+            lds_barrier();
             const int g0 = t * kGrainB, g1 = min(g0 + kGrainB, e_a);
 #pragma unroll
             for (int r = 0; r < kBVT; ++r) {
@@ -357,7 +357,7 @@ __global__ void __launch_bounds__(kBlock) k_batch_expand(BatchParams p) {
             return;
         }
         const int64_t g0 = (int64_t)t * kGrainB, g1 = min(g0 + kGrainB, p.m);
-        __syncthreads();
+        lds_barrier();
         // slice: row start | vertex | 1 if the vertex still misses a source
         for (int i = threadIdx.x; i < nv; i += kBlock) {
             const int v = p.nz_v[j0 + i];
@@ -371,7 +371,7 @@ __global__ void __launch_bounds__(kBlock) k_batch_expand(BatchParams p) {
 #pragma unroll
             for (int w = 0; w < 4; ++w) lds.acc[i * 4 + w] = 0ull;
         }
-        __syncthreads();
+        lds_barrier();
 #pragma unroll
         for (int r = 0; r < kBVT; ++r) {
             const int64_t g = g0 + r * kBlock + threadIdx.x;
@@ -395,7 +395,7 @@ __global__ void __launch_bounds__(kBlock) k_batch_expand(BatchParams p) {
                 }
             }
         }
-        __syncthreads();
+        lds_barrier();
         // hand the accumulated masks to N: rows cut by the sub-tile's ends may also be
         // accumulated by a neighbouring sub-tile, so those use atomics
         for (int i = threadIdx.x; i < nv; i += kBlock) {

@@ -29,6 +29,17 @@ __device__ __forceinline__ void st_rel(T* p, T v) {
 
 __device__ __forceinline__ uint64_t now_ticks() { return __builtin_amdgcn_s_memrealtime(); }
 
+// Workgroup barrier that orders LDS only.  A full __syncthreads() also
+// waits for every outstanding global load, store and atomic of the wave;
+// this one lets them stay in flight (prefetched loads, fire-and-forget
+// stores), so it may only be used where no lane reads global data another
+// lane of the workgroup wrote since the last full barrier.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Inclusive prefix sum over a full wave (all 64 lanes must be active):
 // DPP row shifts scan each row of 16 lanes, then the row totals are added
 // from lanes 15, 31 and 47.
@@ -46,11 +57,12 @@ __device__ __forceinline__ int wave_incl_scan(int x) {
 }
 
 // Exclusive block-wide prefix sum of one int per thread; *total gets the sum.
-// s_tmp holds kWaves ints.  Must be called by the whole workgroup.
+// s_tmp holds kWaves ints.  Must be called by the whole workgroup; orders
+// LDS only.
 __device__ __forceinline__ int block_excl_scan(int x, int* s_tmp, int* total) {
     const int incl = wave_incl_scan(x);
     if (lane_id() == 63) s_tmp[wave_id()] = incl;
-    __syncthreads();
+    lds_barrier();
     int base = 0, tot = 0;
 #pragma unroll
     for (int w = 0; w < kWaves; ++w) {
@@ -58,7 +70,7 @@ __device__ __forceinline__ int block_excl_scan(int x, int* s_tmp, int* total) {
         base += (w < wave_id()) ? t : 0;
         tot += t;
     }
-    __syncthreads();
+    lds_barrier();
     *total = tot;
     return base + incl - x;
 }

@@ -107,14 +107,14 @@ __device__ int first_parent_wg(const Params& p, int rs, int d, int l, int* s_red
         }
         const uint64_t bb = ballot(hit);
         if (lane_id() == 0) s_red[wave_id()] = bb ? wave_id() * 64 + __builtin_ctzll(bb) : INT32_MAX;
-        __syncthreads();
+        lds_barrier();
         int first = INT32_MAX;
 #pragma unroll
         for (int w = 0; w < kWaves; ++w) first = min(first, s_red[w]);
         if (first != INT32_MAX && threadIdx.x == first) s_red[kWaves] = c;
-        __syncthreads();
+        lds_barrier();
         const int found = s_red[kWaves];
-        __syncthreads();
+        lds_barrier();
         if (first != INT32_MAX) return found;
     }
     return -1;
@@ -192,7 +192,7 @@ __device__ void expand_share(const Params& p, int l, int b, int P, int ntiles, i
         stage_slice(buf0, a0, z0);
         if (tb + 1 < te) stage_slice(buf1, a1, z1);
     }
-    __syncthreads();
+    lds_barrier();
     int vc[kVT], uc[kVT];
 #pragma unroll
     for (int i = 0; i < kVT; ++i) vc[i] = uc[i] = -1;
@@ -264,7 +264,7 @@ __device__ void expand_share(const Params& p, int l, int b, int P, int ntiles, i
             wt += __popcll(bb);
         }
         if (lane_id() == 0) s_wave[wave_id()] = wt;
-        __syncthreads();
+        lds_barrier();
         int wbase = 0, tot = 0;
 #pragma unroll
         for (int w = 0; w < kWaves; ++w) {
@@ -303,13 +303,13 @@ __device__ void expand_share(const Params& p, int l, int b, int P, int ntiles, i
             vc[i] = vn[i];
             uc[i] = un[i];
         }
-        __syncthreads();
+        lds_barrier();
     }
     if (threadIdx.x == 0) {
         if (bad) flag_internal(p.ctrl);
         p.cnt[b] = qn;
     }
-    __syncthreads();
+    lds_barrier();
 }
 
 // ---- de-duplication and linearisation of one share's queue -----------------------------------
@@ -365,7 +365,7 @@ __device__ bool compact_share(const Params& p, int l, int b, int P, int ntiles, 
         const int pos0 = block_excl_scan(tc, s_wave, &C);
         block_excl_scan(ts, s_wave2, &S);
         block_excl_scan(tr, s_wave, &R);
-        // in place: every read of this chunk happened before the scans' barriers
+        // in place: every read of this chunk fed the scans, so it completed before their barriers
         int pos = surv + pos0;
 #pragma unroll
         for (int i = 0; i < kVT; ++i)
@@ -373,7 +373,7 @@ __device__ bool compact_share(const Params& p, int l, int b, int P, int ntiles, 
         surv += C;
         degsum += S;
         raw += R;
-        __syncthreads();
+        lds_barrier();  // the next chunk's queue entries lie beyond every position written here
     }
     // Sizes prefix sum over the shares
     if (wave_id() == 0) {
@@ -392,10 +392,10 @@ __device__ bool compact_share(const Params& p, int l, int b, int P, int ntiles, 
             }
         }
     }
-    __syncthreads();
+    __syncthreads();  // full: pass 2 reads queue entries other lanes compacted in pass 1
     const int pc = s_b[0], ps = s_b[1];
     const bool ok = s_b[2] != 0;
-    __syncthreads();
+    lds_barrier();
     if (!ok) return false;
     // pass 2
     const bool pull = p.parent && l >= 0 && pull_parents;
@@ -425,7 +425,7 @@ __device__ bool compact_share(const Params& p, int l, int b, int P, int ntiles, 
             int* s_red = lds + 3 * kGrain;    // kWaves + 1 ints
             int* s_nh = s_red + kWaves + 1;
             if (threadIdx.x == 0) *s_nh = 0;
-            __syncthreads();
+            lds_barrier();
 #pragma unroll
             for (int i = 0; i < kVT; ++i) {
                 if (v[i] >= 0) {
@@ -440,14 +440,14 @@ __device__ bool compact_share(const Params& p, int l, int b, int P, int ntiles, 
                     }
                 }
             }
-            __syncthreads();
+            lds_barrier();
             const int nh = *s_nh;
             for (int h = 0; h < nh; ++h) {
                 const int hv = s_hard[3 * h], hrs = s_hard[3 * h + 1], hd = s_hard[3 * h + 2];
                 const int f = first_parent_wg(p, hrs, hd, l, s_red);
                 if (threadIdx.x == 0) p.parent[hv] = f;
             }
-            __syncthreads();
+            lds_barrier();
         }
 #pragma unroll
         for (int i = 0; i < kVT; ++i) {
@@ -547,7 +547,7 @@ __device__ void small_levels(const Params& p, int l, int n_l, int e_l, int* lds)
                 wt += __popcll(bb);
             }
             if (lane_id() == 0) s_wave[wave_id()] = wt;
-            __syncthreads();
+            lds_barrier();
             int wb = 0, tot = 0;
 #pragma unroll
             for (int w = 0; w < kWaves; ++w) {
@@ -564,8 +564,9 @@ __device__ void small_levels(const Params& p, int l, int n_l, int e_l, int* lds)
                 }
             }
             ncand += tot;
-            __syncthreads();
+            lds_barrier();
         }
+        __syncthreads();  // full: de-duplication reads owner and candidates other lanes wrote
         if (threadIdx.x == 0 && l < kStatCap) p.stat_ts[3 * l + 1] = now_ticks();
         // de-duplicate and build the next frontier (LDS and global copies)
         int outc = 0, outs = 0, outr = 0;
@@ -622,7 +623,7 @@ __device__ void small_levels(const Params& p, int l, int n_l, int e_l, int* lds)
             outc += C;
             outs += S;
             outr += R;
-            __syncthreads();
+            lds_barrier();
         }
         if (threadIdx.x == 0 && l < kStatCap) p.stat_ts[3 * l + 2] = now_ticks();
         ++l;
