@@ -224,18 +224,24 @@ def bench_c4(torch, W, Graph, Workspace, g=None, srcs=None):
     G = Graph(g.offsets, g.cols)
     ws = Workspace(G, max_sources=256, profile=1)
     out = torch.empty(g.n * 256, dtype=torch.uint8, device="cuda")
-    ws.run_batch(srcs, out)
-    ws.sync()
-    ws.kernel_times()
-    times = []
-    for _ in range(5):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
+
+    def timed_batches(reps=5):
         ws.run_batch(srcs, out)
-        torch.cuda.synchronize()
-        times.append((time.perf_counter() - t0) * 1e3)
-    kt = ws.kernel_times()
-    tb = float(np.median(times))
+        ws.sync()
+        ws.kernel_times()
+        times = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ws.run_batch(srcs, out)
+            torch.cuda.synchronize()
+            times.append((time.perf_counter() - t0) * 1e3)
+        return float(np.median(times)), ws.kernel_times()
+
+    t_default, _ = timed_batches()
+    # the autotuner picks grain, update tile, pull threshold and replay length on this graph
+    tune = ws.autotune(srcs, batch=True)
+    tb, kt = timed_batches()
     lev = out.view(g.n, 256)
     deg = torch.from_numpy(np.diff(g.offsets.astype(np.int64))).cuda()
     edges = float(sum(int(deg[lev[:, j] != 255].sum()) for j in range(256))) / 2
@@ -254,8 +260,15 @@ def bench_c4(torch, W, Graph, Workspace, g=None, srcs=None):
     pm, _, _ = time_single_source(ss, lv, pa, srcs[:4], 4, torch, mc[:4])
     plain_ms = float(np.mean(pm))
     gteps = edges / (tb * 1e-3) / 1e9
+    # algorithmic bytes of one batch: the uint8 output, each active row's columns, 40 B of
+    # offsets and frontier mask per active vertex, 96 B of mask updates per newly reached vertex
+    a_sum = float(np.sum(n_l))
+    b_b = g.n * 256 + 4.0 * float(np.sum(e_l)) + 40.0 * a_sum + 96.0 * a_sum
     return {"workload": "rmat22 (scale 22, EF 16), 256 sources in one batched run",
-            "ms_per_batch": round(tb, 3), "loop_ms": round(float(np.median(kt)), 3),
+            "ms_per_batch": round(tb, 3), "ms_per_batch_untuned": round(t_default, 3),
+            "tuned": {k: tune[k] for k in ("batch_grain", "batch_tile", "batch_pull", "batch_levels", "trials")},
+            "loop_ms": round(float(np.median(kt)), 3),
+            "algorithmic_bytes": int(b_b), "hbm_frac_algorithmic": round(b_b / (tb * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
             "gteps_aggregate": round(gteps, 1), "levels": len(n_l),
             "active_per_level": n_l.tolist(), "active_edges_per_level": e_l.tolist(),
             "single_source_ms_mean": round(single_ms, 3),

@@ -71,6 +71,10 @@ typedef struct bfs_workspace_s* bfs_workspace_t;  /* scratch for one in-flight r
 #define BFS_OPT_PUSH_EDGES  6  /* levels with at most this many edges push parents (atomic
                                   minimum per edge); larger ones pull them from sorted rows
                                   (default m / 8) */
+#define BFS_OPT_BATCH_GRAIN 8  /* batched search: edges per expansion sub-tile, the grain of
+                                  the equal edge split (512, 1024 or 2048; default 1024) */
+#define BFS_OPT_BATCH_TILE  9  /* batched search: vertices per tile of the dense update pass
+                                  (1024, 2048 or 4096; default 2048) */
 
 typedef struct {
     int32_t levels;          /* frontiers processed: max level + 1 */
@@ -182,6 +186,48 @@ bfs_status_t bfs_last_level_times(bfs_workspace_t ws, int32_t cap, double* expan
 
 const char* bfs_status_str(bfs_status_t s);
 const char* bfs_last_error(void);
+
+/* ---- autotuning ------------------------------------------------------------------------ */
+
+/*
+ * Launch shape chosen for one workspace and its graph.  The grain of the
+ * equal edge split (Figure 1, Find-StartExpPoint: shares of a fixed number
+ * of edges) and the tile shapes are free parameters of the method; the
+ * tuner picks them by timing real runs.
+ */
+typedef struct {
+    int32_t batch_grain;   /* BFS_OPT_BATCH_GRAIN */
+    int32_t batch_tile;    /* BFS_OPT_BATCH_TILE */
+    int32_t batch_levels;  /* BFS_OPT_BATCH_LEVELS */
+    int32_t batch_pull;    /* BFS_OPT_BATCH_PULL (-1 = never pull) */
+    int32_t grid;          /* BFS_OPT_GRID (0 = fill the GPU) */
+    int32_t small_edges;   /* BFS_OPT_SMALL_EDGES */
+    int32_t push_edges;    /* BFS_OPT_PUSH_EDGES */
+    int32_t trials;        /* configurations timed by the last bfs_autotune */
+    double  default_ms;    /* one pass over the sample with the settings the call started from */
+    double  best_ms;       /* one pass over the sample with the chosen settings */
+} bfs_tune_t;
+
+#define BFS_TUNE_BATCH  1u  /* tune the batched launch: grain, update tile, pull threshold, replay length */
+#define BFS_TUNE_SINGLE 2u  /* tune single-source runs: grid, single-workgroup and push thresholds */
+
+/*
+ * Times candidate settings on the workspace's own graph and keeps the
+ * fastest (coordinate descent: grain and tile together, then each
+ * threshold in turn; each candidate is run once untimed, then three times,
+ * and its median wall time counts).  sources: host array of k vertices.
+ * BFS_TUNE_BATCH runs them as one batch (2 <= k <= max_sources);
+ * BFS_TUNE_SINGLE runs each with levels and parents (1 <= k <= 64).  The
+ * chosen settings are applied to ws and written to *out (which may be
+ * NULL); results do not depend on them.  Allocates and frees temporary
+ * output arrays; synchronous; do not call while ws is in flight elsewhere.
+ * Errors: EINVAL (bad arguments), ERANGE (a source outside [0, n)), or a
+ * run's error.
+ */
+bfs_status_t bfs_autotune(bfs_workspace_t ws, const int32_t* sources, int32_t k, uint32_t what, bfs_tune_t* out);
+
+/* The workspace's current settings, in the same form (trials and times 0). */
+bfs_status_t bfs_workspace_get_tuning(bfs_workspace_t ws, bfs_tune_t* out);
 
 /* ---- primitives of the level loop, exposed for testing ------------------------------ */
 

@@ -14,18 +14,19 @@ import numpy as np
 
 from . import _lib
 from ._lib import (BFS_DEVICE_PTRS, BFS_HOST_PTRS, BFS_MODE_AUTO, BFS_MODE_INSENSITIVE, BFS_MODE_LEVEL,
-                   BFS_MODE_PLAIN, BFS_OPT_BATCH_PULL, BFS_OPT_GRID, BFS_OPT_MODE, BFS_OPT_PROFILE,
-                   BFS_OPT_BATCH_LEVELS, BFS_OPT_PUSH_EDGES, BFS_OPT_SMALL_EDGES, BFS_VALIDATE, BFSError, bfs_stats_t)
+                   BFS_MODE_PLAIN, BFS_OPT_BATCH_GRAIN, BFS_OPT_BATCH_LEVELS, BFS_OPT_BATCH_PULL, BFS_OPT_BATCH_TILE,
+                   BFS_OPT_GRID, BFS_OPT_MODE, BFS_OPT_PROFILE, BFS_OPT_PUSH_EDGES, BFS_OPT_SMALL_EDGES,
+                   BFS_TUNE_BATCH, BFS_TUNE_SINGLE, BFS_VALIDATE, BFSError, bfs_stats_t, bfs_tune_t)
 
 __all__ = [
     "bfs_init", "bfs_graph_free", "bfs_graph_info", "bfs_workspace_bytes", "bfs_workspace_create",
     "bfs_workspace_free", "bfs_workspace_set_option", "bfs_run", "bfs_run_multiroot", "bfs_run_batch",
     "bfs_sync", "bfs_last_stats", "bfs_last_level_stats", "bfs_last_level_times", "bfs_kernel_times", "bfs_status_str",
     "bfs_prim_compact",
-    "bfs_prim_grain", "Graph", "Workspace", "BFSError",
+    "bfs_prim_grain", "bfs_autotune", "bfs_workspace_get_tuning", "Graph", "Workspace", "BFSError",
     "BFS_MODE_AUTO", "BFS_MODE_LEVEL", "BFS_MODE_PLAIN", "BFS_MODE_INSENSITIVE", "BFS_OPT_MODE",
     "BFS_OPT_SMALL_EDGES", "BFS_OPT_GRID", "BFS_OPT_PROFILE", "BFS_OPT_BATCH_PULL", "BFS_OPT_PUSH_EDGES", "BFS_OPT_BATCH_LEVELS",
-    "BFS_HOST_PTRS",
+    "BFS_OPT_BATCH_GRAIN", "BFS_OPT_BATCH_TILE", "BFS_TUNE_BATCH", "BFS_TUNE_SINGLE", "BFS_HOST_PTRS",
     "BFS_DEVICE_PTRS", "BFS_VALIDATE",
 ]
 
@@ -185,6 +186,21 @@ def bfs_prim_compact(offsets, owner, cand, cnt, out_v, out_rs, out_ex, out_tstar
         "bfs_prim_compact")
 
 
+def bfs_autotune(ws: int, sources, what: int) -> dict:
+    """Time candidate launch settings on the workspace's graph and keep the fastest (synchronous)."""
+    src = np.ascontiguousarray(np.asarray(sources, dtype=np.int32))
+    out = bfs_tune_t()
+    _lib.check(_lib.load().bfs_autotune(ws, src.ctypes.data, int(src.size), int(what), ctypes.byref(out)),
+               "bfs_autotune")
+    return out.as_dict()
+
+
+def bfs_workspace_get_tuning(ws: int) -> dict:
+    out = bfs_tune_t()
+    _lib.check(_lib.load().bfs_workspace_get_tuning(ws, ctypes.byref(out)), "bfs_workspace_get_tuning")
+    return out.as_dict()
+
+
 class Graph:
     """A device-resident graph (owns the handle and keeps borrowed tensors alive)."""
 
@@ -222,7 +238,8 @@ class Workspace:
             bfs_workspace_set_option(self.handle, BFS_OPT_MODE, mode)
         names = {"small_edges": BFS_OPT_SMALL_EDGES, "grid": BFS_OPT_GRID, "profile": BFS_OPT_PROFILE,
                  "batch_pull": BFS_OPT_BATCH_PULL, "push_edges": BFS_OPT_PUSH_EDGES,
-                 "batch_levels": BFS_OPT_BATCH_LEVELS}
+                 "batch_levels": BFS_OPT_BATCH_LEVELS, "batch_grain": BFS_OPT_BATCH_GRAIN,
+                 "batch_tile": BFS_OPT_BATCH_TILE}
         for k, v in opts.items():
             bfs_workspace_set_option(self.handle, names[k], v)
 
@@ -259,6 +276,14 @@ class Workspace:
 
     def sync(self):
         bfs_sync(self.handle)
+
+    def tuning(self) -> dict:
+        return bfs_workspace_get_tuning(self.handle)
+
+    def autotune(self, sources, batch: bool | None = None, cache: str | None = None) -> dict:
+        """Pick launch settings for this graph (see tuning.autotune); returns them."""
+        from .tuning import autotune
+        return autotune(self, sources, batch=batch, cache=cache)
 
     def stats(self):
         return bfs_last_stats(self.handle)

@@ -38,6 +38,11 @@ BFS_OPT_PROFILE = 4
 BFS_OPT_BATCH_PULL = 5
 BFS_OPT_PUSH_EDGES = 6
 BFS_OPT_BATCH_LEVELS = 7
+BFS_OPT_BATCH_GRAIN = 8
+BFS_OPT_BATCH_TILE = 9
+
+BFS_TUNE_BATCH = 1
+BFS_TUNE_SINGLE = 2
 
 MODE_NAMES = {BFS_MODE_AUTO: "auto", BFS_MODE_LEVEL: "level", BFS_MODE_PLAIN: "plain",
               BFS_MODE_INSENSITIVE: "insensitive"}
@@ -55,6 +60,24 @@ class bfs_stats_t(ctypes.Structure):
         ("status", ctypes.c_int32),
         ("stats_truncated", ctypes.c_int32),
     ]
+
+
+class bfs_tune_t(ctypes.Structure):
+    _fields_ = [
+        ("batch_grain", ctypes.c_int32),
+        ("batch_tile", ctypes.c_int32),
+        ("batch_levels", ctypes.c_int32),
+        ("batch_pull", ctypes.c_int32),
+        ("grid", ctypes.c_int32),
+        ("small_edges", ctypes.c_int32),
+        ("push_edges", ctypes.c_int32),
+        ("trials", ctypes.c_int32),
+        ("default_ms", ctypes.c_double),
+        ("best_ms", ctypes.c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 class BFSError(RuntimeError):
@@ -96,6 +119,9 @@ _SIGS = {
                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                           ctypes.c_void_p]),
     "bfs_prim_grain": (ctypes.c_int32, []),
+    "bfs_autotune": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32,
+                                      ctypes.POINTER(bfs_tune_t)]),
+    "bfs_workspace_get_tuning": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(bfs_tune_t)]),
 }
 
 EXPORTED = tuple(_SIGS)

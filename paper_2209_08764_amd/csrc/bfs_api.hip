@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -90,7 +92,10 @@ struct bfs_workspace_s {
     int32_t* b_sources = nullptr;
     int32_t b_max_tiles = 0;
     int32_t b_utiles = 0;
+    int32_t b_desc_cap = 0;
     int32_t b_grid_cap = 0;
+    int32_t b_bvt = kBVTDefault;         // edges per thread of an expansion sub-tile
+    int32_t b_uv = kUVDefault;           // vertices per thread of an update tile
     int32_t batch_levels = 8;            // levels per replay of the captured loop
     hipStream_t own_stream = nullptr;    // the workspace's private stream (set-up and capture)
     hipGraphExec_t b_exec = nullptr;
@@ -353,6 +358,9 @@ BatchParams make_batch_params(bfs_workspace_s* ws) {
     bp.stat_el = ws->stat_el;
     bp.max_tiles = ws->b_max_tiles;
     bp.utiles = ws->b_utiles;
+    bp.desc_cap = ws->b_desc_cap;
+    bp.bvt = ws->b_bvt;
+    bp.uv = ws->b_uv;
     bp.spin_ticks = kSpinTicks;
     return bp;
 }
@@ -390,6 +398,27 @@ bfs_status_t capture_batch(bfs_workspace_s* ws) {
     HIP_TRY(hipStreamEndCapture(ws->own_stream, &ws->b_graph));
     HIP_TRY(hipGraphInstantiate(&ws->b_exec, ws->b_graph, nullptr, nullptr, 0));
     return BFS_OK;
+}
+
+// Waits for the workspace's last run, so that its launch shape can change.
+bfs_status_t quiesce(bfs_workspace_s* ws) {
+    if (ws->has_run) HIP_TRY(hipEventSynchronize(ws->ev_done));
+    return BFS_OK;
+}
+
+// The grain-dependent set-up (sub-tile starts over all edges) and the
+// occupancy of the expansion kernel, then a new capture of the level loop.
+bfs_status_t setup_batch(bfs_workspace_s* ws) {
+    hipStream_t os = ws->own_stream;
+    ws->b_grid_cap = batch_grid_capacity(ws->device, ws->b_bvt);
+    if (ws->b_grid_cap <= 0) return fail(BFS_EHIP, "could not size the batched grid");
+    ws->b_utiles = (int32_t)(((int64_t)ws->g->n + (int64_t)kBlock * ws->b_uv - 1) / ((int64_t)kBlock * ws->b_uv));
+    *ws->h_args = BatchArgs{nullptr, 0, 0, batch_pull_edges(ws), 0};
+    const BatchParams bp = make_batch_params(ws);
+    HIP_TRY(hipMemcpyAsync(ws->b_args, ws->h_args, sizeof(BatchArgs), hipMemcpyHostToDevice, os));
+    HIP_TRY(launch_batch_setup(bp, ws->b_grid_cap, os));
+    HIP_TRY(hipStreamSynchronize(os));
+    return capture_batch(ws);
 }
 
 }  // namespace
@@ -485,23 +514,36 @@ static int64_t tiles_for(const bfs_graph_s* g) {
     return (items + kGrain - 1) / kGrain + 2;
 }
 
+static int64_t batch_max_tiles(const bfs_graph_s* g) {
+    const int64_t G = (int64_t)kBlock * kBVTMin;   // the finest grain
+    return (g->m + G - 1) / G + 2;
+}
+
+static int64_t batch_desc_cap(const bfs_graph_s* g) {
+    const int64_t a = ((int64_t)g->n + (int64_t)kBlock * kUVMin - 1) / ((int64_t)kBlock * kUVMin);
+    const int64_t b = ((int64_t)g->n + kNzTile - 1) / kNzTile;
+    return std::max<int64_t>(std::max(a, b), 1);
+}
+
 size_t bfs_workspace_bytes(bfs_graph_t g, int32_t max_sources) {
     if (!g || max_sources < 1 || max_sources > 256) return 0;
     const size_t n = (size_t)g->n, T = (size_t)tiles_for(g);
     size_t b = 0;
     b += ((n + 31) / 32) * 4;          // bitmap
     b += n * 4;                        // owner
-    b += 4 * (n + 2) * 4;              // frontier rs/ex x2
+    b += 6 * (n + 2) * 4;              // frontier ids / row starts / degree sums, x2
     b += 2 * T * 4;                    // tstart x2
     b += T * kGrain * 4;               // candidates
     b += T * 4;                        // counts
     b += 2 * T * 8;                    // descriptors
-    b += sizeof(Ctrl) + 2 * (size_t)kStatCap * 4 + n * 4;  // ctrl, stats, roots
+    b += sizeof(Ctrl) + 2 * (size_t)kStatCap * 4 + 3 * (size_t)kStatCap * 8 + n * 4;  // ctrl, stats, roots
     if (max_sources > 1) {
+        const size_t BT = (size_t)batch_max_tiles(g), D = (size_t)batch_desc_cap(g);
         b += 3 * n * 32;               // frontier/next/visited masks
-        b += 4 * (n + 2) * 4;          // active lists x2
-        b += 2 * T * 4 + 2 * T * 8;    // batch tstart, descriptors
-        b += ((n + 31) / 32) * 4 + 256 * 4;
+        b += 6 * (n + 2) * 4;          // active ids / row starts / degree sums, x2
+        b += 3 * BT * 4;               // sub-tile starts x2, over all edges
+        b += 2 * D * 8;                // update descriptors x2
+        b += ((n + 31) / 32 + 1) * 4 + (n + 1) * 4 + 256 * 4 + sizeof(BatchArgs);  // active bits, nz list, sources
     }
     return b;
 }
@@ -568,8 +610,8 @@ bfs_status_t bfs_workspace_create(bfs_graph_t g, int32_t max_sources, bfs_worksp
     A(dalloc(&ws->stat_ts, 3 * (size_t)kStatCap));
     A(dalloc(&ws->roots, n));
     if (max_sources > 1) {
-        ws->b_max_tiles = (int32_t)((g->m + kGrainB - 1) / kGrainB + 2);
-        ws->b_utiles = (int32_t)((n + kUTile - 1) / kUTile);
+        ws->b_max_tiles = (int32_t)batch_max_tiles(g);
+        ws->b_desc_cap = (int32_t)batch_desc_cap(g);
         A(dalloc(&ws->b_fr, n * 4));
         A(dalloc(&ws->b_nx, n * 4));
         A(dalloc(&ws->b_vis, n * 4));
@@ -578,7 +620,7 @@ bfs_status_t bfs_workspace_create(bfs_graph_t g, int32_t max_sources, bfs_worksp
             A(dalloc(&ws->b_act_rs[i], n + 2));
             A(dalloc(&ws->b_act_ex[i], n + 2));
             A(dalloc(&ws->b_tstart[i], (size_t)ws->b_max_tiles));
-            A(dalloc(&ws->b_desc[i], (size_t)std::max(ws->b_utiles, 1)));
+            A(dalloc(&ws->b_desc[i], (size_t)ws->b_desc_cap));
         }
         A(dalloc(&ws->b_act_bits, (n + 31) / 32 + 1));
         A(dalloc(&ws->b_nz_v, n + 1));
@@ -620,20 +662,12 @@ bfs_status_t bfs_workspace_create(bfs_graph_t g, int32_t max_sources, bfs_worksp
         return fail(BFS_EHIP, "hipMemset failed");
     }
     if (max_sources > 1) {
-        ws->b_grid_cap = batch_grid_capacity(ws->device);
-        if (ws->b_grid_cap <= 0 || dalloc(&ws->b_args, 1) != hipSuccess ||
+        if (dalloc(&ws->b_args, 1) != hipSuccess ||
             hipHostMalloc(reinterpret_cast<void**>(&ws->h_args), sizeof(BatchArgs), hipHostMallocDefault) != hipSuccess) {
             bfs_workspace_free(ws);
             return fail(BFS_EHIP, "could not prepare the batched search");
         }
-        *ws->h_args = BatchArgs{nullptr, 0, 0, batch_pull_edges(ws), 0};
-        const BatchParams bp = make_batch_params(ws);
-        if (hipMemcpyAsync(ws->b_args, ws->h_args, sizeof(BatchArgs), hipMemcpyHostToDevice, os) != hipSuccess ||
-            launch_batch_setup(bp, ws->b_grid_cap, os) != hipSuccess || hipStreamSynchronize(os) != hipSuccess) {
-            bfs_workspace_free(ws);
-            return fail(BFS_EHIP, "batched set-up kernels failed");
-        }
-        bfs_status_t cst = capture_batch(ws);
+        bfs_status_t cst = setup_batch(ws);
         if (cst) {
             bfs_workspace_free(ws);
             return cst;
@@ -654,10 +688,12 @@ bfs_status_t bfs_workspace_set_option(bfs_workspace_t ws, int32_t option, int64_
             if (value < 0 || value > INT32_MAX) return fail(BFS_EINVAL, "bad small-edge threshold");
             ws->small_edges = (int32_t)value;
             return BFS_OK;
-        case BFS_OPT_GRID:
+        case BFS_OPT_GRID: {
             if (value < 0 || value > INT32_MAX) return fail(BFS_EINVAL, "bad grid");
+            if (bfs_status_t q = quiesce(ws)) return q;
             ws->grid_opt = (int32_t)value;
             return ws->b_exec ? capture_batch(ws) : BFS_OK;
+        }
         case BFS_OPT_PROFILE:
             ws->profile = value != 0;
             return BFS_OK;
@@ -665,10 +701,28 @@ bfs_status_t bfs_workspace_set_option(bfs_workspace_t ws, int32_t option, int64_
             if (value < 0 || value > INT32_MAX) return fail(BFS_EINVAL, "bad push threshold");
             ws->push_edges = (int32_t)value;
             return BFS_OK;
-        case BFS_OPT_BATCH_LEVELS:
+        case BFS_OPT_BATCH_LEVELS: {
             if (value < 1 || value > 256) return fail(BFS_EINVAL, "levels per replay must be in [1, 256]");
+            if (bfs_status_t q = quiesce(ws)) return q;
             ws->batch_levels = (int32_t)value;
             return ws->b_exec ? capture_batch(ws) : BFS_OK;
+        }
+        case BFS_OPT_BATCH_GRAIN: {
+            if (value != 512 && value != 1024 && value != 2048)
+                return fail(BFS_EINVAL, "batched grain must be 512, 1024 or 2048 edges");
+            if (ws->max_sources < 2) return fail(BFS_EINVAL, "the workspace has no batched buffers");
+            if (bfs_status_t q = quiesce(ws)) return q;
+            ws->b_bvt = (int32_t)(value / kBlock);
+            return setup_batch(ws);
+        }
+        case BFS_OPT_BATCH_TILE: {
+            if (value != 1024 && value != 2048 && value != 4096)
+                return fail(BFS_EINVAL, "batched update tile must be 1024, 2048 or 4096 vertices");
+            if (ws->max_sources < 2) return fail(BFS_EINVAL, "the workspace has no batched buffers");
+            if (bfs_status_t q = quiesce(ws)) return q;
+            ws->b_uv = (int32_t)(value / kBlock);
+            return setup_batch(ws);
+        }
         case BFS_OPT_BATCH_PULL:
             if (value < -1 || value > INT32_MAX) return fail(BFS_EINVAL, "bad pull threshold");
             ws->batch_pull = (int32_t)value;
@@ -888,6 +942,167 @@ bfs_status_t bfs_run_batch(bfs_workspace_t ws, const int32_t* sources, int32_t k
     if (ws->h_ctrl->error) return fail(BFS_EDEVICE, "device-side failure in the batched search (code %d)", ws->h_ctrl->error);
     if (ws->h_ctrl->batch_overflow) return fail(BFS_EOVERFLOW, "a batched level reached 255");
     return BFS_OK;
+}
+
+}  // extern "C"
+
+// ---- autotuning ---------------------------------------------------------------------------
+
+namespace {
+
+void current_tuning(const bfs_workspace_s* ws, bfs_tune_t* t) {
+    std::memset(t, 0, sizeof(*t));
+    t->batch_grain = kBlock * ws->b_bvt;
+    t->batch_tile = kBlock * ws->b_uv;
+    t->batch_levels = ws->batch_levels;
+    t->batch_pull = ws->batch_pull >= -1 ? ws->batch_pull : batch_pull_edges(ws);
+    t->grid = ws->grid_opt;
+    t->small_edges = ws->small_edges;
+    t->push_edges = ws->push_edges >= 0 ? ws->push_edges : (int32_t)std::min<int64_t>(ws->g->m / 8, INT32_MAX);
+}
+
+// Timed passes over the tuning sample with the workspace's current settings.
+struct TuneSample {
+    bfs_workspace_s* ws;
+    const int32_t* sources;
+    int32_t k;
+    bool batch;
+    uint8_t* out8;
+    int32_t* lv;
+    int32_t* par;
+    int32_t trials = 0;
+
+    double pass() {
+        const auto t0 = std::chrono::steady_clock::now();
+        if (batch) {
+            if (bfs_run_batch(ws, sources, k, out8, ws->own_stream) != BFS_OK) return INFINITY;
+        } else {
+            for (int32_t j = 0; j < k; ++j)
+                if (bfs_run(ws, sources[j], lv, par, ws->own_stream) != BFS_OK) return INFINITY;
+        }
+        if (bfs_sync(ws) != BFS_OK) return INFINITY;
+        return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    // one untimed pass, then the median of three
+    double measure() {
+        ++trials;
+        if (!std::isfinite(pass())) return INFINITY;
+        double t[3];
+        for (double& x : t) x = pass();
+        std::sort(t, t + 3);
+        return t[1];
+    }
+};
+
+// Tries every value of one option (or pair of options) and keeps the fastest.
+template <typename Apply>
+bfs_status_t descend(TuneSample& smp, double* best, const std::vector<std::pair<int64_t, int64_t>>& cands,
+                     std::pair<int64_t, int64_t> keep, Apply apply) {
+    std::pair<int64_t, int64_t> arg = keep;
+    for (const auto& c : cands) {
+        if (c == keep) continue;
+        if (bfs_status_t st = apply(c)) return st;
+        const double t = smp.measure();
+        if (t < *best) {
+            *best = t;
+            arg = c;
+        }
+    }
+    return apply(arg);
+}
+
+}  // namespace
+
+extern "C" {
+
+bfs_status_t bfs_workspace_get_tuning(bfs_workspace_t ws, bfs_tune_t* out) {
+    if (!ws || !out) return fail(BFS_EINVAL, "null argument");
+    current_tuning(ws, out);
+    return BFS_OK;
+}
+
+bfs_status_t bfs_autotune(bfs_workspace_t ws, const int32_t* sources, int32_t k, uint32_t what, bfs_tune_t* out) {
+    if (!ws || !sources) return fail(BFS_EINVAL, "null argument");
+    if (what != BFS_TUNE_BATCH && what != BFS_TUNE_SINGLE) return fail(BFS_EINVAL, "tune BATCH or SINGLE, one at a time");
+    const bool batch = what == BFS_TUNE_BATCH;
+    if (batch && (k < 2 || k > ws->max_sources || !ws->b_fr))
+        return fail(BFS_EINVAL, "batched tuning needs 2 <= k <= max_sources (%d) sources", ws->max_sources);
+    if (!batch && (k < 1 || k > 64)) return fail(BFS_EINVAL, "single-source tuning takes 1 to 64 sources");
+    const bfs_graph_s* g = ws->g;
+    for (int32_t j = 0; j < k; ++j)
+        if (sources[j] < 0 || sources[j] >= g->n) return fail(BFS_ERANGE, "source %d = %d outside [0, %d)", j, sources[j], g->n);
+    if (bfs_status_t q = quiesce(ws)) return q;
+    HIP_TRY(hipSetDevice(ws->device));
+    TuneSample smp{ws, sources, k, batch, nullptr, nullptr, nullptr};
+    bool ok = batch ? dalloc(&smp.out8, (size_t)g->n * (size_t)k) == hipSuccess
+                    : dalloc(&smp.lv, (size_t)g->n) == hipSuccess && dalloc(&smp.par, (size_t)g->n) == hipSuccess;
+    auto release = [&] {
+        if (smp.out8) (void)hipFree(smp.out8);
+        if (smp.lv) (void)hipFree(smp.lv);
+        if (smp.par) (void)hipFree(smp.par);
+    };
+    if (!ok) {
+        release();
+        return fail(BFS_ENOMEM, "tuning output arrays");
+    }
+    const int32_t saved_mode = ws->mode, saved_profile = ws->profile;
+    ws->mode = BFS_MODE_AUTO;
+    ws->profile = 0;
+    bfs_tune_t start;
+    current_tuning(ws, &start);
+    double best = smp.measure();
+    const double t_default = best;
+    bfs_status_t st = std::isfinite(best) ? BFS_OK : fail(BFS_EDEVICE, "the starting configuration failed: %s",
+                                                          bfs_last_error());
+    const int64_t m = g->m;
+    using P = std::pair<int64_t, int64_t>;
+    if (!st && batch) {
+        std::vector<P> shapes;
+        for (int64_t gr : {512, 1024, 2048})
+            for (int64_t ti : {1024, 2048, 4096}) shapes.push_back({gr, ti});
+        st = descend(smp, &best, shapes, P{start.batch_grain, start.batch_tile}, [&](P c) {
+            bfs_status_t e = bfs_workspace_set_option(ws, BFS_OPT_BATCH_GRAIN, c.first);
+            return e ? e : bfs_workspace_set_option(ws, BFS_OPT_BATCH_TILE, c.second);
+        });
+        std::vector<P> pulls;
+        for (int64_t d : {32, 16, 8, 4, 2}) pulls.push_back({std::min<int64_t>(m / d, INT32_MAX), 0});
+        pulls.push_back({-1, 0});
+        if (!st)
+            st = descend(smp, &best, pulls, P{start.batch_pull, 0},
+                         [&](P c) { return bfs_workspace_set_option(ws, BFS_OPT_BATCH_PULL, c.first); });
+        std::vector<P> reps;
+        for (int64_t r : {2, 4, 8, 16}) reps.push_back({r, 0});
+        if (!st)
+            st = descend(smp, &best, reps, P{start.batch_levels, 0},
+                         [&](P c) { return bfs_workspace_set_option(ws, BFS_OPT_BATCH_LEVELS, c.first); });
+    } else if (!st) {
+        const int64_t cap = ws->grid_cap;
+        std::vector<P> grids{{0, 0}};
+        for (int64_t d : {2, 4}) grids.push_back({std::max<int64_t>(cap / d, 1), 0});
+        st = descend(smp, &best, grids, P{start.grid, 0},
+                     [&](P c) { return bfs_workspace_set_option(ws, BFS_OPT_GRID, c.first); });
+        std::vector<P> smalls;
+        for (int64_t e : {0, 4096, 16384, 65536}) smalls.push_back({e, 0});
+        if (!st)
+            st = descend(smp, &best, smalls, P{start.small_edges, 0},
+                         [&](P c) { return bfs_workspace_set_option(ws, BFS_OPT_SMALL_EDGES, c.first); });
+        std::vector<P> pushes;
+        for (int64_t d : {32, 16, 8, 4}) pushes.push_back({std::min<int64_t>(m / d, INT32_MAX), 0});
+        if (!st)
+            st = descend(smp, &best, pushes, P{start.push_edges, 0},
+                         [&](P c) { return bfs_workspace_set_option(ws, BFS_OPT_PUSH_EDGES, c.first); });
+    }
+    ws->mode = saved_mode;
+    ws->profile = saved_profile;
+    if (bfs_status_t q = quiesce(ws); q && !st) st = q;
+    release();
+    if (out) {
+        current_tuning(ws, out);
+        out->trials = smp.trials;
+        out->default_ms = t_default;
+        out->best_ms = best;
+    }
+    return st;
 }
 
 }  // extern "C"

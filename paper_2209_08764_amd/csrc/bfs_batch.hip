@@ -39,9 +39,13 @@ __device__ __forceinline__ void bflag(Ctrl* c) {
     __hip_atomic_store(&c->error, BFS_EINTERNAL_CODE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Sub-tile start points: entry pos (edges [e, e + d)) starts every sub-tile
+// of G = kBlock * BVT edges that begins inside its edge range.
+template <int BVT>
 __device__ __forceinline__ void bscatter(const BatchParams& p, int32_t* ts, int pos, int64_t e, int d) {
-    int64_t t = (e + kGrainB - 1) / kGrainB;
-    const int64_t tend = (e + d + kGrainB - 1) / kGrainB;
+    constexpr int G = kBlock * BVT;
+    int64_t t = (e + G - 1) / G;
+    const int64_t tend = (e + d + G - 1) / G;
     if (t < 0 || tend > p.max_tiles) {
         bflag(p.ctrl);
         return;
@@ -49,10 +53,16 @@ __device__ __forceinline__ void bscatter(const BatchParams& p, int32_t* ts, int 
     for (; t < tend; ++t) ts[t] = pos;
 }
 
-struct BLds {
-    unsigned long long acc[kSliceB * 4];   // pull accumulators (8 B aligned first)
-    int sl[3 * kSliceB];                   // sub-tile slice: ex | rs | v
-    int misc[2 * kWaves + 16 + kUTile / 32];
+template <int BVT>
+struct ExpLds {
+    static constexpr int kSl = kBlock * BVT + 1;   // slice entries of one sub-tile
+    unsigned long long acc[kSl * 4];               // pull accumulators (8 B aligned first)
+    int sl[3 * kSl];                               // sub-tile slice: ex | rs | v
+};
+
+template <int UV>
+struct UpdLds {
+    int misc[2 * kWaves + 16 + kBlock * UV / 32];  // scan partials, look-back result, active bits
 };
 
 }  // namespace
@@ -60,14 +70,16 @@ struct BLds {
 // ---- one-off set-up: the vertices of degree >= 1 and the sub-tiles over all edges ----------
 // nz_v lists them in ascending order; since isolated vertices own no edge,
 // the edges before nz_v[j] are exactly offsets[nz_v[j]].
+template <int BVT>
 __global__ void __launch_bounds__(kBlock) k_batch_nz(BatchParams p) {
-    __shared__ BLds lds;
+    constexpr int NV = kNzTile / kBlock;
+    __shared__ UpdLds<NV> lds;
     int* s_wave = lds.misc;
     const int tile = blockIdx.x;
-    const int v0 = tile * kUTile + threadIdx.x * kUV;
-    int keep[kUV], tc = 0;
+    const int v0 = tile * kNzTile + threadIdx.x * NV;
+    int keep[NV], tc = 0;
 #pragma unroll
-    for (int i = 0; i < kUV; ++i) {
+    for (int i = 0; i < NV; ++i) {
         const int v = v0 + i;
         keep[i] = v < p.n && p.offsets[v + 1] > p.offsets[v];
         tc += keep[i];
@@ -88,11 +100,11 @@ __global__ void __launch_bounds__(kBlock) k_batch_nz(BatchParams p) {
     if (!s_b[1]) return;
     int pos = s_b[0] + pre;
 #pragma unroll
-    for (int i = 0; i < kUV; ++i) {
+    for (int i = 0; i < NV; ++i) {
         if (keep[i]) {
             const int v = v0 + i;
             p.nz_v[pos] = v;
-            bscatter(p, p.nz_ts, pos, p.offsets[v], p.offsets[v + 1] - p.offsets[v]);
+            bscatter<BVT>(p, p.nz_ts, pos, p.offsets[v], p.offsets[v + 1] - p.offsets[v]);
             ++pos;
         }
     }
@@ -114,7 +126,7 @@ __global__ void __launch_bounds__(kBlock) k_batch_prep(BatchParams p) {
         p.nx[i] = 0ull;
     }
     for (int64_t i = tid; i < ((int64_t)p.n + 31) / 32; i += stride) p.act_bits[i] = 0u;
-    for (int64_t i = tid; i < p.utiles; i += stride) p.desc[0][i] = 0ull;
+    for (int64_t i = tid; i < p.desc_cap; i += stride) p.desc[0][i] = 0ull;
     if (tid == 0) {
         Ctrl* c = p.ctrl;
         c->b_nact[0] = c->b_nact[1] = 0;
@@ -138,8 +150,10 @@ __global__ void k_batch_seed(BatchParams p) {
 }
 
 // Dense update after the expansion of level l (l = -1: the seeds).
+template <int BVT, int UV>
 __global__ void __launch_bounds__(kBlock) k_batch_update(BatchParams p) {
-    __shared__ BLds lds;
+    constexpr int UT = kBlock * UV;
+    __shared__ UpdLds<UV> lds;
     Ctrl* c = p.ctrl;
     if (ld_acq(&c->bdone)) return;
     const int l = ld_acq(&c->blevel);
@@ -149,19 +163,19 @@ __global__ void __launch_bounds__(kBlock) k_batch_update(BatchParams p) {
     int* s_b = lds.misc + 2 * kWaves;
     uint32_t* s_bits = reinterpret_cast<uint32_t*>(lds.misc + 2 * kWaves + 16);
     const int tile = blockIdx.x;
-    const int v0 = tile * kUTile + threadIdx.x * kUV;
+    const int v0 = tile * UT + threadIdx.x * UV;
     const int W = p.args->words;
     const int K = p.args->k;
     uint8_t* level = p.args->level;
     const uint8_t lv = (uint8_t)(l + 1);
     const bool fits = l + 1 < 255;
-    if (threadIdx.x < kUTile / 32) s_bits[threadIdx.x] = 0u;
+    if (threadIdx.x < UT / 32) s_bits[threadIdx.x] = 0u;
     lds_barrier();
     int tc = 0, ts = 0;
-    int act[kUV], deg[kUV], rs[kUV];
-    unsigned long long nw[kUV][4];
+    int act[UV], deg[UV], rs[UV];
+    unsigned long long nw[UV][4];
 #pragma unroll
-    for (int i = 0; i < kUV; ++i) {
+    for (int i = 0; i < UV; ++i) {
         const int v = v0 + i;
         act[i] = 0;
         deg[i] = 0;
@@ -196,7 +210,7 @@ __global__ void __launch_bounds__(kBlock) k_batch_update(BatchParams p) {
                         act[i] = 1;
                         rs[i] = p.offsets[v];
                         deg[i] = p.offsets[v + 1] - rs[i];
-                        atomicOr(&s_bits[(threadIdx.x * kUV + i) >> 5], 1u << ((threadIdx.x * kUV + i) & 31));
+                        atomicOr(&s_bits[(threadIdx.x * UV + i) >> 5], 1u << ((threadIdx.x * UV + i) & 31));
                         if (deg[i] > 0) {
                             ++tc;
                             ts += deg[i];
@@ -208,7 +222,7 @@ __global__ void __launch_bounds__(kBlock) k_batch_update(BatchParams p) {
     }
     // level bytes: the wave writes each new vertex's row, lane q covering sources 4q..4q+3
 #pragma unroll
-    for (int i = 0; i < kUV; ++i) {
+    for (int i = 0; i < UV; ++i) {
         uint64_t todo = ballot(act[i] != 0);
         while (todo) {
             const int src_lane = __builtin_ctzll(todo);
@@ -244,22 +258,22 @@ __global__ void __launch_bounds__(kBlock) k_batch_update(BatchParams p) {
         }
     }
     lds_barrier();
-    // active bitmap of the next level (this tile's 2048 vertices are 64 whole words)
-    if (threadIdx.x < kUTile / 32) {
-        const int64_t wi = ((int64_t)tile * kUTile) / 32 + threadIdx.x;
+    // active bitmap of the next level (the tile's vertices are UT / 32 whole words)
+    if (threadIdx.x < UT / 32) {
+        const int64_t wi = ((int64_t)tile * UT) / 32 + threadIdx.x;
         if (wi < ((int64_t)p.n + 31) / 32) p.act_bits[wi] = s_bits[threadIdx.x];
     }
     if (!s_b[2]) return;
     int pos = s_b[0] + pre_c;
     int64_t e = (int64_t)s_b[1] + pre_s;
 #pragma unroll
-    for (int i = 0; i < kUV; ++i) {
+    for (int i = 0; i < UV; ++i) {
         if (act[i] && deg[i] > 0) {
             if ((unsigned)pos < (unsigned)p.n) {
                 p.act[np][pos] = v0 + i;
                 p.act_rs[np][pos] = rs[i];
                 p.act_ex[np][pos] = (int)e;
-                bscatter(p, p.act_ts[np], pos, e, deg[i]);
+                bscatter<BVT>(p, p.act_ts[np], pos, e, deg[i]);
             } else {
                 bflag(c);
             }
@@ -270,8 +284,11 @@ __global__ void __launch_bounds__(kBlock) k_batch_update(BatchParams p) {
 }
 
 // Expansion of level l: push over the active edges or pull over all rows.
+template <int BVT>
 __global__ void __launch_bounds__(kBlock) k_batch_expand(BatchParams p) {
-    __shared__ BLds lds;
+    constexpr int G = kBlock * BVT;
+    constexpr int SL = ExpLds<BVT>::kSl;
+    __shared__ ExpLds<BVT> lds;
     Ctrl* c = p.ctrl;
     if (ld_acq(&c->bdone)) return;
     const int l = ld_acq(&c->blevel);
@@ -286,7 +303,7 @@ __global__ void __launch_bounds__(kBlock) k_batch_expand(BatchParams p) {
     int* sl = lds.sl;
     if (e_a <= p.args->pull_edges) {
         // ---- push over the active list ----
-        const int ntiles = (int)(((int64_t)e_a + kGrainB - 1) / kGrainB);
+        const int ntiles = (int)(((int64_t)e_a + G - 1) / G);
         const int P = ntiles < (int)gridDim.x ? ntiles : (int)gridDim.x;
         if ((int)blockIdx.x >= P) return;
         int tb, te;
@@ -296,20 +313,20 @@ __global__ void __launch_bounds__(kBlock) k_batch_expand(BatchParams p) {
             const int j0 = ts[t];
             const int j1 = t + 1 < ntiles ? ts[t + 1] : n_a - 1;
             const int nv = j1 - j0 + 1;
-            if (j0 < 0 || j1 >= n_a || nv < 1 || nv > kSliceB) {
+            if (j0 < 0 || j1 >= n_a || nv < 1 || nv > SL) {
                 if (threadIdx.x == 0) bflag(c);
                 return;
             }
             lds_barrier();
             for (int i = threadIdx.x; i < nv; i += kBlock) {
                 sl[i] = p.act_ex[par][j0 + i];
-                sl[kSliceB + i] = p.act_rs[par][j0 + i];
-                sl[2 * kSliceB + i] = p.act[par][j0 + i];
+                sl[SL + i] = p.act_rs[par][j0 + i];
+                sl[2 * SL + i] = p.act[par][j0 + i];
             }
             lds_barrier();
-            const int g0 = t * kGrainB, g1 = min(g0 + kGrainB, e_a);
+            const int g0 = t * G, g1 = min(g0 + G, e_a);
 #pragma unroll
-            for (int r = 0; r < kBVT; ++r) {
+            for (int r = 0; r < BVT; ++r) {
                 const int g = g0 + r * kBlock + threadIdx.x;
                 if (g < g1) {
                     int lo = 0, hi = nv;
@@ -317,8 +334,8 @@ __global__ void __launch_bounds__(kBlock) k_batch_expand(BatchParams p) {
                         const int mid = (lo + hi) >> 1;
                         if (sl[mid] <= g) lo = mid; else hi = mid;
                     }
-                    const int idx = sl[kSliceB + lo] + (g - sl[lo]);
-                    const int u = sl[2 * kSliceB + lo];
+                    const int idx = sl[SL + lo] + (g - sl[lo]);
+                    const int u = sl[2 * SL + lo];
                     if ((unsigned)idx >= (unsigned)p.m) {
                         bflag(c);
                         continue;
@@ -339,7 +356,7 @@ __global__ void __launch_bounds__(kBlock) k_batch_expand(BatchParams p) {
     }
     // ---- pull over every row that still misses a source ----
     const int nz = ld_acq(&c->nz_count);
-    const int ntiles = (int)((p.m + kGrainB - 1) / kGrainB);
+    const int ntiles = (int)((p.m + G - 1) / G);
     const int P = ntiles < (int)gridDim.x ? ntiles : (int)gridDim.x;
     if ((int)blockIdx.x >= P) return;
     int tb, te;
@@ -352,28 +369,28 @@ __global__ void __launch_bounds__(kBlock) k_batch_expand(BatchParams p) {
         const int j0 = p.nz_ts[t];
         const int j1 = t + 1 < ntiles ? p.nz_ts[t + 1] : nz - 1;
         const int nv = j1 - j0 + 1;
-        if (j0 < 0 || j1 >= nz || nv < 1 || nv > kSliceB) {
+        if (j0 < 0 || j1 >= nz || nv < 1 || nv > SL) {
             if (threadIdx.x == 0) bflag(c);
             return;
         }
-        const int64_t g0 = (int64_t)t * kGrainB, g1 = min(g0 + kGrainB, p.m);
+        const int64_t g0 = (int64_t)t * G, g1 = min(g0 + G, p.m);
         lds_barrier();
         // slice: row start | vertex | 1 if the vertex still misses a source
         for (int i = threadIdx.x; i < nv; i += kBlock) {
             const int v = p.nz_v[j0 + i];
             sl[i] = p.offsets[v];
-            sl[kSliceB + i] = v;
+            sl[SL + i] = v;
             bool need = false;
 #pragma unroll
             for (int w = 0; w < 4; ++w)
                 if (w < W) need |= p.vis[(int64_t)v * 4 + w] != full[w];
-            sl[2 * kSliceB + i] = need;
+            sl[2 * SL + i] = need;
 #pragma unroll
             for (int w = 0; w < 4; ++w) lds.acc[i * 4 + w] = 0ull;
         }
         lds_barrier();
 #pragma unroll
-        for (int r = 0; r < kBVT; ++r) {
+        for (int r = 0; r < BVT; ++r) {
             const int64_t g = g0 + r * kBlock + threadIdx.x;
             if (g < g1) {
                 int lo = 0, hi = nv;
@@ -381,7 +398,7 @@ __global__ void __launch_bounds__(kBlock) k_batch_expand(BatchParams p) {
                     const int mid = (lo + hi) >> 1;
                     if (sl[mid] <= g) lo = mid; else hi = mid;
                 }
-                if (sl[2 * kSliceB + lo]) {
+                if (sl[2 * SL + lo]) {
                     const int u = p.cols[g];
                     if ((unsigned)u < (unsigned)p.n && ((p.act_bits[u >> 5] >> (u & 31)) & 1u)) {
 #pragma unroll
@@ -399,7 +416,7 @@ __global__ void __launch_bounds__(kBlock) k_batch_expand(BatchParams p) {
         // hand the accumulated masks to N: rows cut by the sub-tile's ends may also be
         // accumulated by a neighbouring sub-tile, so those use atomics
         for (int i = threadIdx.x; i < nv; i += kBlock) {
-            const int v = sl[kSliceB + i];
+            const int v = sl[SL + i];
             const int64_t r0 = sl[i], r1 = p.offsets[v + 1];
             const bool cut = r0 < g0 || r1 > g1;
 #pragma unroll
@@ -436,11 +453,15 @@ __global__ void k_batch_next(BatchParams p) {
 
 // ---- host launchers ----------------------------------------------------------------------------
 
-int batch_grid_capacity(int device) {
+template <int BVT>
+static const void* expand_kernel() {
+    return reinterpret_cast<const void*>(k_batch_expand<BVT>);
+}
+
+int batch_grid_capacity(int device, int bvt) {
+    const void* k = bvt == 1 ? expand_kernel<1>() : bvt == 4 ? expand_kernel<4>() : expand_kernel<2>();
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k_batch_expand), kBlock,
-                                                     0) != hipSuccess)
-        return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kBlock, 0) != hipSuccess) return 0;
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
     return per_cu * cus;
@@ -453,27 +474,65 @@ static int bfill_grid(int64_t items) {
     return (int)g;
 }
 
-// Once per workspace: the list of vertices of degree >= 1 and its sub-tile starts.
+static bool tiling_ok(const BatchParams& p) {
+    return (p.bvt == 1 || p.bvt == 2 || p.bvt == 4) && (p.uv == 2 || p.uv == 4 || p.uv == 8);
+}
+
+template <int BVT>
+static void launch_nz(const BatchParams& p, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_nz<BVT>, dim3((p.n + kNzTile - 1) / kNzTile), dim3(kBlock), 0, s, p);
+}
+
+template <int BVT, int UV>
+static void launch_update_t(const BatchParams& p, hipStream_t s) {
+    hipLaunchKernelGGL((k_batch_update<BVT, UV>), dim3(p.utiles), dim3(kBlock), 0, s, p);
+}
+
+template <int BVT>
+static void launch_update_b(const BatchParams& p, hipStream_t s) {
+    if (p.uv == 2) launch_update_t<BVT, 2>(p, s);
+    else if (p.uv == 8) launch_update_t<BVT, 8>(p, s);
+    else launch_update_t<BVT, 4>(p, s);
+}
+
+static void launch_update(const BatchParams& p, hipStream_t s) {
+    if (p.bvt == 1) launch_update_b<1>(p, s);
+    else if (p.bvt == 4) launch_update_b<4>(p, s);
+    else launch_update_b<2>(p, s);
+}
+
+static void launch_expand(const BatchParams& p, int grid, hipStream_t s) {
+    if (p.bvt == 1) hipLaunchKernelGGL(k_batch_expand<1>, dim3(grid), dim3(kBlock), 0, s, p);
+    else if (p.bvt == 4) hipLaunchKernelGGL(k_batch_expand<4>, dim3(grid), dim3(kBlock), 0, s, p);
+    else hipLaunchKernelGGL(k_batch_expand<2>, dim3(grid), dim3(kBlock), 0, s, p);
+}
+
+// Per grain: the list of vertices of degree >= 1 and its sub-tile starts.
 hipError_t launch_batch_setup(const BatchParams& p, int grid, hipStream_t s) {
     (void)grid;
+    if (!tiling_ok(p)) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_batch_prep, dim3(bfill_grid(p.n)), dim3(kBlock), 0, s, p);
-    hipLaunchKernelGGL(k_batch_nz, dim3(p.utiles), dim3(kBlock), 0, s, p);
+    if (p.bvt == 1) launch_nz<1>(p, s);
+    else if (p.bvt == 4) launch_nz<4>(p, s);
+    else launch_nz<2>(p, s);
     return hipGetLastError();
 }
 
 // Per run: reset, seed, and the update that turns the seeds into level 0.
 hipError_t launch_batch_start(const BatchParams& p, hipStream_t s) {
+    if (!tiling_ok(p)) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_batch_prep, dim3(bfill_grid((int64_t)p.n * 4)), dim3(kBlock), 0, s, p);
     hipLaunchKernelGGL(k_batch_seed, dim3(1), dim3(64), 0, s, p);
-    hipLaunchKernelGGL(k_batch_update, dim3(p.utiles), dim3(kBlock), 0, s, p);
+    launch_update(p, s);
     hipLaunchKernelGGL(k_batch_next, dim3(1), dim3(64), 0, s, p);
     return hipGetLastError();
 }
 
 // One level: expand, update, next (captured into a graph by the caller).
 hipError_t launch_batch_level(const BatchParams& p, int grid, hipStream_t s) {
-    hipLaunchKernelGGL(k_batch_expand, dim3(grid), dim3(kBlock), 0, s, p);
-    hipLaunchKernelGGL(k_batch_update, dim3(p.utiles), dim3(kBlock), 0, s, p);
+    if (!tiling_ok(p)) return hipErrorInvalidValue;
+    launch_expand(p, grid, s);
+    launch_update(p, s);
     hipLaunchKernelGGL(k_batch_next, dim3(1), dim3(64), 0, s, p);
     return hipGetLastError();
 }

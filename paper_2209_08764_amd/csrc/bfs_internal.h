@@ -84,11 +84,14 @@ struct Params {
 };
 
 // Batched multi-source search (up to 256 sources, 4 x 64-bit masks per vertex).
-constexpr int kBVT = 2;                   // edges per thread in one batched sub-tile
-constexpr int kGrainB = kBlock * kBVT;    // edges per batched sub-tile, 1024
-constexpr int kSliceB = kGrainB + 1;
-constexpr int kUV = 4;                    // vertices per thread in the dense update pass
-constexpr int kUTile = kBlock * kUV;      // vertices per update tile, 2048
+// The expansion's sub-tile (grain) and the dense update's tile are launch
+// parameters chosen per workspace: grain = kBlock * bvt edges with bvt in
+// {1, 2, 4}, update tile = kBlock * uv vertices with uv in {2, 4, 8}.
+constexpr int kBVTMin = 1, kBVTMax = 4;
+constexpr int kUVMin = 2, kUVMax = 8;
+constexpr int kBVTDefault = 2;            // 1024 edges per sub-tile
+constexpr int kUVDefault = 4;             // 2048 vertices per update tile
+constexpr int kNzTile = 2048;             // vertices per tile of the one-off degree >= 1 listing
 
 // Per-run arguments of a batched search, read by the kernels from device
 // memory so that one captured level loop serves every run of a workspace.
@@ -121,8 +124,11 @@ struct BatchParams {
     Ctrl* ctrl;
     int32_t* stat_nl;
     int32_t* stat_el;
-    int32_t max_tiles;        // entries of act_ts / nz_ts
-    int32_t utiles;           // update tiles, ceil(n / kUTile)
+    int32_t max_tiles;        // entries of act_ts / nz_ts (sized for the finest grain)
+    int32_t utiles;           // update tiles, ceil(n / (kBlock * uv))
+    int32_t desc_cap;         // entries of each descriptor array
+    int32_t bvt;              // edges per thread in one expansion sub-tile
+    int32_t uv;               // vertices per thread in one update tile
     uint64_t spin_ticks;
 };
 
@@ -146,6 +152,6 @@ hipError_t launch_prim_compact(const int32_t* offsets, int32_t n, const int32_t*
 hipError_t launch_batch_setup(const BatchParams& p, int grid, hipStream_t s);
 hipError_t launch_batch_start(const BatchParams& p, hipStream_t s);
 hipError_t launch_batch_level(const BatchParams& p, int grid, hipStream_t s);
-int batch_grid_capacity(int device);
+int batch_grid_capacity(int device, int bvt);
 
 }  // namespace s3bfs

@@ -91,3 +91,39 @@ def test_batch_errors(rmat13):
     single = Workspace(G)          # max_sources = 1 has no batched buffers
     with pytest.raises(BFSError):
         single.run_batch([1, 2])
+
+
+@pytest.mark.parametrize("grain", [512, 1024, 2048])
+@pytest.mark.parametrize("tile", [1024, 2048, 4096])
+def test_every_launch_shape_matches_oracle(rmat13, grain, tile):
+    g, G = rmat13
+    ws = Workspace(G, max_sources=256, batch_grain=grain, batch_tile=tile)
+    t = ws.tuning()
+    assert (t["batch_grain"], t["batch_tile"]) == (grain, tile)
+    _check(ws, g, gg.pick_sources(g, 150, seed=grain + tile))
+    # a pull-only and a push-only pass with the same shape
+    ws.set(_lib.BFS_OPT_BATCH_PULL, 0)
+    _check(ws, g, gg.pick_sources(g, 40, seed=1))
+    ws.set(_lib.BFS_OPT_BATCH_PULL, -1)
+    _check(ws, g, gg.pick_sources(g, 40, seed=1))
+
+
+@pytest.mark.parametrize("grain,tile", [(512, 4096), (2048, 1024)])
+def test_launch_shapes_on_ragged_graphs(grain, tile):
+    # n not a multiple of any tile, long rows cut by many sub-tiles, isolated vertices
+    g, _ = gg.disjoint_union([gg.grid(37, 29), gg.rmat(10, seed=4), gg.powerlaw_forest(777, seed=9)])
+    G = Graph(g.offsets, g.cols)
+    ws = Workspace(G, max_sources=256, batch_grain=grain, batch_tile=tile)
+    _check(ws, g, gg.pick_sources(g, 255, seed=5))
+
+
+def test_bad_launch_shape_rejected(rmat13):
+    g, G = rmat13
+    ws = Workspace(G, max_sources=4)
+    for opt, val in [(_lib.BFS_OPT_BATCH_GRAIN, 768), (_lib.BFS_OPT_BATCH_TILE, 512)]:
+        with pytest.raises(BFSError) as e:
+            ws.set(opt, val)
+        assert e.value.status == _lib.BFS_EINVAL
+    single = Workspace(G)
+    with pytest.raises(BFSError):
+        single.set(_lib.BFS_OPT_BATCH_GRAIN, 512)
