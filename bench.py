@@ -305,6 +305,32 @@ def bench_c5(torch, W, count: int, rmat22=None):
             "batched_fraction": round(summ["batched_fraction"], 3), "budget_bytes": budget}
 
 
+def probe_ceiling(torch, n: int, count: int = 1 << 28, reps: int = 5) -> dict:
+    """Random-probe rate of the device for the expansion's two probe patterns: a bit of an
+    n-bit bitmap (n / 8 bytes, L2-resident) and an entry of an n-entry int32 array (4n bytes)."""
+    from paper_2209_08764_amd import bfs_probe_rate_kernel
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(7)
+    idx = torch.randint(0, n, (count,), dtype=torch.int32, device="cuda", generator=gen)
+    sink = torch.zeros(1, dtype=torch.int32, device="cuda")
+    out = {}
+    for name, words, shift in [("bitmap", (n + 31) // 32, 5), ("level_array", n, 0)]:
+        table = torch.zeros(words, dtype=torch.int32, device="cuda")
+        bfs_probe_rate_kernel(idx, table, shift, sink)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            bfs_probe_rate_kernel(idx, table, shift, sink)
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[f"{name}_{words * 4 // 1024}KiB_gprobes_per_s"] = round(count / (ms * 1e-3) / 1e9, 1)
+        del table
+    del idx
+    torch.cuda.empty_cache()
+    return out
+
+
 def run(args):
     import torch
 
@@ -359,6 +385,14 @@ def run(args):
         f"{achieved:.0f} GB/s algorithmic")
 
     extras = {"levels": levels_used, "n": n, "m": g.m, "step_ms_median": round(float(np.median(step_ms)), 4)}
+    # the secondary ceiling: every scanned edge probes the visited bitmap at a random word
+    ceil = probe_ceiling(torch, n)
+    probes = float(np.mean([2 * mc_half[i % len(sources)] for i in range(args.steps)])) / (kt * 1e-3) / 1e9
+    bkey = next(k for k in ceil if k.startswith("bitmap"))
+    extras["probe_ceiling"] = ceil
+    extras["probe_rate_gprobes_per_s"] = round(probes, 1)
+    extras["probe_ceiling_frac"] = round(probes / ceil[bkey], 4)
+    log(f"probe ceiling {ceil}; the search probes at {probes:.1f} G/s")
     if not args.quick:
         ws.set(BFS_OPT_PROFILE, 0)
         for name, mode, nsrc in [("plain", BFS_MODE_PLAIN, 8), ("level", BFS_MODE_LEVEL, 8),
@@ -374,6 +408,20 @@ def run(args):
             log(f"{name}: {extras[f'{name}_gteps_hm']} GTEPS")
         ws.set(BFS_OPT_MODE, BFS_MODE_AUTO)
         extras["speedup_vs_plain"] = round(value / extras["plain_gteps_hm"], 2)
+        # ablation: the same search without the hot-vertex filter (same resident CSR, borrowed)
+        if G.aux_bytes:
+            lean = Graph(G.offsets, G.cols, hot=False)
+            wl = Workspace(lean)
+            sub = sources[:16]
+            for s in sub[:2]:
+                wl.run(int(s), level, parent)
+            wl.sync()
+            sm, _, _ = time_single_source(wl, level, parent, sub, len(sub), torch, mc_half)
+            extras["no_hot_filter_gteps_hm"] = round(per_source_hm(sm, sub, mc_half[:16]), 3)
+            extras["hot_filter_aux_bytes"] = G.aux_bytes
+            log(f"without the hot-vertex filter: {extras['no_hot_filter_gteps_hm']} GTEPS")
+            wl.free()
+            lean.free()
 
     cpu = None
     if not args.no_cpu:

@@ -53,6 +53,8 @@ typedef struct bfs_workspace_s* bfs_workspace_t;  /* scratch for one in-flight r
 #define BFS_HOST_PTRS   1u  /* offsets/cols are host memory: the library copies them */
 #define BFS_DEVICE_PTRS 2u  /* offsets/cols are device memory: borrowed until bfs_graph_free */
 #define BFS_VALIDATE    4u  /* check the CSR on the host (O(m log m); meant for tests) */
+#define BFS_HOT_FILTER  8u  /* always build the hot-vertex filter (see bfs_init) */
+#define BFS_LEAN       16u  /* never build it (no per-edge memory beyond the CSR) */
 
 /* Execution modes (bfs_workspace_set_option(ws, BFS_OPT_MODE, ...)). */
 #define BFS_MODE_AUTO        0  /* one persistent launch; single-workgroup levels while small */
@@ -94,8 +96,17 @@ typedef struct {
  *   (synchronously; the call returns after the copy).  With BFS_DEVICE_PTRS
  *   the caller keeps them alive and unchanged until bfs_graph_free.
  *   stream: used for the upload.  *out receives the handle.
- * Errors: EINVAL (null pointers, n < 0, m < 0, both or neither pointer flag),
- *         EBADCSR (BFS_VALIDATE failed), ENOMEM, EHIP.
+ *   Unless BFS_LEAN is given, graphs with m >= 2^22 (or any graph with
+ *   BFS_HOT_FILTER) also get a hot-vertex filter: the 2^18 vertices of
+ *   highest degree (ties by id) are numbered, and an int32 per edge holds
+ *   the number of its target (or -1).  Large levels then test these
+ *   targets against a workgroup-local copy of their visited bits before
+ *   the global visited bitmap (EXPLORE-VERTEX's visited test; results are
+ *   unchanged).  This costs 4 B per edge of device memory
+ *   (bfs_graph_aux_bytes) and a host pass over the degrees.
+ * Errors: EINVAL (null pointers, n < 0, m < 0, both or neither pointer flag,
+ *         both BFS_HOT_FILTER and BFS_LEAN), EBADCSR (BFS_VALIDATE failed),
+ *         ENOMEM, EHIP.
  */
 bfs_status_t bfs_init(const int32_t* offsets, const int32_t* cols, int32_t n, int64_t m,
                       uint32_t flags, void* stream, bfs_graph_t* out);
@@ -105,6 +116,11 @@ bfs_status_t bfs_graph_free(bfs_graph_t g);
 
 /* n and m of a resident graph. */
 bfs_status_t bfs_graph_info(bfs_graph_t g, int32_t* n, int64_t* m);
+
+/* Device bytes the library allocated for g beyond the CSR itself (the
+   hot-vertex filter; 0 if it has none, and 0 for a null handle).  With
+   BFS_HOST_PTRS the copied CSR is not counted. */
+int64_t bfs_graph_aux_bytes(bfs_graph_t g);
 
 /* Device bytes a workspace for up to max_sources batched sources needs
    (max_sources = 1: single-source and multi-root runs only). 0 on error. */
@@ -260,6 +276,24 @@ bfs_status_t bfs_prim_compact(const int32_t* offsets, int32_t n, const int32_t* 
 
 /* Edges per share (tile) of the multi-workgroup level loop. */
 int32_t bfs_prim_grain(void);
+
+/* ---- measurement aid ---------------------------------------------------------------- */
+
+/*
+ * Random-probe ceiling.  The expansion step (Figure 1, EXPLORE-VERTEX)
+ * streams the column array and probes per-vertex state at the neighbour
+ * ids it reads.  This kernel reproduces that access pattern alone: it
+ * streams idx[0 .. count) and, for each entry v, reads table[v >> shift]
+ * (shift 5: a bit of a bitmap of 32-bit words, as the visited filter;
+ * shift 0: a 32-bit entry, as the level array); entries outside
+ * [0, table_words) are skipped.  All pointers are device memory; *sink
+ * receives nothing unless a checksum hits a fixed value (it only keeps the
+ * reads alive).  Asynchronous on stream: time it with events there.
+ * EINVAL for a null pointer, count < 0, table_words < 1 or shift outside
+ * [0, 5]; EHIP if the launch fails.
+ */
+bfs_status_t bfs_probe_rate_kernel(const int32_t* idx, int64_t count, const uint32_t* table,
+                                   int64_t table_words, int32_t shift, int32_t* sink, void* stream);
 
 #ifdef __cplusplus
 }

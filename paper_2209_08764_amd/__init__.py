@@ -13,21 +13,21 @@ import ctypes
 import numpy as np
 
 from . import _lib
-from ._lib import (BFS_DEVICE_PTRS, BFS_HOST_PTRS, BFS_MODE_AUTO, BFS_MODE_INSENSITIVE, BFS_MODE_LEVEL,
+from ._lib import (BFS_DEVICE_PTRS, BFS_HOST_PTRS, BFS_HOT_FILTER, BFS_LEAN, BFS_MODE_AUTO, BFS_MODE_INSENSITIVE, BFS_MODE_LEVEL,
                    BFS_MODE_PLAIN, BFS_OPT_BATCH_GRAIN, BFS_OPT_BATCH_LEVELS, BFS_OPT_BATCH_PULL, BFS_OPT_BATCH_TILE,
                    BFS_OPT_GRID, BFS_OPT_MODE, BFS_OPT_PROFILE, BFS_OPT_PUSH_EDGES, BFS_OPT_SMALL_EDGES,
                    BFS_TUNE_BATCH, BFS_TUNE_SINGLE, BFS_VALIDATE, BFSError, bfs_stats_t, bfs_tune_t)
 
 __all__ = [
-    "bfs_init", "bfs_graph_free", "bfs_graph_info", "bfs_workspace_bytes", "bfs_workspace_create",
+    "bfs_init", "bfs_graph_free", "bfs_graph_info", "bfs_graph_aux_bytes", "bfs_workspace_bytes", "bfs_workspace_create",
     "bfs_workspace_free", "bfs_workspace_set_option", "bfs_run", "bfs_run_multiroot", "bfs_run_batch",
     "bfs_sync", "bfs_last_stats", "bfs_last_level_stats", "bfs_last_level_times", "bfs_kernel_times", "bfs_status_str",
     "bfs_prim_compact",
-    "bfs_prim_grain", "bfs_autotune", "bfs_workspace_get_tuning", "Graph", "Workspace", "BFSError",
+    "bfs_prim_grain", "bfs_probe_rate_kernel", "bfs_autotune", "bfs_workspace_get_tuning", "Graph", "Workspace", "BFSError",
     "BFS_MODE_AUTO", "BFS_MODE_LEVEL", "BFS_MODE_PLAIN", "BFS_MODE_INSENSITIVE", "BFS_OPT_MODE",
     "BFS_OPT_SMALL_EDGES", "BFS_OPT_GRID", "BFS_OPT_PROFILE", "BFS_OPT_BATCH_PULL", "BFS_OPT_PUSH_EDGES", "BFS_OPT_BATCH_LEVELS",
     "BFS_OPT_BATCH_GRAIN", "BFS_OPT_BATCH_TILE", "BFS_TUNE_BATCH", "BFS_TUNE_SINGLE", "BFS_HOST_PTRS",
-    "BFS_DEVICE_PTRS", "BFS_VALIDATE",
+    "BFS_DEVICE_PTRS", "BFS_VALIDATE", "BFS_HOT_FILTER", "BFS_LEAN",
 ]
 
 
@@ -58,8 +58,10 @@ def bfs_status_str(status: int) -> str:
     return _lib.load().bfs_status_str(status).decode()
 
 
-def bfs_init(offsets, cols, flags: int | None = None, stream=None, validate: bool = False) -> int:
-    """Make a CSR graph resident; numpy arrays are copied, device tensors borrowed."""
+def bfs_init(offsets, cols, flags: int | None = None, stream=None, validate: bool = False,
+             hot: bool | None = None) -> int:
+    """Make a CSR graph resident; numpy arrays are copied, device tensors borrowed.
+    hot: None = the library's size rule for the hot-vertex filter, True/False = force it on/off."""
     torch = _torch()
     lib = _lib.load()
     out = ctypes.c_void_p()
@@ -79,6 +81,8 @@ def bfs_init(offsets, cols, flags: int | None = None, stream=None, validate: boo
         pc = cols.ctypes.data if m else None
     if validate:
         fl |= BFS_VALIDATE
+    if hot is not None:
+        fl |= BFS_HOT_FILTER if hot else BFS_LEAN
     _lib.check(lib.bfs_init(po, pc, n, m, fl, _stream_ptr(stream), ctypes.byref(out)), "bfs_init")
     return out.value
 
@@ -92,6 +96,10 @@ def bfs_graph_info(g: int):
     m = ctypes.c_int64()
     _lib.check(_lib.load().bfs_graph_info(g, ctypes.byref(n), ctypes.byref(m)), "bfs_graph_info")
     return n.value, m.value
+
+
+def bfs_graph_aux_bytes(g: int) -> int:
+    return int(_lib.load().bfs_graph_aux_bytes(g))
 
 
 def bfs_workspace_bytes(g: int, max_sources: int = 1) -> int:
@@ -186,6 +194,14 @@ def bfs_prim_compact(offsets, owner, cand, cnt, out_v, out_rs, out_ex, out_tstar
         "bfs_prim_compact")
 
 
+def bfs_probe_rate_kernel(idx, table, shift: int, sink, stream=None) -> None:
+    """Launch the random-probe measurement kernel (asynchronous on stream)."""
+    torch = _torch()
+    _lib.check(_lib.load().bfs_probe_rate_kernel(
+        _dptr(idx, torch.int32, "idx"), idx.numel(), _dptr(table, torch.int32, "table"), table.numel(), int(shift),
+        _dptr(sink, torch.int32, "sink"), _stream_ptr(stream)), "bfs_probe_rate_kernel")
+
+
 def bfs_autotune(ws: int, sources, what: int) -> dict:
     """Time candidate launch settings on the workspace's graph and keep the fastest (synchronous)."""
     src = np.ascontiguousarray(np.asarray(sources, dtype=np.int32))
@@ -204,14 +220,16 @@ def bfs_workspace_get_tuning(ws: int) -> dict:
 class Graph:
     """A device-resident graph (owns the handle and keeps borrowed tensors alive)."""
 
-    def __init__(self, offsets, cols, device="cuda", validate: bool = False, copy: bool = False):
+    def __init__(self, offsets, cols, device="cuda", validate: bool = False, copy: bool = False,
+                 hot: bool | None = None):
         torch = _torch()
         if isinstance(offsets, np.ndarray) and not copy:
             offsets = torch.from_numpy(np.ascontiguousarray(offsets, dtype=np.int32)).to(device)
             cols = torch.from_numpy(np.ascontiguousarray(cols, dtype=np.int32)).to(device)
         self._keep = (offsets, cols)
-        self.handle = bfs_init(offsets, cols, validate=validate)
+        self.handle = bfs_init(offsets, cols, validate=validate, hot=hot)
         self.n, self.m = bfs_graph_info(self.handle)
+        self.aux_bytes = bfs_graph_aux_bytes(self.handle)
         self.offsets = offsets
         self.cols = cols
 

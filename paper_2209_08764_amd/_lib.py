@@ -25,6 +25,8 @@ BFS_EDEVICE = -8
 BFS_HOST_PTRS = 1
 BFS_DEVICE_PTRS = 2
 BFS_VALIDATE = 4
+BFS_HOT_FILTER = 8
+BFS_LEAN = 16
 
 BFS_MODE_AUTO = 0
 BFS_MODE_LEVEL = 1
@@ -94,6 +96,7 @@ _SIGS = {
     "bfs_graph_free": (ctypes.c_int32, [ctypes.c_void_p]),
     "bfs_graph_info": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
                                         ctypes.POINTER(ctypes.c_int64)]),
+    "bfs_graph_aux_bytes": (ctypes.c_int64, [ctypes.c_void_p]),
     "bfs_workspace_bytes": (ctypes.c_size_t, [ctypes.c_void_p, ctypes.c_int32]),
     "bfs_workspace_create": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)]),
     "bfs_workspace_free": (ctypes.c_int32, [ctypes.c_void_p]),
@@ -122,6 +125,8 @@ _SIGS = {
     "bfs_autotune": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32,
                                       ctypes.POINTER(bfs_tune_t)]),
     "bfs_workspace_get_tuning": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(bfs_tune_t)]),
+    "bfs_probe_rate_kernel": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
+                                               ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
 }
 
 EXPORTED = tuple(_SIGS)

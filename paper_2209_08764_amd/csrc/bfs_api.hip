@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <functional>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -53,6 +54,8 @@ struct bfs_graph_s {
     int32_t* offsets = nullptr;
     int32_t* cols = nullptr;
     bool owned = false;
+    int32_t* colsh = nullptr;   // hot-vertex filter: hot number of each edge's target, or -1
+    int32_t hot_words = 0;      // words of a workspace's hot-bit arrays (0: no filter)
 };
 
 struct bfs_workspace_s {
@@ -63,6 +66,7 @@ struct bfs_workspace_s {
     int32_t grid_cap = 0;
     // single-source buffers
     uint32_t* bitmap = nullptr;
+    uint32_t* hot[2] = {nullptr, nullptr};
     int32_t* owner = nullptr;
     int32_t* f_rs[2] = {nullptr, nullptr};
     int32_t* f_ex[2] = {nullptr, nullptr};
@@ -150,6 +154,10 @@ Params make_params(bfs_workspace_s* ws, int32_t* level, int32_t* parent) {
     Params p{};
     p.offsets = ws->g->offsets;
     p.cols = ws->g->cols;
+    p.colsh = ws->g->colsh;
+    p.hot[0] = ws->hot[0];
+    p.hot[1] = ws->hot[1];
+    p.hot_words = ws->g->colsh ? ws->g->hot_words : 0;
     p.n = ws->g->n;
     p.m = ws->g->m;
     p.level = level;
@@ -423,6 +431,52 @@ bfs_status_t setup_batch(bfs_workspace_s* ws) {
 
 }  // namespace
 
+// Hot-vertex filter of a resident graph: number the (at most kHotBits) vertices
+// of highest degree, ties by id, and store each edge's target number in colsh.
+static bfs_status_t build_hot_filter(bfs_graph_s* g, const int32_t* host_offsets, hipStream_t s) {
+    const int32_t n = g->n;
+    std::vector<int32_t> ho;
+    if (!host_offsets) {
+        ho.resize((size_t)n + 1);
+        HIP_TRY(hipMemcpy(ho.data(), g->offsets, sizeof(int32_t) * ((size_t)n + 1), hipMemcpyDeviceToHost));
+        host_offsets = ho.data();
+    }
+    std::vector<int32_t> deg((size_t)n);
+    int64_t nz = 0;
+    for (int32_t v = 0; v < n; ++v) {
+        deg[v] = host_offsets[v + 1] - host_offsets[v];
+        nz += deg[v] > 0;
+    }
+    const int64_t K = std::min<int64_t>(kHotBits, nz);
+    if (K == 0) return BFS_OK;
+    // t = the K-th largest degree: every vertex above it is hot, then ties by id
+    std::vector<int32_t> tmp(deg);
+    std::nth_element(tmp.begin(), tmp.begin() + (K - 1), tmp.end(), std::greater<int32_t>());
+    const int32_t t = std::max(tmp[K - 1], 1);
+    tmp.clear();
+    tmp.shrink_to_fit();
+    std::vector<int32_t> hidx((size_t)n, -1);
+    int32_t cnt = 0;
+    for (int32_t v = 0; v < n; ++v)
+        if (deg[v] > t) hidx[v] = cnt++;
+    for (int32_t v = 0; v < n && cnt < K; ++v)
+        if (deg[v] == t) hidx[v] = cnt++;
+    int32_t* d_hidx = nullptr;
+    if (dalloc(&d_hidx, (size_t)n) != hipSuccess || dalloc(&g->colsh, (size_t)g->m) != hipSuccess) {
+        (void)hipFree(d_hidx);
+        (void)hipFree(g->colsh);
+        g->colsh = nullptr;
+        return fail(BFS_ENOMEM, "device allocation of the hot-vertex filter failed");
+    }
+    hipError_t e = hipMemcpyAsync(d_hidx, hidx.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_hot_gather(g->cols, g->m, d_hidx, g->colsh, n, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(d_hidx);
+    if (e != hipSuccess) return fail(BFS_EHIP, "building the hot-vertex filter: %s", hipGetErrorString(e));
+    g->hot_words = (cnt + 31) / 32;
+    return BFS_OK;
+}
+
 extern "C" {
 
 const char* bfs_last_error(void) { return g_last_error.c_str(); }
@@ -450,7 +504,9 @@ bfs_status_t bfs_init(const int32_t* offsets, const int32_t* cols, int32_t n, in
     if (n < 0 || m < 0 || m > INT32_MAX) return fail(BFS_EINVAL, "n or m out of range");
     const bool host = flags & BFS_HOST_PTRS, dev = flags & BFS_DEVICE_PTRS;
     if (host == dev) return fail(BFS_EINVAL, "exactly one of BFS_HOST_PTRS / BFS_DEVICE_PTRS");
-    if (flags & ~(BFS_HOST_PTRS | BFS_DEVICE_PTRS | BFS_VALIDATE)) return fail(BFS_EINVAL, "unknown flag");
+    if (flags & ~(BFS_HOST_PTRS | BFS_DEVICE_PTRS | BFS_VALIDATE | BFS_HOT_FILTER | BFS_LEAN))
+        return fail(BFS_EINVAL, "unknown flag");
+    if ((flags & BFS_HOT_FILTER) && (flags & BFS_LEAN)) return fail(BFS_EINVAL, "BFS_HOT_FILTER and BFS_LEAN together");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     if (flags & BFS_VALIDATE) {
         std::vector<int32_t> ho, hc;
@@ -488,6 +544,14 @@ bfs_status_t bfs_init(const int32_t* offsets, const int32_t* cols, int32_t n, in
         if (m) HIP_TRY(hipMemcpyAsync(g->cols, cols, sizeof(int32_t) * (size_t)m, hipMemcpyHostToDevice, s));
         HIP_TRY(hipStreamSynchronize(s));
     }
+    const bool want_hot = !(flags & BFS_LEAN) && ((flags & BFS_HOT_FILTER) || m >= kHotMinEdges) && n > 0 && m > 0;
+    if (want_hot) {
+        bfs_status_t st = build_hot_filter(g, host ? offsets : nullptr, s);
+        if (st) {
+            bfs_graph_free(g);
+            return st;
+        }
+    }
     *out = g;
     return BFS_OK;
 }
@@ -498,8 +562,13 @@ bfs_status_t bfs_graph_free(bfs_graph_t g) {
         (void)hipFree(g->offsets);
         (void)hipFree(g->cols);
     }
+    if (g->colsh) (void)hipFree(g->colsh);
     delete g;
     return BFS_OK;
+}
+
+int64_t bfs_graph_aux_bytes(bfs_graph_t g) {
+    return g && g->colsh ? g->m * (int64_t)sizeof(int32_t) : 0;
 }
 
 bfs_status_t bfs_graph_info(bfs_graph_t g, int32_t* n, int64_t* m) {
@@ -530,6 +599,7 @@ size_t bfs_workspace_bytes(bfs_graph_t g, int32_t max_sources) {
     const size_t n = (size_t)g->n, T = (size_t)tiles_for(g);
     size_t b = 0;
     b += ((n + 31) / 32) * 4;          // bitmap
+    if (g->colsh) b += 2 * (size_t)g->hot_words * 4;  // hot-vertex bits x2
     b += n * 4;                        // owner
     b += 6 * (n + 2) * 4;              // frontier ids / row starts / degree sums, x2
     b += 2 * T * 4;                    // tstart x2
@@ -552,7 +622,7 @@ bfs_status_t bfs_workspace_free(bfs_workspace_t ws) {
     if (!ws) return fail(BFS_EINVAL, "null workspace");
     (void)hipSetDevice(ws->device);
     if (ws->has_run) (void)hipEventSynchronize(ws->ev_done);
-    void* ptrs[] = {ws->bitmap, ws->owner, ws->f_rs[0], ws->f_rs[1], ws->f_ex[0], ws->f_ex[1], ws->f_v[0],
+    void* ptrs[] = {ws->bitmap, ws->hot[0], ws->hot[1], ws->owner, ws->f_rs[0], ws->f_rs[1], ws->f_ex[0], ws->f_ex[1], ws->f_v[0],
                     ws->f_v[1], ws->tstart[0],
                     ws->tstart[1], ws->cand, ws->cnt, ws->desc[0], ws->desc[1], ws->ctrl, ws->stat_nl,
                     ws->stat_el, ws->stat_ts, ws->roots, ws->plain_fv[0], ws->plain_fv[1], ws->b_fr, ws->b_nx, ws->b_vis,
@@ -594,6 +664,10 @@ bfs_status_t bfs_workspace_create(bfs_graph_t g, int32_t max_sources, bfs_worksp
     bool okk = true;
     auto A = [&](hipError_t e) { okk = okk && e == hipSuccess; };
     A(dalloc(&ws->bitmap, (n + 31) / 32));
+    if (g->colsh) {
+        A(dalloc(&ws->hot[0], (size_t)g->hot_words));
+        A(dalloc(&ws->hot[1], (size_t)g->hot_words));
+    }
     A(dalloc(&ws->owner, n));
     for (int i = 0; i < 2; ++i) {
         A(dalloc(&ws->f_rs[i], n + 2));

@@ -20,9 +20,16 @@ constexpr int kStatCap = 1 << 16;         // per-level statistics kept
 constexpr int kDefaultSmallEdges = 4 * kBlock * kVTS;
 constexpr int kPullScan = 16;             // neighbours a lane tests before a row goes to the whole workgroup
 
+// Hot-vertex filter: the kHotBits vertices of highest degree carry a number
+// in [0, kHotBits), and large levels keep their visited bits in LDS.
+constexpr int kHotBits = 1 << 18;
+constexpr int kHotWords = kHotBits / 32;   // 32 KiB of LDS
+constexpr int64_t kHotMinEdges = 1 << 22;  // graphs from this size get the filter by default
+constexpr int kHotMinTiles = 4;            // sub-tiles per share for the LDS copy to pay off
+
 // LDS words used by the level loop (the two layouts share one allocation).
 constexpr int kLdsSmall = 2 * kSmallN + 1 + kSmallC;   // frontier (rs, ex) + candidates
-constexpr int kLdsLarge = 2 * 2 * kSlice;              // double-buffered sub-tile slices (ex, rs)
+constexpr int kLdsLarge = 2 * 2 * kSlice + kHotWords;  // double-buffered sub-tile slices (ex, rs), hot bits
 constexpr int kLdsWords = (kLdsSmall > kLdsLarge ? kLdsSmall : kLdsLarge) + 2 * kWaves + 8;
 
 // ---- device control block --------------------------------------------------------------
@@ -53,6 +60,9 @@ struct Params {
     // graph
     const int32_t* offsets;
     const int32_t* cols;
+    const int32_t* colsh;     // hot number of each edge's target (-1: not hot), or null
+    uint32_t* hot[2];         // visited bits of hot vertices: levels <= l in hot[l & 1]
+    int32_t hot_words;        // words of each hot array (0: no filter)
     int32_t n;
     int64_t m;
     // outputs (caller-owned)
@@ -135,6 +145,8 @@ struct BatchParams {
 // ---- host-side launchers (bfs_kernels.hip) ---------------------------------------------
 int persistent_grid_capacity(int device);   // workgroups that can be co-resident
 hipError_t launch_prep(const Params& p, int prep_shares, bool fill_parent, hipStream_t s);
+hipError_t launch_hot_gather(const int32_t* cols, int64_t m, const int32_t* hidx, int32_t* colsh, int32_t n,
+                             hipStream_t s);
 hipError_t launch_persistent(const Params& p, int grid, hipStream_t s);
 hipError_t launch_level_roots(const Params& p, int shares, hipStream_t s);
 hipError_t launch_level_compact(const Params& p, int l, int ntiles, int shares, hipStream_t s);

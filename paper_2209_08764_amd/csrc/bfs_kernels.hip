@@ -123,13 +123,15 @@ __device__ int first_parent_wg(const Params& p, int rs, int d, int l, int* s_red
 // Reads the neighbours of this lane's kVT edges among [g0, g1) of the
 // current frontier, whose entries [j0, j0 + nv) are staged in `sl`
 // (ex | rs); -1 where there is no edge.  With `fv` also the frontier vertex
-// each edge comes from (for pushed parents).
+// each edge comes from (for pushed parents); with the hot-vertex filter
+// also each target's hot number (-1 if it has none).
 __device__ __forceinline__ void gather_tile(const Params& p, const int* sl, int nv, int g0, int g1, int* v,
-                                            const int32_t* fv, int j0, int* u) {
+                                            const int32_t* fv, int j0, int* u, int* h) {
 #pragma unroll
     for (int i = 0; i < kVT; ++i) {
         const int g = g0 + i * kBlock + threadIdx.x;
         v[i] = -1;
+        h[i] = -1;
         if (g < g1) {
             int lo = 0, hi = nv;
             while (hi - lo > 1) {
@@ -140,6 +142,7 @@ __device__ __forceinline__ void gather_tile(const Params& p, const int* sl, int 
             const int idx = sl[kSlice + lo] + (g - sl[lo]);
             if ((unsigned)idx < (unsigned)p.m) {
                 v[i] = __builtin_nontemporal_load(p.cols + idx);
+                if (p.colsh) h[i] = __builtin_nontemporal_load(p.colsh + idx);
                 if ((unsigned)v[i] >= (unsigned)p.n) v[i] = -1;
             } else {
                 flag_internal(p.ctrl);
@@ -159,14 +162,35 @@ __device__ __forceinline__ void gather_tile(const Params& p, const int* sl, int 
 // lane maps its edge to an entry by binary search there.  A new vertex gets
 // level = l + 1, its visited bit, owner = its queue slot and a place in the
 // queue (the benign race: several lanes may append the same vertex).
+//
+// Hot-vertex filter: when the graph numbers its highest-degree vertices,
+// each share with enough edges copies the visited bits of those vertices
+// for levels <= l (hot[l & 1], untouched during level l) into LDS and tests
+// hot targets there before the global bitmap; new hot vertices go to
+// hot[(l + 1) & 1], which the shares also merge hot[l & 1] into.  A set bit
+// still means "visited before this level", so results are unchanged.
 __device__ void expand_share(const Params& p, int l, int b, int P, int ntiles, int n_l, int e_l, int* lds) {
     int* s_wave = lds_wave(lds);
+    uint32_t* hnext = nullptr;
+    const uint32_t* hcur = nullptr;
+    if (p.hot_words > 0) {
+        hcur = p.hot[l & 1];
+        hnext = p.hot[(l + 1) & 1];
+        const int w0 = (int)(((int64_t)b * p.hot_words) / P), w1 = (int)(((int64_t)(b + 1) * p.hot_words) / P);
+        for (int w = w0 + threadIdx.x; w < w1; w += kBlock) {
+            const uint32_t x = hcur[w];
+            if (x) __hip_atomic_fetch_or(&hnext[w], x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
     int tb, te;
     share_range(b, P, ntiles, &tb, &te);
     if (tb >= te) {
         if (threadIdx.x == 0) p.cnt[b] = 0;
         return;
     }
+    const bool use_hot = hcur && te - tb >= kHotMinTiles;
+    const int hot_bits = p.hot_words * 32;
+    uint32_t* s_hot = reinterpret_cast<uint32_t*>(lds + 4 * kSlice);
     const int par = l & 1;
     const int32_t* tst = p.tstart[par];
     const int32_t* fex = p.f_ex[par];
@@ -192,11 +216,13 @@ __device__ void expand_share(const Params& p, int l, int b, int P, int ntiles, i
         stage_slice(buf0, a0, z0);
         if (tb + 1 < te) stage_slice(buf1, a1, z1);
     }
+    if (use_hot)
+        for (int w = threadIdx.x; w < p.hot_words; w += kBlock) s_hot[w] = hcur[w];
     lds_barrier();
-    int vc[kVT], uc[kVT];
+    int vc[kVT], uc[kVT], hc[kVT];
 #pragma unroll
-    for (int i = 0; i < kVT; ++i) vc[i] = uc[i] = -1;
-    if (!bad) gather_tile(p, buf0, z0 - a0 + 1, tb * kGrain, min(tb * kGrain + kGrain, e_l), vc, fvp, a0, uc);
+    for (int i = 0; i < kVT; ++i) vc[i] = uc[i] = hc[i] = -1;
+    if (!bad) gather_tile(p, buf0, z0 - a0 + 1, tb * kGrain, min(tb * kGrain + kGrain, e_l), vc, fvp, a0, uc, hc);
     for (int t = tb; t < te && !bad; ++t) {
         int* cur1 = ((t + 1 - tb) & 1) ? buf1 : buf0;   // slice of sub-tile t + 1
         int* free2 = ((t - tb) & 1) ? buf1 : buf0;      // receives the slice of sub-tile t + 2
@@ -214,14 +240,20 @@ __device__ void expand_share(const Params& p, int l, int b, int P, int ntiles, i
             }
         }
         // issue the neighbour reads of sub-tile t + 1
-        int vn[kVT], un[kVT];
+        int vn[kVT], un[kVT], hn[kVT];
 #pragma unroll
-        for (int i = 0; i < kVT; ++i) vn[i] = un[i] = -1;
+        for (int i = 0; i < kVT; ++i) vn[i] = un[i] = hn[i] = -1;
         if (t + 1 < te)
             gather_tile(p, cur1, z1 - a1 + 1, (t + 1) * kGrain, min((t + 1) * kGrain + kGrain, e_l), vn, fvp, a1,
-                        un);
-        // filter and append the neighbours of sub-tile t
+                        un, hn);
+        // filter and append the neighbours of sub-tile t: hot targets against the
+        // LDS copy, then everything left against the global visited bitmap
         bool fresh[kVT];
+#pragma unroll
+        for (int i = 0; i < kVT; ++i) {
+            if ((unsigned)hc[i] >= (unsigned)hot_bits) hc[i] = -1;
+            if (vc[i] >= 0 && use_hot && hc[i] >= 0 && ((s_hot[hc[i] >> 5] >> (hc[i] & 31)) & 1u)) vc[i] = -1;
+        }
 #pragma unroll
         for (int i = 0; i < kVT; ++i)
             if (vc[i] >= 0 && ((p.bitmap[vc[i] >> 5] >> (vc[i] & 31)) & 1u)) vc[i] = -1;
@@ -252,6 +284,9 @@ __device__ void expand_share(const Params& p, int l, int b, int P, int ntiles, i
                 p.level[vc[i]] = l + 1;
                 if (!fvp)
                     __hip_atomic_fetch_or(&p.bitmap[vc[i] >> 5], 1u << (vc[i] & 31), __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
+                if (hnext && hc[i] >= 0)
+                    __hip_atomic_fetch_or(&hnext[hc[i] >> 5], 1u << (hc[i] & 31), __ATOMIC_RELAXED,
                                           __HIP_MEMORY_SCOPE_AGENT);
             }
         }
@@ -302,6 +337,7 @@ __device__ void expand_share(const Params& p, int l, int b, int P, int ntiles, i
         for (int i = 0; i < kVT; ++i) {
             vc[i] = vn[i];
             uc[i] = un[i];
+            hc[i] = hn[i];
         }
         lds_barrier();
     }
@@ -693,6 +729,7 @@ __global__ void __launch_bounds__(kBlock) k_prep(Params p, int prep_shares, int 
     }
     const int64_t words = ((int64_t)p.n + 31) >> 5;
     for (int64_t w = tid; w < words; w += stride) p.bitmap[w] = 0u;
+    for (int64_t w = tid; w < p.hot_words; w += stride) p.hot[0][w] = p.hot[1][w] = 0u;
     for (int64_t t = tid; t < prep_shares; t += stride) p.desc[1][t] = 0ull;
     if (tid == 0) {
         Ctrl* c = p.ctrl;
@@ -888,6 +925,21 @@ static int fill_grid(int64_t items) {
     if (g < 1) g = 1;
     if (g > 4096) g = 4096;
     return (int)g;
+}
+
+// Graph set-up for the hot-vertex filter: colsh[e] = hidx[cols[e]].
+__global__ void k_hot_gather(const int32_t* cols, int64_t m, const int32_t* hidx, int32_t* colsh, int32_t n) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += stride) {
+        const int32_t v = cols[e];
+        colsh[e] = (unsigned)v < (unsigned)n ? hidx[v] : -1;
+    }
+}
+
+hipError_t launch_hot_gather(const int32_t* cols, int64_t m, const int32_t* hidx, int32_t* colsh, int32_t n,
+                             hipStream_t s) {
+    if (m > 0) hipLaunchKernelGGL(k_hot_gather, dim3(fill_grid(m)), dim3(kBlock), 0, s, cols, m, hidx, colsh, n);
+    return hipGetLastError();
 }
 
 hipError_t launch_prep(const Params& p, int prep_shares, bool fill_parent, hipStream_t s) {
