@@ -272,8 +272,11 @@ __device__ void expand_share(const Params& p, int l, int b, int P, int ntiles, i
             for (int i = 0; i < kVT; ++i)
                 if (vc[i] >= 0) parent_push(p, vc[i], uc[i]);
         } else {
+            // pull level: the bitmap holds every vertex visited before level l, so a
+            // target that passed it is new; its level is written at de-duplication
+            // (a target reached twice in this level is a duplicate the owner test drops)
 #pragma unroll
-            for (int i = 0; i < kVT; ++i) fresh[i] = vc[i] >= 0 && p.level[vc[i]] == -1;
+            for (int i = 0; i < kVT; ++i) fresh[i] = vc[i] >= 0;
         }
         // A pull level sets the visited bit at discovery, so later edges into
         // the vertex stop at the bitmap; a push level must let every such edge
@@ -281,8 +284,8 @@ __device__ void expand_share(const Params& p, int l, int b, int P, int ntiles, i
 #pragma unroll
         for (int i = 0; i < kVT; ++i) {
             if (fresh[i]) {
-                p.level[vc[i]] = l + 1;
-                if (!fvp)
+                if (fvp) p.level[vc[i]] = l + 1;
+                else
                     __hip_atomic_fetch_or(&p.bitmap[vc[i] >> 5], 1u << (vc[i] & 31), __ATOMIC_RELAXED,
                                           __HIP_MEMORY_SCOPE_AGENT);
                 if (hnext && hc[i] >= 0)
@@ -349,9 +352,11 @@ __device__ void expand_share(const Params& p, int l, int b, int P, int ntiles, i
 }
 
 // ---- de-duplication and linearisation of one share's queue -----------------------------------
-// Pass 1 keeps queue entries whose slot still owns the vertex (Owner[v] = i),
-// sets their visited bits, and compacts the survivors of degree >= 1 in
-// place; the share's (count, edge total) then gets its exclusive prefix by
+// Pass 1 keeps queue entries whose slot still owns the vertex (Owner[v] = i).
+// On pull levels the expansion left levels unwritten, so pass 1 also drops
+// vertices already reached and writes level l + 1 for the others; on push
+// levels and for the roots it sets their visited bits instead.  It compacts
+// the survivors of degree >= 1 in place; the share's (count, edge total) then gets its exclusive prefix by
 // decoupled look-back over the shares (the Sizes prefix sum).  Pass 2 writes
 // the survivors to the next frontier with their exclusive degree sums and
 // the start points of the next level's sub-tiles.  l = -1 compacts the roots.
@@ -362,6 +367,7 @@ __device__ bool compact_share(const Params& p, int l, int b, int P, int ntiles, 
     int* s_b = lds_misc(lds);
     const int par = l & 1;
     const int np = (l + 1) & 1;
+    const bool settle = set_bits || l < 0;  // levels already written at expansion (push levels, roots)
     int tb, te;
     share_range(b, P, ntiles, &tb, &te);
     const int qbase = tb * kGrain;
@@ -382,13 +388,14 @@ __device__ bool compact_share(const Params& p, int l, int b, int P, int ntiles, 
             if (idx < qn) {
                 const int vv = p.cand[qbase + idx];
                 if ((unsigned)vv >= (unsigned)p.n) flag_internal(p.ctrl);
-                else if (p.owner[vv] == qbase + idx) v[i] = vv;
+                else if (p.owner[vv] == qbase + idx && (settle || p.level[vv] == -1)) v[i] = vv;
             }
         }
 #pragma unroll
         for (int i = 0; i < kVT; ++i) {
             d[i] = 0;
             if (v[i] >= 0) {
+                if (!settle) p.level[v[i]] = l + 1;
                 d[i] = p.offsets[v[i] + 1] - p.offsets[v[i]];
                 ++tr;
                 if (set_bits)  // roots and push levels; pull levels set bits at discovery
