@@ -336,8 +336,8 @@ def run(args):
 
     import graphgen as gg
     from graphgen import workloads as W
-    from paper_2209_08764_amd import (BFS_MODE_AUTO, BFS_MODE_INSENSITIVE, BFS_MODE_LEVEL, BFS_MODE_PLAIN,
-                                      BFS_OPT_MODE, BFS_OPT_PROFILE, Graph, Workspace, _lib)
+    from paper_2209_08764_amd import (BFS_MODE_AUTO, BFS_MODE_DIRECTION, BFS_MODE_INSENSITIVE, BFS_MODE_LEVEL,
+                                      BFS_MODE_PLAIN, BFS_OPT_MODE, BFS_OPT_PROFILE, Graph, Workspace, _lib)
 
     _lib.load()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
@@ -396,7 +396,7 @@ def run(args):
     if not args.quick:
         ws.set(BFS_OPT_PROFILE, 0)
         for name, mode, nsrc in [("plain", BFS_MODE_PLAIN, 8), ("level", BFS_MODE_LEVEL, 8),
-                                 ("insensitive", BFS_MODE_INSENSITIVE, 16)]:
+                                 ("insensitive", BFS_MODE_INSENSITIVE, 16), ("direction", BFS_MODE_DIRECTION, 64)]:
             ws.set(BFS_OPT_MODE, mode)
             sub = sources[:nsrc]
             for s in sub[:2]:

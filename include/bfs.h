@@ -61,6 +61,8 @@ typedef struct bfs_workspace_s* bfs_workspace_t;  /* scratch for one in-flight r
 #define BFS_MODE_LEVEL       1  /* one launch pair per level, grid sized to the level's edges */
 #define BFS_MODE_PLAIN       2  /* plain per-level kernel: one thread per frontier vertex */
 #define BFS_MODE_INSENSITIVE 3  /* persistent, every workgroup active at every step */
+#define BFS_MODE_DIRECTION   4  /* AUTO, with bottom-up levels where the frontier is large
+                                   (direction optimisation; same levels and parents) */
 
 /* Options */
 #define BFS_OPT_MODE        1  /* one of BFS_MODE_* (default AUTO) */
@@ -77,6 +79,11 @@ typedef struct bfs_workspace_s* bfs_workspace_t;  /* scratch for one in-flight r
                                   the equal edge split (512, 1024 or 2048; default 1024) */
 #define BFS_OPT_BATCH_TILE  9  /* batched search: vertices per tile of the dense update pass
                                   (1024, 2048 or 4096; default 2048) */
+#define BFS_OPT_BU_ALPHA   10  /* BFS_MODE_DIRECTION: a level runs bottom-up when its frontier
+                                  edges times alpha exceed the edges of unreached vertices
+                                  (default 14) */
+#define BFS_OPT_BU_BETA    11  /* BFS_MODE_DIRECTION: bottom-up stops once the frontier holds
+                                  fewer than n / beta vertices (default 24) */
 
 typedef struct {
     int32_t levels;          /* frontiers processed: max level + 1 */
@@ -88,6 +95,7 @@ typedef struct {
     double  kernel_ms;       /* main-kernel time if BFS_OPT_PROFILE, else -1 */
     int32_t status;          /* device status of the run (BFS_OK or BFS_EDEVICE) */
     int32_t stats_truncated; /* 1 if more levels ran than per-level records kept */
+    int32_t bottom_up_levels;/* levels run bottom-up (BFS_MODE_DIRECTION) */
 } bfs_stats_t;
 
 /*

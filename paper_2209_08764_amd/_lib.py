@@ -32,6 +32,7 @@ BFS_MODE_AUTO = 0
 BFS_MODE_LEVEL = 1
 BFS_MODE_PLAIN = 2
 BFS_MODE_INSENSITIVE = 3
+BFS_MODE_DIRECTION = 4
 
 BFS_OPT_MODE = 1
 BFS_OPT_SMALL_EDGES = 2
@@ -42,12 +43,14 @@ BFS_OPT_PUSH_EDGES = 6
 BFS_OPT_BATCH_LEVELS = 7
 BFS_OPT_BATCH_GRAIN = 8
 BFS_OPT_BATCH_TILE = 9
+BFS_OPT_BU_ALPHA = 10
+BFS_OPT_BU_BETA = 11
 
 BFS_TUNE_BATCH = 1
 BFS_TUNE_SINGLE = 2
 
 MODE_NAMES = {BFS_MODE_AUTO: "auto", BFS_MODE_LEVEL: "level", BFS_MODE_PLAIN: "plain",
-              BFS_MODE_INSENSITIVE: "insensitive"}
+              BFS_MODE_INSENSITIVE: "insensitive", BFS_MODE_DIRECTION: "direction"}
 
 
 class bfs_stats_t(ctypes.Structure):
@@ -61,6 +64,7 @@ class bfs_stats_t(ctypes.Structure):
         ("kernel_ms", ctypes.c_double),
         ("status", ctypes.c_int32),
         ("stats_truncated", ctypes.c_int32),
+        ("bottom_up_levels", ctypes.c_int32),
     ]
 
 

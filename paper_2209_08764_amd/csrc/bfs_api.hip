@@ -67,6 +67,7 @@ struct bfs_workspace_s {
     // single-source buffers
     uint32_t* bitmap = nullptr;
     uint32_t* hot[2] = {nullptr, nullptr};
+    uint32_t* fbits[2] = {nullptr, nullptr};
     int32_t* owner = nullptr;
     int32_t* f_rs[2] = {nullptr, nullptr};
     int32_t* f_ex[2] = {nullptr, nullptr};
@@ -114,6 +115,8 @@ struct bfs_workspace_s {
     bool profiled = false;
     int32_t mode = BFS_MODE_AUTO;
     int32_t small_edges = kDefaultSmallEdges;
+    int32_t bu_alpha = 14;
+    int32_t bu_beta = 24;
     int32_t push_edges = -1;  // -1: m / 8 of the workspace's graph
     int32_t grid_opt = 0;
     int32_t profile = 0;
@@ -158,6 +161,11 @@ Params make_params(bfs_workspace_s* ws, int32_t* level, int32_t* parent) {
     p.hot[0] = ws->hot[0];
     p.hot[1] = ws->hot[1];
     p.hot_words = ws->g->colsh ? ws->g->hot_words : 0;
+    p.fbits[0] = ws->fbits[0];
+    p.fbits[1] = ws->fbits[1];
+    p.direction = ws->mode == BFS_MODE_DIRECTION;
+    p.bu_alpha = ws->bu_alpha;
+    p.bu_beta = ws->bu_beta;
     p.n = ws->g->n;
     p.m = ws->g->m;
     p.level = level;
@@ -598,13 +606,13 @@ size_t bfs_workspace_bytes(bfs_graph_t g, int32_t max_sources) {
     if (!g || max_sources < 1 || max_sources > 256) return 0;
     const size_t n = (size_t)g->n, T = (size_t)tiles_for(g);
     size_t b = 0;
-    b += ((n + 31) / 32) * 4;          // bitmap
+    b += 3 * ((n + 31) / 32) * 4;      // visited bitmap, frontier bits x2
     if (g->colsh) b += 2 * (size_t)g->hot_words * 4;  // hot-vertex bits x2
     b += n * 4;                        // owner
     b += 6 * (n + 2) * 4;              // frontier ids / row starts / degree sums, x2
     b += 2 * T * 4;                    // tstart x2
     b += T * kGrain * 4;               // candidates
-    b += T * 4;                        // counts
+    b += 2 * T * 4;                    // counts, bottom-up edge totals
     b += 2 * T * 8;                    // descriptors
     b += sizeof(Ctrl) + 2 * (size_t)kStatCap * 4 + 3 * (size_t)kStatCap * 8 + n * 4;  // ctrl, stats, roots
     if (max_sources > 1) {
@@ -622,7 +630,7 @@ bfs_status_t bfs_workspace_free(bfs_workspace_t ws) {
     if (!ws) return fail(BFS_EINVAL, "null workspace");
     (void)hipSetDevice(ws->device);
     if (ws->has_run) (void)hipEventSynchronize(ws->ev_done);
-    void* ptrs[] = {ws->bitmap, ws->hot[0], ws->hot[1], ws->owner, ws->f_rs[0], ws->f_rs[1], ws->f_ex[0], ws->f_ex[1], ws->f_v[0],
+    void* ptrs[] = {ws->bitmap, ws->hot[0], ws->hot[1], ws->fbits[0], ws->fbits[1], ws->owner, ws->f_rs[0], ws->f_rs[1], ws->f_ex[0], ws->f_ex[1], ws->f_v[0],
                     ws->f_v[1], ws->tstart[0],
                     ws->tstart[1], ws->cand, ws->cnt, ws->desc[0], ws->desc[1], ws->ctrl, ws->stat_nl,
                     ws->stat_el, ws->stat_ts, ws->roots, ws->plain_fv[0], ws->plain_fv[1], ws->b_fr, ws->b_nx, ws->b_vis,
@@ -664,6 +672,8 @@ bfs_status_t bfs_workspace_create(bfs_graph_t g, int32_t max_sources, bfs_worksp
     bool okk = true;
     auto A = [&](hipError_t e) { okk = okk && e == hipSuccess; };
     A(dalloc(&ws->bitmap, (n + 31) / 32));
+    A(dalloc(&ws->fbits[0], (n + 31) / 32));
+    A(dalloc(&ws->fbits[1], (n + 31) / 32));
     if (g->colsh) {
         A(dalloc(&ws->hot[0], (size_t)g->hot_words));
         A(dalloc(&ws->hot[1], (size_t)g->hot_words));
@@ -677,7 +687,7 @@ bfs_status_t bfs_workspace_create(bfs_graph_t g, int32_t max_sources, bfs_worksp
         A(dalloc(&ws->desc[i], (size_t)T));
     }
     A(dalloc(&ws->cand, (size_t)T * kGrain));
-    A(dalloc(&ws->cnt, (size_t)T));
+    A(dalloc(&ws->cnt, 2 * (size_t)T));    // queue lengths, then bottom-up edge totals
     A(dalloc(&ws->ctrl, 1));
     A(dalloc(&ws->stat_nl, kStatCap));
     A(dalloc(&ws->stat_el, kStatCap));
@@ -722,7 +732,7 @@ bfs_status_t bfs_workspace_create(bfs_graph_t g, int32_t max_sources, bfs_worksp
         return fail(BFS_EHIP, "could not create the workspace stream");
     }
     hipStream_t os = ws->own_stream;
-    bool zok = hipMemsetAsync(ws->cnt, 0, sizeof(int32_t) * (size_t)T, os) == hipSuccess &&
+    bool zok = hipMemsetAsync(ws->cnt, 0, sizeof(int32_t) * 2 * (size_t)T, os) == hipSuccess &&
                hipMemsetAsync(ws->cand, 0, sizeof(int32_t) * (size_t)T * kGrain, os) == hipSuccess &&
                hipMemsetAsync(ws->owner, 0xff, sizeof(int32_t) * n, os) == hipSuccess;
     for (int i = 0; i < 2 && zok; ++i)
@@ -755,7 +765,7 @@ bfs_status_t bfs_workspace_set_option(bfs_workspace_t ws, int32_t option, int64_
     if (!ws) return fail(BFS_EINVAL, "null workspace");
     switch (option) {
         case BFS_OPT_MODE:
-            if (value < BFS_MODE_AUTO || value > BFS_MODE_INSENSITIVE) return fail(BFS_EINVAL, "bad mode");
+            if (value < BFS_MODE_AUTO || value > BFS_MODE_DIRECTION) return fail(BFS_EINVAL, "bad mode");
             ws->mode = (int32_t)value;
             return BFS_OK;
         case BFS_OPT_SMALL_EDGES:
@@ -768,6 +778,14 @@ bfs_status_t bfs_workspace_set_option(bfs_workspace_t ws, int32_t option, int64_
             ws->grid_opt = (int32_t)value;
             return ws->b_exec ? capture_batch(ws) : BFS_OK;
         }
+        case BFS_OPT_BU_ALPHA:
+            if (value < 1 || value > (1 << 20)) return fail(BFS_EINVAL, "alpha must be in [1, 2^20]");
+            ws->bu_alpha = (int32_t)value;
+            return BFS_OK;
+        case BFS_OPT_BU_BETA:
+            if (value < 1 || value > (1 << 20)) return fail(BFS_EINVAL, "beta must be in [1, 2^20]");
+            ws->bu_beta = (int32_t)value;
+            return BFS_OK;
         case BFS_OPT_PROFILE:
             ws->profile = value != 0;
             return BFS_OK;
@@ -855,6 +873,7 @@ bfs_status_t bfs_last_stats(bfs_workspace_t ws, bfs_stats_t* out) {
     }
     out->levels = ws->h_ctrl->levels;
     out->small_levels = ws->h_ctrl->small_levels;
+    out->bottom_up_levels = ws->h_ctrl->bu_levels;
     const int cnt = std::min(out->levels, kStatCap);
     out->stats_truncated = out->levels > kStatCap;
     std::vector<int32_t> a((size_t)std::max(cnt, 1)), b((size_t)std::max(cnt, 1));

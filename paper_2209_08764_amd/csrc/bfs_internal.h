@@ -53,7 +53,8 @@ struct Ctrl {
     int batch_overflow;       // batched: a level reached 255
     int r_nl, r_el, r_kept;   // frontier handed back by a lone workgroup (level = resume)
     int nz_count;             // batched: vertices of degree >= 1
-    int pad[5];
+    int bu_levels;            // levels run bottom-up
+    int pad[4];
 };
 
 struct Params {
@@ -89,6 +90,11 @@ struct Params {
     // tuning
     int32_t small_edges;      // 0 disables single-workgroup levels
     int32_t push_edges;       // levels with at most this many edges push parents, larger ones pull
+    // direction optimisation (persistent loop only)
+    uint32_t* fbits[2];       // frontier bits: exactly the level-l vertices of degree >= 1 in fbits[l & 1]
+    int32_t direction;        // 1: levels may run bottom-up
+    int32_t bu_alpha;         // go bottom-up when e_l * alpha > edges of unreached vertices
+    int32_t bu_beta;          // return top-down when n_l * beta < n
     int32_t max_tiles;
     uint64_t spin_ticks;      // s_memrealtime ticks a wait may last without progress
 };

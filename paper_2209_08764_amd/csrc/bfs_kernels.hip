@@ -93,17 +93,18 @@ __device__ __forceinline__ int first_parent_lane(const Params& p, int rs, int d,
     return d > kPullScan ? -2 : -1;
 }
 
-// The whole workgroup reads the rest of a long row, kBlock neighbours per
-// step, and keeps the first position holding a level-l neighbour.  Uniform
-// arguments; s_red holds kWaves + 1 ints.
-__device__ int first_parent_wg(const Params& p, int rs, int d, int l, int* s_red) {
+// The whole workgroup reads the rest of a long row from position kPullScan,
+// kBlock neighbours per step, and returns the first neighbour c with hit(c)
+// (-1 if none).  Uniform arguments; s_red holds kWaves + 1 ints.
+template <typename Hit>
+__device__ __forceinline__ int first_hit_wg(const Params& p, int rs, int d, Hit hit_of, int* s_red) {
     for (int base = kPullScan; base < d; base += kBlock) {
         const int e = rs + base + threadIdx.x;
         int c = -1;
         bool hit = false;
         if (base + threadIdx.x < d) {
             c = p.cols[e];
-            hit = (unsigned)c < (unsigned)p.n && p.level[c] == l;
+            hit = (unsigned)c < (unsigned)p.n && hit_of(c);
         }
         const uint64_t bb = ballot(hit);
         if (lane_id() == 0) s_red[wave_id()] = bb ? wave_id() * 64 + __builtin_ctzll(bb) : INT32_MAX;
@@ -119,6 +120,12 @@ __device__ int first_parent_wg(const Params& p, int rs, int d, int l, int* s_red
     }
     return -1;
 }
+
+__device__ int first_parent_wg(const Params& p, int rs, int d, int l, int* s_red) {
+    return first_hit_wg(p, rs, d, [&](int c) { return p.level[c] == l; }, s_red);
+}
+
+__device__ __forceinline__ bool frontier_bit(const uint32_t* fb, int c) { return (fb[c >> 5] >> (c & 31)) & 1u; }
 
 // Reads the neighbours of this lane's kVT edges among [g0, g1) of the
 // current frontier, whose entries [j0, j0 + nv) are staged in `sl`
@@ -361,13 +368,16 @@ __device__ void expand_share(const Params& p, int l, int b, int P, int ntiles, i
 // the survivors to the next frontier with their exclusive degree sums and
 // the start points of the next level's sub-tiles.  l = -1 compacts the roots.
 __device__ bool compact_share(const Params& p, int l, int b, int P, int ntiles, bool pull_parents, bool set_bits,
-                              int* lds) {
+                              int* lds, bool after_bottom_up = false) {
     int* s_wave = lds_wave(lds);
     int* s_wave2 = lds_wave2(lds);
     int* s_b = lds_misc(lds);
     const int par = l & 1;
     const int np = (l + 1) & 1;
-    const bool settle = set_bits || l < 0;  // levels already written at expansion (push levels, roots)
+    // levels already written at expansion (push levels, roots, bottom-up levels); a
+    // bottom-up level has no duplicates and has set the visited and frontier bits
+    const bool settle = set_bits || l < 0 || after_bottom_up;
+    const bool dedup = !after_bottom_up;
     int tb, te;
     share_range(b, P, ntiles, &tb, &te);
     const int qbase = tb * kGrain;
@@ -388,7 +398,7 @@ __device__ bool compact_share(const Params& p, int l, int b, int P, int ntiles, 
             if (idx < qn) {
                 const int vv = p.cand[qbase + idx];
                 if ((unsigned)vv >= (unsigned)p.n) flag_internal(p.ctrl);
-                else if (p.owner[vv] == qbase + idx && (settle || p.level[vv] == -1)) v[i] = vv;
+                else if (!dedup || (p.owner[vv] == qbase + idx && (settle || p.level[vv] == -1))) v[i] = vv;
             }
         }
 #pragma unroll
@@ -400,6 +410,9 @@ __device__ bool compact_share(const Params& p, int l, int b, int P, int ntiles, 
                 ++tr;
                 if (set_bits)  // roots and push levels; pull levels set bits at discovery
                     __hip_atomic_fetch_or(&p.bitmap[v[i] >> 5], 1u << (v[i] & 31), __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
+                if (p.direction && d[i] > 0 && !after_bottom_up)  // frontier bits of level l + 1 for a bottom-up step
+                    __hip_atomic_fetch_or(&p.fbits[np][v[i] >> 5], 1u << (v[i] & 31), __ATOMIC_RELAXED,
                                           __HIP_MEMORY_SCOPE_AGENT);
                 if (d[i] > 0) { ++tc; ts += d[i]; }
             }
@@ -510,6 +523,131 @@ __device__ bool compact_share(const Params& p, int l, int b, int P, int ntiles, 
         run_e += S;
     }
     return true;
+}
+
+// ---- bottom-up step (direction optimisation) ----------------------------------------------
+// Instead of scanning the frontier's edges, every unreached vertex of this
+// share's vertex range [tb * kGrain, te * kGrain) scans its sorted row for the
+// first neighbour in the frontier (fbits[l & 1]); if there is one it is at
+// level l + 1 and that neighbour is its smallest-id parent.  Each vertex is
+// handled by one lane, so there are no duplicates.  Found vertices get their
+// visited and frontier bits at once and go to the share's queue, whose length
+// and edge total the share leaves in cnt[b] and cnt[max_tiles + b]; the queue
+// is linearised only if the next level runs top-down.  A lane tests
+// kPullScan neighbours; longer rows go to the whole workgroup.
+// Vertex v reached from u at level l + 1 (where ok): level, parent, visited
+// and frontier bits, and a slot of the share's queue; the wave reserves its
+// slots with one LDS atomic.  With `packed` the wave's 64 vertices are
+// consecutive from a multiple of 32, so each half-wave's bits form one word
+// and go out as one atomic instead of 32 on the same address.
+__device__ __forceinline__ void bu_settle(const Params& p, int l, int qbase, int* s_cnt, int v, int u, bool ok,
+                                          bool packed) {
+    const uint64_t bb = ballot(ok);
+    int wbase = 0;
+    if (lane_id() == 0 && bb) wbase = atomicAdd(s_cnt, __popcll(bb));
+    wbase = __shfl(wbase, 0);
+    uint32_t* fbn = p.fbits[(l + 1) & 1];
+    if (ok) {
+        const int slot = qbase + wbase + mbcnt(bb);
+        p.level[v] = l + 1;
+        if (p.parent) p.parent[v] = u;
+        p.cand[slot] = v;
+        if (!packed) {
+            __hip_atomic_fetch_or(&p.bitmap[v >> 5], 1u << (v & 31), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_or(&fbn[v >> 5], 1u << (v & 31), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+    if (packed && (lane_id() & 31) == 0) {
+        const uint32_t word = (uint32_t)(bb >> (lane_id() & 32));
+        if (word) {
+            __hip_atomic_fetch_or(&p.bitmap[v >> 5], word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_or(&fbn[v >> 5], word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+__device__ __forceinline__ void bottom_up_share(const Params& p, int l, int b, int P, int ntiles, int* lds) {
+    constexpr int kBU = 4;  // vertices per thread per round, their row reads interleaved
+    int tb, te;
+    share_range(b, P, ntiles, &tb, &te);
+    const int qbase = tb * kGrain;
+    const int v1 = (int)min((int64_t)te * kGrain, (int64_t)p.n);
+    const uint32_t* fb = p.fbits[l & 1];
+    int* s_hard = lds;                     // (v, rs, d) triples, kBU per thread at most
+    int* s_red = lds + 3 * kBU * kBlock;   // kWaves + 1 ints
+    int* s_nh = s_red + kWaves + 1;
+    int* s_cnt = s_nh + 1;
+    int* s_esum = s_cnt + 1;
+    if (threadIdx.x == 0) {
+        *s_nh = 0;
+        *s_cnt = 0;
+        *s_esum = 0;
+    }
+    lds_barrier();
+    int my_e = 0;  // degrees of the vertices this thread settles
+    for (int base = tb * kGrain; base < v1; base += kBU * kBlock) {
+        int v[kBU], rs[kBU], d[kBU], found[kBU];
+#pragma unroll
+        for (int i = 0; i < kBU; ++i) {
+            v[i] = base + i * kBlock + threadIdx.x;
+            rs[i] = d[i] = 0;
+            found[i] = -1;
+            if (v[i] < v1 && !((p.bitmap[v[i] >> 5] >> (v[i] & 31)) & 1u)) {
+                rs[i] = p.offsets[v[i]];
+                d[i] = p.offsets[v[i] + 1] - rs[i];
+            }
+        }
+        // the first four neighbours of every row at once
+        int c[kBU][4];
+#pragma unroll
+        for (int i = 0; i < kBU; ++i)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) c[i][q] = q < d[i] ? p.cols[rs[i] + q] : -1;
+#pragma unroll
+        for (int i = 0; i < kBU; ++i)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (found[i] < 0 && (unsigned)c[i][q] < (unsigned)p.n && frontier_bit(fb, c[i][q])) found[i] = c[i][q];
+        // the rest of the first kPullScan neighbours of rows still open
+#pragma unroll
+        for (int i = 0; i < kBU; ++i) {
+            const int end = rs[i] + min(d[i], kPullScan);
+            for (int e = rs[i] + 4; e < end && found[i] < 0; ++e) {
+                const int cc = p.cols[e];
+                if ((unsigned)cc < (unsigned)p.n && frontier_bit(fb, cc)) found[i] = cc;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < kBU; ++i) {
+            bu_settle(p, l, qbase, s_cnt, v[i], found[i], found[i] >= 0, true);
+            if (found[i] >= 0) my_e += d[i];
+            if (found[i] < 0 && d[i] > kPullScan) {
+                const int h = atomicAdd(s_nh, 1);
+                s_hard[3 * h] = v[i];
+                s_hard[3 * h + 1] = rs[i];
+                s_hard[3 * h + 2] = d[i];
+            }
+        }
+        lds_barrier();
+        const int nh = *s_nh;
+        for (int h = 0; h < nh; ++h) {
+            const int hv = s_hard[3 * h], hrs = s_hard[3 * h + 1], hd = s_hard[3 * h + 2];
+            const int f = first_hit_wg(p, hrs, hd, [&](int cc) { return frontier_bit(fb, cc); }, s_red);
+            bu_settle(p, l, qbase, s_cnt, hv, f, threadIdx.x == 0 && f >= 0, false);
+            if (threadIdx.x == 0 && f >= 0) my_e += hd;
+        }
+        lds_barrier();
+        if (threadIdx.x == 0) *s_nh = 0;
+        lds_barrier();
+    }
+    const int we = wave_incl_scan(my_e);
+    if (lane_id() == 63 && we) atomicAdd(s_esum, we);
+    lds_barrier();
+    if (threadIdx.x == 0) {
+        p.cnt[b] = *s_cnt;
+        p.cnt[p.max_tiles + b] = *s_esum;
+    }
+    lds_barrier();
 }
 
 // ---- a stretch of small levels run by one workgroup out of LDS -----------------------------
@@ -737,6 +875,8 @@ __global__ void __launch_bounds__(kBlock) k_prep(Params p, int prep_shares, int 
     const int64_t words = ((int64_t)p.n + 31) >> 5;
     for (int64_t w = tid; w < words; w += stride) p.bitmap[w] = 0u;
     for (int64_t w = tid; w < p.hot_words; w += stride) p.hot[0][w] = p.hot[1][w] = 0u;
+    if (p.direction)
+        for (int64_t w = tid; w < words; w += stride) p.fbits[0][w] = p.fbits[1][w] = 0u;
     for (int64_t t = tid; t < prep_shares; t += stride) p.desc[1][t] = 0ull;
     if (tid == 0) {
         Ctrl* c = p.ctrl;
@@ -751,6 +891,7 @@ __global__ void __launch_bounds__(kBlock) k_prep(Params p, int prep_shares, int 
         c->heartbeat = 0;
         c->plain_next = 0;
         c->r_nl = c->r_el = c->r_kept = 0;
+        c->bu_levels = 0;
     }
 }
 
@@ -779,6 +920,9 @@ __device__ __forceinline__ int shares_for(int ntiles, int G) { return ntiles < G
 #ifndef BFS_PERSISTENT_WAVES_PER_EU
 #define BFS_PERSISTENT_WAVES_PER_EU 4
 #endif
+// DIR: bottom-up levels are possible (BFS_MODE_DIRECTION).  The two variants
+// are separate kernels so that the top-down one keeps its own register budget.
+template <bool DIR>
 __global__ void __attribute__((amdgpu_waves_per_eu(BFS_PERSISTENT_WAVES_PER_EU))) __launch_bounds__(kBlock)
 k_persistent(Params p) {
     __shared__ Lds lds_s;
@@ -789,9 +933,21 @@ k_persistent(Params p) {
 
     const int rtiles = (p.nroots + kGrain - 1) / kGrain;
     const int Pr = shares_for(rtiles, G);
-    roots_range(p, Pr, (int64_t)blockIdx.x * kBlock + threadIdx.x, (int64_t)G * kBlock);
+    if constexpr (DIR) {
+        [[clang::always_inline]] roots_range(p, Pr, (int64_t)blockIdx.x * kBlock + threadIdx.x, (int64_t)G * kBlock);
+    } else {
+        roots_range(p, Pr, (int64_t)blockIdx.x * kBlock + threadIdx.x, (int64_t)G * kBlock);
+    }
     if (!grid_barrier(c, p.spin_ticks, s_flag)) return;
-    if (blockIdx.x < Pr && !compact_share(p, -1, blockIdx.x, Pr, rtiles, false, true, lds)) return;
+    bool ok = true;
+    if (blockIdx.x < Pr) {
+        if constexpr (DIR) {
+            [[clang::always_inline]] ok = compact_share(p, -1, blockIdx.x, Pr, rtiles, false, true, lds);
+        } else {
+            ok = compact_share(p, -1, blockIdx.x, Pr, rtiles, false, true, lds);
+        }
+    }
+    if (!ok) return;
     if (!grid_barrier(c, p.spin_ticks, s_flag)) return;
 
     // The size of each level is read once, right after the barrier that
@@ -801,6 +957,11 @@ k_persistent(Params p) {
     int n_l = ld_acq(&c->nl[0]);
     int e_l = ld_acq(&c->el[0]);
     int kept = ld_acq(&c->kept[0]);
+    // direction optimisation: fbits[l & 1] is exact when level l - 1 went through
+    // compact_share (the roots do); edges of vertices reached so far, for the switch rule
+    bool fbits_ok = true, bottom_up = false;
+    int64_t reached_edges = 0;
+    const int fwords = (p.n + 31) >> 5;
     for (;;) {
         const int par = l & 1;
         const bool rec = blockIdx.x == 0 && threadIdx.x == 0 && l < kStatCap;
@@ -810,26 +971,95 @@ k_persistent(Params p) {
             st_rel(&c->levels, l + 1);
         }
         if (n_l == 0) break;
+        reached_edges += e_l;
         if (p.small_edges > 0 && n_l <= kSmallN && e_l <= p.small_edges) {
-            if (blockIdx.x == 0) small_levels(p, l, n_l, e_l, lds);
+            if (blockIdx.x == 0) {
+                if constexpr (DIR) {
+                    [[clang::always_inline]] small_levels(p, l, n_l, e_l, lds);
+                } else {
+                    small_levels(p, l, n_l, e_l, lds);
+                }
+            }
             if (!grid_barrier(c, p.spin_ticks, s_flag)) return;
             l = ld_acq(&c->resume);
             n_l = ld_acq(&c->r_nl);
             e_l = ld_acq(&c->r_el);
             kept = ld_acq(&c->r_kept);
+            fbits_ok = false;  // levels run out of LDS keep no frontier bits
+            bottom_up = false;
             continue;
         }
-        const int ntiles = (int)(((int64_t)e_l + kGrain - 1) / kGrain);
+        // Beamer's rule: go bottom-up once the frontier's edges outweigh those of the
+        // unreached vertices (by alpha), return when the frontier is small (by beta)
+        if (DIR) {
+            const int64_t unreached = p.m - reached_edges;
+            bottom_up = fbits_ok && (bottom_up ? (int64_t)n_l * p.bu_beta >= p.n
+                                               : (int64_t)e_l * p.bu_alpha > unreached);
+        }
+        const int ntiles = bottom_up ? (p.n + kGrain - 1) / kGrain : (int)(((int64_t)e_l + kGrain - 1) / kGrain);
         const int P = shares_for(ntiles, G);  // P_l = min(P, W_l)
         const int np = (l + 1) & 1;
         // reset this level's compaction state (last used two levels ago)
-        if (blockIdx.x == 0 && threadIdx.x == 0) st_rel(&c->kept[np], 0);
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            st_rel(&c->kept[np], 0);
+            if (bottom_up) c->bu_levels += 1;
+        }
         for (int t = blockIdx.x * kBlock + threadIdx.x; t < P; t += G * kBlock) p.desc[par][t] = 0ull;
-        if (blockIdx.x < P) expand_share(p, l, blockIdx.x, P, ntiles, n_l, e_l, lds);
+        // Frontier bits: fbits[np] is zero when a level starts (its own level cleared it
+        // after reading it), except right after a stretch of single-workgroup levels,
+        // which keep none; that level runs top-down, so nothing writes fbits[np] before
+        // its compaction and it can be cleared now.
+        if (DIR && !fbits_ok)
+            for (int w = blockIdx.x * kBlock + threadIdx.x; w < fwords; w += G * kBlock) p.fbits[np][w] = 0u;
+        if (DIR && bottom_up) {
+            if (blockIdx.x < P) bottom_up_share(p, l, blockIdx.x, P, ntiles, lds);
+        } else if (blockIdx.x < P) {
+            if constexpr (DIR) {
+                [[clang::always_inline]] expand_share(p, l, blockIdx.x, P, ntiles, n_l, e_l, lds);
+            } else {
+                expand_share(p, l, blockIdx.x, P, ntiles, n_l, e_l, lds);
+            }
+        }
         if (!grid_barrier(c, p.spin_ticks, s_flag)) return;
         if (rec) p.stat_ts[3 * l + 1] = now_ticks();
-        const bool push = p.parent && e_l <= p.push_edges;
-        if (blockIdx.x < P && !compact_share(p, l, blockIdx.x, P, ntiles, !push, push, lds)) return;
+        if (DIR)  // this level's frontier bits have been read: clear them for level l + 2
+            for (int w = blockIdx.x * kBlock + threadIdx.x; w < fwords; w += G * kBlock) p.fbits[par][w] = 0u;
+        if (DIR && bottom_up) {
+            // next frontier size from the shares' counts; a following bottom-up level
+            // needs only the frontier bits, so the queue is linearised only otherwise
+            int tn = 0, te_sum = 0;
+            for (int j = threadIdx.x; j < P; j += kBlock) {
+                tn += p.cnt[j];
+                te_sum += p.cnt[p.max_tiles + j];
+            }
+            int n_next, e_next;
+            block_excl_scan(tn, lds_wave(lds), &n_next);
+            block_excl_scan(te_sum, lds_wave2(lds), &e_next);
+            const bool next_small = p.small_edges > 0 && n_next <= kSmallN && e_next <= p.small_edges;
+            if (n_next > 0 && !next_small && (int64_t)n_next * p.bu_beta >= p.n) {
+                if (!grid_barrier(c, p.spin_ticks, s_flag)) return;
+                if (rec) p.stat_ts[3 * l + 2] = now_ticks();
+                ++l;
+                n_l = n_next;
+                e_l = e_next;
+                kept = n_next;
+                fbits_ok = true;
+                continue;
+            }
+            if (blockIdx.x < P) {
+                [[clang::always_inline]] ok = compact_share(p, l, blockIdx.x, P, ntiles, false, false, lds, true);
+                if (!ok) return;
+            }
+        } else if (blockIdx.x < P) {
+            const bool push = p.parent && e_l <= p.push_edges;
+            if constexpr (DIR) {
+                [[clang::always_inline]] ok = compact_share(p, l, blockIdx.x, P, ntiles, !push, push, lds);
+            } else {
+                ok = compact_share(p, l, blockIdx.x, P, ntiles, !push, push, lds);
+            }
+            if (!ok) return;
+        }
+        fbits_ok = true;
         if (!grid_barrier(c, p.spin_ticks, s_flag)) return;
         if (rec) p.stat_ts[3 * l + 2] = now_ticks();
         ++l;
@@ -918,10 +1148,13 @@ __global__ void k_prim_totals(Params p, int32_t* totals) {
 // ---- host launchers ----------------------------------------------------------------------------
 
 int persistent_grid_capacity(int device) {
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k_persistent),
+    int per_cu = 0, per_cu_dir = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k_persistent<false>),
+                                                     kBlock, 0) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_dir, reinterpret_cast<const void*>(k_persistent<true>),
                                                      kBlock, 0) != hipSuccess)
         return 0;
+    per_cu = per_cu < per_cu_dir ? per_cu : per_cu_dir;  // one grid size serves both variants
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
     return per_cu * cus;
@@ -955,7 +1188,8 @@ hipError_t launch_prep(const Params& p, int prep_shares, bool fill_parent, hipSt
 }
 
 hipError_t launch_persistent(const Params& p, int grid, hipStream_t s) {
-    hipLaunchKernelGGL(k_persistent, dim3(grid), dim3(kBlock), 0, s, p);
+    if (p.direction) hipLaunchKernelGGL(k_persistent<true>, dim3(grid), dim3(kBlock), 0, s, p);
+    else hipLaunchKernelGGL(k_persistent<false>, dim3(grid), dim3(kBlock), 0, s, p);
     return hipGetLastError();
 }
 
