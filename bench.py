@@ -50,9 +50,12 @@ def kernel_source_hash() -> str:
 
 
 def algorithmic_bytes(n: int, n_c: int, m_c: int):
-    """Bytes the search must move at least once (whole run, persistent kernel)."""
+    """Bytes the search must move at least once: each reached row's columns (4 m_c), level and
+    parent of every vertex (8 n), and per reached vertex its offsets pair and one frontier
+    write and read (16 n_c).  The search kernel's share leaves out the -1 fill of unreached
+    vertices, which the preparation kernel does: 4 m_c + 8 n_c + 16 n_c."""
     run = 4 * m_c + 8 * n + 16 * n_c
-    kernel = run - 4 * n          # the level fill is done by the preparation kernel
+    kernel = 4 * m_c + 24 * n_c
     return run, kernel
 
 
@@ -142,6 +145,11 @@ def host_cores() -> int:
     return max(1, min(n, 16))
 
 
+def short_name(name: str, width: int = 72) -> str:
+    name = name.replace("s3bfs::", "").replace("(anonymous namespace)::", "")
+    return name if len(name) <= width else name[: width - 3] + "..."
+
+
 def rocpd_summary(paths):
     """Per-kernel summary of rocprofv3 databases (kernel trace and/or counters), as text."""
     import sqlite3
@@ -155,7 +163,7 @@ def rocpd_summary(paths):
             if rows:
                 print("kernel | calls | total_us | avg_us | percent")
                 for r in rows:
-                    print(f"{r[0]} | {r[1]} | {r[2]:.1f} | {r[3]:.1f} | {r[4]:.2f}")
+                    print(f"{short_name(r[0])} | {r[1]} | {r[2]:.1f} | {r[3]:.1f} | {r[4]:.2f}")
         if "counters_collection" in tabs:
             rows = con.execute("select kernel_name, counter_name, count(*), avg(value), min(value), max(value) "
                                "from counters_collection group by kernel_name, counter_name "
@@ -163,7 +171,57 @@ def rocpd_summary(paths):
             if rows:
                 print("kernel | counter | dispatches | avg | min | max")
                 for r in rows:
-                    print(f"{r[0]} | {r[1]} | {r[2]} | {r[3]:.1f} | {r[4]:.1f} | {r[5]:.1f}")
+                    print(f"{short_name(r[0])} | {r[1]} | {r[2]} | {r[3]:.1f} | {r[4]:.1f} | {r[5]:.1f}")
+
+
+def rocpd_dispatches(kernel: str, skip: int, take: int, path: str):
+    """Durations of dispatches [skip, skip + take) of one kernel, in start order, from a
+    rocprofv3 kernel-trace database (e.g. only the timed launches of the headline section)."""
+    import sqlite3
+    con = sqlite3.connect(path)
+    rows = con.execute("select duration from kernels where name like ? order by start", (f"%{kernel}%",)).fetchall()
+    d = np.array([r[0] for r in rows], dtype=np.float64)[skip: skip + take] / 1e6
+    print(json.dumps({"kernel": kernel, "database": path, "dispatches_total": len(rows), "skip": skip,
+                      "taken": int(d.size), "mean_ms": round(float(d.mean()), 4) if d.size else None,
+                      "median_ms": round(float(np.median(d)), 4) if d.size else None,
+                      "min_ms": round(float(d.min()), 4) if d.size else None,
+                      "max_ms": round(float(d.max()), 4) if d.size else None}))
+
+
+def traffic_from(paths, workload: str = "rmat24", kernel: str = "k_persistent<false>"):
+    """Writes the HBM traffic per launch of the search kernel from four rocprofv3 counter
+    databases (FETCH_SIZE and WRITE_SIZE of the bench run, then of the 1 GiB copy run), scaled
+    by what the counters read for the copy, with the hash of the kernel source it belongs to."""
+    import sqlite3
+
+    def avg(path, counter, pattern):
+        con = sqlite3.connect(path)
+        r = con.execute("select avg(value), count(*) from counters_collection where counter_name = ? and "
+                        "kernel_name like ?", (counter, pattern)).fetchone()
+        return float(r[0] or 0.0), int(r[1])
+
+    fetch_db, write_db, cfetch_db, cwrite_db = paths
+    kpat = f"%{kernel}%"
+    fetch, nd = avg(fetch_db, "FETCH_SIZE", kpat)
+    write, nw = avg(write_db, "WRITE_SIZE", kpat)
+    if nd == 0 or nw == 0:
+        sys.exit(f"no dispatch of {kernel} in the counter databases")
+    copy_bytes = 1 << 30
+    cf, _ = avg(cfetch_db, "FETCH_SIZE", "%copyBuffer%")
+    cw, _ = avg(cwrite_db, "WRITE_SIZE", "%copyBuffer%")
+    ff = copy_bytes / (cf * 1024) if cf else float("nan")
+    wf = copy_bytes / (cw * 1024) if cw else float("nan")
+    out = {"kernel": kernel, "workload": f"{workload} (R-MAT scale 24, EF 16, 64 seeded sources cycled)",
+           "kernel_source_sha256_16": kernel_source_hash(), "dispatches": nd,
+           "fetch_kib_per_dispatch": round(fetch, 1), "write_kib_per_dispatch": round(write, 1),
+           "copy_calibration": {"bytes": copy_bytes, "fetch_kib": round(cf, 1), "write_kib": round(cw, 1),
+                                "fetch_factor": round(ff, 4), "write_factor": round(wf, 4)},
+           "hbm_fetch_bytes_per_launch": int(fetch * 1024 * ff), "hbm_write_bytes_per_launch": int(write * 1024 * wf)}
+    out["hbm_bytes_per_launch"] = out["hbm_fetch_bytes_per_launch"] + out["hbm_write_bytes_per_launch"]
+    path = os.path.join(PROFILE_DIR, f"traffic_persistent_{workload}.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out))
 
 
 def calib_copy(args):
@@ -486,7 +544,19 @@ def main():
     ap.add_argument("--serve-queries", type=int, default=2000, help="queries in the serving run (0 skips it)")
     ap.add_argument("--calib-copy", action="store_true", help="only run a 1 GiB device copy (counter calibration)")
     ap.add_argument("--rocpd-summary", nargs="+", metavar="DB", help="summarise rocprofv3 result databases and exit")
+    ap.add_argument("--rocpd-dispatches", nargs=4, metavar=("KERNEL", "SKIP", "TAKE", "DB"),
+                    help="duration statistics of dispatches [SKIP, SKIP+TAKE) of KERNEL in start order, and exit")
+    ap.add_argument("--traffic-from", nargs=4, metavar="DB",
+                    help="FETCH_SIZE and WRITE_SIZE databases of the bench run, then of --calib-copy: write the "
+                         "search kernel's HBM traffic per launch to profiles/ and exit")
     args = ap.parse_args()
+    if args.traffic_from:
+        traffic_from(args.traffic_from)
+        return
+    if args.rocpd_dispatches:
+        k, skip, take, db = args.rocpd_dispatches
+        rocpd_dispatches(k, int(skip), int(take), db)
+        return
     if args.rocpd_summary:
         rocpd_summary(args.rocpd_summary)
         return
