@@ -325,15 +325,15 @@ __global__ void __launch_bounds__(kBlock) k_batch_expand(BatchParams p) {
             }
             lds_barrier();
             const int g0 = t * G, g1 = min(g0 + G, e_a);
+            int gg[BVT], own[BVT];
+#pragma unroll
+            for (int r = 0; r < BVT; ++r) gg[r] = min(g0 + r * kBlock + (int)threadIdx.x, g1 - 1);
+            search_owners<BVT>(sl, nv, gg, own);
 #pragma unroll
             for (int r = 0; r < BVT; ++r) {
                 const int g = g0 + r * kBlock + threadIdx.x;
                 if (g < g1) {
-                    int lo = 0, hi = nv;
-                    while (hi - lo > 1) {
-                        const int mid = (lo + hi) >> 1;
-                        if (sl[mid] <= g) lo = mid; else hi = mid;
-                    }
+                    const int lo = own[r];
                     const int idx = sl[SL + lo] + (g - sl[lo]);
                     const int u = sl[2 * SL + lo];
                     if ((unsigned)idx >= (unsigned)p.m) {
@@ -389,15 +389,15 @@ __global__ void __launch_bounds__(kBlock) k_batch_expand(BatchParams p) {
             for (int w = 0; w < 4; ++w) lds.acc[i * 4 + w] = 0ull;
         }
         lds_barrier();
+        int gg[BVT], own[BVT];
+#pragma unroll
+        for (int r = 0; r < BVT; ++r) gg[r] = (int)min(g0 + r * kBlock + (int64_t)threadIdx.x, g1 - 1);
+        search_owners<BVT>(sl, nv, gg, own);
 #pragma unroll
         for (int r = 0; r < BVT; ++r) {
             const int64_t g = g0 + r * kBlock + threadIdx.x;
             if (g < g1) {
-                int lo = 0, hi = nv;
-                while (hi - lo > 1) {
-                    const int mid = (lo + hi) >> 1;
-                    if (sl[mid] <= g) lo = mid; else hi = mid;
-                }
+                const int lo = own[r];
                 if (sl[2 * SL + lo]) {
                     const int u = p.cols[g];
                     if ((unsigned)u < (unsigned)p.n && ((p.act_bits[u >> 5] >> (u & 31)) & 1u)) {

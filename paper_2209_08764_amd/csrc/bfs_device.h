@@ -56,6 +56,31 @@ __device__ __forceinline__ int wave_incl_scan(int x) {
     return x;
 }
 
+// For each of N edge indices g[i], the entry lo[i] of a sorted array of
+// exclusive degree sums ex[0..nv) with ex[lo] <= g[i] < ex[lo + 1] (the
+// frontier entry owning the edge).  The N searches advance in lockstep, so
+// their LDS reads are in flight together instead of one search after another.
+// ex[0] <= g[i] is assumed; every search takes ceil(log2 nv) steps.
+template <int N>
+__device__ __forceinline__ void search_owners(const int* ex, int nv, const int* g, int* lo) {
+    int hi[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        lo[i] = 0;
+        hi[i] = nv;
+    }
+    const int steps = nv > 1 ? 32 - __builtin_clz((unsigned)(nv - 1)) : 0;
+    for (int s = 0; s < steps; ++s) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            const int mid = (lo[i] + hi[i]) >> 1;   // mid == lo once the range holds one entry
+            const bool right = ex[mid] <= g[i];
+            lo[i] = right ? mid : lo[i];
+            hi[i] = right ? hi[i] : mid;
+        }
+    }
+}
+
 // Exclusive block-wide prefix sum of one int per thread; *total gets the sum.
 // s_tmp holds kWaves ints.  Must be called by the whole workgroup; orders
 // LDS only.
@@ -87,8 +112,12 @@ template <typename Pred>
 __device__ inline bool spin_until(Ctrl* c, uint64_t spin_ticks, Pred pred) {
     uint64_t t0 = now_ticks();
     int hb = ld_acq(&c->heartbeat);
+    // exponential back-off (64 to 2048 cycles between polls): hundreds of waiting
+    // workgroups polling the control block flat out slow down the ones at work
+    int backoff = 1;
     while (!pred()) {
-        __builtin_amdgcn_s_sleep(1);
+        for (int k = 0; k < backoff; ++k) __builtin_amdgcn_s_sleep(1);
+        backoff = backoff < 32 ? 2 * backoff : 32;
         if (ld_acq(&c->error) != 0) return false;
         const int hb2 = ld_acq(&c->heartbeat);
         if (hb2 != hb) { hb = hb2; t0 = now_ticks(); }

@@ -28,7 +28,7 @@ constexpr int64_t kHotMinEdges = 1 << 22;  // graphs from this size get the filt
 constexpr int kHotMinTiles = 4;            // sub-tiles per share for the LDS copy to pay off
 
 // LDS words used by the level loop (the two layouts share one allocation).
-constexpr int kLdsSmall = 2 * kSmallN + 1 + kSmallC;   // frontier (rs, ex) + candidates
+constexpr int kLdsSmall = 3 * kSmallN + 1 + kSmallC;   // frontier (v, rs, ex) + claimed vertices
 constexpr int kLdsLarge = 2 * 2 * kSlice + kHotWords;  // double-buffered sub-tile slices (ex, rs), hot bits
 constexpr int kLdsWords = (kLdsSmall > kLdsLarge ? kLdsSmall : kLdsLarge) + 2 * kWaves + 8;
 

@@ -134,17 +134,17 @@ __device__ __forceinline__ bool frontier_bit(const uint32_t* fb, int c) { return
 // also each target's hot number (-1 if it has none).
 __device__ __forceinline__ void gather_tile(const Params& p, const int* sl, int nv, int g0, int g1, int* v,
                                             const int32_t* fv, int j0, int* u, int* h) {
+    int gg[kVT], own[kVT];
+#pragma unroll
+    for (int i = 0; i < kVT; ++i) gg[i] = min(g0 + i * kBlock + (int)threadIdx.x, g1 - 1);
+    search_owners<kVT>(sl, nv, gg, own);
 #pragma unroll
     for (int i = 0; i < kVT; ++i) {
         const int g = g0 + i * kBlock + threadIdx.x;
         v[i] = -1;
         h[i] = -1;
         if (g < g1) {
-            int lo = 0, hi = nv;
-            while (hi - lo > 1) {
-                const int mid = (lo + hi) >> 1;
-                if (sl[mid] <= g) lo = mid; else hi = mid;
-            }
+            const int lo = own[i];
             if (fv) u[i] = fv[j0 + lo];
             const int idx = sl[kSlice + lo] + (g - sl[lo]);
             if ((unsigned)idx < (unsigned)p.m) {
@@ -653,16 +653,26 @@ __device__ __forceinline__ void bottom_up_share(const Params& p, int l, int b, i
 // ---- a stretch of small levels run by one workgroup out of LDS -----------------------------
 // Entered at level l with the frontier in global memory (parity l & 1).
 // Leaves with the frontier of level ctrl->resume in global memory and its
-// size in the resume slot.
+// size in the resume slot.  Alone on the GPU, the workgroup claims each new
+// vertex with a returning atomic OR on the visited bitmap, so every vertex
+// is queued exactly once and no de-duplication pass is needed; the
+// frontier (ids, row starts, degree sums) stays in LDS and is written to
+// global memory only when the stretch ends.  Parents are pushed: every edge
+// into a vertex reached in this level offers its source (atomic minimum).
+// An edge that loses the claim tells such a vertex from an older one by its
+// level, which is l + 1 or still unwritten (-1) only for this level's.
 __device__ void small_levels(const Params& p, int l, int n_l, int e_l, int* lds) {
-    int* s_rs = lds;
-    int* s_ex = lds + kSmallN;
-    int* s_cand = s_ex + kSmallN + 1;
+    int* s_v = lds;                        // frontier ids
+    int* s_rs = lds + kSmallN;             // row starts
+    int* s_ex = lds + 2 * kSmallN;         // exclusive degree sums (+ total)
+    int* s_cand = lds + 3 * kSmallN + 1;   // vertices claimed in the level (first kSmallC)
     int* s_wave = lds_wave(lds);
     int* s_wave2 = lds_wave2(lds);
+    int* s_misc = lds_misc(lds);           // [0] claim counter
     {
         const int par = l & 1;
         for (int i = threadIdx.x; i < n_l; i += kBlock) {
+            s_v[i] = p.f_v[par][i];
             s_rs[i] = p.f_rs[par][i];
             s_ex[i] = p.f_ex[par][i];
         }
@@ -672,25 +682,26 @@ __device__ void small_levels(const Params& p, int l, int n_l, int e_l, int* lds)
     int done_levels = 0;
     for (;;) {
         const int np = (l + 1) & 1;
-        const int32_t* fvc = p.f_v[l & 1];  // this level's frontier ids (global copy)
-        if (threadIdx.x == 0 && l < kStatCap) p.stat_ts[3 * l] = now_ticks();
-        // expand level l: every frontier edge, kBlock * kVTS per round
-        int ncand = 0;
+        if (threadIdx.x == 0) {
+            if (l < kStatCap) p.stat_ts[3 * l] = now_ticks();
+            s_misc[0] = 0;
+        }
+        lds_barrier();
+        // expand level l: every frontier edge, kBlock * kVTS per round; a lane that flips a
+        // vertex's visited bit owns it
         for (int base0 = 0; base0 < e_l; base0 += kBlock * kVTS) {
-            int v[kVTS], u[kVTS];
-            bool fresh[kVTS];
+            int v[kVTS], u[kVTS], gg[kVTS], own[kVTS];
+#pragma unroll
+            for (int i = 0; i < kVTS; ++i) gg[i] = min(base0 + i * kBlock + (int)threadIdx.x, e_l - 1);
+            search_owners<kVTS>(s_ex, n_l, gg, own);
 #pragma unroll
             for (int i = 0; i < kVTS; ++i) {
                 const int g = base0 + i * kBlock + threadIdx.x;
                 v[i] = -1;
                 u[i] = -1;
                 if (g < e_l) {
-                    int lo = 0, hi = n_l;
-                    while (hi - lo > 1) {
-                        const int mid = (lo + hi) >> 1;
-                        if (s_ex[mid] <= g) lo = mid; else hi = mid;
-                    }
-                    if (p.parent) u[i] = fvc[lo];
+                    const int lo = own[i];
+                    u[i] = s_v[lo];
                     const int idx = s_rs[lo] + (g - s_ex[lo]);
                     if ((unsigned)idx < (unsigned)p.m) {
                         v[i] = p.cols[idx];
@@ -700,90 +711,87 @@ __device__ void small_levels(const Params& p, int l, int n_l, int e_l, int* lds)
                     }
                 }
             }
-            // parents are pushed: every edge into an unsettled vertex offers its source
+            bool fresh[kVTS];
 #pragma unroll
             for (int i = 0; i < kVTS; ++i) {
                 fresh[i] = false;
                 if (v[i] >= 0) {
-                    const int lv = p.level[v[i]];
-                    if (lv == -1) fresh[i] = true;
-                    else if (lv != l + 1) v[i] = -1;
+                    const uint32_t bit = 1u << (v[i] & 31);
+                    const uint32_t old = __hip_atomic_fetch_or(&p.bitmap[v[i] >> 5], bit, __ATOMIC_RELAXED,
+                                                               __HIP_MEMORY_SCOPE_AGENT);
+                    fresh[i] = !(old & bit);
                 }
             }
+            if (p.parent) {
 #pragma unroll
-            for (int i = 0; i < kVTS; ++i) {
-                if (v[i] >= 0 && p.parent) parent_push(p, v[i], u[i]);
-                if (fresh[i]) {
-                    p.level[v[i]] = l + 1;
-                    __hip_atomic_fetch_or(&p.bitmap[v[i] >> 5], 1u << (v[i] & 31), __ATOMIC_RELAXED,
-                                          __HIP_MEMORY_SCOPE_AGENT);
+                for (int i = 0; i < kVTS; ++i) {
+                    if (v[i] >= 0 && !fresh[i]) {
+                        const int lv = p.level[v[i]];
+                        if (lv != -1 && lv != l + 1) v[i] = -1;  // reached before this level
+                    }
                 }
+#pragma unroll
+                for (int i = 0; i < kVTS; ++i)
+                    if (v[i] >= 0) parent_push(p, v[i], u[i]);
             }
-            int slot[kVTS];
-            int wt = 0;
 #pragma unroll
             for (int i = 0; i < kVTS; ++i) {
                 const uint64_t bb = ballot(fresh[i]);
-                slot[i] = wt + mbcnt(bb);
-                wt += __popcll(bb);
-            }
-            if (lane_id() == 0) s_wave[wave_id()] = wt;
-            lds_barrier();
-            int wb = 0, tot = 0;
-#pragma unroll
-            for (int w = 0; w < kWaves; ++w) {
-                const int t = s_wave[w];
-                wb += (w < wave_id()) ? t : 0;
-                tot += t;
-            }
-#pragma unroll
-            for (int i = 0; i < kVTS; ++i) {
+                int base = 0;
+                if (lane_id() == 0 && bb) base = atomicAdd(&s_misc[0], __popcll(bb));
+                base = __shfl(base, 0);
                 if (fresh[i]) {
-                    const int s = ncand + wb + slot[i];
-                    p.owner[v[i]] = s;
-                    if (s < kSmallC) s_cand[s] = v[i]; else p.cand[s] = v[i];
+                    p.level[v[i]] = l + 1;
+                    const int s = base + mbcnt(bb);
+                    if (s < kSmallC) s_cand[s] = v[i];
+                    else if ((int64_t)s < (int64_t)p.max_tiles * kGrain) p.cand[s] = v[i];
+                    else flag_internal(p.ctrl);
                 }
             }
-            ncand += tot;
-            lds_barrier();
         }
-        __syncthreads();  // full: de-duplication reads owner and candidates other lanes wrote
+        __syncthreads();  // full: the level's stores are complete before the next level pulls parents
+        const int ncand = s_misc[0];
         if (threadIdx.x == 0 && l < kStatCap) p.stat_ts[3 * l + 1] = now_ticks();
-        // de-duplicate and build the next frontier (LDS and global copies)
-        int outc = 0, outs = 0, outr = 0;
+        // the next frontier from the claimed vertices (degree >= 1), parents pulled
+        int outc = 0, outs = 0;
+        bool hand = false;
         for (int base0 = 0; base0 < ncand; base0 += kBlock * kVTS) {
             int v[kVTS], rs[kVTS], d[kVTS];
-            int tc = 0, ts = 0, tr = 0;
+            int tc = 0, ts = 0;
 #pragma unroll
             for (int i = 0; i < kVTS; ++i) {
                 const int idx = base0 + i * kBlock + threadIdx.x;
                 v[i] = -1;
+                rs[i] = d[i] = 0;
                 if (idx < ncand) {
                     const int vv = idx < kSmallC ? s_cand[idx] : p.cand[idx];
-                    if ((unsigned)vv >= (unsigned)p.n) flag_internal(p.ctrl);
-                    else if (p.owner[vv] == idx) v[i] = vv;
+                    if ((unsigned)vv >= (unsigned)p.n) {
+                        flag_internal(p.ctrl);
+                    } else {
+                        v[i] = vv;
+                        rs[i] = p.offsets[vv];
+                        d[i] = p.offsets[vv + 1] - rs[i];
+                        if (d[i] > 0) { ++tc; ts += d[i]; }
+                    }
                 }
             }
-#pragma unroll
-            for (int i = 0; i < kVTS; ++i) {
-                rs[i] = 0;
-                d[i] = 0;
-                if (v[i] >= 0) {
-                    rs[i] = p.offsets[v[i]];
-                    d[i] = p.offsets[v[i] + 1] - rs[i];
-                    ++tr;
-                    if (d[i] > 0) { ++tc; ts += d[i]; }
-                }
-            }
-            int C, S, R;
+            int C, S;
             const int c_ex = block_excl_scan(tc, s_wave, &C);
             const int s_ex2 = block_excl_scan(ts, s_wave2, &S);
-            block_excl_scan(tr, s_wave, &R);
+            // a one-chunk level knows its totals here; larger ones always hand over
+            const int tot_c = outc + C, tot_s = outs + S;
+            if (base0 == 0)
+                hand = ncand > kBlock * kVTS || tot_c == 0 || tot_c > kSmallN || tot_s > p.small_edges;
             int pos = outc + c_ex, e = outs + s_ex2;
 #pragma unroll
             for (int i = 0; i < kVTS; ++i) {
-                if (v[i] >= 0) {
-                    if (d[i] > 0) {
+                if (v[i] >= 0 && d[i] > 0) {
+                    if (pos < kSmallN) {
+                        s_v[pos] = v[i];
+                        s_rs[pos] = rs[i];
+                        s_ex[pos] = e;
+                    }
+                    if (hand) {
                         if ((unsigned)pos < (unsigned)p.n) {
                             p.f_v[np][pos] = v[i];
                             p.f_rs[np][pos] = rs[i];
@@ -792,42 +800,38 @@ __device__ void small_levels(const Params& p, int l, int n_l, int e_l, int* lds)
                         } else {
                             flag_internal(p.ctrl);
                         }
-                        if (pos < kSmallN) {
-                            s_rs[pos] = rs[i];
-                            s_ex[pos] = e;
-                        }
-                        ++pos;
-                        e += d[i];
                     }
+                    ++pos;
+                    e += d[i];
                 }
             }
-            outc += C;
-            outs += S;
-            outr += R;
+            outc = tot_c;
+            outs = tot_s;
             lds_barrier();
         }
+        if (ncand == 0) hand = true;
         if (threadIdx.x == 0 && l < kStatCap) p.stat_ts[3 * l + 2] = now_ticks();
         ++l;
         ++done_levels;
         if (threadIdx.x == 0) {
-            if (outc <= p.n) p.f_ex[np][outc] = outs;
-            if (outr > 0 && l < kStatCap) {
-                p.stat_nl[l] = outr;
+            if (ncand > 0 && l < kStatCap) {
+                p.stat_nl[l] = ncand;
                 p.stat_el[l] = outs;
             }
-            if (outr > 0) st_rel(&p.ctrl->levels, l + 1);
+            if (ncand > 0) st_rel(&p.ctrl->levels, l + 1);
             st_rel(&p.ctrl->heartbeat, l);
         }
         n_l = outc;
         e_l = outs;
-        if (n_l == 0 || n_l > kSmallN || e_l > p.small_edges) {
+        if (hand) {
             // hand the frontier back through the resume slot: the parity slots
             // may still be read by workgroups that have not left the level the
             // stretch started at
             if (threadIdx.x == 0) {
+                if (outc <= p.n) p.f_ex[np][outc] = outs;
                 st_rel(&p.ctrl->r_nl, n_l);
                 st_rel(&p.ctrl->r_el, e_l);
-                st_rel(&p.ctrl->r_kept, outr);
+                st_rel(&p.ctrl->r_kept, ncand);
                 st_rel(&p.ctrl->resume, l);
                 __hip_atomic_fetch_add(&p.ctrl->small_levels, done_levels, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
@@ -836,7 +840,7 @@ __device__ void small_levels(const Params& p, int l, int n_l, int e_l, int* lds)
             return;
         }
         if (threadIdx.x == 0) s_ex[n_l] = e_l;
-        __syncthreads();
+        lds_barrier();
     }
 }
 
@@ -941,11 +945,7 @@ k_persistent(Params p) {
     if (!grid_barrier(c, p.spin_ticks, s_flag)) return;
     bool ok = true;
     if (blockIdx.x < Pr) {
-        if constexpr (DIR) {
-            [[clang::always_inline]] ok = compact_share(p, -1, blockIdx.x, Pr, rtiles, false, true, lds);
-        } else {
-            ok = compact_share(p, -1, blockIdx.x, Pr, rtiles, false, true, lds);
-        }
+        [[clang::always_inline]] ok = compact_share(p, -1, blockIdx.x, Pr, rtiles, false, true, lds);
     }
     if (!ok) return;
     if (!grid_barrier(c, p.spin_ticks, s_flag)) return;
@@ -1052,11 +1052,7 @@ k_persistent(Params p) {
             }
         } else if (blockIdx.x < P) {
             const bool push = p.parent && e_l <= p.push_edges;
-            if constexpr (DIR) {
-                [[clang::always_inline]] ok = compact_share(p, l, blockIdx.x, P, ntiles, !push, push, lds);
-            } else {
-                ok = compact_share(p, l, blockIdx.x, P, ntiles, !push, push, lds);
-            }
+            [[clang::always_inline]] ok = compact_share(p, l, blockIdx.x, P, ntiles, !push, push, lds);
             if (!ok) return;
         }
         fbits_ok = true;
