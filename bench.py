@@ -33,7 +33,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 METRIC = "GTEPS single-source & 256-source batch vs plain; p50/p99 query latency"
 PROFILE_DIR = os.path.join(ROOT, "profiles")
-KERNEL_SRC = os.path.join(ROOT, "paper_2209_08764_amd", "csrc", "bfs_kernels.hip")
+KERNEL_SRC = [os.path.join(ROOT, "paper_2209_08764_amd", "csrc", f)
+              for f in ("bfs_kernels.hip", "bfs_device.h", "bfs_internal.h")]
 
 
 def log(*a):
@@ -46,7 +47,11 @@ def hmean(x):
 
 
 def kernel_source_hash() -> str:
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    """Hash of the search kernel's sources (the kernel file and the device headers it includes)."""
+    h = hashlib.sha256()
+    for path in KERNEL_SRC:
+        h.update(open(path, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def algorithmic_bytes(n: int, n_c: int, m_c: int):
@@ -188,7 +193,7 @@ def rocpd_dispatches(kernel: str, skip: int, take: int, path: str):
                       "max_ms": round(float(d.max()), 4) if d.size else None}))
 
 
-def traffic_from(paths, workload: str = "rmat24", kernel: str = "k_persistent<false>"):
+def traffic_from(paths, workload: str = "rmat24", kernel: str = "k_persistent<false>", out_dir: str = PROFILE_DIR):
     """Writes the HBM traffic per launch of the search kernel from four rocprofv3 counter
     databases (FETCH_SIZE and WRITE_SIZE of the bench run, then of the 1 GiB copy run), scaled
     by what the counters read for the copy, with the hash of the kernel source it belongs to."""
@@ -218,10 +223,11 @@ def traffic_from(paths, workload: str = "rmat24", kernel: str = "k_persistent<fa
                                 "fetch_factor": round(ff, 4), "write_factor": round(wf, 4)},
            "hbm_fetch_bytes_per_launch": int(fetch * 1024 * ff), "hbm_write_bytes_per_launch": int(write * 1024 * wf)}
     out["hbm_bytes_per_launch"] = out["hbm_fetch_bytes_per_launch"] + out["hbm_write_bytes_per_launch"]
-    path = os.path.join(PROFILE_DIR, f"traffic_persistent_{workload}.json")
+    path = os.path.join(out_dir, f"traffic_persistent_{workload}.json")
     with open(path, "w") as f:
         json.dump(out, f, indent=1)
     print(json.dumps(out))
+    return out
 
 
 def calib_copy(args):
@@ -272,6 +278,94 @@ def bench_c2(torch, W, Graph, Workspace):
             "us_per_level": round(t * 1e3 / st["levels"], 2), "levels": st["levels"],
             "small_levels": st["small_levels"], "gteps": round(st["edges"] / 2 / (t * 1e-3) / 1e9, 3),
             "closed_form_levels_ok": closed}
+
+
+class EnergyMeter:
+    """GPU energy from amd-smi's accumulator (it advances about once a second): a sampling
+    thread records each update, and the average power of a window is the energy between the
+    first and last updates inside it over their time difference."""
+
+    def __init__(self):
+        import amdsmi
+        self.smi = amdsmi
+        amdsmi.amdsmi_init()
+        self.h = amdsmi.amdsmi_get_processor_handles()[0]
+        self.samples = []
+        self.stop = threading.Event()
+        self.thread = threading.Thread(target=self._run, daemon=True)
+        self.thread.start()
+
+    def _run(self):
+        last = None
+        while not self.stop.is_set():
+            e = self.smi.amdsmi_get_energy_count(self.h)
+            key = (e["timestamp"], e["energy_accumulator"])
+            if key != last:
+                self.samples.append((time.perf_counter(), e["timestamp"], e["energy_accumulator"],
+                                     e["counter_resolution"]))
+                last = key
+            time.sleep(0.02)
+
+    def power(self, t0: float, t1: float):
+        """Average watts between the first and last accumulator updates seen in [t0, t1]."""
+        inside = [x for x in self.samples if t0 <= x[0] <= t1]
+        if len(inside) < 2:
+            return None
+        a, b = inside[0], inside[-1]
+        dt = (b[1] - a[1]) * 1e-9
+        return (b[2] - a[2]) * b[3] * 1e-6 / dt if dt > 0 else None
+
+    def close(self):
+        self.stop.set()
+        self.thread.join()
+        self.smi.amdsmi_shut_down()
+
+
+def energy_compare(torch, Graph, Workspace, graphs, seconds: float = 4.0) -> dict:
+    """The paper's work-sensitivity claim on this GPU: energy per search of the work-sized level
+    loop (BFS_MODE_AUTO: P_l = min(P, W_l) workgroups, single-workgroup levels) against the
+    work-insensitive variant (every workgroup active at every level), plus idle power."""
+    from paper_2209_08764_amd import BFS_MODE_AUTO, BFS_MODE_INSENSITIVE
+    try:
+        meter = EnergyMeter()
+    except Exception as ex:  # amd-smi missing or counters not readable
+        return {"skipped": f"energy counters unavailable: {ex!r}"}
+    out = {"method": "amd-smi energy accumulator (about 1 s updates), average power over a "
+                     f"{seconds:.0f} s run of back-to-back searches x time per search"}
+    try:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        time.sleep(2.5)
+        idle = meter.power(t0, time.perf_counter())
+        out["idle_w"] = round(idle, 1) if idle else None
+        for name, (G, sources) in graphs.items():
+            n = G.n
+            lv = torch.empty(n, dtype=torch.int32, device="cuda")
+            pa = torch.empty_like(lv)
+            for mode_name, mode in (("work_sensitive", BFS_MODE_AUTO), ("work_insensitive", BFS_MODE_INSENSITIVE)):
+                ws = Workspace(G, mode=mode)
+                ws.run(int(sources[0]), lv, pa)
+                torch.cuda.synchronize()
+                k = 0
+                t0 = time.perf_counter()
+                while time.perf_counter() - t0 < seconds or k < 2:
+                    ws.run(int(sources[k % len(sources)]), lv, pa)
+                    k += 1
+                    if k % 4 == 0:
+                        torch.cuda.synchronize()
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                w = meter.power(t0, t1)
+                ms = (t1 - t0) * 1e3 / k
+                rec = {"ms_per_search": round(ms, 3), "avg_w": round(w, 1) if w else None,
+                       "j_per_search": round(w * ms * 1e-3, 4) if w else None,
+                       "dynamic_j_per_search": round((w - idle) * ms * 1e-3, 4) if (w and idle) else None}
+                out[f"{name}_{mode_name}"] = rec
+                ws.free()
+            del lv, pa
+    finally:
+        meter.close()
+    return out
 
 
 def bench_c4(torch, W, Graph, Workspace, g=None, srcs=None):
@@ -466,6 +560,15 @@ def run(args):
             log(f"{name}: {extras[f'{name}_gteps_hm']} GTEPS")
         ws.set(BFS_OPT_MODE, BFS_MODE_AUTO)
         extras["speedup_vs_plain"] = round(value / extras["plain_gteps_hm"], 2)
+        # energy: work-sized against work-insensitive levels, on this graph and on the grid
+        log("energy: work-sensitive vs work-insensitive (R-MAT 24, grid 4096^2)")
+        gg2, _ = W.c2_grid4096()
+        Ggrid = Graph(gg2.offsets, gg2.cols)
+        extras["energy"] = energy_compare(torch, Graph, Workspace,
+                                          {"rmat24": (G, sources), "grid4096": (Ggrid, [0])})
+        Ggrid.free()
+        del gg2
+        log(f"  {extras['energy']}")
         # ablation: the same search without the hot-vertex filter (same resident CSR, borrowed)
         if G.aux_bytes:
             lean = Graph(G.offsets, G.cols, hot=False)

@@ -112,12 +112,8 @@ template <typename Pred>
 __device__ inline bool spin_until(Ctrl* c, uint64_t spin_ticks, Pred pred) {
     uint64_t t0 = now_ticks();
     int hb = ld_acq(&c->heartbeat);
-    // exponential back-off (64 to 2048 cycles between polls): hundreds of waiting
-    // workgroups polling the control block flat out slow down the ones at work
-    int backoff = 1;
     while (!pred()) {
-        for (int k = 0; k < backoff; ++k) __builtin_amdgcn_s_sleep(1);
-        backoff = backoff < 32 ? 2 * backoff : 32;
+        __builtin_amdgcn_s_sleep(1);
         if (ld_acq(&c->error) != 0) return false;
         const int hb2 = ld_acq(&c->heartbeat);
         if (hb2 != hb) { hb = hb2; t0 = now_ticks(); }
