@@ -112,8 +112,11 @@ template <typename Pred>
 __device__ inline bool spin_until(Ctrl* c, uint64_t spin_ticks, Pred pred) {
     uint64_t t0 = now_ticks();
     int hb = ld_acq(&c->heartbeat);
-    while (!pred()) {
+    // the condition is polled every time, the error and heartbeat words every 32nd time: a
+    // waiting workgroup adds little traffic next to the ones still at work
+    for (int polls = 1; !pred(); ++polls) {
         __builtin_amdgcn_s_sleep(1);
+        if (polls & 31) continue;
         if (ld_acq(&c->error) != 0) return false;
         const int hb2 = ld_acq(&c->heartbeat);
         if (hb2 != hb) { hb = hb2; t0 = now_ticks(); }
