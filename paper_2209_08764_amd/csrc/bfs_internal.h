@@ -57,6 +57,18 @@ struct Ctrl {
     int pad[4];
 };
 
+// State of the grid barrier grouped by XCD (accelerator die).  Each counter
+// sits on a line of its own, so the XCDs' arrivals and polls do not meet on
+// one address.
+constexpr int kMaxXcd = 16;   // XCC ids are four bits wide
+constexpr int kXLine = 32;    // 64-bit words between two counters (256 bytes)
+struct XBar {
+    unsigned long long wgs[kMaxXcd * kXLine];     // workgroups of the launch on each XCD
+    unsigned long long arrive[kMaxXcd * kXLine];  // arrivals on each XCD, monotone within a launch
+    unsigned long long gen[kMaxXcd * kXLine];     // barriers completed, one copy per XCD
+    unsigned long long top[kXLine];               // XCD groups complete, monotone within a launch
+};
+
 struct Params {
     // graph
     const int32_t* offsets;
@@ -80,6 +92,7 @@ struct Params {
     int32_t* cnt;             // queue length per share
     unsigned long long* desc[2];  // look-back descriptors per share, per parity
     Ctrl* ctrl;
+    XBar* xbar;               // persistent loop's barrier state
     int32_t* stat_nl;
     int32_t* stat_el;
     uint64_t* stat_ts;        // per level: start, start of compaction, end (s_memrealtime ticks)

@@ -882,6 +882,8 @@ __global__ void __launch_bounds__(kBlock) k_prep(Params p, int prep_shares, int 
     if (p.direction)
         for (int64_t w = tid; w < words; w += stride) p.fbits[0][w] = p.fbits[1][w] = 0u;
     for (int64_t t = tid; t < prep_shares; t += stride) p.desc[1][t] = 0ull;
+    constexpr int64_t xwords = sizeof(XBar) / sizeof(unsigned long long);
+    for (int64_t w = tid; w < xwords; w += stride) reinterpret_cast<unsigned long long*>(p.xbar)[w] = 0ull;
     if (tid == 0) {
         Ctrl* c = p.ctrl;
         c->bar = 0;
@@ -942,13 +944,17 @@ k_persistent(Params p) {
     } else {
         roots_range(p, Pr, (int64_t)blockIdx.x * kBlock + threadIdx.x, (int64_t)G * kBlock);
     }
+    // the first barrier is the flat one; it also counts the workgroups on each XCD
+    XGroup xg{0, 1, 1};
+    if (threadIdx.x == 0) xbar_join(p.xbar, xcd_id());
     if (!grid_barrier(c, p.spin_ticks, s_flag)) return;
+    if (threadIdx.x == 0) xg = xbar_group(p.xbar, xcd_id());
     bool ok = true;
     if (blockIdx.x < Pr) {
         [[clang::always_inline]] ok = compact_share(p, -1, blockIdx.x, Pr, rtiles, false, true, lds);
     }
     if (!ok) return;
-    if (!grid_barrier(c, p.spin_ticks, s_flag)) return;
+    if (!xcd_barrier(c, p.xbar, xg, p.spin_ticks, s_flag)) return;
 
     // The size of each level is read once, right after the barrier that
     // publishes it, into loop-carried values: the slot it came from may be
@@ -980,7 +986,7 @@ k_persistent(Params p) {
                     small_levels(p, l, n_l, e_l, lds);
                 }
             }
-            if (!grid_barrier(c, p.spin_ticks, s_flag)) return;
+            if (!xcd_barrier(c, p.xbar, xg, p.spin_ticks, s_flag)) return;
             l = ld_acq(&c->resume);
             n_l = ld_acq(&c->r_nl);
             e_l = ld_acq(&c->r_el);
@@ -1020,7 +1026,7 @@ k_persistent(Params p) {
                 expand_share(p, l, blockIdx.x, P, ntiles, n_l, e_l, lds);
             }
         }
-        if (!grid_barrier(c, p.spin_ticks, s_flag)) return;
+        if (!xcd_barrier(c, p.xbar, xg, p.spin_ticks, s_flag)) return;
         if (rec) p.stat_ts[3 * l + 1] = now_ticks();
         if (DIR)  // this level's frontier bits have been read: clear them for level l + 2
             for (int w = blockIdx.x * kBlock + threadIdx.x; w < fwords; w += G * kBlock) p.fbits[par][w] = 0u;
@@ -1037,7 +1043,7 @@ k_persistent(Params p) {
             block_excl_scan(te_sum, lds_wave2(lds), &e_next);
             const bool next_small = p.small_edges > 0 && n_next <= kSmallN && e_next <= p.small_edges;
             if (n_next > 0 && !next_small && (int64_t)n_next * p.bu_beta >= p.n) {
-                if (!grid_barrier(c, p.spin_ticks, s_flag)) return;
+                if (!xcd_barrier(c, p.xbar, xg, p.spin_ticks, s_flag)) return;
                 if (rec) p.stat_ts[3 * l + 2] = now_ticks();
                 ++l;
                 n_l = n_next;
@@ -1056,7 +1062,7 @@ k_persistent(Params p) {
             if (!ok) return;
         }
         fbits_ok = true;
-        if (!grid_barrier(c, p.spin_ticks, s_flag)) return;
+        if (!xcd_barrier(c, p.xbar, xg, p.spin_ticks, s_flag)) return;
         if (rec) p.stat_ts[3 * l + 2] = now_ticks();
         ++l;
         n_l = ld_acq(&c->nl[np]);
