@@ -66,7 +66,7 @@ typedef struct bfs_workspace_s* bfs_workspace_t;  /* scratch for one in-flight r
 
 /* Options */
 #define BFS_OPT_MODE        1  /* one of BFS_MODE_* (default AUTO) */
-#define BFS_OPT_SMALL_EDGES 2  /* largest e_l run by a single workgroup (0 disables) */
+#define BFS_OPT_SMALL_EDGES 2  /* largest e_l run by a single workgroup (0 disables; default 4096) */
 #define BFS_OPT_GRID        3  /* workgroups of the persistent kernel (0 = fill the GPU) */
 #define BFS_OPT_PROFILE     4  /* 1: time the main kernel with HIP events (bfs_stats_t.kernel_ms) */
 #define BFS_OPT_BATCH_PULL  5  /* batched search: active edges above which a level pulls instead
@@ -110,8 +110,10 @@ typedef struct {
  *   the number of its target (or -1).  Large levels then test these
  *   targets against a workgroup-local copy of their visited bits before
  *   the global visited bitmap (EXPLORE-VERTEX's visited test; results are
- *   unchanged).  This costs 4 B per edge of device memory
- *   (bfs_graph_aux_bytes) and a host pass over the degrees.
+ *   unchanged).  The expansion then reads one 4 B word per edge that holds
+ *   either the target or its hot number.  This costs 4 B per edge plus 4 B
+ *   per hot vertex of device memory (bfs_graph_aux_bytes) and a host pass
+ *   over the degrees.
  * Errors: EINVAL (null pointers, n < 0, m < 0, both or neither pointer flag,
  *         both BFS_HOT_FILTER and BFS_LEAN), EBADCSR (BFS_VALIDATE failed),
  *         ENOMEM, EHIP.

@@ -54,7 +54,9 @@ struct bfs_graph_s {
     int32_t* offsets = nullptr;
     int32_t* cols = nullptr;
     bool owned = false;
-    int32_t* colsh = nullptr;   // hot-vertex filter: hot number of each edge's target, or -1
+    int32_t* colx = nullptr;    // hot-vertex filter: each edge's target, or -1 - its hot number
+    int32_t* hot_vid = nullptr; // vertex id of each hot number
+    int32_t hot_count = 0;      // hot vertices
     int32_t hot_words = 0;      // words of a workspace's hot-bit arrays (0: no filter)
 };
 
@@ -158,10 +160,11 @@ Params make_params(bfs_workspace_s* ws, int32_t* level, int32_t* parent) {
     Params p{};
     p.offsets = ws->g->offsets;
     p.cols = ws->g->cols;
-    p.colsh = ws->g->colsh;
+    p.colx = ws->g->colx;
+    p.hot_vid = ws->g->hot_vid;
     p.hot[0] = ws->hot[0];
     p.hot[1] = ws->hot[1];
-    p.hot_words = ws->g->colsh ? ws->g->hot_words : 0;
+    p.hot_words = ws->g->colx ? ws->g->hot_words : 0;
     p.fbits[0] = ws->fbits[0];
     p.fbits[1] = ws->fbits[1];
     p.direction = ws->mode == BFS_MODE_DIRECTION;
@@ -442,7 +445,8 @@ bfs_status_t setup_batch(bfs_workspace_s* ws) {
 }  // namespace
 
 // Hot-vertex filter of a resident graph: number the (at most kHotBits) vertices
-// of highest degree, ties by id, and store each edge's target number in colsh.
+// of highest degree, ties by id; each edge's entry of colx holds its target,
+// or -1 - the target's hot number, and hot_vid maps hot numbers back to ids.
 static bfs_status_t build_hot_filter(bfs_graph_s* g, const int32_t* host_offsets, hipStream_t s) {
     const int32_t n = g->n;
     std::vector<int32_t> ho;
@@ -465,24 +469,36 @@ static bfs_status_t build_hot_filter(bfs_graph_s* g, const int32_t* host_offsets
     const int32_t t = std::max(tmp[K - 1], 1);
     tmp.clear();
     tmp.shrink_to_fit();
-    std::vector<int32_t> hidx((size_t)n, -1);
-    int32_t cnt = 0;
+    std::vector<int32_t> hidx((size_t)n, -1), hvid;
+    hvid.reserve((size_t)K);
     for (int32_t v = 0; v < n; ++v)
-        if (deg[v] > t) hidx[v] = cnt++;
-    for (int32_t v = 0; v < n && cnt < K; ++v)
-        if (deg[v] == t) hidx[v] = cnt++;
+        if (deg[v] > t) {
+            hidx[v] = (int32_t)hvid.size();
+            hvid.push_back(v);
+        }
+    for (int32_t v = 0; v < n && (int64_t)hvid.size() < K; ++v)
+        if (deg[v] == t) {
+            hidx[v] = (int32_t)hvid.size();
+            hvid.push_back(v);
+        }
+    const int32_t cnt = (int32_t)hvid.size();
     int32_t* d_hidx = nullptr;
-    if (dalloc(&d_hidx, (size_t)n) != hipSuccess || dalloc(&g->colsh, (size_t)g->m) != hipSuccess) {
+    if (dalloc(&d_hidx, (size_t)n) != hipSuccess || dalloc(&g->colx, (size_t)g->m) != hipSuccess ||
+        dalloc(&g->hot_vid, (size_t)cnt) != hipSuccess) {
         (void)hipFree(d_hidx);
-        (void)hipFree(g->colsh);
-        g->colsh = nullptr;
+        (void)hipFree(g->colx);
+        (void)hipFree(g->hot_vid);
+        g->colx = g->hot_vid = nullptr;
         return fail(BFS_ENOMEM, "device allocation of the hot-vertex filter failed");
     }
     hipError_t e = hipMemcpyAsync(d_hidx, hidx.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = launch_hot_gather(g->cols, g->m, d_hidx, g->colsh, n, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(g->hot_vid, hvid.data(), sizeof(int32_t) * (size_t)cnt, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_hot_gather(g->cols, g->m, d_hidx, g->colx, n, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     (void)hipFree(d_hidx);
     if (e != hipSuccess) return fail(BFS_EHIP, "building the hot-vertex filter: %s", hipGetErrorString(e));
+    g->hot_count = cnt;
     g->hot_words = (cnt + 31) / 32;
     return BFS_OK;
 }
@@ -572,13 +588,14 @@ bfs_status_t bfs_graph_free(bfs_graph_t g) {
         (void)hipFree(g->offsets);
         (void)hipFree(g->cols);
     }
-    if (g->colsh) (void)hipFree(g->colsh);
+    if (g->colx) (void)hipFree(g->colx);
+    if (g->hot_vid) (void)hipFree(g->hot_vid);
     delete g;
     return BFS_OK;
 }
 
 int64_t bfs_graph_aux_bytes(bfs_graph_t g) {
-    return g && g->colsh ? g->m * (int64_t)sizeof(int32_t) : 0;
+    return g && g->colx ? (g->m + g->hot_count) * (int64_t)sizeof(int32_t) : 0;
 }
 
 bfs_status_t bfs_graph_info(bfs_graph_t g, int32_t* n, int64_t* m) {
@@ -609,7 +626,7 @@ size_t bfs_workspace_bytes(bfs_graph_t g, int32_t max_sources) {
     const size_t n = (size_t)g->n, T = (size_t)tiles_for(g);
     size_t b = 0;
     b += 3 * ((n + 31) / 32) * 4;      // visited bitmap, frontier bits x2
-    if (g->colsh) b += 2 * (size_t)g->hot_words * 4;  // hot-vertex bits x2
+    if (g->colx) b += 2 * (size_t)g->hot_words * 4;  // hot-vertex bits x2
     b += n * 4;                        // owner
     b += 6 * (n + 2) * 4;              // frontier ids / row starts / degree sums, x2
     b += 2 * T * 4;                    // tstart x2
@@ -676,7 +693,7 @@ bfs_status_t bfs_workspace_create(bfs_graph_t g, int32_t max_sources, bfs_worksp
     A(dalloc(&ws->bitmap, (n + 31) / 32));
     A(dalloc(&ws->fbits[0], (n + 31) / 32));
     A(dalloc(&ws->fbits[1], (n + 31) / 32));
-    if (g->colsh) {
+    if (g->colx) {
         A(dalloc(&ws->hot[0], (size_t)g->hot_words));
         A(dalloc(&ws->hot[1], (size_t)g->hot_words));
     }
@@ -1178,7 +1195,7 @@ bfs_status_t bfs_autotune(bfs_workspace_t ws, const int32_t* sources, int32_t k,
         st = descend(smp, &best, grids, P{start.grid, 0},
                      [&](P c) { return bfs_workspace_set_option(ws, BFS_OPT_GRID, c.first); });
         std::vector<P> smalls;
-        for (int64_t e : {0, 4096, 16384, 65536}) smalls.push_back({e, 0});
+        for (int64_t e : {0, 2048, 4096, 8192, 16384}) smalls.push_back({e, 0});
         if (!st)
             st = descend(smp, &best, smalls, P{start.small_edges, 0},
                          [&](P c) { return bfs_workspace_set_option(ws, BFS_OPT_SMALL_EDGES, c.first); });

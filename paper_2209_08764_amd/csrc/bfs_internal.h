@@ -17,7 +17,7 @@ constexpr int kVTS = 8;                   // edges per thread per round, single-
 constexpr int kSmallN = 4096;             // frontier capacity of single-workgroup levels (LDS)
 constexpr int kSmallC = 4096;             // candidates held in LDS in single-workgroup levels
 constexpr int kStatCap = 1 << 16;         // per-level statistics kept
-constexpr int kDefaultSmallEdges = 4 * kBlock * kVTS;
+constexpr int kDefaultSmallEdges = kBlock * kVTS;  // one round of the lone workgroup
 constexpr int kPullScan = 16;             // neighbours a lane tests before a row goes to the whole workgroup
 
 // Hot-vertex filter: the kHotBits vertices of highest degree carry a number
@@ -26,6 +26,7 @@ constexpr int kHotBits = 1 << 18;
 constexpr int kHotWords = kHotBits / 32;   // 32 KiB of LDS
 constexpr int64_t kHotMinEdges = 1 << 22;  // graphs from this size get the filter by default
 constexpr int kHotMinTiles = 4;            // sub-tiles per share for the LDS copy to pay off
+constexpr int kHotTarget = -2;             // a gathered edge whose target is hot, id not yet looked up
 
 // LDS words used by the level loop (the two layouts share one allocation).
 constexpr int kLdsSmall = 3 * kSmallN + 1 + kSmallC;   // frontier (v, rs, ex) + claimed vertices
@@ -73,7 +74,8 @@ struct Params {
     // graph
     const int32_t* offsets;
     const int32_t* cols;
-    const int32_t* colsh;     // hot number of each edge's target (-1: not hot), or null
+    const int32_t* colx;      // per edge: the target, or -1 - its hot number (null: no filter)
+    const int32_t* hot_vid;   // vertex id of each hot number
     uint32_t* hot[2];         // visited bits of hot vertices: levels <= l in hot[l & 1]
     int32_t hot_words;        // words of each hot array (0: no filter)
     int32_t n;
@@ -164,7 +166,7 @@ struct BatchParams {
 // ---- host-side launchers (bfs_kernels.hip) ---------------------------------------------
 int persistent_grid_capacity(int device);   // workgroups that can be co-resident
 hipError_t launch_prep(const Params& p, int prep_shares, bool fill_parent, hipStream_t s);
-hipError_t launch_hot_gather(const int32_t* cols, int64_t m, const int32_t* hidx, int32_t* colsh, int32_t n,
+hipError_t launch_hot_gather(const int32_t* cols, int64_t m, const int32_t* hidx, int32_t* colx, int32_t n,
                              hipStream_t s);
 hipError_t launch_persistent(const Params& p, int grid, hipStream_t s);
 hipError_t launch_level_roots(const Params& p, int shares, hipStream_t s);

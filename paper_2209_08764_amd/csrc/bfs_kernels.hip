@@ -130,8 +130,9 @@ __device__ __forceinline__ bool frontier_bit(const uint32_t* fb, int c) { return
 // Reads the neighbours of this lane's kVT edges among [g0, g1) of the
 // current frontier, whose entries [j0, j0 + nv) are staged in `sl`
 // (ex | rs); -1 where there is no edge.  With `fv` also the frontier vertex
-// each edge comes from (for pushed parents); with the hot-vertex filter
-// also each target's hot number (-1 if it has none).
+// each edge comes from (for pushed parents).  With the hot-vertex filter a
+// hot target comes back as kHotTarget with its hot number in h (-1 for the
+// others); expand_share resolves its id once the hot bits leave it open.
 __device__ __forceinline__ void gather_tile(const Params& p, const int* sl, int nv, int g0, int g1, int* v,
                                             const int32_t* fv, int j0, int* u, int* h) {
     int gg[kVT], own[kVT];
@@ -148,9 +149,15 @@ __device__ __forceinline__ void gather_tile(const Params& p, const int* sl, int 
             if (fv) u[i] = fv[j0 + lo];
             const int idx = sl[kSlice + lo] + (g - sl[lo]);
             if ((unsigned)idx < (unsigned)p.m) {
-                v[i] = __builtin_nontemporal_load(p.cols + idx);
-                if (p.colsh) h[i] = __builtin_nontemporal_load(p.colsh + idx);
-                if ((unsigned)v[i] >= (unsigned)p.n) v[i] = -1;
+                // with the hot filter one stream holds both: a target id, or -1 - its
+                // hot number, whose id is looked up only if the hot bits leave it open
+                const int x = __builtin_nontemporal_load((p.colx ? p.colx : p.cols) + idx);
+                if (x >= 0) {
+                    v[i] = x < p.n ? x : -1;
+                } else if (p.colx && -1 - x < p.hot_words * 32) {
+                    h[i] = -1 - x;
+                    v[i] = kHotTarget;
+                }
             } else {
                 flag_internal(p.ctrl);
             }
@@ -195,8 +202,7 @@ __device__ void expand_share(const Params& p, int l, int b, int P, int ntiles, i
         if (threadIdx.x == 0) p.cnt[b] = 0;
         return;
     }
-    const bool use_hot = hcur && te - tb >= kHotMinTiles;
-    const int hot_bits = p.hot_words * 32;
+    const bool use_hot = hcur && te - tb >= kHotMinTiles;  // LDS copy of the hot bits, else read in place
     uint32_t* s_hot = reinterpret_cast<uint32_t*>(lds + 4 * kSlice);
     const int par = l & 1;
     const int32_t* tst = p.tstart[par];
@@ -258,8 +264,10 @@ __device__ void expand_share(const Params& p, int l, int b, int P, int ntiles, i
         bool fresh[kVT];
 #pragma unroll
         for (int i = 0; i < kVT; ++i) {
-            if ((unsigned)hc[i] >= (unsigned)hot_bits) hc[i] = -1;
-            if (vc[i] >= 0 && use_hot && hc[i] >= 0 && ((s_hot[hc[i] >> 5] >> (hc[i] & 31)) & 1u)) vc[i] = -1;
+            if (hc[i] >= 0) {
+                const uint32_t w = use_hot ? s_hot[hc[i] >> 5] : hcur[hc[i] >> 5];
+                vc[i] = ((w >> (hc[i] & 31)) & 1u) ? -1 : p.hot_vid[hc[i]];
+            }
         }
 #pragma unroll
         for (int i = 0; i < kVT; ++i)
@@ -1169,18 +1177,21 @@ static int fill_grid(int64_t items) {
     return (int)g;
 }
 
-// Graph set-up for the hot-vertex filter: colsh[e] = hidx[cols[e]].
-__global__ void k_hot_gather(const int32_t* cols, int64_t m, const int32_t* hidx, int32_t* colsh, int32_t n) {
+// Graph set-up for the hot-vertex filter: colx[e] = cols[e], or -1 - its hot
+// number for a hot target (INT32_MIN for a target outside [0, n)).
+__global__ void k_hot_gather(const int32_t* cols, int64_t m, const int32_t* hidx, int32_t* colx, int32_t n) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += stride) {
         const int32_t v = cols[e];
-        colsh[e] = (unsigned)v < (unsigned)n ? hidx[v] : -1;
+        int32_t x = INT32_MIN;
+        if ((unsigned)v < (unsigned)n) x = hidx[v] >= 0 ? -1 - hidx[v] : v;
+        colx[e] = x;
     }
 }
 
-hipError_t launch_hot_gather(const int32_t* cols, int64_t m, const int32_t* hidx, int32_t* colsh, int32_t n,
+hipError_t launch_hot_gather(const int32_t* cols, int64_t m, const int32_t* hidx, int32_t* colx, int32_t n,
                              hipStream_t s) {
-    if (m > 0) hipLaunchKernelGGL(k_hot_gather, dim3(fill_grid(m)), dim3(kBlock), 0, s, cols, m, hidx, colsh, n);
+    if (m > 0) hipLaunchKernelGGL(k_hot_gather, dim3(fill_grid(m)), dim3(kBlock), 0, s, cols, m, hidx, colx, n);
     return hipGetLastError();
 }
 

@@ -23,10 +23,12 @@ def rmat18():
 def test_size_rule_builds_filter(rmat18):
     g, G, lean = rmat18
     assert g.m >= 1 << 22
-    assert G.aux_bytes == 4 * g.m and lean.aux_bytes == 0
+    # one word per edge, plus the id of each hot vertex (all of degree >= 1 here)
+    hot = lambda h: min(1 << 18, int((np.diff(h.offsets) > 0).sum()))
+    assert G.aux_bytes == 4 * (g.m + hot(g)) and lean.aux_bytes == 0
     small = gg.rmat(10, seed=1)
     assert Graph(small.offsets, small.cols).aux_bytes == 0
-    assert Graph(small.offsets, small.cols, hot=True).aux_bytes == 4 * small.m
+    assert Graph(small.offsets, small.cols, hot=True).aux_bytes == 4 * (small.m + hot(small))
 
 
 @pytest.mark.parametrize("mode", [BFS_MODE_AUTO, BFS_MODE_LEVEL, BFS_MODE_INSENSITIVE])
