@@ -329,6 +329,7 @@ bfs_status_t run_common(bfs_workspace_s* ws, const int32_t* roots_host, int32_t 
         st = run_plain_mode(ws, p, s);
     } else {
         if (mode == BFS_MODE_INSENSITIVE) p.small_edges = 0;
+        p.fb_pull = !p.direction && p.parent != nullptr;
         const int grid = grid_for(ws);
         const int rtiles = (p.nroots + kGrain - 1) / kGrain;
         HIP_TRY(launch_prep(p, std::min(rtiles, grid), p.parent != nullptr, s));

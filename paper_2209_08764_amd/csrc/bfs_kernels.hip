@@ -69,26 +69,32 @@ __device__ __forceinline__ void share_range(int b, int P, int ntiles, int* tb, i
 //        the minima does not matter;
 //  pull  (large levels, where new vertices have many level-l neighbours)
 //        once level l + 1 is final, v's sorted row is read until the first
-//        neighbour at level l.  A lane tests kPullScan neighbours; longer
-//        rows go to the whole workgroup (first_parent_wg).
+//        neighbour at level l: level[c] == l, or its bit in the frontier
+//        bits of level l where the persistent loop keeps them exact.  A lane
+//        tests kPullScan neighbours; longer rows go to the whole workgroup
+//        (first_parent_wg).
 __device__ __forceinline__ void parent_push(const Params& p, int v, int u) {
     __hip_atomic_fetch_min(reinterpret_cast<unsigned*>(p.parent) + v, (unsigned)u, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
 }
 
+__device__ __forceinline__ bool frontier_bit(const uint32_t* fb, int c) { return (fb[c >> 5] >> (c & 31)) & 1u; }
+
 // First neighbour at level l among the first kPullScan of the row, -2 if
 // none there but the row is longer, -1 if the row has none at all.
-__device__ __forceinline__ int first_parent_lane(const Params& p, int rs, int d, int l) {
+__device__ __forceinline__ int first_parent_lane(const Params& p, int rs, int d, int l, const uint32_t* fb) {
     const int end = rs + min(d, kPullScan);
     for (int e = rs; e < end; e += 4) {
-        int c[4], lv[4];
+        int c[4];
+        bool hit[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) c[q] = e + q < end ? p.cols[e + q] : -1;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) lv[q] = (unsigned)c[q] < (unsigned)p.n ? p.level[c[q]] : -2;
+        for (int q = 0; q < 4; ++q)
+            hit[q] = (unsigned)c[q] < (unsigned)p.n && (fb ? frontier_bit(fb, c[q]) : p.level[c[q]] == l);
 #pragma unroll
         for (int q = 0; q < 4; ++q)
-            if (lv[q] == l) return c[q];
+            if (hit[q]) return c[q];
     }
     return d > kPullScan ? -2 : -1;
 }
@@ -121,11 +127,10 @@ __device__ __forceinline__ int first_hit_wg(const Params& p, int rs, int d, Hit 
     return -1;
 }
 
-__device__ int first_parent_wg(const Params& p, int rs, int d, int l, int* s_red) {
+__device__ int first_parent_wg(const Params& p, int rs, int d, int l, const uint32_t* fb, int* s_red) {
+    if (fb) return first_hit_wg(p, rs, d, [&](int c) { return frontier_bit(fb, c); }, s_red);
     return first_hit_wg(p, rs, d, [&](int c) { return p.level[c] == l; }, s_red);
 }
-
-__device__ __forceinline__ bool frontier_bit(const uint32_t* fb, int c) { return (fb[c >> 5] >> (c & 31)) & 1u; }
 
 // Reads the neighbours of this lane's kVT edges among [g0, g1) of the
 // current frontier, whose entries [j0, j0 + nv) are staged in `sl`
@@ -376,7 +381,7 @@ __device__ void expand_share(const Params& p, int l, int b, int P, int ntiles, i
 // the survivors to the next frontier with their exclusive degree sums and
 // the start points of the next level's sub-tiles.  l = -1 compacts the roots.
 __device__ bool compact_share(const Params& p, int l, int b, int P, int ntiles, bool pull_parents, bool set_bits,
-                              int* lds, bool after_bottom_up = false) {
+                              int* lds, bool after_bottom_up = false, const uint32_t* fpull = nullptr) {
     int* s_wave = lds_wave(lds);
     int* s_wave2 = lds_wave2(lds);
     int* s_b = lds_misc(lds);
@@ -419,7 +424,8 @@ __device__ bool compact_share(const Params& p, int l, int b, int P, int ntiles, 
                 if (set_bits)  // roots and push levels; pull levels set bits at discovery
                     __hip_atomic_fetch_or(&p.bitmap[v[i] >> 5], 1u << (v[i] & 31), __ATOMIC_RELAXED,
                                           __HIP_MEMORY_SCOPE_AGENT);
-                if (p.direction && d[i] > 0 && !after_bottom_up)  // frontier bits of level l + 1 for a bottom-up step
+                // frontier bits of level l + 1, for a bottom-up step or the next level's pulls
+                if ((p.direction || p.fb_pull) && d[i] > 0 && !after_bottom_up)
                     __hip_atomic_fetch_or(&p.fbits[np][v[i] >> 5], 1u << (v[i] & 31), __ATOMIC_RELAXED,
                                           __HIP_MEMORY_SCOPE_AGENT);
                 if (d[i] > 0) { ++tc; ts += d[i]; }
@@ -493,7 +499,7 @@ __device__ bool compact_share(const Params& p, int l, int b, int P, int ntiles, 
 #pragma unroll
             for (int i = 0; i < kVT; ++i) {
                 if (v[i] >= 0) {
-                    const int f = first_parent_lane(p, rs[i], d[i], l);
+                    const int f = first_parent_lane(p, rs[i], d[i], l, fpull);
                     if (f == -2) {
                         const int h = atomicAdd(s_nh, 1);
                         s_hard[3 * h] = v[i];
@@ -508,7 +514,7 @@ __device__ bool compact_share(const Params& p, int l, int b, int P, int ntiles, 
             const int nh = *s_nh;
             for (int h = 0; h < nh; ++h) {
                 const int hv = s_hard[3 * h], hrs = s_hard[3 * h + 1], hd = s_hard[3 * h + 2];
-                const int f = first_parent_wg(p, hrs, hd, l, s_red);
+                const int f = first_parent_wg(p, hrs, hd, l, fpull, s_red);
                 if (threadIdx.x == 0) p.parent[hv] = f;
             }
             lds_barrier();
@@ -887,7 +893,7 @@ __global__ void __launch_bounds__(kBlock) k_prep(Params p, int prep_shares, int 
     const int64_t words = ((int64_t)p.n + 31) >> 5;
     for (int64_t w = tid; w < words; w += stride) p.bitmap[w] = 0u;
     for (int64_t w = tid; w < p.hot_words; w += stride) p.hot[0][w] = p.hot[1][w] = 0u;
-    if (p.direction)
+    if (p.direction || p.fb_pull)
         for (int64_t w = tid; w < words; w += stride) p.fbits[0][w] = p.fbits[1][w] = 0u;
     for (int64_t t = tid; t < prep_shares; t += stride) p.desc[1][t] = 0ull;
     constexpr int64_t xwords = sizeof(XBar) / sizeof(unsigned long long);
@@ -1019,11 +1025,13 @@ k_persistent(Params p) {
             if (bottom_up) c->bu_levels += 1;
         }
         for (int t = blockIdx.x * kBlock + threadIdx.x; t < P; t += G * kBlock) p.desc[par][t] = 0ull;
-        // Frontier bits: fbits[np] is zero when a level starts (its own level cleared it
-        // after reading it), except right after a stretch of single-workgroup levels,
-        // which keep none; that level runs top-down, so nothing writes fbits[np] before
-        // its compaction and it can be cleared now.
-        if (DIR && !fbits_ok)
+        // Frontier bits.  Direction mode: fbits[np] is zero when a level starts (its own
+        // level cleared it after reading it), except right after a stretch of
+        // single-workgroup levels, which keep none; that level runs top-down, so nothing
+        // writes fbits[np] before its compaction and it can be cleared now.  Top-down
+        // loop: the previous level's pulls were the last readers of fbits[np], and this
+        // level's compaction is its first writer.
+        if ((DIR && !fbits_ok) || (!DIR && p.fb_pull))
             for (int w = blockIdx.x * kBlock + threadIdx.x; w < fwords; w += G * kBlock) p.fbits[np][w] = 0u;
         if (DIR && bottom_up) {
             if (blockIdx.x < P) bottom_up_share(p, l, blockIdx.x, P, ntiles, lds);
@@ -1066,7 +1074,10 @@ k_persistent(Params p) {
             }
         } else if (blockIdx.x < P) {
             const bool push = p.parent && e_l <= p.push_edges;
-            [[clang::always_inline]] ok = compact_share(p, l, blockIdx.x, P, ntiles, !push, push, lds);
+            // pulls test the frontier bits of level l (2 MiB for 2^24 vertices) instead of the
+            // level array when they are exact: not right after single-workgroup levels
+            const uint32_t* fpull = (!DIR && p.fb_pull && fbits_ok) ? p.fbits[par] : nullptr;
+            [[clang::always_inline]] ok = compact_share(p, l, blockIdx.x, P, ntiles, !push, push, lds, false, fpull);
             if (!ok) return;
         }
         fbits_ok = true;
