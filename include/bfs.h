@@ -84,6 +84,10 @@ typedef struct bfs_workspace_s* bfs_workspace_t;  /* scratch for one in-flight r
                                   (default 14) */
 #define BFS_OPT_BU_BETA    11  /* BFS_MODE_DIRECTION: bottom-up stops once the frontier holds
                                   fewer than n / beta vertices (default 24) */
+#define BFS_OPT_DENSE_EDGES 12 /* BFS_MODE_AUTO / INSENSITIVE: a level that pulls its parents (or
+                                  has none to find) and scans at least this many edges records its
+                                  new vertices as bits instead of private-queue entries and
+                                  linearises them in vertex order (0 = never; default m / 8) */
 
 typedef struct {
     int32_t levels;          /* frontiers processed: max level + 1 */
@@ -229,13 +233,14 @@ typedef struct {
     int32_t grid;          /* BFS_OPT_GRID (0 = fill the GPU) */
     int32_t small_edges;   /* BFS_OPT_SMALL_EDGES */
     int32_t push_edges;    /* BFS_OPT_PUSH_EDGES */
+    int32_t dense_edges;   /* BFS_OPT_DENSE_EDGES */
     int32_t trials;        /* configurations timed by the last bfs_autotune */
     double  default_ms;    /* one pass over the sample with the settings the call started from */
     double  best_ms;       /* one pass over the sample with the chosen settings */
 } bfs_tune_t;
 
 #define BFS_TUNE_BATCH  1u  /* tune the batched launch: grain, update tile, pull threshold, replay length */
-#define BFS_TUNE_SINGLE 2u  /* tune single-source runs: grid, single-workgroup and push thresholds */
+#define BFS_TUNE_SINGLE 2u  /* tune single-source runs: grid, single-workgroup, push and dense thresholds */
 
 /*
  * Times candidate settings on the workspace's own graph and keeps the

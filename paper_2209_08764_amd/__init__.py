@@ -14,7 +14,7 @@ import numpy as np
 
 from . import _lib
 from ._lib import (BFS_DEVICE_PTRS, BFS_HOST_PTRS, BFS_HOT_FILTER, BFS_LEAN, BFS_MODE_AUTO, BFS_MODE_DIRECTION,
-                   BFS_MODE_INSENSITIVE, BFS_MODE_LEVEL, BFS_OPT_BU_ALPHA, BFS_OPT_BU_BETA,
+                   BFS_MODE_INSENSITIVE, BFS_MODE_LEVEL, BFS_OPT_BU_ALPHA, BFS_OPT_BU_BETA, BFS_OPT_DENSE_EDGES,
                    BFS_MODE_PLAIN, BFS_OPT_BATCH_GRAIN, BFS_OPT_BATCH_LEVELS, BFS_OPT_BATCH_PULL, BFS_OPT_BATCH_TILE,
                    BFS_OPT_GRID, BFS_OPT_MODE, BFS_OPT_PROFILE, BFS_OPT_PUSH_EDGES, BFS_OPT_SMALL_EDGES,
                    BFS_TUNE_BATCH, BFS_TUNE_SINGLE, BFS_VALIDATE, BFSError, bfs_stats_t, bfs_tune_t)
@@ -26,7 +26,7 @@ __all__ = [
     "bfs_prim_compact",
     "bfs_prim_grain", "bfs_probe_rate_kernel", "bfs_autotune", "bfs_workspace_get_tuning", "Graph", "Workspace", "BFSError",
     "BFS_MODE_AUTO", "BFS_MODE_LEVEL", "BFS_MODE_PLAIN", "BFS_MODE_INSENSITIVE", "BFS_MODE_DIRECTION",
-    "BFS_OPT_BU_ALPHA", "BFS_OPT_BU_BETA", "BFS_OPT_MODE",
+    "BFS_OPT_BU_ALPHA", "BFS_OPT_BU_BETA", "BFS_OPT_DENSE_EDGES", "BFS_OPT_MODE",
     "BFS_OPT_SMALL_EDGES", "BFS_OPT_GRID", "BFS_OPT_PROFILE", "BFS_OPT_BATCH_PULL", "BFS_OPT_PUSH_EDGES", "BFS_OPT_BATCH_LEVELS",
     "BFS_OPT_BATCH_GRAIN", "BFS_OPT_BATCH_TILE", "BFS_TUNE_BATCH", "BFS_TUNE_SINGLE", "BFS_HOST_PTRS",
     "BFS_DEVICE_PTRS", "BFS_VALIDATE", "BFS_HOT_FILTER", "BFS_LEAN",
@@ -259,7 +259,8 @@ class Workspace:
         names = {"small_edges": BFS_OPT_SMALL_EDGES, "grid": BFS_OPT_GRID, "profile": BFS_OPT_PROFILE,
                  "batch_pull": BFS_OPT_BATCH_PULL, "push_edges": BFS_OPT_PUSH_EDGES,
                  "batch_levels": BFS_OPT_BATCH_LEVELS, "batch_grain": BFS_OPT_BATCH_GRAIN,
-                 "batch_tile": BFS_OPT_BATCH_TILE, "bu_alpha": BFS_OPT_BU_ALPHA, "bu_beta": BFS_OPT_BU_BETA}
+                 "batch_tile": BFS_OPT_BATCH_TILE, "bu_alpha": BFS_OPT_BU_ALPHA, "bu_beta": BFS_OPT_BU_BETA,
+                 "dense_edges": BFS_OPT_DENSE_EDGES}
         for k, v in opts.items():
             bfs_workspace_set_option(self.handle, names[k], v)
 

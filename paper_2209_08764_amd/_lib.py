@@ -45,6 +45,7 @@ BFS_OPT_BATCH_GRAIN = 8
 BFS_OPT_BATCH_TILE = 9
 BFS_OPT_BU_ALPHA = 10
 BFS_OPT_BU_BETA = 11
+BFS_OPT_DENSE_EDGES = 12
 
 BFS_TUNE_BATCH = 1
 BFS_TUNE_SINGLE = 2
@@ -77,6 +78,7 @@ class bfs_tune_t(ctypes.Structure):
         ("grid", ctypes.c_int32),
         ("small_edges", ctypes.c_int32),
         ("push_edges", ctypes.c_int32),
+        ("dense_edges", ctypes.c_int32),
         ("trials", ctypes.c_int32),
         ("default_ms", ctypes.c_double),
         ("best_ms", ctypes.c_double),

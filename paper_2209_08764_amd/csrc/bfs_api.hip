@@ -121,6 +121,7 @@ struct bfs_workspace_s {
     int32_t bu_alpha = 14;
     int32_t bu_beta = 24;
     int32_t push_edges = -1;  // -1: m / 8 of the workspace's graph
+    int32_t dense_edges = -1; // -1: m / 8 of the workspace's graph
     int32_t grid_opt = 0;
     int32_t profile = 0;
     int32_t batch_pull = -2;  // -2: library default
@@ -154,6 +155,10 @@ bfs_status_t validate_csr(const int32_t* off, const int32_t* cols, int32_t n, in
                 return fail(BFS_EBADCSR, "edge (%d,%d) has no reverse: graph is not symmetric", u, v);
         }
     return BFS_OK;
+}
+
+int32_t dense_edges_of(const bfs_workspace_s* ws) {
+    return ws->dense_edges >= 0 ? ws->dense_edges : (int32_t)std::min<int64_t>(std::max<int64_t>(ws->g->m / 8, 1), INT32_MAX);
 }
 
 Params make_params(bfs_workspace_s* ws, int32_t* level, int32_t* parent) {
@@ -330,6 +335,7 @@ bfs_status_t run_common(bfs_workspace_s* ws, const int32_t* roots_host, int32_t 
     } else {
         if (mode == BFS_MODE_INSENSITIVE) p.small_edges = 0;
         p.fb_pull = !p.direction && p.parent != nullptr;
+        p.dense_edges = p.direction ? 0 : dense_edges_of(ws);
         const int grid = grid_for(ws);
         const int rtiles = (p.nroots + kGrain - 1) / kGrain;
         HIP_TRY(launch_prep(p, std::min(rtiles, grid), p.parent != nullptr, s));
@@ -814,6 +820,10 @@ bfs_status_t bfs_workspace_set_option(bfs_workspace_t ws, int32_t option, int64_
             if (value < 0 || value > INT32_MAX) return fail(BFS_EINVAL, "bad push threshold");
             ws->push_edges = (int32_t)value;
             return BFS_OK;
+        case BFS_OPT_DENSE_EDGES:
+            if (value < 0 || value > INT32_MAX) return fail(BFS_EINVAL, "bad dense threshold");
+            ws->dense_edges = (int32_t)value;
+            return BFS_OK;
         case BFS_OPT_BATCH_LEVELS: {
             if (value < 1 || value > 256) return fail(BFS_EINVAL, "levels per replay must be in [1, 256]");
             if (bfs_status_t q = quiesce(ws)) return q;
@@ -1073,6 +1083,7 @@ void current_tuning(const bfs_workspace_s* ws, bfs_tune_t* t) {
     t->grid = ws->grid_opt;
     t->small_edges = ws->small_edges;
     t->push_edges = ws->push_edges >= 0 ? ws->push_edges : (int32_t)std::min<int64_t>(ws->g->m / 8, INT32_MAX);
+    t->dense_edges = dense_edges_of(ws);
 }
 
 // Timed passes over the tuning sample with the workspace's current settings.
@@ -1205,6 +1216,11 @@ bfs_status_t bfs_autotune(bfs_workspace_t ws, const int32_t* sources, int32_t k,
         if (!st)
             st = descend(smp, &best, pushes, P{start.push_edges, 0},
                          [&](P c) { return bfs_workspace_set_option(ws, BFS_OPT_PUSH_EDGES, c.first); });
+        std::vector<P> denses{{0, 0}};
+        for (int64_t d : {16, 8, 4}) denses.push_back({std::min<int64_t>(std::max<int64_t>(m / d, 1), INT32_MAX), 0});
+        if (!st)
+            st = descend(smp, &best, denses, P{start.dense_edges, 0},
+                         [&](P c) { return bfs_workspace_set_option(ws, BFS_OPT_DENSE_EDGES, c.first); });
     }
     ws->mode = saved_mode;
     ws->profile = saved_profile;

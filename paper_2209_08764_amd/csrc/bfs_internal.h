@@ -109,6 +109,8 @@ struct Params {
     uint32_t* fbits[2];       // frontier bits: exactly the level-l vertices of degree >= 1 in fbits[l & 1]
     int32_t direction;        // 1: levels may run bottom-up
     int32_t fb_pull;          // top-down persistent loop: keep frontier bits, pull parents against them
+    int32_t dense_edges;      // top-down persistent loop: pull levels with at least this many edges keep
+                              // the new frontier as bits (0: never)
     int32_t bu_alpha;         // go bottom-up when e_l * alpha > edges of unreached vertices
     int32_t bu_beta;          // return top-down when n_l * beta < n
     int32_t max_tiles;

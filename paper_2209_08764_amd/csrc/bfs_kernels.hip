@@ -127,7 +127,7 @@ __device__ __forceinline__ int first_hit_wg(const Params& p, int rs, int d, Hit 
     return -1;
 }
 
-__device__ int first_parent_wg(const Params& p, int rs, int d, int l, const uint32_t* fb, int* s_red) {
+__device__ __forceinline__ int first_parent_wg(const Params& p, int rs, int d, int l, const uint32_t* fb, int* s_red) {
     if (fb) return first_hit_wg(p, rs, d, [&](int c) { return frontier_bit(fb, c); }, s_red);
     return first_hit_wg(p, rs, d, [&](int c) { return p.level[c] == l; }, s_red);
 }
@@ -188,7 +188,8 @@ __device__ __forceinline__ void gather_tile(const Params& p, const int* sl, int 
 // hot targets there before the global bitmap; new hot vertices go to
 // hot[(l + 1) & 1], which the shares also merge hot[l & 1] into.  A set bit
 // still means "visited before this level", so results are unchanged.
-__device__ void expand_share(const Params& p, int l, int b, int P, int ntiles, int n_l, int e_l, int* lds) {
+__device__ void expand_share(const Params& p, int l, int b, int P, int ntiles, int n_l, int e_l, int* lds,
+                             bool dense = false) {
     int* s_wave = lds_wave(lds);
     uint32_t* hnext = nullptr;
     const uint32_t* hcur = nullptr;
@@ -308,37 +309,42 @@ __device__ void expand_share(const Params& p, int l, int b, int P, int ntiles, i
                 else
                     __hip_atomic_fetch_or(&p.bitmap[vc[i] >> 5], 1u << (vc[i] & 31), __ATOMIC_RELAXED,
                                           __HIP_MEMORY_SCOPE_AGENT);
+                if (dense)  // the new frontier is kept as bits, not queued
+                    __hip_atomic_fetch_or(&p.fbits[(l + 1) & 1][vc[i] >> 5], 1u << (vc[i] & 31), __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
                 if (hnext && hc[i] >= 0)
                     __hip_atomic_fetch_or(&hnext[hc[i] >> 5], 1u << (hc[i] & 31), __ATOMIC_RELAXED,
                                           __HIP_MEMORY_SCOPE_AGENT);
             }
         }
-        int slot[kVT];
-        int wt = 0;
+        if (!dense) {
+            int slot[kVT];
+            int wt = 0;
 #pragma unroll
-        for (int i = 0; i < kVT; ++i) {
-            const uint64_t bb = ballot(fresh[i]);
-            slot[i] = wt + mbcnt(bb);
-            wt += __popcll(bb);
-        }
-        if (lane_id() == 0) s_wave[wave_id()] = wt;
-        lds_barrier();
-        int wbase = 0, tot = 0;
-#pragma unroll
-        for (int w = 0; w < kWaves; ++w) {
-            const int x = s_wave[w];
-            wbase += (w < wave_id()) ? x : 0;
-            tot += x;
-        }
-#pragma unroll
-        for (int i = 0; i < kVT; ++i) {
-            if (fresh[i]) {
-                const int s = qbase + qn + wbase + slot[i];
-                p.owner[vc[i]] = s;
-                p.cand[s] = vc[i];
+            for (int i = 0; i < kVT; ++i) {
+                const uint64_t bb = ballot(fresh[i]);
+                slot[i] = wt + mbcnt(bb);
+                wt += __popcll(bb);
             }
+            if (lane_id() == 0) s_wave[wave_id()] = wt;
+            lds_barrier();
+            int wbase = 0, tot = 0;
+#pragma unroll
+            for (int w = 0; w < kWaves; ++w) {
+                const int x = s_wave[w];
+                wbase += (w < wave_id()) ? x : 0;
+                tot += x;
+            }
+#pragma unroll
+            for (int i = 0; i < kVT; ++i) {
+                if (fresh[i]) {
+                    const int s = qbase + qn + wbase + slot[i];
+                    p.owner[vc[i]] = s;
+                    p.cand[s] = vc[i];
+                }
+            }
+            qn += tot;
         }
-        qn += tot;
         // publish the slice of sub-tile t + 2 (the buffer of sub-tile t is free)
         if (has2) {
             if (!ok2) {
@@ -367,6 +373,40 @@ __device__ void expand_share(const Params& p, int l, int b, int P, int ntiles, i
     if (threadIdx.x == 0) {
         if (bad) flag_internal(p.ctrl);
         p.cnt[b] = qn;
+    }
+    lds_barrier();
+}
+
+// Pulls the parents of one chunk's new vertices (kVT per thread, v = -1 for
+// none).  Rows whose first kPullScan neighbours hold no parent go to the
+// whole workgroup.  Uses the LDS slice buffers; called by the whole workgroup.
+__device__ __forceinline__ void pull_parents_chunk(const Params& p, const int* v, const int* rs, const int* d, int l,
+                                                   const uint32_t* fpull, int* lds) {
+    int* s_hard = lds;                // (v, rs, d) triples
+    int* s_red = lds + 3 * kGrain;    // kWaves + 1 ints
+    int* s_nh = s_red + kWaves + 1;
+    if (threadIdx.x == 0) *s_nh = 0;
+    lds_barrier();
+#pragma unroll
+    for (int i = 0; i < kVT; ++i) {
+        if (v[i] >= 0) {
+            const int f = first_parent_lane(p, rs[i], d[i], l, fpull);
+            if (f == -2) {
+                const int h = atomicAdd(s_nh, 1);
+                s_hard[3 * h] = v[i];
+                s_hard[3 * h + 1] = rs[i];
+                s_hard[3 * h + 2] = d[i];
+            } else {
+                p.parent[v[i]] = f;
+            }
+        }
+    }
+    lds_barrier();
+    const int nh = *s_nh;
+    for (int h = 0; h < nh; ++h) {
+        const int hv = s_hard[3 * h], hrs = s_hard[3 * h + 1], hd = s_hard[3 * h + 2];
+        const int f = first_parent_wg(p, hrs, hd, l, fpull, s_red);
+        if (threadIdx.x == 0) p.parent[hv] = f;
     }
     lds_barrier();
 }
@@ -489,36 +529,7 @@ __device__ bool compact_share(const Params& p, int l, int b, int P, int ntiles, 
         int S;
         int e = ps + run_e + block_excl_scan(ts, s_wave, &S);
         int pos = pc + c0 + threadIdx.x * kVT;
-        if (pull) {
-            // rows whose first kPullScan neighbours hold no parent go to the whole workgroup
-            int* s_hard = lds;                // (v, rs, d) triples: the slice buffers are free now
-            int* s_red = lds + 3 * kGrain;    // kWaves + 1 ints
-            int* s_nh = s_red + kWaves + 1;
-            if (threadIdx.x == 0) *s_nh = 0;
-            lds_barrier();
-#pragma unroll
-            for (int i = 0; i < kVT; ++i) {
-                if (v[i] >= 0) {
-                    const int f = first_parent_lane(p, rs[i], d[i], l, fpull);
-                    if (f == -2) {
-                        const int h = atomicAdd(s_nh, 1);
-                        s_hard[3 * h] = v[i];
-                        s_hard[3 * h + 1] = rs[i];
-                        s_hard[3 * h + 2] = d[i];
-                    } else {
-                        p.parent[v[i]] = f;
-                    }
-                }
-            }
-            lds_barrier();
-            const int nh = *s_nh;
-            for (int h = 0; h < nh; ++h) {
-                const int hv = s_hard[3 * h], hrs = s_hard[3 * h + 1], hd = s_hard[3 * h + 2];
-                const int f = first_parent_wg(p, hrs, hd, l, fpull, s_red);
-                if (threadIdx.x == 0) p.parent[hv] = f;
-            }
-            lds_barrier();
-        }
+        if (pull) pull_parents_chunk(p, v, rs, d, l, fpull, lds);
 #pragma unroll
         for (int i = 0; i < kVT; ++i) {
             if (v[i] >= 0) {
@@ -537,6 +548,120 @@ __device__ bool compact_share(const Params& p, int l, int b, int P, int ntiles, 
         run_e += S;
     }
     return true;
+}
+
+// Compaction of a dense level.  There the expansion records each new vertex
+// by its bit in fbits[(l + 1) & 1] instead of appending it to a private
+// queue, so duplicates merge in the bitmap and the frontier comes out in
+// vertex order: the next level then reads its rows, and this level pulls its
+// parents, in the order they lie in memory.  Share b of P takes a range of
+// whole kGrain-vertex chunks.  Pass 1 writes level l + 1 of every new vertex
+// and counts the share's frontier entries (degree >= 1) and their edges; the
+// look-back over the shares gives their offsets (the Sizes prefix sum);
+// pass 2 writes the entries, the start points of the next level's sub-tiles
+// and the pulled parents.
+__device__ bool dense_compact_share(const Params& p, int l, int b, int P, int* lds, const uint32_t* fpull) {
+    int* s_wave = lds_wave(lds);
+    int* s_wave2 = lds_wave2(lds);
+    int* s_b = lds_misc(lds);
+    const int par = l & 1;
+    const int np = (l + 1) & 1;
+    const uint32_t* fb = p.fbits[np];
+    const int64_t chunks = ((int64_t)p.n + kGrain - 1) / kGrain;
+    const int v0 = (int)(chunks * b / P * kGrain);
+    const int v1 = (int)min((int64_t)p.n, chunks * (b + 1) / P * kGrain);
+    // pass 1: thread t takes the kVT consecutive vertices from base + t * kVT
+    int tc = 0, ts = 0, tr = 0;
+    for (int base = v0; base < v1; base += kGrain) {
+#pragma unroll
+        for (int i = 0; i < kVT; ++i) {
+            const int v = base + (int)threadIdx.x * kVT + i;
+            if (v < v1 && frontier_bit(fb, v)) {
+                p.level[v] = l + 1;
+                const int d = p.offsets[v + 1] - p.offsets[v];
+                ++tr;
+                if (d > 0) { ++tc; ts += d; }
+            }
+        }
+    }
+    int surv, degsum, raw;
+    block_excl_scan(tc, s_wave, &surv);
+    block_excl_scan(ts, s_wave2, &degsum);
+    block_excl_scan(tr, s_wave, &raw);
+    if (wave_id() == 0) {
+        int pc = 0, ps = 0;
+        const bool okw = lookback_wave(p.desc[par], b, surv, degsum, p.ctrl, p.spin_ticks, &pc, &ps);
+        if (threadIdx.x == 0) {
+            s_b[0] = pc;
+            s_b[1] = ps;
+            s_b[2] = okw;
+            if (raw) __hip_atomic_fetch_add(&p.ctrl->kept[np], raw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (okw && b == P - 1) {
+                st_rel(&p.ctrl->nl[np], pc + surv);
+                st_rel(&p.ctrl->el[np], ps + degsum);
+                if (pc + surv <= p.n) p.f_ex[np][pc + surv] = ps + degsum;
+                else flag_internal(p.ctrl);
+            }
+        }
+    }
+    __syncthreads();
+    const int pc = s_b[0], ps = s_b[1];
+    const bool ok = s_b[2] != 0;
+    lds_barrier();
+    if (!ok) return false;
+    // pass 2: the same vertices in the same order
+    const bool pull = p.parent != nullptr;
+    int run_c = 0, run_e = 0;
+    for (int base = v0; base < v1; base += kGrain) {
+        int v[kVT], rs[kVT], d[kVT];
+        int cc = 0, cs = 0;
+#pragma unroll
+        for (int i = 0; i < kVT; ++i) {
+            const int vv = base + (int)threadIdx.x * kVT + i;
+            v[i] = -1;
+            rs[i] = d[i] = 0;
+            if (vv < v1 && frontier_bit(fb, vv)) {
+                const int r = p.offsets[vv];
+                const int dd = p.offsets[vv + 1] - r;
+                if (dd > 0) {
+                    v[i] = vv;
+                    rs[i] = r;
+                    d[i] = dd;
+                    ++cc;
+                    cs += dd;
+                }
+            }
+        }
+        int C, S;
+        int pos = pc + run_c + block_excl_scan(cc, s_wave, &C);
+        int e = ps + run_e + block_excl_scan(cs, s_wave2, &S);
+        if (pull) pull_parents_chunk(p, v, rs, d, l, fpull, lds);
+#pragma unroll
+        for (int i = 0; i < kVT; ++i) {
+            if (v[i] >= 0) {
+                if ((unsigned)pos < (unsigned)p.n) {
+                    p.f_v[np][pos] = v[i];
+                    p.f_rs[np][pos] = rs[i];
+                    p.f_ex[np][pos] = e;
+                    scatter_starts(p, p.tstart[np], pos, e, d[i]);
+                } else {
+                    flag_internal(p.ctrl);
+                }
+                e += d[i];
+                ++pos;
+            }
+        }
+        run_c += C;
+        run_e += S;
+    }
+    return true;
+}
+
+// Shares of a dense level's compaction: whole kGrain-vertex chunks, at most
+// one share per workgroup and per descriptor.
+__device__ __forceinline__ int dense_shares(const Params& p, int G) {
+    const int64_t chunks = ((int64_t)p.n + kGrain - 1) / kGrain;
+    return (int)min(min((int64_t)G, (int64_t)p.max_tiles), max(chunks, (int64_t)1));
 }
 
 // ---- bottom-up step (direction optimisation) ----------------------------------------------
@@ -893,7 +1018,7 @@ __global__ void __launch_bounds__(kBlock) k_prep(Params p, int prep_shares, int 
     const int64_t words = ((int64_t)p.n + 31) >> 5;
     for (int64_t w = tid; w < words; w += stride) p.bitmap[w] = 0u;
     for (int64_t w = tid; w < p.hot_words; w += stride) p.hot[0][w] = p.hot[1][w] = 0u;
-    if (p.direction || p.fb_pull)
+    if (p.direction || p.fb_pull || p.dense_edges > 0)
         for (int64_t w = tid; w < words; w += stride) p.fbits[0][w] = p.fbits[1][w] = 0u;
     for (int64_t t = tid; t < prep_shares; t += stride) p.desc[1][t] = 0ull;
     constexpr int64_t xwords = sizeof(XBar) / sizeof(unsigned long long);
@@ -953,11 +1078,7 @@ k_persistent(Params p) {
 
     const int rtiles = (p.nroots + kGrain - 1) / kGrain;
     const int Pr = shares_for(rtiles, G);
-    if constexpr (DIR) {
-        [[clang::always_inline]] roots_range(p, Pr, (int64_t)blockIdx.x * kBlock + threadIdx.x, (int64_t)G * kBlock);
-    } else {
-        roots_range(p, Pr, (int64_t)blockIdx.x * kBlock + threadIdx.x, (int64_t)G * kBlock);
-    }
+    [[clang::always_inline]] roots_range(p, Pr, (int64_t)blockIdx.x * kBlock + threadIdx.x, (int64_t)G * kBlock);
     // the first barrier is the flat one; it also counts the workgroups on each XCD
     XGroup xg{0, 1, 1};
     if (threadIdx.x == 0) xbar_join(p.xbar, xcd_id());
@@ -994,11 +1115,7 @@ k_persistent(Params p) {
         reached_edges += e_l;
         if (p.small_edges > 0 && n_l <= kSmallN && e_l <= p.small_edges) {
             if (blockIdx.x == 0) {
-                if constexpr (DIR) {
-                    [[clang::always_inline]] small_levels(p, l, n_l, e_l, lds);
-                } else {
-                    small_levels(p, l, n_l, e_l, lds);
-                }
+                [[clang::always_inline]] small_levels(p, l, n_l, e_l, lds);
             }
             if (!xcd_barrier(c, p.xbar, xg, p.spin_ticks, s_flag)) return;
             l = ld_acq(&c->resume);
@@ -1019,28 +1136,30 @@ k_persistent(Params p) {
         const int ntiles = bottom_up ? (p.n + kGrain - 1) / kGrain : (int)(((int64_t)e_l + kGrain - 1) / kGrain);
         const int P = shares_for(ntiles, G);  // P_l = min(P, W_l)
         const int np = (l + 1) & 1;
+        const bool push = p.parent && e_l <= p.push_edges;
+        // a dense level keeps its new frontier as bits and compacts it in vertex order
+        const bool dense = !DIR && !push && p.dense_edges > 0 && e_l >= p.dense_edges;
+        const int Pd = dense ? dense_shares(p, G) : 0;
         // reset this level's compaction state (last used two levels ago)
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             st_rel(&c->kept[np], 0);
             if (bottom_up) c->bu_levels += 1;
         }
-        for (int t = blockIdx.x * kBlock + threadIdx.x; t < P; t += G * kBlock) p.desc[par][t] = 0ull;
+        for (int t = blockIdx.x * kBlock + threadIdx.x; t < max(P, Pd); t += G * kBlock) p.desc[par][t] = 0ull;
         // Frontier bits.  Direction mode: fbits[np] is zero when a level starts (its own
         // level cleared it after reading it), except right after a stretch of
         // single-workgroup levels, which keep none; that level runs top-down, so nothing
         // writes fbits[np] before its compaction and it can be cleared now.  Top-down
         // loop: the previous level's pulls were the last readers of fbits[np], and this
-        // level's compaction is its first writer.
-        if ((DIR && !fbits_ok) || (!DIR && p.fb_pull))
+        // level's compaction is its first writer, or its expansion on a dense level, which
+        // therefore waits for the clearing at an extra barrier.
+        if ((DIR && !fbits_ok) || (!DIR && (p.fb_pull || dense)))
             for (int w = blockIdx.x * kBlock + threadIdx.x; w < fwords; w += G * kBlock) p.fbits[np][w] = 0u;
+        if (dense && !xcd_barrier(c, p.xbar, xg, p.spin_ticks, s_flag)) return;
         if (DIR && bottom_up) {
             if (blockIdx.x < P) bottom_up_share(p, l, blockIdx.x, P, ntiles, lds);
         } else if (blockIdx.x < P) {
-            if constexpr (DIR) {
-                [[clang::always_inline]] expand_share(p, l, blockIdx.x, P, ntiles, n_l, e_l, lds);
-            } else {
-                expand_share(p, l, blockIdx.x, P, ntiles, n_l, e_l, lds);
-            }
+            [[clang::always_inline]] expand_share(p, l, blockIdx.x, P, ntiles, n_l, e_l, lds, dense);
         }
         if (!xcd_barrier(c, p.xbar, xg, p.spin_ticks, s_flag)) return;
         if (rec) p.stat_ts[3 * l + 1] = now_ticks();
@@ -1072,12 +1191,16 @@ k_persistent(Params p) {
                 [[clang::always_inline]] ok = compact_share(p, l, blockIdx.x, P, ntiles, false, false, lds, true);
                 if (!ok) return;
             }
-        } else if (blockIdx.x < P) {
-            const bool push = p.parent && e_l <= p.push_edges;
+        } else {
             // pulls test the frontier bits of level l (2 MiB for 2^24 vertices) instead of the
             // level array when they are exact: not right after single-workgroup levels
             const uint32_t* fpull = (!DIR && p.fb_pull && fbits_ok) ? p.fbits[par] : nullptr;
-            [[clang::always_inline]] ok = compact_share(p, l, blockIdx.x, P, ntiles, !push, push, lds, false, fpull);
+            if (dense) {
+                if (blockIdx.x < Pd) [[clang::always_inline]] ok = dense_compact_share(p, l, blockIdx.x, Pd, lds, fpull);
+            } else if (blockIdx.x < P) {
+                [[clang::always_inline]] ok =
+                    compact_share(p, l, blockIdx.x, P, ntiles, !push, push, lds, false, fpull);
+            }
             if (!ok) return;
         }
         fbits_ok = true;

@@ -13,12 +13,13 @@ import json
 import os
 
 from . import (BFS_OPT_BATCH_GRAIN, BFS_OPT_BATCH_LEVELS, BFS_OPT_BATCH_PULL, BFS_OPT_BATCH_TILE, BFS_OPT_GRID,
-               BFS_OPT_PUSH_EDGES, BFS_OPT_SMALL_EDGES, BFS_TUNE_BATCH, BFS_TUNE_SINGLE, bfs_autotune,
+               BFS_OPT_DENSE_EDGES, BFS_OPT_PUSH_EDGES, BFS_OPT_SMALL_EDGES, BFS_TUNE_BATCH, BFS_TUNE_SINGLE, bfs_autotune,
                bfs_workspace_set_option)
 
 _BATCH_KEYS = {"batch_grain": BFS_OPT_BATCH_GRAIN, "batch_tile": BFS_OPT_BATCH_TILE,
                "batch_pull": BFS_OPT_BATCH_PULL, "batch_levels": BFS_OPT_BATCH_LEVELS}
-_SINGLE_KEYS = {"grid": BFS_OPT_GRID, "small_edges": BFS_OPT_SMALL_EDGES, "push_edges": BFS_OPT_PUSH_EDGES}
+_SINGLE_KEYS = {"grid": BFS_OPT_GRID, "small_edges": BFS_OPT_SMALL_EDGES, "push_edges": BFS_OPT_PUSH_EDGES,
+                "dense_edges": BFS_OPT_DENSE_EDGES}
 
 
 def graph_signature(graph) -> str:
