@@ -167,6 +167,7 @@ Params make_params(bfs_workspace_s* ws, int32_t* level, int32_t* parent) {
     p.cols = ws->g->cols;
     p.colx = ws->g->colx;
     p.hot_vid = ws->g->hot_vid;
+    p.hot_count = ws->g->colx ? ws->g->hot_count : 0;
     p.hot[0] = ws->hot[0];
     p.hot[1] = ws->hot[1];
     p.hot_words = ws->g->colx ? ws->g->hot_words : 0;

@@ -78,6 +78,7 @@ struct Params {
     const int32_t* hot_vid;   // vertex id of each hot number
     uint32_t* hot[2];         // visited bits of hot vertices: levels <= l in hot[l & 1]
     int32_t hot_words;        // words of each hot array (0: no filter)
+    int32_t hot_count;        // hot numbers in use (entries of hot_vid)
     int32_t n;
     int64_t m;
     // outputs (caller-owned)

@@ -132,39 +132,51 @@ __device__ __forceinline__ int first_parent_wg(const Params& p, int rs, int d, i
     return first_hit_wg(p, rs, d, [&](int c) { return p.level[c] == l; }, s_red);
 }
 
-// Reads the neighbours of this lane's kVT edges among [g0, g1) of the
-// current frontier, whose entries [j0, j0 + nv) are staged in `sl`
-// (ex | rs); -1 where there is no edge.  With `fv` also the frontier vertex
-// each edge comes from (for pushed parents).  With the hot-vertex filter a
-// hot target comes back as kHotTarget with its hot number in h (-1 for the
-// others); expand_share resolves its id once the hot bits leave it open.
-__device__ __forceinline__ void gather_tile(const Params& p, const int* sl, int nv, int g0, int g1, int* v,
-                                            const int32_t* fv, int j0, int* u, int* h) {
+// Issues the neighbour reads of this lane's kVT edges among [g0, g1) of the
+// current frontier, whose entries [j0, j0 + nv) are staged in `sl` (ex | rs):
+// raw words of the neighbour stream into x (decode_tile interprets them) and
+// bit i of *ok set where edge i exists; from `fsrc` also the frontier entry
+// each edge comes from (its vertex, for pushed parents).  Every load is
+// issued, from a clamped address where a lane has no edge, and nothing
+// reads its result here: the reads stay in flight while the previous
+// sub-tile is filtered, and the waits before that filtering can count them.
+__device__ __forceinline__ void gather_tile(const Params& p, const int* sl, int nv, int g0, int g1, int* x,
+                                            uint32_t* ok, const int32_t* fsrc, int j0, int* u) {
     int gg[kVT], own[kVT];
 #pragma unroll
     for (int i = 0; i < kVT; ++i) gg[i] = min(g0 + i * kBlock + (int)threadIdx.x, g1 - 1);
     search_owners<kVT>(sl, nv, gg, own);
+    const int32_t* src = p.colx ? p.colx : p.cols;
+    uint32_t m = 0;
 #pragma unroll
     for (int i = 0; i < kVT; ++i) {
         const int g = g0 + i * kBlock + threadIdx.x;
+        const int lo = own[i];
+        const int idx = sl[kSlice + lo] + (gg[i] - sl[lo]);
+        const bool in = (unsigned)idx < (unsigned)p.m;
+        if (g < g1 && in) m |= 1u << i;
+        if (g < g1 && !in) flag_internal(p.ctrl);
+        x[i] = __builtin_nontemporal_load(src + (in ? idx : 0));
+        u[i] = fsrc[j0 + lo];
+    }
+    *ok = m;
+}
+
+// Interprets the words gather_tile read: v = the target (-1: no edge, or a
+// target outside [0, n)); with the hot-vertex filter a hot target comes
+// back as kHotTarget with its hot number in h (-1 for the others), and
+// expand_share resolves its id once the hot bits leave it open.
+__device__ __forceinline__ void decode_tile(const Params& p, const int* x, uint32_t ok, int* v, int* h) {
+#pragma unroll
+    for (int i = 0; i < kVT; ++i) {
         v[i] = -1;
         h[i] = -1;
-        if (g < g1) {
-            const int lo = own[i];
-            if (fv) u[i] = fv[j0 + lo];
-            const int idx = sl[kSlice + lo] + (g - sl[lo]);
-            if ((unsigned)idx < (unsigned)p.m) {
-                // with the hot filter one stream holds both: a target id, or -1 - its
-                // hot number, whose id is looked up only if the hot bits leave it open
-                const int x = __builtin_nontemporal_load((p.colx ? p.colx : p.cols) + idx);
-                if (x >= 0) {
-                    v[i] = x < p.n ? x : -1;
-                } else if (p.colx && -1 - x < p.hot_words * 32) {
-                    h[i] = -1 - x;
-                    v[i] = kHotTarget;
-                }
-            } else {
-                flag_internal(p.ctrl);
+        if ((ok >> i) & 1u) {
+            if (x[i] >= 0) {
+                v[i] = x[i] < p.n ? x[i] : -1;
+            } else if (p.colx && -1 - x[i] < p.hot_count) {
+                h[i] = -1 - x[i];
+                v[i] = kHotTarget;
             }
         }
     }
@@ -238,13 +250,41 @@ __device__ void expand_share(const Params& p, int l, int b, int P, int ntiles, i
     if (use_hot)
         for (int w = threadIdx.x; w < p.hot_words; w += kBlock) s_hot[w] = hcur[w];
     lds_barrier();
-    int vc[kVT], uc[kVT], hc[kVT];
+    // raw neighbour words of the sub-tile to filter next, which of them are edges, and
+    // their frontier entries' vertices (read from f_ex where no parents are pushed)
+    const int32_t* fsrc = fvp ? fvp : fex;
+    int xc[kVT], uc[kVT];
+    uint32_t okc = 0u;
 #pragma unroll
-    for (int i = 0; i < kVT; ++i) vc[i] = uc[i] = hc[i] = -1;
-    if (!bad) gather_tile(p, buf0, z0 - a0 + 1, tb * kGrain, min(tb * kGrain + kGrain, e_l), vc, fvp, a0, uc, hc);
+    for (int i = 0; i < kVT; ++i) xc[i] = uc[i] = -1;
+    if (!bad) gather_tile(p, buf0, z0 - a0 + 1, tb * kGrain, min(tb * kGrain + kGrain, e_l), xc, &okc, fsrc, a0, uc);
     for (int t = tb; t < te && !bad; ++t) {
         int* cur1 = ((t + 1 - tb) & 1) ? buf1 : buf0;   // slice of sub-tile t + 1
         int* free2 = ((t - tb) & 1) ? buf1 : buf0;      // receives the slice of sub-tile t + 2
+        // Probes of sub-tile t go out before the reads for sub-tiles t + 1 and t + 2:
+        // reads return in issue order, so waiting for the probes then does not wait for
+        // the reads behind them.  Hot targets are tested against the LDS copy; one that
+        // passes is new to this level unless another edge found it first, which its
+        // bit in hnext tells (pull levels); its id comes from hot_vid.  The other
+        // targets are tested against the visited bitmap.
+        int vc[kVT], hc[kVT];
+        decode_tile(p, xc, okc, vc, hc);
+        const int32_t* hvid = p.hot_vid ? p.hot_vid : p.offsets;
+        uint32_t pw[kVT];
+        int hid[kVT];
+#pragma unroll
+        for (int i = 0; i < kVT; ++i) {
+            bool hot_open = false;
+            if (hc[i] >= 0) {
+                const uint32_t w = use_hot ? s_hot[hc[i] >> 5] : hcur[hc[i] >> 5];
+                hot_open = !((w >> (hc[i] & 31)) & 1u);
+                if (!hot_open) vc[i] = -1;
+            }
+            const uint32_t* pa = (hot_open && !fvp) ? hnext + (hc[i] >> 5) : p.bitmap + (max(vc[i], 0) >> 5);
+            pw[i] = *pa;
+            hid[i] = hvid[hot_open ? hc[i] : 0];
+            if (!hot_open) hc[i] = -1;
+        }
         // fetch the slice of sub-tile t + 2 into registers
         const bool has2 = t + 2 < te;
         const int a2 = z1, z2 = has2 ? slice_end(t + 2) : z1;
@@ -252,32 +292,28 @@ __device__ void expand_share(const Params& p, int l, int b, int P, int ntiles, i
         int pe[kPre], pr[kPre];
 #pragma unroll
         for (int r = 0; r < kPre; ++r) {
-            const int i = threadIdx.x + r * kBlock;
-            if (has2 && ok2 && i <= z2 - a2) {
-                pe[r] = fex[a2 + i];
-                pr[r] = frs[a2 + i];
-            }
+            const int j = min(max(a2 + (int)threadIdx.x + r * kBlock, 0), n_l - 1);
+            pe[r] = fex[j];
+            pr[r] = frs[j];
         }
         // issue the neighbour reads of sub-tile t + 1
-        int vn[kVT], un[kVT], hn[kVT];
+        int xn[kVT], un[kVT];
+        uint32_t okn = 0u;
 #pragma unroll
-        for (int i = 0; i < kVT; ++i) vn[i] = un[i] = hn[i] = -1;
+        for (int i = 0; i < kVT; ++i) xn[i] = un[i] = -1;
         if (t + 1 < te)
-            gather_tile(p, cur1, z1 - a1 + 1, (t + 1) * kGrain, min((t + 1) * kGrain + kGrain, e_l), vn, fvp, a1,
-                        un, hn);
-        // filter and append the neighbours of sub-tile t: hot targets against the
-        // LDS copy, then everything left against the global visited bitmap
+            gather_tile(p, cur1, z1 - a1 + 1, (t + 1) * kGrain, min((t + 1) * kGrain + kGrain, e_l), xn, &okn, fsrc,
+                        a1, un);
+        // decide sub-tile t
         bool fresh[kVT];
 #pragma unroll
         for (int i = 0; i < kVT; ++i) {
-            if (hc[i] >= 0) {
-                const uint32_t w = use_hot ? s_hot[hc[i] >> 5] : hcur[hc[i] >> 5];
-                vc[i] = ((w >> (hc[i] & 31)) & 1u) ? -1 : p.hot_vid[hc[i]];
-            }
+            const bool hot = hc[i] >= 0;
+            if (hot) vc[i] = hid[i];
+            // a push level tests an open hot target by its level below, like any other
+            const bool seen = hot ? !fvp && ((pw[i] >> (hc[i] & 31)) & 1u) : ((pw[i] >> (vc[i] & 31)) & 1u);
+            if (vc[i] >= 0 && seen) vc[i] = -1;
         }
-#pragma unroll
-        for (int i = 0; i < kVT; ++i)
-            if (vc[i] >= 0 && ((p.bitmap[vc[i] >> 5] >> (vc[i] & 31)) & 1u)) vc[i] = -1;
         if (fvp) {
             // push level: every edge into an unsettled vertex offers its source as parent
 #pragma unroll
@@ -364,10 +400,10 @@ __device__ void expand_share(const Params& p, int l, int b, int P, int ntiles, i
         z1 = z2;
 #pragma unroll
         for (int i = 0; i < kVT; ++i) {
-            vc[i] = vn[i];
+            xc[i] = xn[i];
             uc[i] = un[i];
-            hc[i] = hn[i];
         }
+        okc = okn;
         lds_barrier();
     }
     if (threadIdx.x == 0) {
@@ -1058,6 +1094,23 @@ __device__ void roots_range(const Params& p, int P, int64_t first, int64_t strid
     }
 }
 
+// hot[w] bit j = visited bit of the vertex with hot number 32 w + j (0 past
+// hot_count), 64 hot numbers per wave step: the hot bits of levels <= l when
+// the visited bitmap holds exactly the vertices of levels <= l.
+__device__ __forceinline__ void rebuild_hot_bits(const Params& p, uint32_t* hot, int64_t first, int64_t stride) {
+    const int64_t nh = (int64_t)p.hot_words * 32;
+    for (int64_t h0 = first - lane_id(); h0 < nh; h0 += stride) {  // wave-uniform base, a multiple of 64
+        const int64_t h = h0 + lane_id();
+        bool bit = false;
+        if (h < p.hot_count) {
+            const int v = p.hot_vid[h];
+            bit = (unsigned)v < (unsigned)p.n && ((p.bitmap[v >> 5] >> (v & 31)) & 1u);
+        }
+        const uint64_t bb = ballot(bit);
+        if ((lane_id() & 31) == 0 && h < nh) hot[h >> 5] = (uint32_t)(bb >> (lane_id() & 32));
+    }
+}
+
 __device__ __forceinline__ int shares_for(int ntiles, int G) { return ntiles < G ? ntiles : G; }
 
 // Register budget of the persistent kernel: its occupancy (workgroups per
@@ -1101,6 +1154,9 @@ k_persistent(Params p) {
     // direction optimisation: fbits[l & 1] is exact when level l - 1 went through
     // compact_share (the roots do); edges of vertices reached so far, for the switch rule
     bool fbits_ok = true, bottom_up = false;
+    // hot[l & 1] holds exactly the hot vertices visited up to level l: the expansion keeps
+    // it so once it is, but the roots and single-workgroup levels set no hot bits
+    bool hot_ok = false;
     int64_t reached_edges = 0;
     const int fwords = (p.n + 31) >> 5;
     for (;;) {
@@ -1122,7 +1178,8 @@ k_persistent(Params p) {
             n_l = ld_acq(&c->r_nl);
             e_l = ld_acq(&c->r_el);
             kept = ld_acq(&c->r_kept);
-            fbits_ok = false;  // levels run out of LDS keep no frontier bits
+            fbits_ok = false;  // levels run out of LDS keep no frontier or hot bits
+            hot_ok = false;
             bottom_up = false;
             continue;
         }
@@ -1155,6 +1212,13 @@ k_persistent(Params p) {
         // therefore waits for the clearing at an extra barrier.
         if ((DIR && !fbits_ok) || (!DIR && (p.fb_pull || dense)))
             for (int w = blockIdx.x * kBlock + threadIdx.x; w < fwords; w += G * kBlock) p.fbits[np][w] = 0u;
+        // A dense level's compaction takes every bit its expansion sets as a new vertex,
+        // and that expansion drops a hot target only by its hot bits, so those must be
+        // exact: rebuilt here from the visited bitmap (exactly the vertices of levels <= l)
+        if (dense && p.hot_words > 0 && !hot_ok) {
+            rebuild_hot_bits(p, p.hot[par], blockIdx.x * kBlock + threadIdx.x, G * kBlock);
+            hot_ok = true;
+        }
         if (dense && !xcd_barrier(c, p.xbar, xg, p.spin_ticks, s_flag)) return;
         if (DIR && bottom_up) {
             if (blockIdx.x < P) bottom_up_share(p, l, blockIdx.x, P, ntiles, lds);
