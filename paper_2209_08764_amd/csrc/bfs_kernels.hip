@@ -261,14 +261,30 @@ __device__ void expand_share(const Params& p, int l, int b, int P, int ntiles, i
     for (int t = tb; t < te && !bad; ++t) {
         int* cur1 = ((t + 1 - tb) & 1) ? buf1 : buf0;   // slice of sub-tile t + 1
         int* free2 = ((t - tb) & 1) ? buf1 : buf0;      // receives the slice of sub-tile t + 2
-        // Probes of sub-tile t go out before the reads for sub-tiles t + 1 and t + 2:
-        // reads return in issue order, so waiting for the probes then does not wait for
-        // the reads behind them.  Hot targets are tested against the LDS copy; one that
-        // passes is new to this level unless another edge found it first, which its
-        // bit in hnext tells (pull levels); its id comes from hot_vid.  The other
-        // targets are tested against the visited bitmap.
+        // Sub-tile t's neighbour words (read during the previous sub-tile) are decoded
+        // first.  Then the slice reads for sub-tile t + 2 go out, then the probes of
+        // sub-tile t, then the neighbour reads for sub-tile t + 1, which every lane
+        // issues: reads return in issue order, so waiting for the probes does not wait
+        // for the neighbour reads behind them, and the slice reads ahead of the probes
+        // may be skipped by lanes with no entry.  Hot targets are tested against the LDS
+        // copy; one that passes is new to this level unless another edge found it
+        // first, which its bit in hnext tells (pull levels); its id comes from hot_vid.
+        // The other targets are tested against the visited bitmap.
         int vc[kVT], hc[kVT];
         decode_tile(p, xc, okc, vc, hc);
+        // fetch the slice of sub-tile t + 2 into registers
+        const bool has2 = t + 2 < te;
+        const int a2 = z1, z2 = has2 ? slice_end(t + 2) : z1;
+        const bool ok2 = !has2 || slice_ok(a2, z2);
+        int pe[kPre], pr[kPre];
+#pragma unroll
+        for (int r = 0; r < kPre; ++r) {
+            const int i = threadIdx.x + r * kBlock;
+            if (has2 && ok2 && i <= z2 - a2) {
+                pe[r] = fex[a2 + i];
+                pr[r] = frs[a2 + i];
+            }
+        }
         const int32_t* hvid = p.hot_vid ? p.hot_vid : p.offsets;
         uint32_t pw[kVT];
         int hid[kVT];
@@ -284,17 +300,6 @@ __device__ void expand_share(const Params& p, int l, int b, int P, int ntiles, i
             pw[i] = *pa;
             hid[i] = hvid[hot_open ? hc[i] : 0];
             if (!hot_open) hc[i] = -1;
-        }
-        // fetch the slice of sub-tile t + 2 into registers
-        const bool has2 = t + 2 < te;
-        const int a2 = z1, z2 = has2 ? slice_end(t + 2) : z1;
-        const bool ok2 = !has2 || slice_ok(a2, z2);
-        int pe[kPre], pr[kPre];
-#pragma unroll
-        for (int r = 0; r < kPre; ++r) {
-            const int j = min(max(a2 + (int)threadIdx.x + r * kBlock, 0), n_l - 1);
-            pe[r] = fex[j];
-            pr[r] = frs[j];
         }
         // issue the neighbour reads of sub-tile t + 1
         int xn[kVT], un[kVT];
