@@ -135,18 +135,24 @@ __device__ __forceinline__ int first_parent_wg(const Params& p, int rs, int d, i
 // Issues the neighbour reads of this lane's kVT edges among [g0, g1) of the
 // current frontier, whose entries [j0, j0 + nv) are staged in `sl` (ex | rs):
 // raw words of the neighbour stream into x (decode_tile interprets them) and
-// bit i of *ok set where edge i exists; from `fsrc` also the frontier entry
-// each edge comes from (its vertex, for pushed parents).  Every load is
+// bit i of *ok set where edge i exists; with `fv` also the frontier vertex
+// each edge comes from (for pushed parents).  Every neighbour read is
 // issued, from a clamped address where a lane has no edge, and nothing
 // reads its result here: the reads stay in flight while the previous
 // sub-tile is filtered, and the waits before that filtering can count them.
 __device__ __forceinline__ void gather_tile(const Params& p, const int* sl, int nv, int g0, int g1, int* x,
-                                            uint32_t* ok, const int32_t* fsrc, int j0, int* u) {
+                                            uint32_t* ok, const int32_t* fv, int j0, int* u) {
     int gg[kVT], own[kVT];
 #pragma unroll
     for (int i = 0; i < kVT; ++i) gg[i] = min(g0 + i * kBlock + (int)threadIdx.x, g1 - 1);
     search_owners<kVT>(sl, nv, gg, own);
     const int32_t* src = p.colx ? p.colx : p.cols;
+    // frontier vertices first (push levels only), then the neighbour words, which every
+    // lane issues: a wait for anything issued before them can leave them in flight
+    if (fv) {
+#pragma unroll
+        for (int i = 0; i < kVT; ++i) u[i] = fv[j0 + own[i]];
+    }
     uint32_t m = 0;
 #pragma unroll
     for (int i = 0; i < kVT; ++i) {
@@ -157,7 +163,6 @@ __device__ __forceinline__ void gather_tile(const Params& p, const int* sl, int 
         if (g < g1 && in) m |= 1u << i;
         if (g < g1 && !in) flag_internal(p.ctrl);
         x[i] = __builtin_nontemporal_load(src + (in ? idx : 0));
-        u[i] = fsrc[j0 + lo];
     }
     *ok = m;
 }
@@ -251,13 +256,12 @@ __device__ void expand_share(const Params& p, int l, int b, int P, int ntiles, i
         for (int w = threadIdx.x; w < p.hot_words; w += kBlock) s_hot[w] = hcur[w];
     lds_barrier();
     // raw neighbour words of the sub-tile to filter next, which of them are edges, and
-    // their frontier entries' vertices (read from f_ex where no parents are pushed)
-    const int32_t* fsrc = fvp ? fvp : fex;
+    // (push levels) their frontier entries' vertices
     int xc[kVT], uc[kVT];
     uint32_t okc = 0u;
 #pragma unroll
     for (int i = 0; i < kVT; ++i) xc[i] = uc[i] = -1;
-    if (!bad) gather_tile(p, buf0, z0 - a0 + 1, tb * kGrain, min(tb * kGrain + kGrain, e_l), xc, &okc, fsrc, a0, uc);
+    if (!bad) gather_tile(p, buf0, z0 - a0 + 1, tb * kGrain, min(tb * kGrain + kGrain, e_l), xc, &okc, fvp, a0, uc);
     for (int t = tb; t < te && !bad; ++t) {
         int* cur1 = ((t + 1 - tb) & 1) ? buf1 : buf0;   // slice of sub-tile t + 1
         int* free2 = ((t - tb) & 1) ? buf1 : buf0;      // receives the slice of sub-tile t + 2
@@ -285,21 +289,30 @@ __device__ void expand_share(const Params& p, int l, int b, int P, int ntiles, i
                 pr[r] = frs[a2 + i];
             }
         }
-        const int32_t* hvid = p.hot_vid ? p.hot_vid : p.offsets;
         uint32_t pw[kVT];
         int hid[kVT];
+        bool any_open = false;
+#pragma unroll
+        for (int i = 0; i < kVT; ++i) hid[i] = -1;
 #pragma unroll
         for (int i = 0; i < kVT; ++i) {
             bool hot_open = false;
             if (hc[i] >= 0) {
                 const uint32_t w = use_hot ? s_hot[hc[i] >> 5] : hcur[hc[i] >> 5];
                 hot_open = !((w >> (hc[i] & 31)) & 1u);
-                if (!hot_open) vc[i] = -1;
+                if (!hot_open) {
+                    vc[i] = -1;
+                    hc[i] = -1;
+                }
             }
+            any_open |= hot_open;
             const uint32_t* pa = (hot_open && !fvp) ? hnext + (hc[i] >> 5) : p.bitmap + (max(vc[i], 0) >> 5);
             pw[i] = *pa;
-            hid[i] = hvid[hot_open ? hc[i] : 0];
-            if (!hot_open) hc[i] = -1;
+        }
+        // ids of open hot targets, only in waves that have one (the reads behind stay unconditional)
+        if (ballot(any_open)) {
+#pragma unroll
+            for (int i = 0; i < kVT; ++i) hid[i] = p.hot_vid[hc[i] >= 0 ? hc[i] : 0];
         }
         // issue the neighbour reads of sub-tile t + 1
         int xn[kVT], un[kVT];
@@ -307,7 +320,7 @@ __device__ void expand_share(const Params& p, int l, int b, int P, int ntiles, i
 #pragma unroll
         for (int i = 0; i < kVT; ++i) xn[i] = un[i] = -1;
         if (t + 1 < te)
-            gather_tile(p, cur1, z1 - a1 + 1, (t + 1) * kGrain, min((t + 1) * kGrain + kGrain, e_l), xn, &okn, fsrc,
+            gather_tile(p, cur1, z1 - a1 + 1, (t + 1) * kGrain, min((t + 1) * kGrain + kGrain, e_l), xn, &okn, fvp,
                         a1, un);
         // decide sub-tile t
         bool fresh[kVT];
