@@ -614,6 +614,23 @@ __device__ bool compact_share(const Params& p, int l, int b, int P, int ntiles, 
 // look-back over the shares gives their offsets (the Sizes prefix sum);
 // pass 2 writes the entries, the start points of the next level's sub-tiles
 // and the pulled parents.
+// Inputs of one dense-compaction chunk for this thread's kVT consecutive
+// vertices from v: their frontier-bit word and kVT + 1 row offsets.  Read by
+// every lane from clamped addresses, so a chunk can be fetched while the
+// previous one is processed and the wait for it counts exactly.
+struct DenseIn {
+    uint32_t w;
+    int off[kVT + 1];
+};
+__device__ __forceinline__ DenseIn dense_load(const Params& p, const uint32_t* fb, int v) {
+    DenseIn r;
+    const int vb = min(v, p.n - 1);  // n >= 1; a vertex below n keeps its own data
+    r.w = fb[vb >> 5];
+#pragma unroll
+    for (int k = 0; k <= kVT; ++k) r.off[k] = p.offsets[min(vb + k, p.n)];
+    return r;
+}
+
 __device__ bool dense_compact_share(const Params& p, int l, int b, int P, int* lds, const uint32_t* fpull) {
     int* s_wave = lds_wave(lds);
     int* s_wave2 = lds_wave2(lds);
@@ -624,19 +641,24 @@ __device__ bool dense_compact_share(const Params& p, int l, int b, int P, int* l
     const int64_t chunks = ((int64_t)p.n + kGrain - 1) / kGrain;
     const int v0 = (int)(chunks * b / P * kGrain);
     const int v1 = (int)min((int64_t)p.n, chunks * (b + 1) / P * kGrain);
-    // pass 1: thread t takes the kVT consecutive vertices from base + t * kVT
+    // pass 1: thread t takes the kVT consecutive vertices from base + t * kVT; the next
+    // chunk's bits and offsets are in flight while this one is counted
+    const int tv = (int)threadIdx.x * kVT;
     int tc = 0, ts = 0, tr = 0;
+    DenseIn cur = dense_load(p, fb, v0 + tv);
     for (int base = v0; base < v1; base += kGrain) {
+        const DenseIn nxt = dense_load(p, fb, base + kGrain + tv);
 #pragma unroll
         for (int i = 0; i < kVT; ++i) {
-            const int v = base + (int)threadIdx.x * kVT + i;
-            if (v < v1 && frontier_bit(fb, v)) {
+            const int v = base + tv + i;
+            if (v < v1 && ((cur.w >> (v & 31)) & 1u)) {
                 p.level[v] = l + 1;
-                const int d = p.offsets[v + 1] - p.offsets[v];
+                const int d = cur.off[i + 1] - cur.off[i];
                 ++tr;
                 if (d > 0) { ++tc; ts += d; }
             }
         }
+        cur = nxt;
     }
     int surv, degsum, raw;
     block_excl_scan(tc, s_wave, &surv);
@@ -666,24 +688,23 @@ __device__ bool dense_compact_share(const Params& p, int l, int b, int P, int* l
     // pass 2: the same vertices in the same order
     const bool pull = p.parent != nullptr;
     int run_c = 0, run_e = 0;
+    cur = dense_load(p, fb, v0 + tv);
     for (int base = v0; base < v1; base += kGrain) {
+        const DenseIn nxt = dense_load(p, fb, base + kGrain + tv);
         int v[kVT], rs[kVT], d[kVT];
         int cc = 0, cs = 0;
 #pragma unroll
         for (int i = 0; i < kVT; ++i) {
-            const int vv = base + (int)threadIdx.x * kVT + i;
+            const int vv = base + tv + i;
             v[i] = -1;
             rs[i] = d[i] = 0;
-            if (vv < v1 && frontier_bit(fb, vv)) {
-                const int r = p.offsets[vv];
-                const int dd = p.offsets[vv + 1] - r;
-                if (dd > 0) {
-                    v[i] = vv;
-                    rs[i] = r;
-                    d[i] = dd;
-                    ++cc;
-                    cs += dd;
-                }
+            const int dd = cur.off[i + 1] - cur.off[i];
+            if (vv < v1 && ((cur.w >> (vv & 31)) & 1u) && dd > 0) {
+                v[i] = vv;
+                rs[i] = cur.off[i];
+                d[i] = dd;
+                ++cc;
+                cs += dd;
             }
         }
         int C, S;
@@ -707,6 +728,7 @@ __device__ bool dense_compact_share(const Params& p, int l, int b, int P, int* l
         }
         run_c += C;
         run_e += S;
+        cur = nxt;
     }
     return true;
 }
