@@ -441,10 +441,31 @@ __device__ __forceinline__ void pull_parents_chunk(const Params& p, const int* v
     int* s_nh = s_red + kWaves + 1;
     if (threadIdx.x == 0) *s_nh = 0;
     lds_barrier();
+    // the first kFirst neighbours of all kVT rows at once, then the next kPullScan of each
+    // row still open, one row at a time
+    constexpr int kFirst = 2;
+    int c[kVT][kFirst];
+    bool h[kVT][kFirst];
+#pragma unroll
+    for (int i = 0; i < kVT; ++i)
+#pragma unroll
+        for (int q = 0; q < kFirst; ++q) c[i][q] = v[i] >= 0 && q < d[i] ? p.cols[rs[i] + q] : -1;
+#pragma unroll
+    for (int i = 0; i < kVT; ++i)
+#pragma unroll
+        for (int q = 0; q < kFirst; ++q)
+            h[i][q] = (unsigned)c[i][q] < (unsigned)p.n &&
+                      (fpull ? frontier_bit(fpull, c[i][q]) : p.level[c[i][q]] == l);
 #pragma unroll
     for (int i = 0; i < kVT; ++i) {
         if (v[i] >= 0) {
-            const int f = first_parent_lane(p, rs[i], d[i], l, fpull);
+            int f = -1;
+#pragma unroll
+            for (int q = kFirst - 1; q >= 0; --q)
+                if (h[i][q]) f = c[i][q];
+            // rows scanned past position kFirst + kPullScan go on from kPullScan, which
+            // repeats a few neighbours known to miss
+            if (f < 0 && d[i] > kFirst) f = first_parent_lane(p, rs[i] + kFirst, d[i] - kFirst, l, fpull);
             if (f == -2) {
                 const int h = atomicAdd(s_nh, 1);
                 s_hard[3 * h] = v[i];
