@@ -334,7 +334,10 @@ bfs_status_t run_common(bfs_workspace_s* ws, const int32_t* roots_host, int32_t 
     } else if (mode == BFS_MODE_PLAIN) {
         st = run_plain_mode(ws, p, s);
     } else {
-        if (mode == BFS_MODE_INSENSITIVE) p.small_edges = 0;
+        if (mode == BFS_MODE_INSENSITIVE) {
+            p.small_edges = 0;
+            p.insensitive = 1;
+        }
         p.fb_pull = !p.direction && p.parent != nullptr;
         p.dense_edges = p.direction ? 0 : dense_edges_of(ws);
         const int grid = grid_for(ws);

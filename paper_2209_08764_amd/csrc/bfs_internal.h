@@ -26,6 +26,7 @@ constexpr int kHotBits = 1 << 18;
 constexpr int kHotWords = kHotBits / 32;   // 32 KiB of LDS
 constexpr int64_t kHotMinEdges = 1 << 22;  // graphs from this size get the filter by default
 constexpr int kHotMinTiles = 4;            // sub-tiles per share for the LDS copy to pay off
+constexpr int kLiteShares = 32;            // fewer active workgroups: no hot or frontier bit upkeep
 constexpr int kHotTarget = -2;             // a gathered edge whose target is hot, id not yet looked up
 
 // LDS words used by the level loop (the two layouts share one allocation).
@@ -110,6 +111,7 @@ struct Params {
     uint32_t* fbits[2];       // frontier bits: exactly the level-l vertices of degree >= 1 in fbits[l & 1]
     int32_t direction;        // 1: levels may run bottom-up
     int32_t fb_pull;          // top-down persistent loop: keep frontier bits, pull parents against them
+    int32_t insensitive;      // persistent loop: every level is split over every workgroup (P_l = P)
     int32_t dense_edges;      // top-down persistent loop: pull levels with at least this many edges keep
                               // the new frontier as bits (0: never)
     int32_t bu_alpha;         // go bottom-up when e_l * alpha > edges of unreached vertices

@@ -206,14 +206,16 @@ __device__ __forceinline__ void decode_tile(const Params& p, const int* x, uint3
 // hot[(l + 1) & 1], which the shares also merge hot[l & 1] into.  A set bit
 // still means "visited before this level", so results are unchanged.
 __device__ void expand_share(const Params& p, int l, int b, int P, int ntiles, int n_l, int e_l, int* lds,
-                             bool dense = false) {
+                             bool dense = false, bool lite = false) {
     int* s_wave = lds_wave(lds);
     uint32_t* hnext = nullptr;
     const uint32_t* hcur = nullptr;
     if (p.hot_words > 0) {
         hcur = p.hot[l & 1];
         hnext = p.hot[(l + 1) & 1];
-        const int w0 = (int)(((int64_t)b * p.hot_words) / P), w1 = (int)(((int64_t)(b + 1) * p.hot_words) / P);
+        // a lite level (few workgroups) leaves the hot bits alone: they are then inexact
+        const int w0 = (int)(((int64_t)b * p.hot_words) / P);
+        const int w1 = lite ? w0 : (int)(((int64_t)(b + 1) * p.hot_words) / P);
         for (int w = w0 + threadIdx.x; w < w1; w += kBlock) {
             const uint32_t x = hcur[w];
             if (x) __hip_atomic_fetch_or(&hnext[w], x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -366,7 +368,7 @@ __device__ void expand_share(const Params& p, int l, int b, int P, int ntiles, i
                 if (dense)  // the new frontier is kept as bits, not queued
                     __hip_atomic_fetch_or(&p.fbits[(l + 1) & 1][vc[i] >> 5], 1u << (vc[i] & 31), __ATOMIC_RELAXED,
                                           __HIP_MEMORY_SCOPE_AGENT);
-                if (hnext && hc[i] >= 0)
+                if (hnext && hc[i] >= 0 && !lite)
                     __hip_atomic_fetch_or(&hnext[hc[i] >> 5], 1u << (hc[i] & 31), __ATOMIC_RELAXED,
                                           __HIP_MEMORY_SCOPE_AGENT);
             }
@@ -496,7 +498,8 @@ __device__ __forceinline__ void pull_parents_chunk(const Params& p, const int* v
 // the survivors to the next frontier with their exclusive degree sums and
 // the start points of the next level's sub-tiles.  l = -1 compacts the roots.
 __device__ bool compact_share(const Params& p, int l, int b, int P, int ntiles, bool pull_parents, bool set_bits,
-                              int* lds, bool after_bottom_up = false, const uint32_t* fpull = nullptr) {
+                              int* lds, bool after_bottom_up = false, const uint32_t* fpull = nullptr,
+                              bool keep_fb = true) {
     int* s_wave = lds_wave(lds);
     int* s_wave2 = lds_wave2(lds);
     int* s_b = lds_misc(lds);
@@ -540,7 +543,7 @@ __device__ bool compact_share(const Params& p, int l, int b, int P, int ntiles, 
                     __hip_atomic_fetch_or(&p.bitmap[v[i] >> 5], 1u << (v[i] & 31), __ATOMIC_RELAXED,
                                           __HIP_MEMORY_SCOPE_AGENT);
                 // frontier bits of level l + 1, for a bottom-up step or the next level's pulls
-                if ((p.direction || p.fb_pull) && d[i] > 0 && !after_bottom_up)
+                if ((p.direction || (p.fb_pull && keep_fb)) && d[i] > 0 && !after_bottom_up)
                     __hip_atomic_fetch_or(&p.fbits[np][v[i] >> 5], 1u << (v[i] & 31), __ATOMIC_RELAXED,
                                           __HIP_MEMORY_SCOPE_AGENT);
                 if (d[i] > 0) { ++tc; ts += d[i]; }
@@ -1218,6 +1221,8 @@ k_persistent(Params p) {
     // hot[l & 1] holds exactly the hot vertices visited up to level l: the expansion keeps
     // it so once it is, but the roots and single-workgroup levels set no hot bits
     bool hot_ok = false;
+    // top-down loop: fbits[x] holds bits a later writer must clear first
+    bool fb_dirty[2] = {p.fb_pull != 0, false};
     int64_t reached_edges = 0;
     const int fwords = (p.n + 31) >> 5;
     for (;;) {
@@ -1252,12 +1257,18 @@ k_persistent(Params p) {
                                                : (int64_t)e_l * p.bu_alpha > unreached);
         }
         const int ntiles = bottom_up ? (p.n + kGrain - 1) / kGrain : (int)(((int64_t)e_l + kGrain - 1) / kGrain);
-        const int P = shares_for(ntiles, G);  // P_l = min(P, W_l)
+        // P_l = min(P, W_l); the work-insensitive variant splits every level over all P
+        // workgroups (one share per look-back descriptor), most of them empty on small levels
+        const int P = p.insensitive ? min(G, p.max_tiles) : shares_for(ntiles, G);
         const int np = (l + 1) & 1;
         const bool push = p.parent && e_l <= p.push_edges;
         // a dense level keeps its new frontier as bits and compacts it in vertex order
         const bool dense = !DIR && !push && p.dense_edges > 0 && e_l >= p.dense_edges;
         const int Pd = dense ? dense_shares(p, G) : 0;
+        // A lite level (few workgroups, not dense) skips the upkeep that only pays on large
+        // levels: it merges no hot bits and keeps no frontier bits for the next level's pulls
+        const bool lite = !DIR && !dense && P < kLiteShares;
+        const bool keep_fb = !DIR && p.fb_pull && !lite;  // this level's compaction keeps frontier bits
         // reset this level's compaction state (last used two levels ago)
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             st_rel(&c->kept[np], 0);
@@ -1270,9 +1281,12 @@ k_persistent(Params p) {
         // writes fbits[np] before its compaction and it can be cleared now.  Top-down
         // loop: the previous level's pulls were the last readers of fbits[np], and this
         // level's compaction is its first writer, or its expansion on a dense level, which
-        // therefore waits for the clearing at an extra barrier.
-        if ((DIR && !fbits_ok) || (!DIR && (p.fb_pull || dense)))
+        // therefore waits for the clearing at an extra barrier; a level that writes none
+        // leaves the buffer as it is.
+        const bool fb_write = !DIR && (keep_fb || dense);
+        if ((DIR && !fbits_ok) || (fb_write && fb_dirty[np]))
             for (int w = blockIdx.x * kBlock + threadIdx.x; w < fwords; w += G * kBlock) p.fbits[np][w] = 0u;
+        if (fb_write) fb_dirty[np] = true;
         // A dense level's compaction takes every bit its expansion sets as a new vertex,
         // and that expansion drops a hot target only by its hot bits, so those must be
         // exact: rebuilt here from the visited bitmap (exactly the vertices of levels <= l)
@@ -1284,9 +1298,10 @@ k_persistent(Params p) {
         if (DIR && bottom_up) {
             if (blockIdx.x < P) bottom_up_share(p, l, blockIdx.x, P, ntiles, lds);
         } else if (blockIdx.x < P) {
-            [[clang::always_inline]] expand_share(p, l, blockIdx.x, P, ntiles, n_l, e_l, lds, dense);
+            [[clang::always_inline]] expand_share(p, l, blockIdx.x, P, ntiles, n_l, e_l, lds, dense, lite);
         }
         if (!xcd_barrier(c, p.xbar, xg, p.spin_ticks, s_flag)) return;
+        if (lite) hot_ok = false;
         if (rec) p.stat_ts[3 * l + 1] = now_ticks();
         if (DIR)  // this level's frontier bits have been read: clear them for level l + 2
             for (int w = blockIdx.x * kBlock + threadIdx.x; w < fwords; w += G * kBlock) p.fbits[par][w] = 0u;
@@ -1324,11 +1339,11 @@ k_persistent(Params p) {
                 if (blockIdx.x < Pd) [[clang::always_inline]] ok = dense_compact_share(p, l, blockIdx.x, Pd, lds, fpull);
             } else if (blockIdx.x < P) {
                 [[clang::always_inline]] ok =
-                    compact_share(p, l, blockIdx.x, P, ntiles, !push, push, lds, false, fpull);
+                    compact_share(p, l, blockIdx.x, P, ntiles, !push, push, lds, false, fpull, keep_fb);
             }
             if (!ok) return;
         }
-        fbits_ok = true;
+        fbits_ok = DIR || fb_write;  // top-down: fbits[np] holds exactly the next frontier
         if (!xcd_barrier(c, p.xbar, xg, p.spin_ticks, s_flag)) return;
         if (rec) p.stat_ts[3 * l + 2] = now_ticks();
         ++l;
