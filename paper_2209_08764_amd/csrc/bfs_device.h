@@ -205,6 +205,32 @@ __device__ inline bool xcd_barrier(Ctrl* c, XBar* xb, const XGroup& g, uint64_t 
     return *s_flag != 0;
 }
 
+// Barrier among the first P workgroups only (the active ones of a lite level
+// l); the others do not take part.  Each arrives after an agent-scope release;
+// the last one resets the counter for the next such barrier and publishes
+// level l + 1 as the generation, which every arrival waits for (levels only
+// grow within a launch).
+__device__ inline bool sub_barrier(Ctrl* c, XBar* xb, int l, int P, uint64_t spin_ticks, int* s_flag) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const unsigned long long a =
+            __hip_atomic_fetch_add(&xb->pcnt[0], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned long long gen = (unsigned long long)l + 1;
+        if (a == (unsigned long long)P - 1) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+            st_rel(&xb->pcnt[0], 0ull);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            st_rel(&xb->pgen[0], gen);
+        }
+        const bool ok = spin_until(c, spin_ticks, [&] { return ld_acq(&xb->pgen[0]) >= gen; });
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        *s_flag = ok && ld_acq(&c->error) == 0;
+    }
+    __syncthreads();
+    return *s_flag != 0;
+}
+
 // Records an internal inconsistency; the caller then skips the access that
 // would have gone out of bounds and the run reports BFS_EDEVICE.
 __device__ __forceinline__ void flag_internal(Ctrl* c) {

@@ -69,6 +69,8 @@ struct XBar {
     unsigned long long arrive[kMaxXcd * kXLine];  // arrivals on each XCD, monotone within a launch
     unsigned long long gen[kMaxXcd * kXLine];     // barriers completed, one copy per XCD
     unsigned long long top[kXLine];               // XCD groups complete, monotone within a launch
+    unsigned long long pcnt[kXLine];              // arrivals at a barrier of a lite level's workgroups
+    unsigned long long pgen[kXLine];              // last lite level whose workgroups met, + 1
 };
 
 struct Params {

@@ -1300,8 +1300,14 @@ k_persistent(Params p) {
         } else if (blockIdx.x < P) {
             [[clang::always_inline]] expand_share(p, l, blockIdx.x, P, ntiles, n_l, e_l, lds, dense, lite);
         }
-        if (!xcd_barrier(c, p.xbar, xg, p.spin_ticks, s_flag)) return;
-        if (lite) hot_ok = false;
+        // a lite level's compaction needs only its own workgroups' expansion, so only they
+        // meet here; the others go on to the end-of-level barrier
+        if (lite) {
+            if (blockIdx.x < P && !sub_barrier(c, p.xbar, l, P, p.spin_ticks, s_flag)) return;
+            hot_ok = false;
+        } else if (!xcd_barrier(c, p.xbar, xg, p.spin_ticks, s_flag)) {
+            return;
+        }
         if (rec) p.stat_ts[3 * l + 1] = now_ticks();
         if (DIR)  // this level's frontier bits have been read: clear them for level l + 2
             for (int w = blockIdx.x * kBlock + threadIdx.x; w < fwords; w += G * kBlock) p.fbits[par][w] = 0u;
