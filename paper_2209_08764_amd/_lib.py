@@ -144,7 +144,7 @@ def load(path: str = LIB_PATH):
     if _lib is not None:
         return _lib
     if not os.path.exists(path):
-        raise ImportError(f"libbfs.so not found at {path}; build it with __graft_entry__.build()")
+        raise ImportError(f"libbfs.so not found at {path}; build it with python -m paper_2209_08764_amd._build")
     lib = ctypes.CDLL(path)
     for name, (res, args) in _SIGS.items():
         f = getattr(lib, name)
