@@ -70,6 +70,7 @@ struct bfs_workspace_s {
     uint32_t* bitmap = nullptr;
     uint32_t* hot[2] = {nullptr, nullptr};
     uint32_t* fbits[2] = {nullptr, nullptr};
+    uint32_t* snap = nullptr;
     int32_t* owner = nullptr;
     int32_t* f_rs[2] = {nullptr, nullptr};
     int32_t* f_ex[2] = {nullptr, nullptr};
@@ -173,6 +174,7 @@ Params make_params(bfs_workspace_s* ws, int32_t* level, int32_t* parent) {
     p.hot_words = ws->g->colx ? ws->g->hot_words : 0;
     p.fbits[0] = ws->fbits[0];
     p.fbits[1] = ws->fbits[1];
+    p.snap = ws->snap;
     p.direction = ws->mode == BFS_MODE_DIRECTION;
     p.bu_alpha = ws->bu_alpha;
     p.bu_beta = ws->bu_beta;
@@ -636,7 +638,7 @@ size_t bfs_workspace_bytes(bfs_graph_t g, int32_t max_sources) {
     if (!g || max_sources < 1 || max_sources > 256) return 0;
     const size_t n = (size_t)g->n, T = (size_t)tiles_for(g);
     size_t b = 0;
-    b += 3 * ((n + 31) / 32) * 4;      // visited bitmap, frontier bits x2
+    b += 4 * ((n + 31) / 32) * 4;      // visited bitmap, frontier bits x2, dense-level snapshot
     if (g->colx) b += 2 * (size_t)g->hot_words * 4;  // hot-vertex bits x2
     b += n * 4;                        // owner
     b += 6 * (n + 2) * 4;              // frontier ids / row starts / degree sums, x2
@@ -660,7 +662,7 @@ bfs_status_t bfs_workspace_free(bfs_workspace_t ws) {
     if (!ws) return fail(BFS_EINVAL, "null workspace");
     (void)hipSetDevice(ws->device);
     if (ws->has_run) (void)hipEventSynchronize(ws->ev_done);
-    void* ptrs[] = {ws->bitmap, ws->hot[0], ws->hot[1], ws->fbits[0], ws->fbits[1], ws->owner, ws->f_rs[0], ws->f_rs[1], ws->f_ex[0], ws->f_ex[1], ws->f_v[0],
+    void* ptrs[] = {ws->bitmap, ws->hot[0], ws->hot[1], ws->fbits[0], ws->fbits[1], ws->snap, ws->owner, ws->f_rs[0], ws->f_rs[1], ws->f_ex[0], ws->f_ex[1], ws->f_v[0],
                     ws->f_v[1], ws->tstart[0],
                     ws->tstart[1], ws->cand, ws->cnt, ws->desc[0], ws->desc[1], ws->ctrl, ws->xbar, ws->stat_nl,
                     ws->stat_el, ws->stat_ts, ws->roots, ws->plain_fv[0], ws->plain_fv[1], ws->b_fr, ws->b_nx, ws->b_vis,
@@ -704,6 +706,7 @@ bfs_status_t bfs_workspace_create(bfs_graph_t g, int32_t max_sources, bfs_worksp
     A(dalloc(&ws->bitmap, (n + 31) / 32));
     A(dalloc(&ws->fbits[0], (n + 31) / 32));
     A(dalloc(&ws->fbits[1], (n + 31) / 32));
+    A(dalloc(&ws->snap, (n + 31) / 32));
     if (g->colx) {
         A(dalloc(&ws->hot[0], (size_t)g->hot_words));
         A(dalloc(&ws->hot[1], (size_t)g->hot_words));

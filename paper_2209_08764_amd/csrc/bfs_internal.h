@@ -111,6 +111,7 @@ struct Params {
     int32_t push_edges;       // levels with at most this many edges push parents, larger ones pull
     // direction optimisation (persistent loop only)
     uint32_t* fbits[2];       // frontier bits: exactly the level-l vertices of degree >= 1 in fbits[l & 1]
+    uint32_t* snap;           // visited bits at the start of a dense level
     int32_t direction;        // 1: levels may run bottom-up
     int32_t fb_pull;          // top-down persistent loop: keep frontier bits, pull parents against them
     int32_t insensitive;      // persistent loop: every level is split over every workgroup (P_l = P)

@@ -365,9 +365,6 @@ __device__ void expand_share(const Params& p, int l, int b, int P, int ntiles, i
                 else
                     __hip_atomic_fetch_or(&p.bitmap[vc[i] >> 5], 1u << (vc[i] & 31), __ATOMIC_RELAXED,
                                           __HIP_MEMORY_SCOPE_AGENT);
-                if (dense)  // the new frontier is kept as bits, not queued
-                    __hip_atomic_fetch_or(&p.fbits[(l + 1) & 1][vc[i] >> 5], 1u << (vc[i] & 31), __ATOMIC_RELAXED,
-                                          __HIP_MEMORY_SCOPE_AGENT);
                 if (hnext && hc[i] >= 0 && !lite)
                     __hip_atomic_fetch_or(&hnext[hc[i] >> 5], 1u << (hc[i] & 31), __ATOMIC_RELAXED,
                                           __HIP_MEMORY_SCOPE_AGENT);
@@ -628,28 +625,31 @@ __device__ bool compact_share(const Params& p, int l, int b, int P, int ntiles, 
     return true;
 }
 
-// Compaction of a dense level.  There the expansion records each new vertex
-// by its bit in fbits[(l + 1) & 1] instead of appending it to a private
-// queue, so duplicates merge in the bitmap and the frontier comes out in
-// vertex order: the next level then reads its rows, and this level pulls its
-// parents, in the order they lie in memory.  Share b of P takes a range of
-// whole kGrain-vertex chunks.  Pass 1 writes level l + 1 of every new vertex
-// and counts the share's frontier entries (degree >= 1) and their edges; the
-// look-back over the shares gives their offsets (the Sizes prefix sum);
-// pass 2 writes the entries, the start points of the next level's sub-tiles
-// and the pulled parents.
+// Compaction of a dense level.  There the expansion only sets each new
+// vertex's visited bit instead of appending it to a private queue, and the
+// level's new vertices are the bits set since the snapshot taken at its
+// start: duplicates merge in the bitmap and the frontier comes out in vertex
+// order, so the next level reads its rows, and this level pulls its parents,
+// in the order they lie in memory.  Share b of P takes a range of whole
+// kGrain-vertex chunks.  Pass 1 writes level l + 1 of every new vertex, the
+// new-vertex words into fbits[(l + 1) & 1] (the next level's exact frontier
+// bits), and counts the share's frontier entries (degree >= 1) and their
+// edges; the look-back over the shares gives their offsets (the Sizes prefix
+// sum); pass 2 writes the entries, the start points of the next level's
+// sub-tiles and the pulled parents.
 // Inputs of one dense-compaction chunk for this thread's kVT consecutive
-// vertices from v: their frontier-bit word and kVT + 1 row offsets.  Read by
+// vertices from v: the word of their new-vertex bits (visited now and not at
+// the level's start) and kVT + 1 row offsets.  Read by
 // every lane from clamped addresses, so a chunk can be fetched while the
 // previous one is processed and the wait for it counts exactly.
 struct DenseIn {
     uint32_t w;
     int off[kVT + 1];
 };
-__device__ __forceinline__ DenseIn dense_load(const Params& p, const uint32_t* fb, int v) {
+__device__ __forceinline__ DenseIn dense_load(const Params& p, int v) {
     DenseIn r;
     const int vb = min(v, p.n - 1);  // n >= 1; a vertex below n keeps its own data
-    r.w = fb[vb >> 5];
+    r.w = p.bitmap[vb >> 5] & ~p.snap[vb >> 5];
 #pragma unroll
     for (int k = 0; k <= kVT; ++k) r.off[k] = p.offsets[min(vb + k, p.n)];
     return r;
@@ -661,7 +661,7 @@ __device__ bool dense_compact_share(const Params& p, int l, int b, int P, int* l
     int* s_b = lds_misc(lds);
     const int par = l & 1;
     const int np = (l + 1) & 1;
-    const uint32_t* fb = p.fbits[np];
+    uint32_t* fb = p.fbits[np];
     const int64_t chunks = ((int64_t)p.n + kGrain - 1) / kGrain;
     const int v0 = (int)(chunks * b / P * kGrain);
     const int v1 = (int)min((int64_t)p.n, chunks * (b + 1) / P * kGrain);
@@ -669,9 +669,10 @@ __device__ bool dense_compact_share(const Params& p, int l, int b, int P, int* l
     // chunk's bits and offsets are in flight while this one is counted
     const int tv = (int)threadIdx.x * kVT;
     int tc = 0, ts = 0, tr = 0;
-    DenseIn cur = dense_load(p, fb, v0 + tv);
+    DenseIn cur = dense_load(p, v0 + tv);
     for (int base = v0; base < v1; base += kGrain) {
-        const DenseIn nxt = dense_load(p, fb, base + kGrain + tv);
+        const DenseIn nxt = dense_load(p, base + kGrain + tv);
+        if (((base + tv) & 31) == 0 && base + tv < v1) fb[(base + tv) >> 5] = cur.w;  // one lane per word
 #pragma unroll
         for (int i = 0; i < kVT; ++i) {
             const int v = base + tv + i;
@@ -712,9 +713,9 @@ __device__ bool dense_compact_share(const Params& p, int l, int b, int P, int* l
     // pass 2: the same vertices in the same order
     const bool pull = p.parent != nullptr;
     int run_c = 0, run_e = 0;
-    cur = dense_load(p, fb, v0 + tv);
+    cur = dense_load(p, v0 + tv);
     for (int base = v0; base < v1; base += kGrain) {
-        const DenseIn nxt = dense_load(p, fb, base + kGrain + tv);
+        const DenseIn nxt = dense_load(p, base + kGrain + tv);
         int v[kVT], rs[kVT], d[kVT];
         int cc = 0, cs = 0;
 #pragma unroll
@@ -1280,16 +1281,19 @@ k_persistent(Params p) {
         // single-workgroup levels, which keep none; that level runs top-down, so nothing
         // writes fbits[np] before its compaction and it can be cleared now.  Top-down
         // loop: the previous level's pulls were the last readers of fbits[np], and this
-        // level's compaction is its first writer, or its expansion on a dense level, which
-        // therefore waits for the clearing at an extra barrier; a level that writes none
-        // leaves the buffer as it is.
+        // level's compaction is its first writer; a level that writes none leaves the buffer
+        // as it is.  A dense level's compaction overwrites every word of fbits[np], and its
+        // expansion waits at an extra barrier for the snapshot of the visited bits.
         const bool fb_write = !DIR && (keep_fb || dense);
-        if ((DIR && !fbits_ok) || (fb_write && fb_dirty[np]))
+        if ((DIR && !fbits_ok) || (!dense && fb_write && fb_dirty[np]))
             for (int w = blockIdx.x * kBlock + threadIdx.x; w < fwords; w += G * kBlock) p.fbits[np][w] = 0u;
+        if (dense)  // the visited bits before the level; the compaction writes every word of fbits[np]
+            for (int w = blockIdx.x * kBlock + threadIdx.x; w < fwords; w += G * kBlock) p.snap[w] = p.bitmap[w];
         if (fb_write) fb_dirty[np] = true;
-        // A dense level's compaction takes every bit its expansion sets as a new vertex,
-        // and that expansion drops a hot target only by its hot bits, so those must be
-        // exact: rebuilt here from the visited bitmap (exactly the vertices of levels <= l)
+        // A dense level drops a hot target only by its hot bits; where those miss visited
+        // vertices (the roots and single-workgroup levels set none), each such edge would
+        // set a visited bit again, which the snapshot then does not count as new, so the
+        // bits are rebuilt here from the visited bitmap (exactly the vertices of levels <= l)
         if (dense && p.hot_words > 0 && !hot_ok) {
             rebuild_hot_bits(p, p.hot[par], blockIdx.x * kBlock + threadIdx.x, G * kBlock);
             hot_ok = true;
