@@ -67,7 +67,8 @@ typedef struct bfs_workspace_s* bfs_workspace_t;  /* scratch for one in-flight r
 /* Options */
 #define BFS_OPT_MODE        1  /* one of BFS_MODE_* (default AUTO) */
 #define BFS_OPT_SMALL_EDGES 2  /* largest e_l run by a single workgroup (0 disables; default 4096) */
-#define BFS_OPT_GRID        3  /* workgroups of the persistent kernel (0 = fill the GPU) */
+#define BFS_OPT_GRID        3  /* workgroups of the level loop (0 = one per 16384 edges, a multiple
+                                  of 8, at least 64 and at most what the GPU holds at once) */
 #define BFS_OPT_PROFILE     4  /* 1: time the main kernel with HIP events (bfs_stats_t.kernel_ms) */
 #define BFS_OPT_BATCH_PULL  5  /* batched search: active edges above which a level pulls instead
                                   of pushing (-1 = never pull; default m / 8) */
@@ -230,7 +231,7 @@ typedef struct {
     int32_t batch_tile;    /* BFS_OPT_BATCH_TILE */
     int32_t batch_levels;  /* BFS_OPT_BATCH_LEVELS */
     int32_t batch_pull;    /* BFS_OPT_BATCH_PULL (-1 = never pull) */
-    int32_t grid;          /* BFS_OPT_GRID (0 = fill the GPU) */
+    int32_t grid;          /* BFS_OPT_GRID (0 = sized to the graph) */
     int32_t small_edges;   /* BFS_OPT_SMALL_EDGES */
     int32_t push_edges;    /* BFS_OPT_PUSH_EDGES */
     int32_t dense_edges;   /* BFS_OPT_DENSE_EDGES */

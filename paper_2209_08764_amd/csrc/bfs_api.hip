@@ -217,9 +217,20 @@ bfs_status_t check_busy(bfs_workspace_s* ws, hipStream_t s) {
     return BFS_OK;
 }
 
+// Workgroups of the level loop.  By default the grid follows the graph: one
+// workgroup per kEdgesPerWg edges (a multiple of 8, so that every XCD gets as
+// many), at least kMinGrid and at most what fits on the GPU at once.  A level
+// cannot use more workgroups than it has 2048-edge sub-tiles, and every extra
+// workgroup lengthens each grid barrier.
 int grid_for(bfs_workspace_s* ws) {
+    constexpr int64_t kEdgesPerWg = 16384, kMinGrid = 64;
     int g = ws->grid_cap;
-    if (ws->grid_opt > 0) g = std::min(g, ws->grid_opt);
+    if (ws->grid_opt > 0) {
+        g = std::min(g, ws->grid_opt);
+    } else {
+        const int64_t want = std::max<int64_t>(kMinGrid, (ws->g->m / kEdgesPerWg + 7) / 8 * 8);
+        g = (int)std::min<int64_t>(g, want);
+    }
     return std::max(g, 1);
 }
 
@@ -1210,7 +1221,7 @@ bfs_status_t bfs_autotune(bfs_workspace_t ws, const int32_t* sources, int32_t k,
     } else if (!st) {
         const int64_t cap = ws->grid_cap;
         std::vector<P> grids{{0, 0}};
-        for (int64_t d : {2, 4}) grids.push_back({std::max<int64_t>(cap / d, 1), 0});
+        for (int64_t d : {1, 2, 4, 8}) grids.push_back({std::max<int64_t>(cap / d, 1), 0});
         st = descend(smp, &best, grids, P{start.grid, 0},
                      [&](P c) { return bfs_workspace_set_option(ws, BFS_OPT_GRID, c.first); });
         std::vector<P> smalls;
