@@ -205,25 +205,30 @@ __device__ inline bool xcd_barrier(Ctrl* c, XBar* xb, const XGroup& g, uint64_t 
     return *s_flag != 0;
 }
 
-// Barrier among the first P workgroups only (the active ones of a lite level
-// l); the others do not take part.  Each arrives after an agent-scope release;
-// the last one resets the counter for the next such barrier and publishes
-// level l + 1 as the generation, which every arrival waits for (levels only
-// grow within a launch).
-__device__ inline bool sub_barrier(Ctrl* c, XBar* xb, int l, int P, uint64_t spin_ticks, int* s_flag) {
+// Barrier of a lite level's P active workgroups (the first P).  Each active
+// workgroup arrives after an agent-scope release; the last one resets the
+// counter for the next such barrier and publishes `gen` on every XCD's line.
+// Workgroups that do not take part (participate = false) only wait for the
+// generation, which hands them the level's results; generations grow within a
+// launch.  Grid barriers count every workgroup of the launch, so a lite level
+// uses this one for both of its barriers, and no workgroup arrives at a grid
+// barrier meanwhile.
+__device__ inline bool sub_barrier(Ctrl* c, XBar* xb, int xcd, unsigned long long gen, int P, bool participate,
+                                   uint64_t spin_ticks, int* s_flag) {
     __syncthreads();
     if (threadIdx.x == 0) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        const unsigned long long a =
-            __hip_atomic_fetch_add(&xb->pcnt[0], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const unsigned long long gen = (unsigned long long)l + 1;
-        if (a == (unsigned long long)P - 1) {
-            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
-            st_rel(&xb->pcnt[0], 0ull);
+        if (participate) {
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            st_rel(&xb->pgen[0], gen);
+            const unsigned long long a =
+                __hip_atomic_fetch_add(&xb->pcnt[0], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (a == (unsigned long long)P - 1) {
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+                st_rel(&xb->pcnt[0], 0ull);
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                for (int x = 0; x < kMaxXcd; ++x) st_rel(&xb->pgen[x * kXLine], gen);
+            }
         }
-        const bool ok = spin_until(c, spin_ticks, [&] { return ld_acq(&xb->pgen[0]) >= gen; });
+        const bool ok = spin_until(c, spin_ticks, [&] { return ld_acq(&xb->pgen[xcd * kXLine]) >= gen; });
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         *s_flag = ok && ld_acq(&c->error) == 0;
     }

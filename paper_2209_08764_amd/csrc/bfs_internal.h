@@ -70,7 +70,7 @@ struct XBar {
     unsigned long long gen[kMaxXcd * kXLine];     // barriers completed, one copy per XCD
     unsigned long long top[kXLine];               // XCD groups complete, monotone within a launch
     unsigned long long pcnt[kXLine];              // arrivals at a barrier of a lite level's workgroups
-    unsigned long long pgen[kXLine];              // last lite level whose workgroups met, + 1
+    unsigned long long pgen[kMaxXcd * kXLine];    // generation of those barriers, one copy per XCD
 };
 
 struct Params {

@@ -1305,9 +1305,10 @@ k_persistent(Params p) {
             [[clang::always_inline]] expand_share(p, l, blockIdx.x, P, ntiles, n_l, e_l, lds, dense, lite);
         }
         // a lite level's compaction needs only its own workgroups' expansion, so only they
-        // meet here; the others go on to the end-of-level barrier
+        // meet here; the others wait for the level's end
         if (lite) {
-            if (blockIdx.x < P && !sub_barrier(c, p.xbar, l, P, p.spin_ticks, s_flag)) return;
+            if (blockIdx.x < P && !sub_barrier(c, p.xbar, xg.xcd, 2ull * l + 1, P, true, p.spin_ticks, s_flag))
+                return;
             hot_ok = false;
         } else if (!xcd_barrier(c, p.xbar, xg, p.spin_ticks, s_flag)) {
             return;
@@ -1354,7 +1355,11 @@ k_persistent(Params p) {
             if (!ok) return;
         }
         fbits_ok = DIR || fb_write;  // top-down: fbits[np] holds exactly the next frontier
-        if (!xcd_barrier(c, p.xbar, xg, p.spin_ticks, s_flag)) return;
+        if (lite) {
+            if (!sub_barrier(c, p.xbar, xg.xcd, 2ull * l + 2, P, blockIdx.x < P, p.spin_ticks, s_flag)) return;
+        } else if (!xcd_barrier(c, p.xbar, xg, p.spin_ticks, s_flag)) {
+            return;
+        }
         if (rec) p.stat_ts[3 * l + 2] = now_ticks();
         ++l;
         n_l = ld_acq(&c->nl[np]);
