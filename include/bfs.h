@@ -110,13 +110,12 @@ typedef struct {
  *   the caller keeps them alive and unchanged until bfs_graph_free.
  *   stream: used for the upload.  *out receives the handle.
  *   Unless BFS_LEAN is given, graphs with m >= 2^22 (or any graph with
- *   BFS_HOT_FILTER) also get a hot-vertex filter: the 2^18 vertices of
+ *   BFS_HOT_FILTER) also get a hot-vertex filter: the 391168 vertices of
  *   highest degree (ties by id) are numbered, and an int32 per edge holds
- *   the number of its target (or -1).  Large levels then test these
+ *   its target, or -1 minus the target's number.  Large levels then test these
  *   targets against a workgroup-local copy of their visited bits before
  *   the global visited bitmap (EXPLORE-VERTEX's visited test; results are
- *   unchanged).  The expansion then reads one 4 B word per edge that holds
- *   either the target or its hot number.  This costs 4 B per edge plus 4 B
+ *   unchanged).  This costs 4 B per edge plus 4 B
  *   per hot vertex of device memory (bfs_graph_aux_bytes) and a host pass
  *   over the degrees.
  * Errors: EINVAL (null pointers, n < 0, m < 0, both or neither pointer flag,

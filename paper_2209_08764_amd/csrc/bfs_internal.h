@@ -22,8 +22,8 @@ constexpr int kPullScan = 16;             // neighbours a lane tests before a ro
 
 // Hot-vertex filter: the kHotBits vertices of highest degree carry a number
 // in [0, kHotBits), and large levels keep their visited bits in LDS.
-constexpr int kHotBits = 1 << 18;
-constexpr int kHotWords = kHotBits / 32;   // 32 KiB of LDS
+constexpr int kHotWords = 12224;          // 47.75 KiB of LDS: with the slices, two workgroups still fit a CU
+constexpr int kHotBits = kHotWords * 32;  // 391168 hot vertices
 constexpr int64_t kHotMinEdges = 1 << 22;  // graphs from this size get the filter by default
 constexpr int kHotMinTiles = 4;            // sub-tiles per share for the LDS copy to pay off
 constexpr int kLiteShares = 32;            // fewer active workgroups: no hot or frontier bit upkeep
