@@ -6,12 +6,11 @@
 //            the paper's per-thread share of e_l) is scanned by one
 //            workgroup.  The tile's slice of the frontier's degree prefix
 //            sums is staged in LDS; every lane finds the vertex owning its
-//            edge by binary search there, reads the neighbour id (coalesced
-//            int32 reads of cols), filters it through the visited bitmap and
-//            the level array, stores level = l + 1 (every racing writer
-//            stores the same value) and owner = its candidate slot, and
-//            appends the vertex to the tile's private queue (EXPLORE-VERTEX,
-//            with the benign race of the Algorithm paragraph).
+//            edge by binary search there, reads the neighbour word, filters
+//            the target through the visited filters, and records each new
+//            vertex (EXPLORE-VERTEX, with the benign race of the Algorithm
+//            paragraph): owner = its candidate slot and a place in the
+//            tile's private queue.
 //   compact  Each tile's queue keeps the entries whose slot still owns the
 //            vertex (Owner de-duplication), reads the survivors' degrees,
 //            and a decoupled look-back scan over tiles gives every survivor
@@ -21,11 +20,14 @@
 //            then writes itself as the start point of every share that
 //            begins inside its edge range (Find-StartExpPoint's scatter).
 //
-// The persistent kernel runs all levels in one launch with a grid barrier
-// between phases; only ceil(e_l / kGrain) workgroups have work in a phase
-// (P_l = min(P, W_l)), and while a level is small a single workgroup runs
-// it alone out of LDS, synchronising with __syncthreads only, so the rest of
-// the grid idles (the paper's "no more cores than the work needs").
+// Dense levels (most edges scanned) record new vertices by their visited
+// bits alone and linearise them by vertex range instead of by queue.  The
+// persistent kernel runs all levels in one launch with grid barriers between
+// phases; only ceil(e_l / kGrain) workgroups have work in a phase
+// (P_l = min(P, W_l)), levels with few workgroups synchronise only those, and
+// while a level is small a single workgroup runs it alone out of LDS,
+// synchronising with __syncthreads only, so the rest of the grid idles: a
+// level occupies only as many cores as its work can use.
 #include "bfs_device.h"
 
 #include <hip/hip_runtime.h>
@@ -189,22 +191,26 @@ __device__ __forceinline__ void decode_tile(const Params& p, const int* x, uint3
 
 // ---- EXPLORE-VERTEX over one share ---------------------------------------------------------
 // The share's sub-tiles are scanned in order, software-pipelined: while the
-// neighbours of sub-tile t are filtered (visited bitmap, then level array)
-// and the new ones appended to the share's private queue, the neighbour
-// reads of sub-tile t + 1 are already in flight and the frontier entries of
-// sub-tile t + 2 are being fetched into registers.  Sub-tile t needs the
-// frontier entries [tstart[t], tstart[t+1]] (at most kSlice of them, since
-// every frontier vertex has an edge), staged in one of two LDS buffers; each
-// lane maps its edge to an entry by binary search there.  A new vertex gets
-// level = l + 1, its visited bit, owner = its queue slot and a place in the
-// queue (the benign race: several lanes may append the same vertex).
+// neighbours of sub-tile t are filtered, the neighbour reads of sub-tile
+// t + 1 are in flight and the frontier entries of sub-tile t + 2 are being
+// fetched into registers.  Sub-tile t needs the frontier entries
+// [tstart[t], tstart[t+1]] (at most kSlice of them, since every frontier
+// vertex has an edge), staged in one of two LDS buffers; each lane maps its
+// edge to an entry by binary search there.  A target passes the visited
+// filters (hot bits, then the visited bitmap) only if it was not reached
+// before this level; push levels then test its level, since every edge into
+// a vertex reached in this level offers its source.  A new vertex gets its
+// visited bit and, except on dense levels (which record new vertices by
+// their visited bits alone), owner = its queue slot and a place in the queue
+// (the benign race: several lanes may append the same vertex).
 //
 // Hot-vertex filter: when the graph numbers its highest-degree vertices,
 // each share with enough edges copies the visited bits of those vertices
 // for levels <= l (hot[l & 1], untouched during level l) into LDS and tests
-// hot targets there before the global bitmap; new hot vertices go to
-// hot[(l + 1) & 1], which the shares also merge hot[l & 1] into.  A set bit
-// still means "visited before this level", so results are unchanged.
+// hot targets there before anything else; new hot vertices go to
+// hot[(l + 1) & 1], which the shares also merge hot[l & 1] into (not on lite
+// levels, which leave the hot bits inexact).  A set bit still means the
+// vertex was visited before this level, so results are unchanged.
 __device__ void expand_share(const Params& p, int l, int b, int P, int ntiles, int n_l, int e_l, int* lds,
                              bool dense = false, bool lite = false) {
     int* s_wave = lds_wave(lds);

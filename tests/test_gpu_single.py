@@ -201,3 +201,23 @@ def test_parent_rules_agree(push_edges, small_edges):
         for s in srcs:
             lv, par = run_single(ws, s)
             assert_same(lv, par, g, [s])
+
+
+def test_default_grid_follows_graph_size():
+    # one workgroup per 16384 edges, a multiple of 8, at least 64; an explicit grid wins
+    g = gg.rmat(12, seed=33)
+    G = Graph(g.offsets, g.cols)
+    s = int(gg.pick_sources(g, 1, seed=2)[0])
+    ws = Workspace(G)
+    lv, par = run_single(ws, s)
+    assert_same(lv, par, g, [s])
+    assert ws.stats()["grid"] == 64
+    ws = Workspace(G, grid=40)
+    lv, par = run_single(ws, s)
+    assert_same(lv, par, g, [s])
+    assert ws.stats()["grid"] == 40
+    big = gg.rmat(17, seed=34)
+    ws = Workspace(Graph(big.offsets, big.cols))
+    run_single(ws, int(gg.pick_sources(big, 1, seed=3)[0]))
+    want = max(64, (big.m // 16384 + 7) // 8 * 8)
+    assert 64 < want < 512 and ws.stats()["grid"] == want  # below what two workgroups per CU allow
