@@ -7,6 +7,7 @@ The mutant tests show that the pins have teeth: plausible mistakes in a BFS
 (a wrong parent rule, a dropped +1, a stale visited check) fail them.
 """
 import itertools
+import math
 import random
 
 import numpy as np
@@ -137,6 +138,51 @@ def test_complete_bipartite_and_heap_tree():
     v = np.arange(n)
     np.testing.assert_array_equal(lv, np.floor(np.log2(v + 1)).astype(np.int32))
     np.testing.assert_array_equal(par[1:], (v[1:] - 1) // 2)
+
+
+def _gen_petersen(n, k):
+    # generalised Petersen graph GP(n, k): outer cycle 0..n-1, spokes i - n+i, inner i+n - (i+k mod n)+n
+    return gg.from_edges(2 * n, [(i, (i + 1) % n) for i in range(n)] + [(i, n + i) for i in range(n)]
+                         + [(n + i, n + (i + k) % n) for i in range(n)])
+
+
+def test_distance_regular_level_counts():
+    # distance-regular graphs have the same number of vertices at distance i from every vertex:
+    # Petersen GP(5,2) 1,3,6; dodecahedron GP(10,2) 1,3,6,6,3,1; Desargues GP(10,3) 1,3,6,6,3,1;
+    # hypercube Q_d the binomial coefficients C(d, i).  Petersen and the dodecahedron have odd
+    # cycles (girth 5); Desargues and Q_d are bipartite.
+    cases = [(_gen_petersen(5, 2), [1, 3, 6]), (_gen_petersen(10, 2), [1, 3, 6, 6, 3, 1]),
+             (_gen_petersen(10, 3), [1, 3, 6, 6, 3, 1])]
+    for d in (3, 5, 7):
+        q = gg.from_edges(1 << d, [(v, v ^ (1 << b)) for v in range(1 << d) for b in range(d) if v < v ^ (1 << b)])
+        cases.append((q, [math.comb(d, i) for i in range(d + 1)]))
+    for g, counts in cases:
+        for s in range(g.n):
+            lv, _ = oracle.bfs(g.offsets, g.cols, s)
+            assert np.bincount(lv).tolist() == counts, (g.n, s)
+
+
+def test_petersen_parents_by_hand():
+    # GP(5,2) from vertex 0: level 1 = {1, 4, 5}; every level-2 vertex has exactly one neighbour
+    # at level 1 (girth 5), so its parent is that neighbour: 2-1, 3-4, 6-1, 7-5, 8-5, 9-4
+    g = _gen_petersen(5, 2)
+    lv, par = oracle.bfs(g.offsets, g.cols, 0)
+    assert lv.tolist() == [0, 1, 2, 2, 1, 1, 2, 2, 2, 2]
+    assert par.tolist() == [0, 0, 1, 4, 0, 0, 1, 5, 5, 4]
+
+
+def test_hypercube_parents_closed_form():
+    # Q_d from s: level(v) = popcount(v ^ s); the closer neighbours flip one bit of v ^ s, and the
+    # smallest of them clears the highest such bit that v has set, else sets the lowest one v lacks
+    d, s = 8, 0b10110010
+    q = gg.from_edges(1 << d, [(v, v ^ (1 << b)) for v in range(1 << d) for b in range(d) if v < v ^ (1 << b)])
+    lv, par = oracle.bfs(q.offsets, q.cols, s)
+    for v in range(1 << d):
+        diff = v ^ s
+        assert lv[v] == bin(diff).count("1")
+        down = diff & v
+        want = v ^ (1 << (down.bit_length() - 1)) if down else (v | (diff & -diff) if diff else s)
+        assert par[v] == want, v
 
 
 def test_empty_and_isolated():
