@@ -134,6 +134,66 @@ __device__ __forceinline__ int first_parent_wg(const Params& p, int rs, int d, i
     return first_hit_wg(p, rs, d, [&](int c) { return p.level[c] == l; }, s_red);
 }
 
+// Owner of each of this lane's kVT sub-tile positions g0 + i * kBlock +
+// threadIdx.x: the last of the nv staged entries whose exclusive degree sum
+// ex[] is at most the position.  The sums ascend strictly (every staged
+// vertex has an edge) and ex[0] <= g0.  A wave owns rows of 64 consecutive
+// positions and resolves each row together instead of searching per lane:
+// ballots over 64 sampled sums, then over the stretch between two samples,
+// give the entry o covering the row's first position q0; each later entry
+// that starts inside the row sends a flag to the lane of its first position
+// (ds_permute, which hands unaddressed lanes zero), and a lane's owner is o
+// plus the starts at or before it.  Whole waves must call it; the code is
+// branch-free per row, so the rows' LDS round trips overlap.
+template <bool SMALL>  // SMALL: nv <= 64, the samples are all the entries
+__device__ __forceinline__ void owners_of_rows_n(const int* ex, int nv, int g0, int* own) {
+    const int lane = lane_id();
+    const int s = (nv + 63) >> 6;  // sampling stride, 1..33 for nv <= kSlice
+    // Every read is issued from a clamped index and every lane's value is
+    // compared; lanes past the entries are masked out of the ballots (bitwise
+    // tests, so that no read sits behind a branch).  The rows go step by step
+    // together, so that their reads are in flight at once.
+    const int x1 = ex[min(lane * s, nv - 1)];
+    const bool in1 = lane * s < nv;
+    int q0[kVT], o[kVT], xs[kVT];
+    bool ins[kVT];
+#pragma unroll
+    for (int i = 0; i < kVT; ++i) {
+        q0[i] = g0 + i * kBlock + wave_id() * 64;
+        o[i] = (max((int)__popcll(ballot(in1 & (x1 <= q0[i]))), 1) - 1) * s;
+        xs[i] = x1;
+        ins[i] = in1;
+    }
+    if (!SMALL) {
+        int x2[kVT];
+#pragma unroll
+        for (int i = 0; i < kVT; ++i) x2[i] = ex[min(o[i] + lane, nv - 1)];
+#pragma unroll
+        for (int i = 0; i < kVT; ++i) {
+            o[i] += max((int)__popcll(ballot((lane < s) & (o[i] + lane < nv) & (x2[i] <= q0[i]))), 1) - 1;
+            xs[i] = ex[min(o[i] + 1 + lane, nv - 1)];
+            ins[i] = o[i] + 1 + lane < nv;
+        }
+    }
+    int r[kVT];
+#pragma unroll
+    for (int i = 0; i < kVT; ++i) {
+        const int d = xs[i] - q0[i];  // > 0 for the entries after o
+        const bool send = ins[i] & (d >= 1) & (d < 64);
+        r[i] = __builtin_amdgcn_ds_permute((send ? d : 0) << 2, send ? d : 0);
+    }
+#pragma unroll
+    for (int i = 0; i < kVT; ++i) {
+        const bool hit = (lane > 0) & (r[i] == lane);
+        own[i] = min(o[i] + mbcnt(ballot(hit)) + (int)hit, nv - 1);
+    }
+}
+
+__device__ __forceinline__ void owners_of_rows(const int* ex, int nv, int g0, int* own) {
+    if (nv <= 64) owners_of_rows_n<true>(ex, nv, g0, own);
+    else owners_of_rows_n<false>(ex, nv, g0, own);
+}
+
 // Issues the neighbour reads of this lane's kVT edges among [g0, g1) of the
 // current frontier, whose entries [j0, j0 + nv) are staged in `sl` (ex | rs):
 // raw words of the neighbour stream into x (decode_tile interprets them) and
@@ -147,7 +207,7 @@ __device__ __forceinline__ void gather_tile(const Params& p, const int* sl, int 
     int gg[kVT], own[kVT];
 #pragma unroll
     for (int i = 0; i < kVT; ++i) gg[i] = min(g0 + i * kBlock + (int)threadIdx.x, g1 - 1);
-    search_owners<kVT>(sl, nv, gg, own);
+    owners_of_rows(sl, nv, g0, own);
     const int32_t* src = p.colx ? p.colx : p.cols;
     // frontier vertices first (push levels only), then the neighbour words, which every
     // lane issues: a wait for anything issued before them can leave them in flight
