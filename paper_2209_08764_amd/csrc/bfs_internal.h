@@ -31,7 +31,7 @@ constexpr int kHotTarget = -2;             // a gathered edge whose target is ho
 
 // LDS words used by the level loop (the two layouts share one allocation).
 constexpr int kLdsSmall = 3 * kSmallN + 1 + kSmallC;   // frontier (v, rs, ex) + claimed vertices
-constexpr int kLdsLarge = 2 * 2 * kSlice + kHotWords;  // double-buffered sub-tile slices (ex, rs), hot bits
+constexpr int kLdsLarge = 2 * 2 * kSlice + kHotWords;  // double-buffered sub-tile slices (ex, rs - ex), hot bits
 constexpr int kLdsWords = (kLdsSmall > kLdsLarge ? kLdsSmall : kLdsLarge) + 2 * kWaves + 8;
 
 // ---- device control block --------------------------------------------------------------

@@ -195,7 +195,7 @@ __device__ __forceinline__ void owners_of_rows(const int* ex, int nv, int g0, in
 }
 
 // Issues the neighbour reads of this lane's kVT edges among [g0, g1) of the
-// current frontier, whose entries [j0, j0 + nv) are staged in `sl` (ex | rs):
+// current frontier, whose entries [j0, j0 + nv) are staged in `sl` (ex | rs - ex):
 // raw words of the neighbour stream into x (decode_tile interprets them) and
 // bit i of *ok set where edge i exists; with `fv` also the frontier vertex
 // each edge comes from (for pushed parents).  Every neighbour read is
@@ -220,7 +220,7 @@ __device__ __forceinline__ void gather_tile(const Params& p, const int* sl, int 
     for (int i = 0; i < kVT; ++i) {
         const int g = g0 + i * kBlock + threadIdx.x;
         const int lo = own[i];
-        const int idx = sl[kSlice + lo] + (gg[i] - sl[lo]);
+        const int idx = sl[kSlice + lo] + gg[i];
         const bool in = (unsigned)idx < (unsigned)p.m;
         if (g < g1 && in) m |= 1u << i;
         if (g < g1 && !in) flag_internal(p.ctrl);
@@ -306,8 +306,9 @@ __device__ void expand_share(const Params& p, int l, int b, int P, int ntiles, i
     auto slice_ok = [&](int a, int z) { return a >= 0 && z < n_l && z >= a && z - a + 1 <= kSlice; };
     auto stage_slice = [&](int* buf, int a, int z) {
         for (int i = threadIdx.x; i <= z - a; i += kBlock) {
-            buf[i] = fex[a + i];
-            buf[kSlice + i] = frs[a + i];
+            const int e = fex[a + i];
+            buf[i] = e;
+            buf[kSlice + i] = frs[a + i] - e;
         }
     };
     int* buf0 = lds;
@@ -474,7 +475,7 @@ __device__ void expand_share(const Params& p, int l, int b, int P, int ntiles, i
                     const int i = threadIdx.x + r * kBlock;
                     if (i <= z2 - a2) {
                         free2[i] = pe[r];
-                        free2[kSlice + i] = pr[r];
+                        free2[kSlice + i] = pr[r] - pe[r];
                     }
                 }
             }
