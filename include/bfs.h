@@ -75,7 +75,7 @@ typedef struct bfs_workspace_s* bfs_workspace_t;  /* scratch for one in-flight r
 #define BFS_OPT_BATCH_LEVELS 7 /* batched search: levels per replay of the captured loop (default 8) */
 #define BFS_OPT_PUSH_EDGES  6  /* levels with at most this many edges push parents (atomic
                                   minimum per edge); larger ones pull them from sorted rows
-                                  (default m / 8) */
+                                  (default m / 12) */
 #define BFS_OPT_BATCH_GRAIN 8  /* batched search: edges per expansion sub-tile, the grain of
                                   the equal edge split (512, 1024 or 2048; default 1024) */
 #define BFS_OPT_BATCH_TILE  9  /* batched search: vertices per tile of the dense update pass
@@ -88,7 +88,7 @@ typedef struct bfs_workspace_s* bfs_workspace_t;  /* scratch for one in-flight r
 #define BFS_OPT_DENSE_EDGES 12 /* BFS_MODE_AUTO / INSENSITIVE: a level that pulls its parents (or
                                   has none to find) and scans at least this many edges records its
                                   new vertices as bits instead of private-queue entries and
-                                  linearises them in vertex order (0 = never; default m / 8) */
+                                  linearises them in vertex order (0 = never; default m / 12) */
 
 typedef struct {
     int32_t levels;          /* frontiers processed: max level + 1 */

@@ -39,6 +39,14 @@ bfs_status_t fail(bfs_status_t code, const char* fmt, ...) {
     } while (0)
 
 constexpr uint64_t kSpinTicks = 300000000ull;  // 3 s at the 100 MHz s_memrealtime clock
+// Default split of levels by their edges: up to m / kLevelSplit a level pushes
+// its parents (an atomic minimum per edge into an unsettled vertex); above it
+// the level pulls them from sorted rows and keeps its new vertices as bits.
+// Pushing pays for small levels and for frontiers of a few hubs, whose new
+// vertices include other hubs with rows too long to scan.  Measured on R-MAT
+// scale 24 over 64 sources: m / 8 gave 4.27 ms, m / 12 4.19, m / 16 4.20,
+// m / 24 4.27 per search.
+constexpr int64_t kLevelSplit = 12;
 
 template <typename T>
 hipError_t dalloc(T** p, size_t count) {
@@ -121,8 +129,8 @@ struct bfs_workspace_s {
     int32_t small_edges = kDefaultSmallEdges;
     int32_t bu_alpha = 14;
     int32_t bu_beta = 24;
-    int32_t push_edges = -1;  // -1: m / 8 of the workspace's graph
-    int32_t dense_edges = -1; // -1: m / 8 of the workspace's graph
+    int32_t push_edges = -1;  // -1: m / kLevelSplit of the workspace's graph
+    int32_t dense_edges = -1; // -1: m / kLevelSplit of the workspace's graph
     int32_t grid_opt = 0;
     int32_t profile = 0;
     int32_t batch_pull = -2;  // -2: library default
@@ -159,7 +167,8 @@ bfs_status_t validate_csr(const int32_t* off, const int32_t* cols, int32_t n, in
 }
 
 int32_t dense_edges_of(const bfs_workspace_s* ws) {
-    return ws->dense_edges >= 0 ? ws->dense_edges : (int32_t)std::min<int64_t>(std::max<int64_t>(ws->g->m / 8, 1), INT32_MAX);
+    return ws->dense_edges >= 0 ? ws->dense_edges
+                                : (int32_t)std::min<int64_t>(std::max<int64_t>(ws->g->m / kLevelSplit, 1), INT32_MAX);
 }
 
 Params make_params(bfs_workspace_s* ws, int32_t* level, int32_t* parent) {
@@ -202,7 +211,7 @@ Params make_params(bfs_workspace_s* ws, int32_t* level, int32_t* parent) {
     // Pushing costs one atomic per scanned edge into an unsettled vertex; pulling
     // costs about one row read per new vertex but long ones when the frontier is
     // small next to what it discovers.  Levels below an eighth of the graph push.
-    p.push_edges = ws->push_edges >= 0 ? ws->push_edges : (int32_t)std::min<int64_t>(ws->g->m / 8, INT32_MAX);
+    p.push_edges = ws->push_edges >= 0 ? ws->push_edges : (int32_t)std::min<int64_t>(ws->g->m / kLevelSplit, INT32_MAX);
     p.max_tiles = ws->max_tiles;
     p.spin_ticks = kSpinTicks;
     return p;
@@ -1100,7 +1109,7 @@ void current_tuning(const bfs_workspace_s* ws, bfs_tune_t* t) {
     t->batch_pull = ws->batch_pull >= -1 ? ws->batch_pull : batch_pull_edges(ws);
     t->grid = ws->grid_opt;
     t->small_edges = ws->small_edges;
-    t->push_edges = ws->push_edges >= 0 ? ws->push_edges : (int32_t)std::min<int64_t>(ws->g->m / 8, INT32_MAX);
+    t->push_edges = ws->push_edges >= 0 ? ws->push_edges : (int32_t)std::min<int64_t>(ws->g->m / kLevelSplit, INT32_MAX);
     t->dense_edges = dense_edges_of(ws);
 }
 
@@ -1229,16 +1238,19 @@ bfs_status_t bfs_autotune(bfs_workspace_t ws, const int32_t* sources, int32_t k,
         if (!st)
             st = descend(smp, &best, smalls, P{start.small_edges, 0},
                          [&](P c) { return bfs_workspace_set_option(ws, BFS_OPT_SMALL_EDGES, c.first); });
-        std::vector<P> pushes;
-        for (int64_t d : {32, 16, 8, 4}) pushes.push_back({std::min<int64_t>(m / d, INT32_MAX), 0});
+        // push and dense thresholds move together: a level above the split pulls its
+        // parents and keeps its new vertices as bits (or, last, never as bits)
+        std::vector<P> splits;
+        for (int64_t d : {32, 16, 12, 8, 4}) {
+            const int64_t e = std::min<int64_t>(std::max<int64_t>(m / d, 1), INT32_MAX);
+            splits.push_back({e, e});
+        }
+        splits.push_back({std::min<int64_t>(m / kLevelSplit, INT32_MAX), 0});
         if (!st)
-            st = descend(smp, &best, pushes, P{start.push_edges, 0},
-                         [&](P c) { return bfs_workspace_set_option(ws, BFS_OPT_PUSH_EDGES, c.first); });
-        std::vector<P> denses{{0, 0}};
-        for (int64_t d : {16, 8, 4}) denses.push_back({std::min<int64_t>(std::max<int64_t>(m / d, 1), INT32_MAX), 0});
-        if (!st)
-            st = descend(smp, &best, denses, P{start.dense_edges, 0},
-                         [&](P c) { return bfs_workspace_set_option(ws, BFS_OPT_DENSE_EDGES, c.first); });
+            st = descend(smp, &best, splits, P{start.push_edges, start.dense_edges}, [&](P c) {
+                bfs_status_t e = bfs_workspace_set_option(ws, BFS_OPT_PUSH_EDGES, c.first);
+                return e ? e : bfs_workspace_set_option(ws, BFS_OPT_DENSE_EDGES, c.second);
+            });
     }
     ws->mode = saved_mode;
     ws->profile = saved_profile;

@@ -98,6 +98,6 @@ def test_dense_threshold_rejects_negative():
     ws = Workspace(Graph(g.offsets, g.cols))
     with pytest.raises(BFSError):
         bfs_workspace_set_option(ws.handle, BFS_OPT_DENSE_EDGES, -1)
-    assert ws.tuning()["dense_edges"] == max(g.m // 8, 1)
+    assert ws.tuning()["dense_edges"] == max(g.m // 12, 1)
     bfs_workspace_set_option(ws.handle, BFS_OPT_DENSE_EDGES, 0)
     assert ws.tuning()["dense_edges"] == 0
