@@ -378,8 +378,10 @@ __device__ void expand_share(const Params& p, int l, int b, int P, int ntiles, i
             const uint32_t* pa = (hot_open && !fvp) ? hnext + (hc[i] >> 5) : p.bitmap + (max(vc[i], 0) >> 5);
             pw[i] = *pa;
         }
-        // ids of open hot targets, only in waves that have one (the reads behind stay unconditional)
-        if (ballot(any_open)) {
+        // ids of open hot targets, only in waves that have one (the reads behind stay
+        // unconditional); a dense level needs none: its hot discoveries reach the visited
+        // bitmap from the hot bits after the level (merge_hot_discoveries)
+        if (!dense && ballot(any_open)) {
 #pragma unroll
             for (int i = 0; i < kVT; ++i) hid[i] = p.hot_vid[hc[i] >= 0 ? hc[i] : 0];
         }
@@ -396,7 +398,7 @@ __device__ void expand_share(const Params& p, int l, int b, int P, int ntiles, i
 #pragma unroll
         for (int i = 0; i < kVT; ++i) {
             const bool hot = hc[i] >= 0;
-            if (hot) vc[i] = hid[i];
+            if (hot) vc[i] = dense ? 0 : hid[i];  // dense: a stand-in id, used by nothing below
             // a push level tests an open hot target by its level below, like any other
             const bool seen = hot ? !fvp && ((pw[i] >> (hc[i] & 31)) & 1u) : ((pw[i] >> (vc[i] & 31)) & 1u);
             if (vc[i] >= 0 && seen) vc[i] = -1;
@@ -429,7 +431,7 @@ __device__ void expand_share(const Params& p, int l, int b, int P, int ntiles, i
         for (int i = 0; i < kVT; ++i) {
             if (fresh[i]) {
                 if (fvp) p.level[vc[i]] = l + 1;
-                else
+                else if (!dense || hc[i] < 0)
                     __hip_atomic_fetch_or(&p.bitmap[vc[i] >> 5], 1u << (vc[i] & 31), __ATOMIC_RELAXED,
                                           __HIP_MEMORY_SCOPE_AGENT);
                 if (hnext && hc[i] >= 0 && !lite)
@@ -1243,6 +1245,27 @@ __device__ __forceinline__ void rebuild_hot_bits(const Params& p, uint32_t* hot,
     }
 }
 
+// After a dense level's expansion: its hot discoveries, hot[next] & ~hot[cur]
+// (the current bits are exact on dense levels), get the visited bits the
+// expansion left unset, so that the compaction finds them among the bits
+// set since the level's snapshot.  Grid-strided over the hot words.
+__device__ __forceinline__ void merge_hot_discoveries(const Params& p, const uint32_t* hcur, const uint32_t* hnext,
+                                                      int64_t first, int64_t stride) {
+    for (int64_t w = first; w < p.hot_words; w += stride) {
+        uint32_t x = hnext[w] & ~hcur[w];
+        while (x) {
+            const int64_t h = w * 32 + __builtin_ctz(x);
+            x &= x - 1;
+            if (h < p.hot_count) {
+                const int v = p.hot_vid[h];
+                if ((unsigned)v < (unsigned)p.n)
+                    __hip_atomic_fetch_or(&p.bitmap[v >> 5], 1u << (v & 31), __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+    }
+}
+
 __device__ __forceinline__ int shares_for(int ntiles, int G) { return ntiles < G ? ntiles : G; }
 
 // Register budget of the persistent kernel: its occupancy (workgroups per
@@ -1379,6 +1402,11 @@ k_persistent(Params p) {
             hot_ok = false;
         } else if (!xcd_barrier(c, p.xbar, xg, p.spin_ticks, s_flag)) {
             return;
+        }
+        if (dense && p.hot_words > 0) {
+            merge_hot_discoveries(p, p.hot[par], p.hot[np], (int64_t)blockIdx.x * kBlock + threadIdx.x,
+                                  (int64_t)G * kBlock);
+            if (!xcd_barrier(c, p.xbar, xg, p.spin_ticks, s_flag)) return;
         }
         if (rec) p.stat_ts[3 * l + 1] = now_ticks();
         if (DIR)  // this level's frontier bits have been read: clear them for level l + 2
