@@ -6,6 +6,8 @@ the same seeded graph.  Sizes span many shares of 2048 edges and ragged
 tails; the mode/threshold/grid sweeps check that the benign race of the
 owner de-duplication never changes a result.
 """
+import math
+
 import numpy as np
 import pytest
 
@@ -72,6 +74,48 @@ def test_structured_graphs(make, srcs, mode):
     for s in srcs:
         lv, par = run_single(ws, s)
         assert_same(lv, par, g, [s])
+
+
+def _gen_petersen(n, k):
+    return gg.from_edges(2 * n, [(i, (i + 1) % n) for i in range(n)] + [(i, n + i) for i in range(n)]
+                         + [(n + i, n + (i + k) % n) for i in range(n)])
+
+
+def _hypercube(d):
+    return gg.from_edges(1 << d, [(v, v ^ (1 << b)) for v in range(1 << d) for b in range(d) if v < v ^ (1 << b)])
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_distance_regular_graphs_every_source(mode):
+    # level counts fixed by the graph (Petersen 1,3,6; dodecahedron and Desargues 1,3,6,6,3,1;
+    # Q_7 binomials), and levels and parents equal to the oracle's, from every vertex
+    cases = [(_gen_petersen(5, 2), [1, 3, 6]), (_gen_petersen(10, 2), [1, 3, 6, 6, 3, 1]),
+             (_gen_petersen(10, 3), [1, 3, 6, 6, 3, 1]), (_hypercube(7), [math.comb(7, i) for i in range(8)])]
+    for g, counts in cases:
+        ws = Workspace(Graph(g.offsets, g.cols), mode=mode)
+        for s in range(g.n):
+            lv, par = run_single(ws, s)
+            assert np.bincount(lv).tolist() == counts, (g.n, s)
+            assert_same(lv, par, g, [s])
+
+
+@pytest.mark.parametrize("small_edges", [0, None])
+def test_hypercube_closed_form(small_edges):
+    # Q_12 (4096 vertices, 24576 directed edges, middle levels over 10 000 edges): level is the
+    # Hamming distance; the min-id closer neighbour clears the highest bit of v ^ s that v has
+    # set, else sets the lowest one it lacks
+    d = 12
+    g = _hypercube(d)
+    ws = Workspace(Graph(g.offsets, g.cols), **({} if small_edges is None else {"small_edges": small_edges}))
+    v = np.arange(1 << d)
+    for s in (0, 0b101101110010, (1 << d) - 1):
+        lv, par = run_single(ws, s)
+        diff = v ^ s
+        np.testing.assert_array_equal(lv, [bin(x).count("1") for x in diff])
+        down = diff & v
+        want = np.where(down > 0, v ^ (1 << (np.floor(np.log2(np.maximum(down, 1))).astype(np.int64))),
+                        np.where(diff > 0, v | (diff & -diff), s))
+        np.testing.assert_array_equal(par, want)
 
 
 def test_isolated_source_and_tiny_graphs():
