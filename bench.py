@@ -21,6 +21,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import threading
 import time
@@ -47,10 +48,15 @@ def hmean(x):
 
 
 def kernel_source_hash() -> str:
-    """Hash of the search kernel's sources (the kernel file and the device headers it includes)."""
+    """Hash of the search kernel's code (the kernel file and the device headers it includes).
+    Comments and layout are left out, so that stored counters stay valid across comment edits
+    and go stale with any change to the code itself."""
     h = hashlib.sha256()
     for path in KERNEL_SRC:
-        h.update(open(path, "rb").read())
+        text = open(path, encoding="utf-8").read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

@@ -5,8 +5,8 @@
 //   expand   Each share of kGrain consecutive frontier edges (a "tile",
 //            the paper's per-thread share of e_l) is scanned by one
 //            workgroup.  The tile's slice of the frontier's degree prefix
-//            sums is staged in LDS; every lane finds the vertex owning its
-//            edge by binary search there, reads the neighbour word, filters
+//            sums is staged in LDS; each wave finds the vertices owning its
+//            rows of 64 edges there, every lane reads its neighbour word, filters
 //            the target through the visited filters, and records each new
 //            vertex (EXPLORE-VERTEX, with the benign race of the Algorithm
 //            paragraph): owner = its candidate slot and a place in the
@@ -255,8 +255,8 @@ __device__ __forceinline__ void decode_tile(const Params& p, const int* x, uint3
 // t + 1 are in flight and the frontier entries of sub-tile t + 2 are being
 // fetched into registers.  Sub-tile t needs the frontier entries
 // [tstart[t], tstart[t+1]] (at most kSlice of them, since every frontier
-// vertex has an edge), staged in one of two LDS buffers; each lane maps its
-// edge to an entry by binary search there.  A target passes the visited
+// vertex has an edge), staged in one of two LDS buffers; each wave maps its
+// rows of 64 edges to entries there (owners_of_rows).  A target passes the visited
 // filters (hot bits, then the visited bitmap) only if it was not reached
 // before this level; push levels then test its level, since every edge into
 // a vertex reached in this level offers its source.  A new vertex gets its

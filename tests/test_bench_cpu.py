@@ -73,3 +73,14 @@ def test_algorithmic_bytes():
     run, kernel = bench.algorithmic_bytes(n=100, n_c=40, m_c=1000)
     assert run == 4 * 1000 + 8 * 100 + 16 * 40
     assert kernel == 4 * 1000 + 24 * 40
+
+
+def test_kernel_hash_ignores_comments_only(tmp_path, monkeypatch):
+    src = tmp_path / "k.hip"
+    src.write_text("// note\nint f(int x) {\n    return x + 1;  /* one */\n}\n")
+    monkeypatch.setattr(bench, "KERNEL_SRC", [str(src)])
+    h0 = bench.kernel_source_hash()
+    src.write_text("// another note\nint f(int x) { return x + 1; }\n")
+    assert bench.kernel_source_hash() == h0
+    src.write_text("int f(int x) { return x + 2; }\n")
+    assert bench.kernel_source_hash() != h0
