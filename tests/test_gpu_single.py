@@ -118,6 +118,32 @@ def test_hypercube_closed_form(small_edges):
         np.testing.assert_array_equal(par, want)
 
 
+def _hubs_and_leaves(hubs, leaves, max_extra, seed):
+    # vertex 0 -> hubs 1..hubs -> leaves; each leaf also links to up to max_extra other leaves, so
+    # the level of leaves has sub-tiles of 2048 edges with anywhere from ~50 to 2049 entries
+    rng = np.random.default_rng(seed)
+    n = 1 + hubs + leaves
+    edges = [(0, h) for h in range(1, hubs + 1)]
+    edges += [(1 + (i % hubs), 1 + hubs + i) for i in range(leaves)]
+    if max_extra:
+        deg = rng.integers(0, max_extra + 1, size=leaves)
+        for i in range(leaves):
+            for j in rng.integers(0, leaves, size=int(deg[i])):
+                if j != i:
+                    edges.append((1 + hubs + i, 1 + hubs + int(j)))
+    return gg.from_edges(n, edges)
+
+
+@pytest.mark.parametrize("max_extra", [0, 1, 3, 40])
+@pytest.mark.parametrize("mode", [BFS_MODE_AUTO, BFS_MODE_INSENSITIVE])
+def test_frontiers_of_short_rows(max_extra, mode):
+    g = _hubs_and_leaves(3, 9000, max_extra, seed=5 + max_extra)
+    ws = Workspace(Graph(g.offsets, g.cols), mode=mode, small_edges=0)
+    for s in (0, 1, g.n - 1):
+        lv, par = run_single(ws, s)
+        assert_same(lv, par, g, [s])
+
+
 def test_isolated_source_and_tiny_graphs():
     g = gg.from_edges(6, [(0, 1), (1, 2)])
     G = Graph(g.offsets, g.cols)
