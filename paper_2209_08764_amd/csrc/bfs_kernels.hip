@@ -517,13 +517,29 @@ __device__ __forceinline__ void pull_parents_chunk(const Params& p, const int* v
 #pragma unroll
     for (int i = 0; i < kVT; ++i)
 #pragma unroll
-        for (int q = 0; q < kFirst; ++q) c[i][q] = v[i] >= 0 && q < d[i] ? p.cols[rs[i] + q] : -1;
+        for (int q = 0; q < kFirst; ++q) {
+            // every lane reads, from a clamped position of its row (of row 0 for no row), and
+            // masks afterwards, so that no read sits behind a branch
+            const int x = p.cols[rs[i] + max(min(q, d[i] - 1), 0)];
+            c[i][q] = ((v[i] >= 0) & (q < d[i])) ? x : -1;
+        }
+    if (fpull) {
 #pragma unroll
-    for (int i = 0; i < kVT; ++i)
+        for (int i = 0; i < kVT; ++i)
 #pragma unroll
-        for (int q = 0; q < kFirst; ++q)
-            h[i][q] = (unsigned)c[i][q] < (unsigned)p.n &&
-                      (fpull ? frontier_bit(fpull, c[i][q]) : p.level[c[i][q]] == l);
+            for (int q = 0; q < kFirst; ++q) {
+                const int x = (unsigned)c[i][q] < (unsigned)p.n ? c[i][q] : 0;
+                h[i][q] = (c[i][q] >= 0) & frontier_bit(fpull, x);
+            }
+    } else {
+#pragma unroll
+        for (int i = 0; i < kVT; ++i)
+#pragma unroll
+            for (int q = 0; q < kFirst; ++q) {
+                const int x = (unsigned)c[i][q] < (unsigned)p.n ? c[i][q] : 0;
+                h[i][q] = (c[i][q] >= 0) & (p.level[x] == l);
+            }
+    }
 #pragma unroll
     for (int i = 0; i < kVT; ++i) {
         if (v[i] >= 0) {
