@@ -18,7 +18,7 @@ constexpr int kSmallN = 4096;             // frontier capacity of single-workgro
 constexpr int kSmallC = 4096;             // candidates held in LDS in single-workgroup levels
 constexpr int kStatCap = 1 << 16;         // per-level statistics kept
 constexpr int kDefaultSmallEdges = kBlock * kVTS;  // one round of the lone workgroup
-constexpr int kPullScan = 16;             // neighbours a lane tests before a row goes to the whole workgroup
+constexpr int kPullScan = 32;             // neighbours a lane tests before a row goes to the whole workgroup
 
 // Hot-vertex filter: the kHotBits vertices of highest degree carry a number
 // in [0, kHotBits), and large levels keep their visited bits in LDS.
