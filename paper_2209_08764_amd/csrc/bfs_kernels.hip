@@ -933,20 +933,22 @@ __device__ __forceinline__ void bottom_up_share(const Params& p, int l, int b, i
 #pragma unroll
             for (int q = 0; q < 4; ++q)
                 if (found[i] < 0 && (unsigned)c[i][q] < (unsigned)p.n && frontier_bit(fb, c[i][q])) found[i] = c[i][q];
-        // the rest of the first kPullScan neighbours of rows still open
+        // the next kPullScan neighbours of rows still open, four at a time
+        bool hard[kBU];
 #pragma unroll
         for (int i = 0; i < kBU; ++i) {
-            const int end = rs[i] + min(d[i], kPullScan);
-            for (int e = rs[i] + 4; e < end && found[i] < 0; ++e) {
-                const int cc = p.cols[e];
-                if ((unsigned)cc < (unsigned)p.n && frontier_bit(fb, cc)) found[i] = cc;
+            hard[i] = false;
+            if (found[i] < 0 && d[i] > 4) {
+                const int f = first_parent_lane(p, rs[i] + 4, d[i] - 4, l, fb);
+                if (f >= 0) found[i] = f;
+                hard[i] = f == -2;
             }
         }
 #pragma unroll
         for (int i = 0; i < kBU; ++i) {
             bu_settle(p, l, qbase, s_cnt, v[i], found[i], found[i] >= 0, true);
             if (found[i] >= 0) my_e += d[i];
-            if (found[i] < 0 && d[i] > kPullScan) {
+            if (hard[i]) {
                 const int h = atomicAdd(s_nh, 1);
                 s_hard[3 * h] = v[i];
                 s_hard[3 * h + 1] = rs[i];
