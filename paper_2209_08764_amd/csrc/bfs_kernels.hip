@@ -599,10 +599,18 @@ __device__ bool compact_share(const Params& p, int l, int b, int P, int ntiles, 
         if (threadIdx.x == 0) flag_internal(p.ctrl);
         qn = 0;
     }
-    // pass 1
+    // pass 1; a queue of one chunk keeps its survivors in registers for pass 2
+    const bool one = qn <= kGrain;
+    int kv[kVT], krs[kVT], kd[kVT], kpos0 = 0, ke0 = 0;
+#pragma unroll
+    for (int i = 0; i < kVT; ++i) {  // an empty queue (qn = 0) runs no chunk: no entries then
+        kv[i] = -1;
+        krs[i] = 0;
+        kd[i] = 0;
+    }
     int surv = 0, degsum = 0, raw = 0;
     for (int c0 = 0; c0 < qn; c0 += kGrain) {
-        int v[kVT], d[kVT];
+        int v[kVT], d[kVT], rs[kVT];
         int tc = 0, ts = 0, tr = 0;
 #pragma unroll
         for (int i = 0; i < kVT; ++i) {
@@ -617,9 +625,11 @@ __device__ bool compact_share(const Params& p, int l, int b, int P, int ntiles, 
 #pragma unroll
         for (int i = 0; i < kVT; ++i) {
             d[i] = 0;
+            rs[i] = 0;
             if (v[i] >= 0) {
                 if (!settle) p.level[v[i]] = l + 1;
-                d[i] = p.offsets[v[i] + 1] - p.offsets[v[i]];
+                rs[i] = p.offsets[v[i]];
+                d[i] = p.offsets[v[i] + 1] - rs[i];
                 ++tr;
                 if (set_bits)  // roots and push levels; pull levels set bits at discovery
                     __hip_atomic_fetch_or(&p.bitmap[v[i] >> 5], 1u << (v[i] & 31), __ATOMIC_RELAXED,
@@ -633,13 +643,26 @@ __device__ bool compact_share(const Params& p, int l, int b, int P, int ntiles, 
         }
         int C, S, R;
         const int pos0 = block_excl_scan(tc, s_wave, &C);
-        block_excl_scan(ts, s_wave2, &S);
+        const int e0 = block_excl_scan(ts, s_wave2, &S);
         block_excl_scan(tr, s_wave, &R);
-        // in place: every read of this chunk fed the scans, so it completed before their barriers
-        int pos = surv + pos0;
+        if (one) {
 #pragma unroll
-        for (int i = 0; i < kVT; ++i)
-            if (v[i] >= 0 && d[i] > 0) p.cand[qbase + pos++] = v[i];
+            for (int i = 0; i < kVT; ++i) {
+                // a slot without an entry has row start and degree 0, as the parent pull's
+                // clamped reads require
+                kv[i] = v[i] >= 0 && d[i] > 0 ? v[i] : -1;
+                krs[i] = kv[i] >= 0 ? rs[i] : 0;
+                kd[i] = kv[i] >= 0 ? d[i] : 0;
+            }
+            kpos0 = pos0;
+            ke0 = e0;
+        } else {
+            // in place: every read of this chunk fed the scans, so it completed before their barriers
+            int pos = surv + pos0;
+#pragma unroll
+            for (int i = 0; i < kVT; ++i)
+                if (v[i] >= 0 && d[i] > 0) p.cand[qbase + pos++] = v[i];
+        }
         surv += C;
         degsum += S;
         raw += R;
@@ -669,6 +692,27 @@ __device__ bool compact_share(const Params& p, int l, int b, int P, int ntiles, 
     if (!ok) return false;
     // pass 2
     const bool pull = p.parent && l >= 0 && pull_parents;
+    if (one) {
+        // the survivors are this thread's own from pass 1, in the order pass 1 counted them
+        int pos = pc + kpos0, e = ps + ke0;
+        if (pull && surv > 0) pull_parents_chunk(p, kv, krs, kd, l, fpull, lds);  // surv: uniform
+#pragma unroll
+        for (int i = 0; i < kVT; ++i) {
+            if (kv[i] >= 0) {
+                if ((unsigned)pos < (unsigned)p.n) {
+                    p.f_v[np][pos] = kv[i];
+                    p.f_rs[np][pos] = krs[i];
+                    p.f_ex[np][pos] = e;
+                    scatter_starts(p, p.tstart[np], pos, e, kd[i]);
+                } else {
+                    flag_internal(p.ctrl);
+                }
+                e += kd[i];
+                ++pos;
+            }
+        }
+        return true;
+    }
     int run_e = 0;
     for (int c0 = 0; c0 < surv; c0 += kGrain) {
         int v[kVT], rs[kVT], d[kVT];
