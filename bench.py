@@ -670,7 +670,7 @@ def main():
         rocpd_summary(args.rocpd_summary)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build runs the search on a single MI355X "
+        print("bench.py measures one GPU only: the search runs on a single MI355X "
               "(sharding across GPUs is not implemented)", file=sys.stderr)
         sys.exit(2)
     if args.calib_copy:
