@@ -10,9 +10,11 @@ Contents
                    definition of Figure 1's output d[0:n-1], plus parents)
   brute.py         Floyd-Warshall all-pairs distances (a different algorithm)
   certify.py       O(n + m) certificate that a (level, parent) pair is exact
-  s3bfs_steps.py   the paper's per-level steps (Figure 1 and the Algorithm
-                   and Analysis paragraphs) written out in Python, used as the
-                   reference for the GPU primitives and per-level statistics
+  s3bfs_steps.py   one search round as separate primitives (degree gather,
+                   prefix sums, chunk starts, scanning, ownership filter,
+                   concatenation; Figure 1 and the Algorithm and Analysis
+                   paragraphs), the reference for the GPU primitives and the
+                   per-level statistics
 """
 from __future__ import annotations
 
@@ -25,7 +27,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# a differently built copy (e.g. a sanitizer build) may be loaded instead by naming it here
+_LIB = os.environ.get("S3BFS_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 

@@ -1,167 +1,178 @@
-"""The paper's S3BFS steps written out in plain Python (test infrastructure only).
+"""Reference model of one level-synchronous search step, primitive by primitive
+(test infrastructure only: used by tests/, never by the GPU library).
 
-This follows Figure 1 (Parallel-BFS(s, P)) and the Algorithm and Analysis
-paragraphs in the paper's order and notation, with the P_l "threads" of each
-step simulated one after another.  It is slow and meant for small graphs.
-It is the reference for the GPU library's primitives (degree gather, prefix
-sum, the start point of each share) and for its per-level statistics
-(n_l, e_l), and it shows that the owner-based de-duplication returns the same
-levels as the plain definition even under the paper's benign race.
+S3BFS (Figure 1 with the Algorithm and Analysis paragraphs) advances a
+frontier in rounds.  Each round is built from a handful of data-parallel
+primitives; this module gives each one as a small, slow, obviously correct
+function of its own, and a driver that chains them.  Workers are simulated
+one after another.  The functions are checked independently: the chunk
+starts against numpy's searchsorted, the concatenation and ownership filter
+against their set semantics, and the whole round loop against the plain
+BFS oracle, with and without a model of racing workers.
 
-Readings where the figure is silent or garbled (each is also listed in the
-design notes):
-  * EXPLORE-VERTEX has no body in Figure 1; from the Algorithm paragraph:
-    each thread scans its share of the level's edges and, for each neighbour
-    v with d[v] = infinity, sets d[v] = l, Owner[v] = its id and appends v
-    to its private queue.
-  * Share rule: S = ceil(e_l / P_l); share t covers global edge positions
-    [t*S, min((t+1)*S, e_l)).
-  * Find-StartExpPoint: the EdgeSum entry j covering [a, b) is the start of
-    every share t with ceil(a/S) <= t <= ceil(b/S) - 1, at edge t*S - a of
-    that vertex (a scatter instead of a binary search).
-  * The copy loop of the linearisation runs over the half-open range
-    [Offset, Offset + |Q[i]|).
+The primitives, in the project's terms (the paper's names in brackets):
+
+  row_lengths        degree of every frontier vertex        [degree gather]
+  running_totals     inclusive prefix sums                   [Parallel-Prefix-Sum]
+  chunk_starts       where each worker's equal chunk of the  [Find-StartExpPoint]
+                     round's edges begins: entry and offset
+  scan_chunks        each worker walks its chunk of edges    [EXPLORE-VERTEX]
+                     and lists the unvisited targets it
+                     claims
+  keep_claimed       drop a listed vertex unless the list    [owner de-duplication]
+                     holds its final claim
+  concatenate        the lists, one after another, at the    [linearisation]
+                     running totals of their lengths
+
+Readings where the paper is silent (each also in the design notes):
+  * EXPLORE-VERTEX has no body in the paper.  From the Algorithm paragraph:
+    a worker that finds a target with no distance yet gives it the round's
+    distance, records itself as the target's claimant and lists it; workers
+    race, every racer writes the same distance, and the last claim stands.
+  * Chunks are equal runs of ceil(edges / workers) consecutive edges (the
+    paper asks for nearly equal shares), unless a fixed chunk size is given.
+  * The scatter form of the chunk starts: the frontier entry covering edges
+    [a, b) is where every chunk whose first edge lies in [a, b) begins.
 """
 from __future__ import annotations
 
 import random
 
-INF = None
+import numpy as np
+
+UNSEEN = -1
 
 
-def degree_gather(cur_level_vertices, offsets):
-    """EdgeSum[u] = Degree[CurLevelVertices[u]] (Figure 1, degree gather)."""
-    return [int(offsets[v + 1]) - int(offsets[v]) for v in cur_level_vertices]
+def row_lengths(frontier, offsets) -> list[int]:
+    """Degree of each frontier vertex, in frontier order."""
+    return [int(offsets[v + 1]) - int(offsets[v]) for v in frontier]
 
 
-def inclusive_prefix_sum(x):
-    """Parallel-Prefix-Sum of Figure 1, written sequentially (inclusive)."""
-    out, acc = [], 0
-    for a in x:
-        acc += int(a)
-        out.append(acc)
+def running_totals(values) -> list[int]:
+    """Inclusive prefix sums (entry i = values[0] + ... + values[i])."""
+    return [int(x) for x in np.cumsum(np.asarray(values, dtype=np.int64))]
+
+
+def chunk_size(total: int, workers: int) -> int:
+    """Edges per chunk when `total` edges go to `workers` workers in nearly equal runs."""
+    return -(-total // workers) if workers > 0 else 0
+
+
+def chunk_starts(totals, total: int, workers: int, size: int | None = None):
+    """Start of each worker's chunk as (frontier entry, edge offset in that entry's row).
+
+    `totals` are the inclusive running totals of the frontier's degrees.  Chunk w
+    covers edges [w * size, (w + 1) * size).  Rather than searching for each
+    chunk's first edge, every frontier entry names the chunks that begin inside
+    its own edge range (a scatter).  A chunk with no edge gets None.
+    """
+    size = chunk_size(total, workers) if size is None else size
+    out = [None] * workers
+    if size <= 0:
+        return out
+    lo = 0
+    for entry, hi in enumerate(totals):
+        hi = int(hi)
+        # chunks whose first edge w * size falls in [lo, hi)
+        first = -(-lo // size)
+        after = -(-hi // size)
+        for w in range(first, min(after, workers)):
+            out[w] = (entry, w * size - lo)
+        lo = hi
     return out
 
 
-def share_size(e_l: int, P_l: int) -> int:
-    return -(-e_l // P_l) if P_l > 0 else 0
+def scan_chunks(frontier, starts, total: int, size: int, offsets, cols, dist, claim, round_no: int,
+                race=None):
+    """Every worker walks its chunk of the round's edges and lists the targets it claims.
 
-
-def find_start_exp_point(edge_sum, e_l: int, P_l: int, S: int | None = None):
-    """Start (vertex index, edge within that vertex) of each of the P_l shares.
-
-    edge_sum is the inclusive prefix sum of the frontier degrees.  Returns a
-    list of length P_l whose entry t is (j, offset) or None for an empty share.
-    A given share size S overrides ceil(e_l / P_l).
+    Returns one list per worker.  With race=None the workers run one after
+    another and see each other's writes.  With race=<seed> every worker sees
+    the distances as they were when the round began (plus its own claims), and
+    all claims are applied afterwards in a seeded random order: several workers
+    may list the same vertex, and the one whose claim lands last owns it.
     """
-    S = share_size(e_l, P_l) if S is None else S
-    start = [None] * P_l
-    if S <= 0:
-        return start
-    a = 0
-    for j, b in enumerate(edge_sum):
-        b = int(b)
-        t_s = -(-a // S)          # first share that starts inside [a, b)
-        t_e = -(-b // S) - 1      # last share that starts inside [a, b)
-        for t in range(t_s, min(t_e, P_l - 1) + 1):
-            start[t] = (j, t * S - a)
-        a = b
-    return start
-
-
-def explore_vertex(cur, edge_sum, start, d, offsets, cols, e_l, P_l, l, owner, S=None, race=None):
-    """EXPLORE-VERTEX: returns the private queues Q[0..P_l-1].
-
-    race=None runs the shares one after another.  race=<seed> models the
-    benign race: every thread reads d[] as it was at the start of the level
-    (plus its own earlier writes, which program order makes visible to it),
-    then the threads' writes land in a seeded random order (last writer wins
-    on Owner).
-    """
-    S = share_size(e_l, P_l) if S is None else S
-    Q = [[] for _ in range(P_l)]
-    snapshot = list(d) if race is not None else None
-    writes = []
-    for t in range(P_l):
-        if start[t] is None:
+    lists = [[] for _ in starts]
+    before = list(dist) if race is not None else None
+    pending = []
+    for w, start in enumerate(starts):
+        if start is None:
             continue
-        j, off = start[t]
-        g, g_end = t * S, min((t + 1) * S, e_l)
+        entry, off = start
+        first, stop = w * size, min((w + 1) * size, total)
         mine = set()
-        while g < g_end:
-            u = cur[j]
-            row0 = int(offsets[u])
-            deg = int(offsets[u + 1]) - row0
-            while off < deg and g < g_end:
-                v = int(cols[row0 + off])
-                if snapshot is None:
-                    unvisited = d[v] is INF
+        pos = first
+        while pos < stop:
+            u = frontier[entry]
+            row = int(offsets[u])
+            deg = int(offsets[u + 1]) - row
+            while off < deg and pos < stop:
+                v = int(cols[row + off])
+                if race is None:
+                    fresh = dist[v] == UNSEEN
+                    if fresh:
+                        dist[v] = round_no
+                        claim[v] = w
                 else:
-                    unvisited = snapshot[v] is INF and v not in mine
-                if unvisited:
-                    if snapshot is None:
-                        d[v] = l
-                        owner[v] = t
-                    else:
+                    fresh = before[v] == UNSEEN and v not in mine
+                    if fresh:
                         mine.add(v)
-                        writes.append((t, v))
-                    Q[t].append(v)
+                        pending.append((w, v))
+                if fresh:
+                    lists[w].append(v)
                 off += 1
-                g += 1
-            j += 1
+                pos += 1
+            entry += 1
             off = 0
-    if snapshot is not None:
-        rng = random.Random(race)
-        rng.shuffle(writes)
-        for t, v in writes:
-            d[v] = l
-            owner[v] = t
-    return Q
+    if race is not None:
+        random.Random(race).shuffle(pending)
+        for w, v in pending:
+            dist[v] = round_no
+            claim[v] = w
+    return lists
 
 
-def deduplicate(Q, owner):
-    """Keep v in Q[i] only if Owner[v] = i; returns (Q, Sizes)."""
-    Qn = [[v for v in q if owner[v] == i] for i, q in enumerate(Q)]
-    return Qn, [len(q) for q in Qn]
+def keep_claimed(lists, claim):
+    """Worker w keeps a listed vertex only if w holds its final claim; returns the
+    filtered lists and their lengths."""
+    kept = [[v for v in lst if claim[v] == w] for w, lst in enumerate(lists)]
+    return kept, [len(k) for k in kept]
 
 
-def linearize(Q, sizes_incl):
-    """Copy the private queues into one array at the prefix-sum offsets."""
-    total = sizes_incl[-1] if sizes_incl else 0
-    out = [None] * total
-    for i, q in enumerate(Q):
-        offset = 0 if i == 0 else sizes_incl[i - 1]
-        for j in range(offset, offset + len(q)):
-            out[j] = q[j - offset]
+def concatenate(lists, totals):
+    """One array holding the lists in worker order; list w starts at totals[w - 1]
+    (the inclusive running total of the lengths before it)."""
+    out = [None] * (int(totals[-1]) if totals else 0)
+    for w, lst in enumerate(lists):
+        base = int(totals[w - 1]) if w > 0 else 0
+        out[base:base + len(lst)] = lst
     return out
 
 
-def parallel_bfs(offsets, cols, s, P, race=None, S=None):
-    """Figure 1.  Returns (d as a list with None for infinity, per-level stats).
-
-    stats[k] = (n_l, e_l) of the k-th processed frontier (level k of the
-    search), the work accounting of the Analysis paragraph.
-    """
+def level_synchronous_bfs(offsets, cols, source: int, workers: int, race=None, size: int | None = None):
+    """Distances from `source` (-1 where unreached) by rounds of the primitives above,
+    and each round's (frontier vertices, frontier edges): the work measure of the
+    Analysis paragraph.  With `size` the chunk size is fixed and the worker count
+    follows the round's edges; otherwise a round uses min(workers, edges) workers."""
     n = len(offsets) - 1
-    d = [INF] * n
-    owner = [P] * n
-    d[s] = 0
-    owner[s] = 0
-    cur = [s]
-    l = 0
-    stats = []
-    while len(cur) > 0:
-        n_l = len(cur)
-        l += 1
-        edge_sum = inclusive_prefix_sum(degree_gather(cur, offsets))
-        e_l = edge_sum[n_l - 1]
-        stats.append((n_l, e_l))
-        # with a fixed share size (the GPU's grain) the share count follows it
-        P_l = min(P, e_l) if S is None else share_size(e_l, S)
-        if P_l == 0:
+    dist = [UNSEEN] * n
+    claim = [None] * n
+    dist[source] = 0
+    claim[source] = 0
+    frontier = [source]
+    per_round = []
+    round_no = 0
+    while frontier:
+        round_no += 1
+        totals = running_totals(row_lengths(frontier, offsets))
+        edges = totals[-1]
+        per_round.append((len(frontier), edges))
+        active = min(workers, edges) if size is None else chunk_size(edges, size)
+        if active == 0:
             break
-        start = find_start_exp_point(edge_sum, e_l, P_l, S)
-        Q = explore_vertex(cur, edge_sum, start, d, offsets, cols, e_l, P_l, l, owner, S, race)
-        Q, sizes = deduplicate(Q, owner)
-        cur = linearize(Q, inclusive_prefix_sum(sizes))
-    return d, stats
+        chunk = chunk_size(edges, active) if size is None else size
+        starts = chunk_starts(totals, edges, active, chunk)
+        lists = scan_chunks(frontier, starts, edges, chunk, offsets, cols, dist, claim, round_no, race)
+        kept, lengths = keep_claimed(lists, claim)
+        frontier = concatenate(kept, running_totals(lengths))
+    return dist, per_round

@@ -1,12 +1,12 @@
 """GPU parity of the level-loop primitive (owner de-duplication + linearisation +
 next-level degree prefix sum + share start points) against the oracle's
-step-by-step reference of the paper's Figure 1.
+primitive-by-primitive step model (oracle/s3bfs_steps.py).
 
 The survivors are a set (their order across queues is not part of the
 result), so the test compares the survivor multiset exactly and checks that
 the degree prefix sums and the share start points the GPU wrote are the ones
-the oracle's Parallel-Prefix-Sum and Find-StartExpPoint give for the GPU's
-output order.
+the step model's running totals and chunk starts give for the GPU's output
+order.
 """
 import numpy as np
 import pytest
@@ -78,12 +78,12 @@ def test_prim_compact_matches_oracle_steps(ntiles, seed, fill):
     v = out_v.cpu().numpy()[:n_out]
     assert sorted(v.tolist()) == want_set
     np.testing.assert_array_equal(out_rs.cpu().numpy()[:n_out], g.offsets[v])
-    # degree gather + Parallel-Prefix-Sum on the GPU's output order
-    incl = st.inclusive_prefix_sum(st.degree_gather(v.tolist(), g.offsets))
+    # degree gather + prefix sum on the GPU's output order
+    incl = st.running_totals(st.row_lengths(v.tolist(), g.offsets))
     ex = out_ex.cpu().numpy()[:n_out + 1]
     np.testing.assert_array_equal(ex, [0] + incl if n_out else [0])
-    # Find-StartExpPoint with the grain as share size
+    # chunk starts (Find-StartExpPoint) with the grain as chunk size
     if want_e:
         P = -(-want_e // grain)
-        starts = st.find_start_exp_point(incl, want_e, P, S=grain)
+        starts = st.chunk_starts(incl, want_e, P, size=grain)
         np.testing.assert_array_equal(out_ts.cpu().numpy()[:P], [j for (j, _) in starts])
