@@ -21,7 +21,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "gen.c")
-_LIB = os.path.join(_HERE, "libgraphgen.so")
+# a differently built copy (e.g. a sanitizer build) may be loaded instead by naming it here
+_LIB = os.environ.get("S3BFS_GRAPHGEN_LIB") or os.path.join(_HERE, "libgraphgen.so")
 _lib = None
 
 RMAT_ABCD = (0.57, 0.19, 0.19, 0.05)
