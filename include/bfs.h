@@ -104,7 +104,9 @@ typedef struct {
 } bfs_stats_t;
 
 /*
- * Make a graph resident on the current HIP device.
+ * Make a graph resident on the current HIP device.  An addition: the paper
+ * takes the graph as given in shared memory (Figure 1 reads Degree and
+ * Neighbor); on a GPU it is uploaded once and searched many times.
  *   offsets[n+1], cols[m]: CSR (int32).  With BFS_HOST_PTRS they are copied
  *   (synchronously; the call returns after the copy).  With BFS_DEVICE_PTRS
  *   the caller keeps them alive and unchanged until bfs_graph_free.
@@ -146,6 +148,12 @@ size_t bfs_workspace_bytes(bfs_graph_t g, int32_t max_sources);
 bfs_status_t bfs_workspace_create(bfs_graph_t g, int32_t max_sources, bfs_workspace_t* out);
 bfs_status_t bfs_workspace_free(bfs_workspace_t ws);
 
+/* Workgroups of the persistent level loop that the device holds at once: the largest useful
+   BFS_OPT_GRID, and the budget that persistent runs in flight together on one device must
+   share (their grids must sum to at most this, or their grid barriers can wait on each other).
+   0 for a null handle. */
+int32_t bfs_workspace_grid_capacity(bfs_workspace_t ws);
+
 /* Set a BFS_OPT_* option.  EINVAL for an unknown option or bad value. */
 bfs_status_t bfs_workspace_set_option(bfs_workspace_t ws, int32_t option, int64_t value);
 
@@ -164,7 +172,8 @@ bfs_status_t bfs_workspace_set_option(bfs_workspace_t ws, int32_t option, int64_
 bfs_status_t bfs_run(bfs_workspace_t ws, int32_t source, int32_t* level, int32_t* parent, void* stream);
 
 /*
- * Multi-root search: every root starts at level 0 (host array roots[k],
+ * Multi-root search (an addition; the paper searches from one source):
+ * every root starts at level 0 (host array roots[k],
  * 1 <= k <= n, repeats allowed).  With one root per component of a
  * disjoint union of graphs this runs independent searches of many small
  * graphs in one launch.  level/parent as in bfs_run (a root's parent is
@@ -174,8 +183,9 @@ bfs_status_t bfs_run_multiroot(bfs_workspace_t ws, const int32_t* roots, int32_t
                                int32_t* level, int32_t* parent, void* stream);
 
 /*
- * Batched search of k <= 256 sources (host array sources[k], repeats
- * allowed) with per-vertex 4 x 64-bit frontier/visited masks.
+ * Batched search (an addition; the paper searches from one source) of
+ * k <= 256 sources (host array sources[k], repeats allowed) with
+ * per-vertex 4 x 64-bit frontier/visited masks.
  *   level[n * k] (device, uint8, written): level[v * k + j] is the distance
  *   of v from sources[j], 255 if unreached.
  * The workspace must have been created with max_sources >= k.  Levels >= 255
@@ -259,56 +269,6 @@ bfs_status_t bfs_autotune(bfs_workspace_t ws, const int32_t* sources, int32_t k,
 
 /* The workspace's current settings, in the same form (trials and times 0). */
 bfs_status_t bfs_workspace_get_tuning(bfs_workspace_t ws, bfs_tune_t* out);
-
-/* ---- primitives of the level loop, exposed for testing ------------------------------ */
-
-/*
- * Owner de-duplication and linearisation of one level (Figure 1: keep a
- * private-queue entry v of queue i only if Owner[v] = i, prefix-sum the
- * queue sizes, copy the survivors to the next CurLevelVertices), fused with
- * the next level's degree gather, degree prefix sum and share start points
- * (Find-StartExpPoint).  All pointers are device memory.
- *   cand[ntiles * grain], cnt[ntiles]: tile t's private queue is
- *     cand[t*grain .. t*grain + cnt[t]); its entries' slot ids are their
- *     positions in cand.
- *   owner[n]: slot id that owns each vertex.
- *   offsets[n+1]: graph CSR offsets (degree = offsets[v+1] - offsets[v]).
- *   Outputs: out_v[i] = v_i, the i-th survivor; out_rs[i] = offsets[v_i];
- *   out_ex[i] = sum of the degrees of the
- *   survivors before i (in output order), out_ex[count] = total;
- *   out_tstart[t] = index of the survivor holding edge t*grain (tstart_cap
- *   entries available; BFS_EDEVICE if the edge total needs more);
- *   totals[0] = survivor count (degree >= 1 only), totals[1] = edge total
- *   (int32 device array of 2).  Survivors of degree 0 are dropped.
- *   out_v and out_rs need n entries, out_ex n + 1.  Output order is unspecified;
- *   the set is exact.  Synchronises with stream.
- * grain must be the library's tile size (bfs_prim_grain()).
- */
-bfs_status_t bfs_prim_compact(const int32_t* offsets, int32_t n, const int32_t* owner,
-                              const int32_t* cand, const int32_t* cnt, int32_t ntiles,
-                              int32_t* out_v, int32_t* out_rs, int32_t* out_ex, int32_t* out_tstart,
-                              int32_t tstart_cap, int32_t* totals, void* stream);
-
-/* Edges per share (tile) of the multi-workgroup level loop. */
-int32_t bfs_prim_grain(void);
-
-/* ---- measurement aid ---------------------------------------------------------------- */
-
-/*
- * Random-probe ceiling.  The expansion step (Figure 1, EXPLORE-VERTEX)
- * streams the column array and probes per-vertex state at the neighbour
- * ids it reads.  This kernel reproduces that access pattern alone: it
- * streams idx[0 .. count) and, for each entry v, reads table[v >> shift]
- * (shift 5: a bit of a bitmap of 32-bit words, as the visited filter;
- * shift 0: a 32-bit entry, as the level array); entries outside
- * [0, table_words) are skipped.  All pointers are device memory; *sink
- * receives nothing unless a checksum hits a fixed value (it only keeps the
- * reads alive).  Asynchronous on stream: time it with events there.
- * EINVAL for a null pointer, count < 0, table_words < 1 or shift outside
- * [0, 5]; EHIP if the launch fails.
- */
-bfs_status_t bfs_probe_rate_kernel(const int32_t* idx, int64_t count, const uint32_t* table,
-                                   int64_t table_words, int32_t shift, int32_t* sink, void* stream);
 
 #ifdef __cplusplus
 }

@@ -21,7 +21,7 @@ from ._lib import (BFS_DEVICE_PTRS, BFS_HOST_PTRS, BFS_HOT_FILTER, BFS_LEAN, BFS
 
 __all__ = [
     "bfs_init", "bfs_graph_free", "bfs_graph_info", "bfs_graph_aux_bytes", "bfs_workspace_bytes", "bfs_workspace_create",
-    "bfs_workspace_free", "bfs_workspace_set_option", "bfs_run", "bfs_run_multiroot", "bfs_run_batch",
+    "bfs_workspace_free", "bfs_workspace_set_option", "bfs_workspace_grid_capacity", "bfs_run", "bfs_run_multiroot", "bfs_run_batch",
     "bfs_sync", "bfs_last_stats", "bfs_last_level_stats", "bfs_last_level_times", "bfs_kernel_times", "bfs_status_str",
     "bfs_prim_compact",
     "bfs_prim_grain", "bfs_probe_rate_kernel", "bfs_autotune", "bfs_workspace_get_tuning", "Graph", "Workspace", "BFSError",
@@ -120,6 +120,10 @@ def bfs_workspace_free(ws: int) -> None:
 
 def bfs_workspace_set_option(ws: int, option: int, value: int) -> None:
     _lib.check(_lib.load().bfs_workspace_set_option(ws, option, int(value)), "bfs_workspace_set_option")
+
+
+def bfs_workspace_grid_capacity(ws: int) -> int:
+    return int(_lib.load().bfs_workspace_grid_capacity(ws))
 
 
 def bfs_run(ws: int, source: int, level, parent=None, stream=None) -> None:
@@ -308,6 +312,9 @@ class Workspace:
 
     def stats(self):
         return bfs_last_stats(self.handle)
+
+    def grid_capacity(self) -> int:
+        return bfs_workspace_grid_capacity(self.handle)
 
     def level_stats(self, cap: int = 1 << 16):
         return bfs_last_level_stats(self.handle, cap)

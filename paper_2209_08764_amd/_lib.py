@@ -107,6 +107,7 @@ _SIGS = {
     "bfs_workspace_create": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)]),
     "bfs_workspace_free": (ctypes.c_int32, [ctypes.c_void_p]),
     "bfs_workspace_set_option": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64]),
+    "bfs_workspace_grid_capacity": (ctypes.c_int32, [ctypes.c_void_p]),
     "bfs_run": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                  ctypes.c_void_p]),
     "bfs_run_multiroot": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,

@@ -1,6 +1,7 @@
 // C ABI of libbfs: graph residency, workspaces and run orchestration.
-// The entry points are declared and documented in include/bfs.h.
-#include "../../include/bfs.h"
+// The entry points are declared and documented in include/bfs.h (users) and
+// include/bfs_test.h (test and measurement aids).
+#include "../../include/bfs_test.h"
 #include "bfs_internal.h"
 
 #include <hip/hip_runtime.h>
@@ -1012,6 +1013,8 @@ bfs_status_t bfs_last_level_times(bfs_workspace_t ws, int32_t cap, double* expan
 }
 
 int32_t bfs_prim_grain(void) { return kGrain; }
+
+int32_t bfs_workspace_grid_capacity(bfs_workspace_t ws) { return ws ? ws->grid_cap : 0; }
 
 bfs_status_t bfs_prim_compact(const int32_t* offsets, int32_t n, const int32_t* owner, const int32_t* cand,
                               const int32_t* cnt, int32_t ntiles, int32_t* out_v, int32_t* out_rs, int32_t* out_ex,

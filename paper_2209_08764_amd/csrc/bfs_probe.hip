@@ -1,7 +1,7 @@
 // Measurement aid: the device's random-probe rate for the expansion's two
 // probe patterns (a word of the visited bitmap, an entry of the level array),
 // which bounds the scan once the column reads are streamed.
-#include "../../include/bfs.h"
+#include "../../include/bfs_test.h"
 #include "bfs_internal.h"
 
 #include <hip/hip_runtime.h>

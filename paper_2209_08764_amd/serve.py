@@ -10,7 +10,9 @@ Queries that arrive while others are on the GPU are admitted as soon as a
 slot and memory free up, so their work overlaps on the device.
 
 Every answer is the level array of its query (int32, -1 unreached), the
-same whether it ran alone, in a batch or next to other queries.
+same whether it ran alone, in a batch or next to other queries.  A query
+whose launch or collection fails is answered with an error (``Query.error``,
+no result); its workspace is dropped and the loop keeps serving the others.
 
 The scheduler talks to an executor (``GpuExecutor`` runs the HIP library;
 tests substitute a CPU executor) and to a clock, so its admission and
@@ -37,6 +39,7 @@ class Query:
     finished: float | None = None
     batched: bool = False
     result: object = None           # int32 levels (executor-specific array type)
+    error: str | None = None        # why the query failed (result is then None)
 
     @property
     def latency(self) -> float:
@@ -135,20 +138,47 @@ class Scheduler:
             for p in group:
                 p.admitted = now
                 p.batched = k > 1
-            handle = self.ex.launch(ws, q.graph, [p.source for p in group])
-            self.inflight.append((handle, ws, q.graph, 256 if k > 1 else 1, group))
+            kind = 256 if k > 1 else 1
+            try:
+                handle = self.ex.launch(ws, q.graph, [p.source for p in group])
+            except Exception as exc:  # a failed launch answers its queries with the error
+                self._fail(group, ws, kind, None, exc)
+                continue
+            self.inflight.append((handle, ws, q.graph, kind, group))
             self.stats["batches" if k > 1 else "singles"] += 1
         while skipped:
             self.pending.appendleft(skipped.pop())
+
+    def _fail(self, group, ws, kind, handle, exc):
+        """Answer `group` with an error and drop its workspace, whose state is unknown."""
+        if handle is not None and hasattr(self.ex, "abandon"):
+            self.ex.abandon(handle)
+        cost = self.pool_bytes.pop(id(ws), 0)
+        self.used -= cost
+        try:
+            self.ex.destroy(ws)
+        except Exception:
+            pass
+        now = self.clock()
+        for p in group:
+            p.finished = now
+            p.result = None
+            p.error = f"{type(exc).__name__}: {exc}"
+            self.done.append(p)
+        self.stats["failed_queries"] += len(group)
 
     def _reap(self):
         still = []
         for item in self.inflight:
             handle, ws, name, kind, group = item
-            if not self.ex.ready(handle):
-                still.append(item)
+            try:
+                if not self.ex.ready(handle):
+                    still.append(item)
+                    continue
+                results = self.ex.collect(handle)
+            except Exception as exc:
+                self._fail(group, ws, kind, handle, exc)
                 continue
-            results = self.ex.collect(handle)
             self._release(name, kind, ws)
             if results is None:
                 # the batch overflowed: answer its queries one by one
@@ -240,11 +270,9 @@ class GpuExecutor:
             self.graphs[name] = G
             probe = Workspace(G)
             if self.grid is None:
-                # concurrent persistent runs must fit on the GPU together
-                probe.run(int(np.flatnonzero(np.diff(g.offsets))[0]) if g.m else 0, want_parent=False)
-                probe.sync()
-                cap = probe.stats()["grid"]
-                self.grid = max(1, cap // max_inflight)
+                # persistent runs in flight together must fit on the GPU together: each of the
+                # max_inflight streams gets an equal part of the device's co-resident workgroups
+                self.grid = max(1, probe.grid_capacity() // max_inflight)
             nz = np.flatnonzero(np.diff(g.offsets))
             probe.run(int(nz[0]) if nz.size else 0, want_parent=False)
             probe.sync()
@@ -268,8 +296,15 @@ class GpuExecutor:
         ws.free()
 
     def launch(self, ws, name, sources):
-        torch = self.torch
         si = self.free_streams.pop()
+        try:
+            return self._launch(si, ws, name, sources)
+        except Exception:
+            self.free_streams.append(si)
+            raise
+
+    def _launch(self, si, ws, name, sources):
+        torch = self.torch
         stream = self.streams[si]
         n = self.graphs[name].n
         if len(sources) == 1:
@@ -296,6 +331,12 @@ class GpuExecutor:
 
         return ("batch", si, self.pool.submit(work), out, len(sources))
 
+    def abandon(self, h):
+        """Give back the stream of a run whose launch or collection failed."""
+        si = h[1]
+        if si not in self.free_streams:
+            self.free_streams.append(si)
+
     def ready(self, h):
         kind, si, ev, out, k = h
         if kind == "batch":
@@ -309,7 +350,7 @@ class GpuExecutor:
     def collect(self, h):
         torch = self.torch
         kind, si, ev, out, k = h
-        self.free_streams.append(si)
+        self.abandon(h)
         if kind == "single":
             return [out]
         if ev.result()[0] == "overflow":

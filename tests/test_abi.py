@@ -1,17 +1,19 @@
-"""The C-ABI library loads on a machine without a GPU and exports every declared symbol."""
+"""The C-ABI library loads on a machine without a GPU and exports every symbol that
+include/*.h declares."""
 import ctypes
+import glob
 import os
 import re
 
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "bfs.h")
+HEADERS = [os.path.join(ROOT, "include", f) for f in ("bfs.h", "bfs_test.h")]
 LIB = os.path.join(ROOT, "paper_2209_08764_amd", "libbfs.so")
 
 
 def declared_functions():
-    text = open(HEADER).read()
+    text = "\n".join(open(h).read() for h in HEADERS)
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"\b(bfs_[a-z_0-9]+)\s*\(", text)))
 
@@ -30,6 +32,10 @@ def test_library_exports_every_declared_symbol():
     lib = ctypes.CDLL(LIB)
     missing = [n for n in declared_functions() if not hasattr(lib, n)]
     assert missing == []
+
+
+def test_every_header_is_covered():
+    assert sorted(glob.glob(os.path.join(ROOT, "include", "*.h"))) == sorted(HEADERS)
 
 
 def test_binding_covers_the_header():

@@ -113,3 +113,39 @@ def test_queries_keep_arrival_order_within_a_graph(graphs):
     sch.run(qs)
     adm = [q.admitted for q in qs]
     assert adm == sorted(adm)
+
+
+class FailingExecutor(FakeExecutor):
+    """Fails every launch on graph "b" and every collection of a batch on graph "c"."""
+
+    def launch(self, ws, name, sources):
+        if name == "b":
+            raise RuntimeError("launch failed")
+        return super().launch(ws, name, sources) + (name, len(sources))
+
+    def ready(self, h):
+        return self.now >= h[0]
+
+    def collect(self, h):
+        if h[2] == "c" and h[3] > 1:
+            raise RuntimeError("device fault")
+        return h[1]
+
+
+def test_failed_requests_do_not_stop_the_loop(graphs):
+    ex = FailingExecutor(graphs)
+    sch = Scheduler(ex, budget_bytes=10 ** 9, max_inflight=3, clock=ex.clock)
+    qs = poisson_queries(graphs, _nonisolated(graphs), rate=2e5, count=200, seed=8)
+    sch.run(qs)
+    failed = [q for q in qs if q.error is not None]
+    served = [q for q in qs if q.error is None]
+    assert {q.graph for q in failed} <= {"b", "c"} and any(q.graph == "b" for q in failed)
+    assert all(q.result is None for q in failed)
+    assert sch.stats["failed_queries"] == len(failed)
+    # every other query is answered, and correctly
+    assert served and all(q.graph == "a" or (q.graph == "c" and not q.batched) for q in served)
+    for q in served:
+        g = graphs[q.graph]
+        assert np.array_equal(q.result, oracle.bfs_levels(g.offsets, g.cols, q.source))
+    # failed runs gave their workspaces back to the budget
+    assert sch.used == sum(sch.pool_bytes.values())
