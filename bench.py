@@ -3,10 +3,12 @@
 
 Headline workload: R-MAT scale 24 (edge factor 16, a/b/c/d = .57/.19/.19/.05,
 symmetrised, deduplicated, vertex-permuted), 64 seeded sources run one at a
-time.  One "step" is one complete single-source search (init, every level,
-parent pass) from the next source; `value` is the harmonic mean over sources
-of GTEPS = (undirected edges in the source's component) / (time of the
-search), with the CSR already resident in HBM.
+time.  One "step" is one pass over all 64 sources, each a complete
+single-source search (init, every level, parents); `value` is the harmonic
+mean over the sources of GTEPS = (undirected edges in the source's
+component) / (median time of its search over the steps), with the CSR
+already resident in HBM.  The oracle's answers for the CPU-baseline sample
+are compared with the GPU's (extras.parity_*).
 
 Printed on one JSON line: the contract fields, a roofline object for the
 dominant kernel (the persistent level-loop kernel, timed with HIP events on
@@ -84,47 +86,80 @@ def stored_traffic(workload: str):
     return d.get("hbm_bytes_per_launch")
 
 
-def time_single_source(ws, level, parent, sources, steps, torch, mc_half):
-    """Runs `steps` searches cycling over sources; returns per-step ms, wall ms, kernel ms."""
+def time_passes(ws, level, parent, sources, passes, torch):
+    """`passes` complete passes over the workload's sources, each search bracketed by HIP
+    events on the current stream.  Returns per-search ms [passes][len(sources)], the wall
+    ms of all passes, and the search kernel's own durations (profiled runs)."""
     from paper_2209_08764_amd import bfs_kernel_times, bfs_run
     ws_h = ws.handle
+    k = len(sources)
+    if passes * k > 4096:
+        raise ValueError("at most 4096 profiled searches per measurement (lower --steps)")
     bfs_kernel_times(ws_h)  # forget earlier profiled runs
-    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
-    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    starts = [[torch.cuda.Event(enable_timing=True) for _ in range(k)] for _ in range(passes)]
+    ends = [[torch.cuda.Event(enable_timing=True) for _ in range(k)] for _ in range(passes)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(steps):
-        s = int(sources[i % len(sources)])
-        starts[i].record()
-        bfs_run(ws_h, s, level, parent)
-        ends[i].record()
+    for p in range(passes):
+        for j in range(k):
+            starts[p][j].record()
+            bfs_run(ws_h, int(sources[j]), level, parent)
+            ends[p][j].record()
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) * 1e3
     ws.sync()
-    step_ms = np.array([a.elapsed_time(b) for a, b in zip(starts, ends)])
-    kms = bfs_kernel_times(ws_h)
-    return step_ms, wall, kms
+    ms = np.array([[a.elapsed_time(b) for a, b in zip(sa, se)] for sa, se in zip(starts, ends)])
+    return ms, wall, bfs_kernel_times(ws_h)
 
 
-def per_source_hm(step_ms, sources, mc_half):
-    per = {}
-    for i, t in enumerate(step_ms):
-        per.setdefault(i % len(sources), []).append(t)
-    gteps = [mc_half[j] / (np.median(ts) * 1e-3) / 1e9 for j, ts in per.items()]
-    return hmean(gteps)
+def hm_gteps(ms, mc_half):
+    """Harmonic mean over sources of GTEPS, each source at its median time over the passes."""
+    ms = np.atleast_2d(ms)
+    return hmean([mc_half[j] / (np.median(ms[:, j]) * 1e-3) / 1e9 for j in range(ms.shape[1])])
 
 
-def cpu_baseline(g, sources, threads: int):
-    """The oracle (plain sequential BFS + parent pass) on `threads` host threads, one source each."""
+def host_info() -> dict:
+    """The host the CPU baseline ran on: logical CPUs, the process's CPU share and the model."""
+    model = None
+    try:
+        import subprocess
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except Exception:
+        pass
+    if model is None:
+        try:
+            for line in open("/proc/cpuinfo"):
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+        except OSError:
+            pass
+    try:
+        share = len(os.sched_getaffinity(0))
+    except Exception:
+        share = None
+    return {"nproc": os.cpu_count(), "cpus_allowed": share, "lscpu_model": model}
+
+
+def cpu_baseline(g, sources, threads: int, keep: bool = False):
+    """The oracle (plain sequential BFS + parent pass) on `threads` host threads, one source
+    each.  With keep, also returns each source's (level, parent) for the parity check."""
     import oracle
     oracle.build(force=False)
     res = [None] * threads
+    outs = [None] * threads
 
     def work(i):
         s = int(sources[i % len(sources)])
-        lv, _, tb, tp = oracle.timed_bfs(g.offsets, g.cols, s)
+        lv, par, tb, tp = oracle.timed_bfs(g.offsets, g.cols, s)
         mc = int(np.diff(g.offsets.astype(np.int64))[lv >= 0].sum())
         res[i] = (mc // 2, tb, tp)
+        if keep:
+            outs[i] = (s, lv, par)
 
     t0 = time.perf_counter()
     th = [threading.Thread(target=work, args=(i,)) for i in range(threads)]
@@ -135,17 +170,20 @@ def cpu_baseline(g, sources, threads: int):
     wall = time.perf_counter() - t0
     edges = sum(r[0] for r in res)
     single = hmean([r[0] / (r[1] + r[2]) / 1e9 for r in res])
-    return {
+    host = host_info()
+    out = {
         "value": round(edges / wall / 1e9, 5),
         "unit": "GTEPS",
         "cores": threads,
         "kind": "oracle",
         "sample": f"{threads} of the workload's sources, one per host thread, search + parent pass each "
-                  f"({wall:.1f} s wall)",
+                  f"({wall:.1f} s wall); the thread count is the process's CPU share capped at 16",
+        "host": host,
         "single_core_gteps_hmean": round(single, 5),
         "search_s_mean": round(float(np.mean([r[1] for r in res])), 3),
         "parent_s_mean": round(float(np.mean([r[2] for r in res])), 3),
     }
+    return (out, outs) if keep else out
 
 
 def host_cores() -> int:
@@ -248,6 +286,16 @@ def calib_copy(args):
     print(json.dumps({"calib_copy_bytes": nbytes, "launches": 4}), flush=True)
 
 
+def level_record(ws, small_edges: int = 4096, small_n: int = 4096):
+    """Per-level (n_l, e_l, expand us, compact us, single-workgroup?) of the workspace's last
+    run, from the level statistics and the device timestamps."""
+    n_l, e_l = ws.level_stats()
+    ex_us, co_us = ws.level_times()
+    k = min(len(n_l), len(ex_us))
+    return [[int(n_l[i]), int(e_l[i]), round(float(ex_us[i]), 2), round(float(co_us[i]), 2),
+             bool(n_l[i] <= small_n and e_l[i] <= small_edges)] for i in range(k)]
+
+
 def bench_c1(torch, W, Graph, Workspace):
     """R-MAT scale 16, one seeded source: microseconds per search."""
     g, srcs = W.c1_rmat16()
@@ -259,11 +307,13 @@ def bench_c1(torch, W, Graph, Workspace):
     ws.run(s, lv, pa)
     st = ws.stats()
     mc_half = st["edges"] / 2
-    step_ms, _, kms = time_single_source(ws, lv, pa, [s], 200, torch, [mc_half])
-    t = float(np.median(step_ms))
+    per_level = level_record(ws)
+    ms, _, kms = time_passes(ws, lv, pa, [s], 200, torch)
+    t = float(np.median(ms))
     return {"workload": "rmat16 (scale 16, EF 16), 1 source", "us_per_search": round(t * 1e3, 1),
             "kernel_us": round(float(np.median(kms)) * 1e3, 1), "gteps": round(mc_half / (t * 1e-3) / 1e9, 3),
-            "levels": st["levels"], "small_levels": st["small_levels"]}
+            "levels": st["levels"], "small_levels": st["small_levels"], "grid": st["grid"],
+            "per_level_nl_el_expand_us_compact_us_single_wg": per_level}
 
 
 def bench_c2(torch, W, Graph, Workspace):
@@ -275,15 +325,29 @@ def bench_c2(torch, W, Graph, Workspace):
     pa = torch.empty_like(lv)
     ws.run(0, lv, pa)
     st = ws.stats()
-    step_ms, _, kms = time_single_source(ws, lv, pa, [0], 3, torch, [st["edges"] / 2])
-    t = float(np.median(step_ms))
+    rec = level_record(ws)
+    ms, _, kms = time_passes(ws, lv, pa, [0], 3, torch)
+    t = float(np.median(ms))
     W_ = 4096
-    r, c = np.divmod(np.arange(g.n), W_)
-    closed = bool(np.array_equal(lv.cpu().numpy(), r + c))
+    r, c = np.divmod(np.arange(g.n, dtype=np.int64), W_)
+    closed_l = bool(np.array_equal(lv.cpu().numpy(), r + c))
+    want_p = np.where(r > 0, (r - 1) * W_ + c, c - 1)
+    want_p[0] = 0
+    closed_p = bool(np.array_equal(pa.cpu().numpy(), want_p))
+    one = [x for x in rec if x[4]]
+    grid_lv = [x for x in rec if not x[4]]
+
+    def us(rows):
+        return round(float(np.mean([x[2] + x[3] for x in rows])), 2) if rows else None
+
     return {"workload": "grid 4096x4096 from vertex 0", "ms_per_search": round(t, 2),
+            "kernel_ms": round(float(np.median(kms)), 2),
             "us_per_level": round(t * 1e3 / st["levels"], 2), "levels": st["levels"],
             "small_levels": st["small_levels"], "gteps": round(st["edges"] / 2 / (t * 1e-3) / 1e9, 3),
-            "closed_form_levels_ok": closed}
+            "closed_form_levels_ok": closed_l, "closed_form_parents_ok": closed_p,
+            "us_per_level_single_workgroup": us(one), "levels_single_workgroup": len(one),
+            "us_per_level_grid": us(grid_lv), "levels_grid": len(grid_lv),
+            "per_level_sample_nl_el_expand_us_compact_us_single_wg": rec[:4] + rec[2040:2052] + rec[4090:4100]}
 
 
 class EnergyMeter:
@@ -374,8 +438,15 @@ def energy_compare(torch, Graph, Workspace, graphs, seconds: float = 4.0) -> dic
     return out
 
 
+TUNE_CACHE = os.path.join(ROOT, "paper_2209_08764_amd", "tuning_cache.json")
+
+
 def bench_c4(torch, W, Graph, Workspace, g=None, srcs=None):
-    """R-MAT scale 22, 256 sources in one batched run; versus single-source and plain runs."""
+    """R-MAT scale 22, 256 sources in one batched run; versus single-source and plain runs,
+    with a parity check of the whole batch against the oracle."""
+    import concurrent.futures
+
+    import oracle
     from paper_2209_08764_amd import BFS_MODE_PLAIN, BFS_OPT_MODE
     if g is None:
         g, srcs = W.c4_rmat22()
@@ -397,25 +468,28 @@ def bench_c4(torch, W, Graph, Workspace, g=None, srcs=None):
         return float(np.median(times)), ws.kernel_times()
 
     t_default, _ = timed_batches()
-    # the autotuner picks grain, update tile, pull threshold and replay length on this graph
-    tune = ws.autotune(srcs, batch=True)
+    # the autotuner's launch shape for this graph and batch size, stored in the package's cache
+    tune = ws.autotune(srcs, batch=True, cache=TUNE_CACHE)
     tb, kt = timed_batches()
     lev = out.view(g.n, 256)
     deg = torch.from_numpy(np.diff(g.offsets.astype(np.int64))).cuda()
     edges = float(sum(int(deg[lev[:, j] != 255].sum()) for j in range(256))) / 2
     n_l, e_l = ws.level_stats()
+    # parity of the timed batch: the oracle's 256 searches on host threads, 16 sources each
+    got = lev.cpu().numpy()
+    blocks = [srcs[i:i + 16] for i in range(0, 256, 16)]
+    with concurrent.futures.ThreadPoolExecutor(max_workers=host_cores()) as pool:
+        parts = list(pool.map(lambda b: oracle.bfs_batch_u8(g.offsets, g.cols, b)[0], blocks))
+    parity = bool(np.array_equal(got, np.concatenate(parts, axis=1)))
+    del got, parts
     # 16 of the sources one at a time (single-source path), and the plain kernel on 4
     ss = Workspace(G, profile=1)
     lv = torch.empty(g.n, dtype=torch.int32, device="cuda")
     pa = torch.empty_like(lv)
-    mc = []
-    for s in srcs[:16]:
-        ss.run(int(s), lv, pa)
-        mc.append(ss.stats()["edges"] / 2)
-    sm, _, _ = time_single_source(ss, lv, pa, srcs[:16], 16, torch, mc)
+    sm, _, _ = time_passes(ss, lv, pa, srcs[:16], 1, torch)
     single_ms = float(np.mean(sm))
     ss.set(BFS_OPT_MODE, BFS_MODE_PLAIN)
-    pm, _, _ = time_single_source(ss, lv, pa, srcs[:4], 4, torch, mc[:4])
+    pm, _, _ = time_passes(ss, lv, pa, srcs[:4], 1, torch)
     plain_ms = float(np.mean(pm))
     gteps = edges / (tb * 1e-3) / 1e9
     # algorithmic bytes of one batch: the uint8 output, each active row's columns, 40 B of
@@ -424,43 +498,168 @@ def bench_c4(torch, W, Graph, Workspace, g=None, srcs=None):
     b_b = g.n * 256 + 4.0 * float(np.sum(e_l)) + 40.0 * a_sum + 96.0 * a_sum
     return {"workload": "rmat22 (scale 22, EF 16), 256 sources in one batched run",
             "ms_per_batch": round(tb, 3), "ms_per_batch_untuned": round(t_default, 3),
-            "tuned": {k: tune[k] for k in ("batch_grain", "batch_tile", "batch_pull", "batch_levels", "trials")},
+            "tuned": {k: tune.get(k) for k in ("batch_grain", "batch_tile", "batch_pull", "batch_levels", "trials",
+                                                "cached")},
             "loop_ms": round(float(np.median(kt)), 3),
             "algorithmic_bytes": int(b_b), "hbm_frac_algorithmic": round(b_b / (tb * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
             "gteps_aggregate": round(gteps, 1), "levels": len(n_l),
             "active_per_level": n_l.tolist(), "active_edges_per_level": e_l.tolist(),
+            "parity_256_sources_bit_exact": parity,
             "single_source_ms_mean": round(single_ms, 3),
             "speedup_vs_256_single_source": round(256 * single_ms / tb, 2),
             "plain_ms_mean": round(plain_ms, 2), "speedup_vs_256_plain": round(256 * plain_ms / tb, 1)}
 
 
-def bench_c5(torch, W, count: int, rmat22=None):
-    """Serving: 8 resident graphs, Poisson queries at 0.7x the closed-loop rate."""
+class BusyMeter:
+    """GPU activity (amd-smi's gfx activity percentage), sampled every 50 ms by a thread."""
+
+    def __init__(self):
+        import amdsmi
+        self.smi = amdsmi
+        amdsmi.amdsmi_init()
+        self.h = amdsmi.amdsmi_get_processor_handles()[0]
+        self.samples = []
+        self.stop = threading.Event()
+        self.thread = threading.Thread(target=self._run, daemon=True)
+        self.thread.start()
+
+    def _run(self):
+        while not self.stop.is_set():
+            try:
+                a = self.smi.amdsmi_get_gpu_activity(self.h)
+                self.samples.append((time.perf_counter(), float(a["gfx_activity"])))
+            except Exception:
+                pass
+            time.sleep(0.05)
+
+    def mean(self, t0, t1):
+        xs = [v for t, v in self.samples if t0 <= t <= t1]
+        return float(np.mean(xs)) if xs else None
+
+    def close(self):
+        self.stop.set()
+        self.thread.join()
+        self.smi.amdsmi_shut_down()
+
+
+def inflight_fraction(queries) -> float:
+    """Fraction of the measured span during which at least one query was on the device."""
+    iv = sorted((q.admitted, q.finished) for q in queries if q.admitted is not None)
+    busy, cur0, cur1 = 0.0, None, None
+    for a, b in iv:
+        if cur1 is None or a > cur1:
+            if cur1 is not None:
+                busy += cur1 - cur0
+            cur0, cur1 = a, b
+        else:
+            cur1 = max(cur1, b)
+    if cur1 is not None:
+        busy += cur1 - cur0
+    span = max(q.finished for q in queries) - min(q.arrival for q in queries)
+    return busy / span if span > 0 else 0.0
+
+
+def bench_c5(torch, W, count: int, rmat22=None, warmup: int = 500):
+    """Serving: 8 resident graphs, Poisson queries at the rate fixed in the workload recipe
+    (0.7 x the closed-loop rate measured once), 2 GB admission budget."""
     from paper_2209_08764_amd.serve import GpuExecutor, Scheduler, latency_summary, poisson_queries
-    graphs = W.c5_graphs() if rmat22 is None else None
-    if graphs is None:
-        graphs = W.c5_graphs_with(rmat22)
+    graphs = W.c5_graphs() if rmat22 is None else W.c5_graphs_with(rmat22)
     ex = GpuExecutor(graphs, max_inflight=4)
     noniso = {k: np.flatnonzero(np.diff(g.offsets)) for k, g in graphs.items()}
-    budget = 16 << 30
-    # closed loop: all queries at t = 0, the saturated rate
+    budget = W.C5_BUDGET_BYTES
     sch = Scheduler(ex, budget_bytes=budget, max_inflight=4)
-    warm = poisson_queries(graphs, noniso, rate=0, count=min(200, count), seed=5)
-    sch.run(warm)
-    closed = poisson_queries(graphs, noniso, rate=0, count=count, seed=6)
+    # closed loop (all queries at t = 0): the saturated rate, reported beside the frozen one
+    closed = poisson_queries(graphs, noniso, rate=0, count=min(2000, count), seed=6)
     sch.run(closed)
     sat = latency_summary(closed)["qps"]
-    rate = 0.7 * sat
+    rate = W.C5_RATE_QPS
+    warm = poisson_queries(graphs, noniso, rate=rate, count=warmup, seed=5)
+    sch.run(warm)
     qs = poisson_queries(graphs, noniso, rate=rate, count=count, seed=7)
+    try:
+        meter = BusyMeter()
+    except Exception:
+        meter = None
+    t0 = time.perf_counter()
     sch.run(qs)
-    summ = latency_summary(qs)
+    t1 = time.perf_counter()
+    busy = meter.mean(t0, t1) if meter else None
+    if meter:
+        meter.close()
+    ok = [q for q in qs if q.error is None]
+    summ = latency_summary(ok)
     sch.close()
     return {"workload": "8 resident graphs (rmat18/20/22/23, G(2^20, 8), grids 1024^2 and 2048^2, "
                         "power-law forest 2^20), Poisson arrivals",
-            "closed_loop_qps": round(sat, 1), "rate_qps": round(rate, 1), "queries": count,
+            "rate_qps": rate, "rate_rule": "0.7 x the closed-loop rate, measured once and fixed in the recipe",
+            "closed_loop_qps_this_run": round(sat, 1), "warmup_queries": warmup, "queries": count,
+            "failed": len(qs) - len(ok),
             "p50_ms": round(summ["p50_ms"], 3), "p99_ms": round(summ["p99_ms"], 3),
             "mean_ms": round(summ["mean_ms"], 3), "qps": round(summ["qps"], 1),
-            "batched_fraction": round(summ["batched_fraction"], 3), "budget_bytes": budget}
+            "batched_fraction": round(summ["batched_fraction"], 3), "budget_bytes": budget,
+            "gpu_busy_pct_amdsmi": round(busy, 1) if busy is not None else None,
+            "inflight_pct": round(100 * inflight_fraction(ok), 1), "scheduler": dict(sch.stats)}
+
+
+def bench_multiroot(torch, Graph, Workspace, count: int = 1024):
+    """Many small graphs: a disjoint union searched from one root per part in one launch
+    (bfs_run_multiroot), against one search per part on its own resident graph."""
+    import graphgen as gg
+    import oracle
+    parts = []
+    for i in range(count):
+        kind = i % 4
+        if kind == 0:
+            parts.append(gg.rmat(10, seed=7000 + i))
+        elif kind == 1:
+            parts.append(gg.grid(16 + i % 17, 24))
+        elif kind == 2:
+            parts.append(gg.powerlaw_forest(1500, nroots=1, seed=7000 + i))
+        else:
+            parts.append(gg.erdos_renyi(1000, 6.0, seed=7000 + i))
+    u, base = gg.disjoint_union(parts)
+    roots = np.array([int(base[i]) + int(gg.pick_sources(p, 1, seed=i)[0]) for i, p in enumerate(parts)], np.int32)
+    G = Graph(u.offsets, u.cols)
+    ws = Workspace(G, profile=1)
+    lv = torch.empty(u.n, dtype=torch.int32, device="cuda")
+    pa = torch.empty_like(lv)
+    ws.run_multiroot(roots, lv, pa)
+    ws.sync()
+    want_l, want_p = oracle.bfs(u.offsets, u.cols, roots)
+    parity = bool(np.array_equal(lv.cpu().numpy(), want_l) and np.array_equal(pa.cpu().numpy(), want_p))
+    times = []
+    for _ in range(5):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ws.run_multiroot(roots, lv, pa)
+        torch.cuda.synchronize()
+        times.append((time.perf_counter() - t0) * 1e3)
+    t_union = float(np.median(times))
+    # one search per part, each part resident on its own, back to back on one stream
+    sep = [(Graph(p.offsets, p.cols), int(r - b)) for p, r, b in zip(parts, roots, base)]
+    wss = [(Workspace(Gp), s, torch.empty(Gp.n, dtype=torch.int32, device="cuda"),
+            torch.empty(Gp.n, dtype=torch.int32, device="cuda")) for Gp, s in sep]
+    for w, s, l, q in wss[:8]:
+        w.run(s, l, q)
+    torch.cuda.synchronize()
+    sp = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for w, s, l, q in wss:
+            w.run(s, l, q)
+        torch.cuda.synchronize()
+        sp.append((time.perf_counter() - t0) * 1e3)
+    t_sep = float(np.median(sp))
+    for w, _, _, _ in wss:
+        w.free()
+    for Gp, _ in sep:
+        Gp.free()
+    mc = int(np.diff(u.offsets.astype(np.int64))[want_l >= 0].sum()) // 2
+    return {"workload": f"disjoint union of {count} small graphs (R-MAT 10, grids, forests, G(1000, 6)), "
+                        "one root each", "n": u.n, "m": u.m, "ms_one_launch": round(t_union, 3),
+            "ms_separate_searches": round(t_sep, 3), "speedup": round(t_sep / t_union, 2),
+            "gteps_one_launch": round(mc / (t_union * 1e-3) / 1e9, 3), "parity_bit_exact": parity}
 
 
 def probe_ceiling(torch, n: int, count: int = 1 << 28, reps: int = 5) -> dict:
@@ -511,9 +710,9 @@ def run(args):
     level = torch.empty(n, dtype=torch.int32, device="cuda")
     parent = torch.empty(n, dtype=torch.int32, device="cuda")
 
-    # per-source component sizes from one untimed pass (also the first warm-up)
-    mc_half, nc = [], []
-    for s in sources:
+    # per-source component sizes and per-level records from one untimed pass (also a warm-up)
+    mc_half, nc, per_level = [], [], []
+    for j, s in enumerate(sources):
         ws.run(int(s), level, parent)
         st = ws.stats()
         if st["status"] != 0:
@@ -521,31 +720,34 @@ def run(args):
         mc_half.append(st["edges"] / 2)
         nc.append(st["reached"])
         levels_used = st["levels"]
-    for i in range(args.warmup):
-        ws.run(int(sources[i % len(sources)]), level, parent)
+        if j < 4:
+            per_level.append({"source": int(s), "grid": st["grid"], "levels": level_record(ws)})
+    for _ in range(args.warmup):
+        for s in sources:
+            ws.run(int(s), level, parent)
     ws.sync()
-    log(f"timing {args.steps} searches")
-    step_ms, wall_ms, kms = time_single_source(ws, level, parent, sources, args.steps, torch, mc_half)
-    value = per_source_hm(step_ms, sources, mc_half)
-    # roofline of the persistent kernel
-    kbytes = []
-    for i in range(args.steps):
-        j = i % len(sources)
-        kbytes.append(algorithmic_bytes(n, nc[j], int(2 * mc_half[j]))[1])
-    kb = float(np.mean(kbytes))
+    log(f"timing {args.steps} passes over the {len(sources)} sources")
+    step_ms, wall_ms, kms = time_passes(ws, level, parent, sources, args.steps, torch)
+    value = hm_gteps(step_ms, mc_half)
+    # roofline of the persistent kernel: every source once per pass, so the mean over sources
+    kb = float(np.mean([algorithmic_bytes(n, nc[j], int(2 * mc_half[j]))[1] for j in range(len(sources))]))
     kt = float(np.mean(kms)) if len(kms) else float("nan")
     achieved = kb / (kt * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": stored_traffic("rmat24"),
-                "kernel": "k_persistent", "kernel_ms_mean": round(kt, 4),
-                "algorithmic_bytes_per_launch": int(kb)}
+                "traffic_source": "stored rocprofv3 FETCH_SIZE + WRITE_SIZE runs of this kernel code "
+                                  "(profiles/traffic_persistent_rmat24.json, keyed by source hash; "
+                                  "null once the code changes)",
+                "kernel": "k_persistent<false>", "kernel_ms_mean": round(kt, 4), "launches": int(len(kms)),
+                "algorithmic_bytes_per_launch": int(kb), "target_frac": 0.40}
     log(f"single-source: {value:.2f} GTEPS hm, {np.mean(step_ms):.3f} ms/search, kernel {kt:.3f} ms, "
         f"{achieved:.0f} GB/s algorithmic")
 
-    extras = {"levels": levels_used, "n": n, "m": g.m, "step_ms_median": round(float(np.median(step_ms)), 4)}
+    extras = {"levels": levels_used, "n": n, "m": g.m, "search_ms_median": round(float(np.median(step_ms)), 4),
+              "searches_timed": int(step_ms.size), "c3_per_level_first_4_sources": per_level}
     # the secondary ceiling: every scanned edge probes the visited bitmap at a random word
     ceil = probe_ceiling(torch, n)
-    probes = float(np.mean([2 * mc_half[i % len(sources)] for i in range(args.steps)])) / (kt * 1e-3) / 1e9
+    probes = float(np.mean([2 * x for x in mc_half])) / (kt * 1e-3) / 1e9
     bkey = next(k for k in ceil if k.startswith("bitmap"))
     extras["probe_ceiling"] = ceil
     extras["probe_rate_gprobes_per_s"] = round(probes, 1)
@@ -560,8 +762,8 @@ def run(args):
             for s in sub[:2]:
                 ws.run(int(s), level, parent)
             ws.sync()
-            sm, _, _ = time_single_source(ws, level, parent, sub, len(sub), torch, mc_half)
-            extras[f"{name}_gteps_hm"] = round(per_source_hm(sm, sub, mc_half[:nsrc]), 3)
+            sm, _, _ = time_passes(ws, level, parent, sub, 1, torch)
+            extras[f"{name}_gteps_hm"] = round(hm_gteps(sm, mc_half[:nsrc]), 3)
             extras[f"{name}_ms_median"] = round(float(np.median(sm)), 3)
             log(f"{name}: {extras[f'{name}_gteps_hm']} GTEPS")
         ws.set(BFS_OPT_MODE, BFS_MODE_AUTO)
@@ -583,8 +785,8 @@ def run(args):
             for s in sub[:2]:
                 wl.run(int(s), level, parent)
             wl.sync()
-            sm, _, _ = time_single_source(wl, level, parent, sub, len(sub), torch, mc_half)
-            extras["no_hot_filter_gteps_hm"] = round(per_source_hm(sm, sub, mc_half[:16]), 3)
+            sm, _, _ = time_passes(wl, level, parent, sub, 1, torch)
+            extras["no_hot_filter_gteps_hm"] = round(hm_gteps(sm, mc_half[:16]), 3)
             extras["hot_filter_aux_bytes"] = G.aux_bytes
             log(f"without the hot-vertex filter: {extras['no_hot_filter_gteps_hm']} GTEPS")
             wl.free()
@@ -594,8 +796,18 @@ def run(args):
     if not args.no_cpu:
         threads = host_cores()
         log(f"CPU oracle baseline on {threads} host threads")
-        cpu = cpu_baseline(g, sources, threads)
-        log(f"  oracle {cpu['value']} GTEPS on {threads} threads")
+        cpu, outs = cpu_baseline(g, sources, threads, keep=True)
+        log(f"  oracle {cpu['value']} GTEPS on {threads} threads ({cpu['host']})")
+        # parity of the timed configuration on the sources the oracle just solved
+        ok = 0
+        for s, want_l, want_p in outs:
+            ws.run(s, level, parent)
+            ws.sync()
+            ok += int(np.array_equal(level.cpu().numpy(), want_l) and np.array_equal(parent.cpu().numpy(), want_p))
+        extras["parity_checked_sources"] = len(outs)
+        extras["parity_bit_exact_sources"] = ok
+        log(f"  parity: {ok} of {len(outs)} sources bit-exact (level and parent)")
+        del outs
     ws.free()
     G.free()
     del level, parent, ws, G, g
@@ -607,12 +819,16 @@ def run(args):
         log(f"  {extras['c1']}")
         log("C2: grid 4096x4096")
         extras["c2"] = bench_c2(torch, W, Graph, Workspace)
-        log(f"  {extras['c2']}")
+        log(f"  {dict((k, v) for k, v in extras['c2'].items() if not k.startswith('per_level'))}")
         torch.cuda.empty_cache()
         log("C4: R-MAT 22, 256 sources batched")
         g22, s22 = W.c4_rmat22()
         extras["c4"] = bench_c4(torch, W, Graph, Workspace, g22, s22)
         log(f"  {extras['c4']}")
+        torch.cuda.empty_cache()
+        log("many small graphs in one multi-root launch")
+        extras["multiroot"] = bench_multiroot(torch, Graph, Workspace)
+        log(f"  {extras['multiroot']}")
         torch.cuda.empty_cache()
         if args.serve_queries > 0:
             log(f"C5: serving, {args.serve_queries} queries")
@@ -634,7 +850,9 @@ def run(args):
         "data": "synthetic",
         "config": {"workload": f"rmat{args.scale}_64src_single", "graph": "R-MAT", "scale": args.scale,
                    "edgefactor": 16, "abcd": [0.57, 0.19, 0.19, 0.05], "symmetrised": True, "permuted": True,
-                   "sources": 64, "mode": "auto", "gteps_edges": "undirected edges in the component"},
+                   "sources": len(sources), "sources_timed_per_step": len(sources),
+                   "step": "one pass over all sources, one search at a time", "mode": "auto",
+                   "hot_vertex_filter": True, "gteps_edges": "undirected edges in the component"},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "extras": extras,
@@ -645,12 +863,12 @@ def run(args):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=192)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5, help="timed passes over the 64 sources")
+    ap.add_argument("--warmup", type=int, default=1, help="untimed passes before them")
     ap.add_argument("--scale", type=int, default=24)
     ap.add_argument("--quick", action="store_true", help="headline workload only")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--serve-queries", type=int, default=2000, help="queries in the serving run (0 skips it)")
+    ap.add_argument("--serve-queries", type=int, default=10000, help="queries in the serving run (0 skips it)")
     ap.add_argument("--calib-copy", action="store_true", help="only run a 1 GiB device copy (counter calibration)")
     ap.add_argument("--rocpd-summary", nargs="+", metavar="DB", help="summarise rocprofv3 result databases and exit")
     ap.add_argument("--rocpd-dispatches", nargs=4, metavar=("KERNEL", "SKIP", "TAKE", "DB"),
