@@ -328,6 +328,13 @@ def bench_c2(torch, W, Graph, Workspace):
     rec = level_record(ws)
     ms, _, kms = time_passes(ws, lv, pa, [0], 3, torch)
     t = float(np.median(ms))
+    # split ablation: share start points by binary search instead of the scatter
+    from paper_2209_08764_amd import BFS_OPT_SPLIT
+    ws.set(BFS_OPT_SPLIT, 1)
+    sm, _, _ = time_passes(ws, lv, pa, [0], 1, torch)
+    ws.set(BFS_OPT_SPLIT, 0)
+    t_search = float(np.median(sm))
+    ws.run(0, lv, pa)
     W_ = 4096
     r, c = np.divmod(np.arange(g.n, dtype=np.int64), W_)
     closed_l = bool(np.array_equal(lv.cpu().numpy(), r + c))
@@ -343,6 +350,7 @@ def bench_c2(torch, W, Graph, Workspace):
     return {"workload": "grid 4096x4096 from vertex 0", "ms_per_search": round(t, 2),
             "kernel_ms": round(float(np.median(kms)), 2),
             "us_per_level": round(t * 1e3 / st["levels"], 2), "levels": st["levels"],
+            "split_search_ms_per_search": round(t_search, 2),
             "small_levels": st["small_levels"], "gteps": round(st["edges"] / 2 / (t * 1e-3) / 1e9, 3),
             "closed_form_levels_ok": closed_l, "closed_form_parents_ok": closed_p,
             "us_per_level_single_workgroup": us(one), "levels_single_workgroup": len(one),
@@ -567,7 +575,8 @@ def bench_c5(torch, W, count: int, rmat22=None, warmup: int = 500):
     ex = GpuExecutor(graphs, max_inflight=4)
     noniso = {k: np.flatnonzero(np.diff(g.offsets)) for k, g in graphs.items()}
     budget = W.C5_BUDGET_BYTES
-    sch = Scheduler(ex, budget_bytes=budget, max_inflight=4)
+    # answers are counted and dropped as they complete (10 000 level arrays would hold ~100 GB)
+    sch = Scheduler(ex, budget_bytes=budget, max_inflight=4, keep_results=False)
     # closed loop (all queries at t = 0): the saturated rate, reported beside the frozen one
     closed = poisson_queries(graphs, noniso, rate=0, count=min(2000, count), seed=6)
     sch.run(closed)
@@ -694,7 +703,8 @@ def run(args):
     import graphgen as gg
     from graphgen import workloads as W
     from paper_2209_08764_amd import (BFS_MODE_AUTO, BFS_MODE_DIRECTION, BFS_MODE_INSENSITIVE, BFS_MODE_LEVEL,
-                                      BFS_MODE_PLAIN, BFS_OPT_MODE, BFS_OPT_PROFILE, Graph, Workspace, _lib)
+                                      BFS_MODE_PLAIN, BFS_OPT_MODE, BFS_OPT_PROFILE, BFS_OPT_SPLIT, Graph, Workspace,
+                                      _lib)
 
     _lib.load()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
@@ -768,6 +778,18 @@ def run(args):
             log(f"{name}: {extras[f'{name}_gteps_hm']} GTEPS")
         ws.set(BFS_OPT_MODE, BFS_MODE_AUTO)
         extras["speedup_vs_plain"] = round(value / extras["plain_gteps_hm"], 2)
+        # split ablation: share start points by binary search instead of the scatter
+        ws.set(BFS_OPT_SPLIT, 1)
+        sub = sources[:16]
+        for s in sub[:2]:
+            ws.run(int(s), level, parent)
+        ws.sync()
+        sm, _, _ = time_passes(ws, level, parent, sub, 1, torch)
+        extras["split_search_gteps_hm"] = round(hm_gteps(sm, mc_half[:16]), 3)
+        extras["split_search_ms_median"] = round(float(np.median(sm)), 3)
+        extras["split_scatter_gteps_hm_same_sources"] = round(hm_gteps(step_ms[:, :16], mc_half[:16]), 3)
+        ws.set(BFS_OPT_SPLIT, 0)
+        log(f"split by binary search: {extras['split_search_gteps_hm']} GTEPS")
         # energy: work-sized against work-insensitive levels, on this graph and on the grid
         log("energy: work-sensitive vs work-insensitive (R-MAT 24, grid 4096^2)")
         gg2, _ = W.c2_grid4096()

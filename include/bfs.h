@@ -89,6 +89,12 @@ typedef struct bfs_workspace_s* bfs_workspace_t;  /* scratch for one in-flight r
                                   has none to find) and scans at least this many edges records its
                                   new vertices as bits instead of private-queue entries and
                                   linearises them in vertex order (0 = never; default m / 12) */
+#define BFS_OPT_SPLIT      13  /* how each level's equal shares find their start points
+                                  (Analysis, Find-StartExpPoint): 0 = every frontier vertex
+                                  writes itself as the start of the shares beginning inside its
+                                  edge range (the paper's scatter, default); 1 = every share
+                                  finds its start by a binary search of the degree prefix sums.
+                                  Same result; an ablation of the cost */
 
 typedef struct {
     int32_t levels;          /* frontiers processed: max level + 1 */
@@ -139,7 +145,12 @@ bfs_status_t bfs_graph_info(bfs_graph_t g, int32_t* n, int64_t* m);
 int64_t bfs_graph_aux_bytes(bfs_graph_t g);
 
 /* Device bytes a workspace for up to max_sources batched sources needs
-   (max_sources = 1: single-source and multi-root runs only). 0 on error. */
+   (max_sources = 1: single-source and multi-root runs only). 0 on error.
+   Its private queues are sized for BFS_MODE_AUTO with the default options
+   (levels of up to m / 12 edges keep queues; larger ones are dense) and one
+   root.  A run whose mode, options or roots let larger levels keep queues
+   (BFS_MODE_LEVEL, BFS_MODE_DIRECTION, BFS_OPT_DENSE_EDGES = 0 or a higher
+   threshold, more roots) first grows them, up to 4 B per edge. */
 size_t bfs_workspace_bytes(bfs_graph_t g, int32_t max_sources);
 
 /* Allocate a workspace (all scratch of one run).  One workspace serves one

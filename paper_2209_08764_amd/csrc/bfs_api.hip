@@ -54,6 +54,32 @@ hipError_t dalloc(T** p, size_t count) {
     return hipMalloc(reinterpret_cast<void**>(p), std::max<size_t>(count, 1) * sizeof(T));
 }
 
+// Entries of the private-queue array that a run needs.  Share b of a level
+// keeps its queue in cand[tb * kGrain, te * kGrain), so a level that keeps
+// queues needs its edges rounded up to whole sub-tiles.  Dense levels keep
+// none, so with the default thresholds only levels up to m / 12 edges do;
+// per-level launches, direction optimisation (whose bottom-up levels queue up
+// to n vertices) and dense levels switched off may queue any level.  Single-
+// workgroup levels put what exceeds their LDS (at most small_edges entries)
+// there too, and the roots sit there as the queues of level -1.
+int64_t cand_need(int64_t m, int64_t n, int32_t mode, int64_t push_edges, int64_t dense_edges, int64_t small_edges,
+                  int64_t nroots, bool parents) {
+    if (mode == BFS_MODE_PLAIN) return kGrain;  // the plain comparator keeps no queues
+    int64_t e;
+    if (mode == BFS_MODE_LEVEL || mode == BFS_MODE_DIRECTION || dense_edges <= 0) e = std::max(m, n);
+    else e = std::min(std::max(parents ? push_edges : 0, dense_edges - 1), m);
+    const int64_t e_small = small_edges > 0 ? std::min(small_edges, m) : 0;
+    auto tiles = [](int64_t x) { return (x + kGrain - 1) / kGrain; };
+    return std::max<int64_t>({tiles(e), tiles(e_small), tiles(nroots), 1}) * kGrain;
+}
+
+// Private-queue entries a workspace starts with: enough for BFS_MODE_AUTO with
+// the default options, parents and one root.
+int64_t default_cand(int64_t m, int64_t n) {
+    const int64_t split = std::min<int64_t>(m / kLevelSplit, INT32_MAX);
+    return cand_need(m, n, BFS_MODE_AUTO, split, std::max<int64_t>(split, 1), kDefaultSmallEdges, 1, true);
+}
+
 }  // namespace
 
 struct bfs_graph_s {
@@ -74,6 +100,7 @@ struct bfs_workspace_s {
     int device = 0;
     int32_t max_sources = 1;
     int32_t max_tiles = 0;
+    int64_t cand_cap = 0;   // entries of the private-queue array (grown when a run needs more)
     int32_t grid_cap = 0;
     // single-source buffers
     uint32_t* bitmap = nullptr;
@@ -135,6 +162,7 @@ struct bfs_workspace_s {
     int32_t grid_opt = 0;
     int32_t profile = 0;
     int32_t batch_pull = -2;  // -2: library default
+    int32_t split_search = 0; // BFS_OPT_SPLIT
     // last run
     int32_t last_mode = 0;
     int32_t last_grid = 0;
@@ -172,6 +200,36 @@ int32_t dense_edges_of(const bfs_workspace_s* ws) {
                                 : (int32_t)std::min<int64_t>(std::max<int64_t>(ws->g->m / kLevelSplit, 1), INT32_MAX);
 }
 
+int32_t push_edges_of(const bfs_workspace_s* ws) {
+    return ws->push_edges >= 0 ? ws->push_edges : (int32_t)std::min<int64_t>(ws->g->m / kLevelSplit, INT32_MAX);
+}
+
+// Private-queue entries a run of ws with its current mode and options needs.
+int64_t ws_cand_need(const bfs_workspace_s* ws, int64_t nroots, bool parents) {
+    return cand_need(ws->g->m, ws->g->n, ws->mode, push_edges_of(ws), dense_edges_of(ws), ws->small_edges, nroots,
+                     parents);
+}
+
+// Grows the private-queue array when this run's mode, options or roots need more
+// than it holds (after the workspace's last run has finished with it).
+bfs_status_t ensure_cand(bfs_workspace_s* ws, int64_t need) {
+    if (need <= ws->cand_cap) return BFS_OK;
+    if (ws->has_run) HIP_TRY(hipEventSynchronize(ws->ev_done));
+    int32_t* grown = nullptr;
+    if (dalloc(&grown, (size_t)need) != hipSuccess)
+        return fail(BFS_ENOMEM, "growing the private queues to %lld entries failed", (long long)need);
+    hipError_t e = hipMemsetAsync(grown, 0, sizeof(int32_t) * (size_t)need, ws->own_stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ws->own_stream);
+    if (e != hipSuccess) {
+        (void)hipFree(grown);
+        return fail(BFS_EHIP, "clearing the private queues: %s", hipGetErrorString(e));
+    }
+    (void)hipFree(ws->cand);
+    ws->cand = grown;
+    ws->cand_cap = need;
+    return BFS_OK;
+}
+
 Params make_params(bfs_workspace_s* ws, int32_t* level, int32_t* parent) {
     Params p{};
     p.offsets = ws->g->offsets;
@@ -202,6 +260,7 @@ Params make_params(bfs_workspace_s* ws, int32_t* level, int32_t* parent) {
         p.desc[i] = ws->desc[i];
     }
     p.cand = ws->cand;
+    p.cand_cap = ws->cand_cap;
     p.cnt = ws->cnt;
     p.ctrl = ws->ctrl;
     p.xbar = ws->xbar;
@@ -212,8 +271,9 @@ Params make_params(bfs_workspace_s* ws, int32_t* level, int32_t* parent) {
     // Pushing costs one atomic per scanned edge into an unsettled vertex; pulling
     // costs about one row read per new vertex but long ones when the frontier is
     // small next to what it discovers.  Levels below an eighth of the graph push.
-    p.push_edges = ws->push_edges >= 0 ? ws->push_edges : (int32_t)std::min<int64_t>(ws->g->m / kLevelSplit, INT32_MAX);
+    p.push_edges = push_edges_of(ws);
     p.max_tiles = ws->max_tiles;
+    p.split_search = ws->split_search;
     p.spin_ticks = kSpinTicks;
     return p;
 }
@@ -232,16 +292,15 @@ bfs_status_t check_busy(bfs_workspace_s* ws, hipStream_t s) {
 // many), at least kMinGrid and at most what fits on the GPU at once.  A level
 // cannot use more workgroups than it has 2048-edge sub-tiles, and every extra
 // workgroup lengthens each grid barrier.
-int grid_for(bfs_workspace_s* ws) {
+int default_grid(int cap, int64_t m) {
     constexpr int64_t kEdgesPerWg = 16384, kMinGrid = 64;
-    int g = ws->grid_cap;
-    if (ws->grid_opt > 0) {
-        g = std::min(g, ws->grid_opt);
-    } else {
-        const int64_t want = std::max<int64_t>(kMinGrid, (ws->g->m / kEdgesPerWg + 7) / 8 * 8);
-        g = (int)std::min<int64_t>(g, want);
-    }
-    return std::max(g, 1);
+    const int64_t want = std::max<int64_t>(kMinGrid, (m / kEdgesPerWg + 7) / 8 * 8);
+    return std::max(1, (int)std::min<int64_t>(cap, want));
+}
+
+int grid_for(bfs_workspace_s* ws) {
+    if (ws->grid_opt > 0) return std::max(1, std::min(ws->grid_cap, ws->grid_opt));
+    return default_grid(ws->grid_cap, ws->g->m);
 }
 
 bfs_status_t read_ctrl(bfs_workspace_s* ws, hipStream_t s) {
@@ -333,6 +392,9 @@ bfs_status_t run_common(bfs_workspace_s* ws, const int32_t* roots_host, int32_t 
     bfs_status_t st = check_busy(ws, s);
     if (st) return st;
     HIP_TRY(hipSetDevice(ws->device));
+    if (roots_host && (k < 1 || k > ws->g->n)) return fail(BFS_EINVAL, "need 1 <= k <= n roots");
+    st = ensure_cand(ws, ws_cand_need(ws, roots_host ? k : 1, parent != nullptr));
+    if (st) return st;
     Params p = make_params(ws, level, parent);
     if (roots_host) {
         for (int32_t i = 0; i < k; ++i)
@@ -664,7 +726,7 @@ size_t bfs_workspace_bytes(bfs_graph_t g, int32_t max_sources) {
     b += n * 4;                        // owner
     b += 6 * (n + 2) * 4;              // frontier ids / row starts / degree sums, x2
     b += 2 * T * 4;                    // tstart x2
-    b += T * kGrain * 4;               // candidates
+    b += (size_t)default_cand(g->m, g->n) * 4;  // private queues (default options; see bfs.h)
     b += 2 * T * 4;                    // counts, bottom-up edge totals
     b += 2 * T * 8;                    // descriptors
     b += sizeof(Ctrl) + sizeof(XBar) + 2 * (size_t)kStatCap * 4 + 3 * (size_t)kStatCap * 8 + n * 4;  // ctrl, barrier, stats, roots
@@ -740,7 +802,8 @@ bfs_status_t bfs_workspace_create(bfs_graph_t g, int32_t max_sources, bfs_worksp
         A(dalloc(&ws->tstart[i], (size_t)T));
         A(dalloc(&ws->desc[i], (size_t)T));
     }
-    A(dalloc(&ws->cand, (size_t)T * kGrain));
+    ws->cand_cap = default_cand(g->m, g->n);
+    A(dalloc(&ws->cand, (size_t)ws->cand_cap));
     A(dalloc(&ws->cnt, 2 * (size_t)T));    // queue lengths, then bottom-up edge totals
     A(dalloc(&ws->ctrl, 1));
     A(dalloc(&ws->xbar, 1));
@@ -788,7 +851,7 @@ bfs_status_t bfs_workspace_create(bfs_graph_t g, int32_t max_sources, bfs_worksp
     }
     hipStream_t os = ws->own_stream;
     bool zok = hipMemsetAsync(ws->cnt, 0, sizeof(int32_t) * 2 * (size_t)T, os) == hipSuccess &&
-               hipMemsetAsync(ws->cand, 0, sizeof(int32_t) * (size_t)T * kGrain, os) == hipSuccess &&
+               hipMemsetAsync(ws->cand, 0, sizeof(int32_t) * (size_t)ws->cand_cap, os) == hipSuccess &&
                hipMemsetAsync(ws->owner, 0xff, sizeof(int32_t) * n, os) == hipSuccess;
     for (int i = 0; i < 2 && zok; ++i)
         zok = hipMemsetAsync(ws->tstart[i], 0, sizeof(int32_t) * (size_t)T, os) == hipSuccess &&
@@ -874,6 +937,10 @@ bfs_status_t bfs_workspace_set_option(bfs_workspace_t ws, int32_t option, int64_
             ws->b_uv = (int32_t)(value / kBlock);
             return setup_batch(ws);
         }
+        case BFS_OPT_SPLIT:
+            if (value != 0 && value != 1) return fail(BFS_EINVAL, "split must be 0 (scatter) or 1 (binary search)");
+            ws->split_search = (int32_t)value;
+            return BFS_OK;
         case BFS_OPT_BATCH_PULL:
             if (value < -1 || value > INT32_MAX) return fail(BFS_EINVAL, "bad pull threshold");
             ws->batch_pull = (int32_t)value;

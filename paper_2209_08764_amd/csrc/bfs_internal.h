@@ -95,6 +95,7 @@ struct Params {
     int32_t* f_v[2];          // frontier vertex ids, per parity (written only if non-null)
     int32_t* tstart[2];       // sub-tile start points, per parity
     int32_t* cand;            // private queues: share b owns cand[tb*kGrain, te*kGrain)
+    int64_t cand_cap;         // entries of cand
     int32_t* cnt;             // queue length per share
     unsigned long long* desc[2];  // look-back descriptors per share, per parity
     Ctrl* ctrl;
@@ -120,6 +121,8 @@ struct Params {
     int32_t bu_alpha;         // go bottom-up when e_l * alpha > edges of unreached vertices
     int32_t bu_beta;          // return top-down when n_l * beta < n
     int32_t max_tiles;
+    int32_t split_search;     // 1: each share finds its sub-tile start points by binary search
+                              // instead of the compaction scattering them (Find-StartExpPoint)
     uint64_t spin_ticks;      // s_memrealtime ticks a wait may last without progress
 };
 

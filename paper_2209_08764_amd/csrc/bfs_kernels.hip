@@ -35,8 +35,11 @@
 
 namespace s3bfs {
 
-// Marks every share that starts inside [e, e + d) as starting at frontier entry pos.
+// Marks every share that starts inside [e, e + d) as starting at frontier entry pos
+// (Find-StartExpPoint).  With split_search the expansion finds the start points
+// by binary search instead (search_starts), and nothing is scattered.
 __device__ __forceinline__ void scatter_starts(const Params& p, int32_t* tstart, int pos, int e, int d) {
+    if (p.split_search) return;
     int64_t t = ((int64_t)e + kGrain - 1) / kGrain;
     int64_t tend = ((int64_t)e + d + kGrain - 1) / kGrain;
     if (t < 0 || tend > p.max_tiles) {
@@ -61,6 +64,32 @@ __device__ __forceinline__ int* lds_misc(int* lds) { return lds + kLdsWords - 8;
 __device__ __forceinline__ void share_range(int b, int P, int ntiles, int* tb, int* te) {
     *tb = (int)(((int64_t)b * ntiles) / P);
     *te = (int)(((int64_t)(b + 1) * ntiles) / P);
+}
+
+// The alternative to the scatter: before its expansion, share b finds the
+// start point of each of its sub-tiles [tb, te] (te too when another sub-tile
+// follows) by a binary search of the level's exclusive degree sums: the last
+// frontier entry j with f_ex[j] <= t * kGrain.  One search per lane, all of
+// them in flight together.  Called by the whole workgroup.
+__device__ __forceinline__ void search_starts(const Params& p, int l, int b, int P, int ntiles, int n_l) {
+    int tb, te;
+    share_range(b, P, ntiles, &tb, &te);
+    const int tend = te < ntiles ? te : ntiles - 1;
+    const int32_t* fex = p.f_ex[l & 1];
+    int32_t* tst = p.tstart[l & 1];
+    const int steps = n_l > 1 ? 32 - __builtin_clz((unsigned)(n_l - 1)) : 0;
+    for (int t = tb + (int)threadIdx.x; t <= tend; t += kBlock) {
+        const int64_t g = (int64_t)t * kGrain;
+        int lo = 0, hi = n_l;  // f_ex[lo] <= g < f_ex[hi] (f_ex[n_l] = e_l)
+        for (int k = 0; k < steps; ++k) {
+            const int mid = (lo + hi) >> 1;
+            const bool right = (int64_t)fex[mid] <= g;
+            lo = right ? mid : lo;
+            hi = right ? hi : mid;
+        }
+        tst[t] = lo;
+    }
+    __syncthreads();  // full: the expansion reads these entries from global memory
 }
 
 // Parent of a vertex v reached at level l + 1 is its smallest-id neighbour
@@ -1115,7 +1144,7 @@ __device__ void small_levels(const Params& p, int l, int n_l, int e_l, int* lds)
                     p.level[v[i]] = l + 1;
                     const int s = base + mbcnt(bb);
                     if (s < kSmallC) s_cand[s] = v[i];
-                    else if ((int64_t)s < (int64_t)p.max_tiles * kGrain) p.cand[s] = v[i];
+                    else if ((int64_t)s < p.cand_cap) p.cand[s] = v[i];
                     else flag_internal(p.ctrl);
                 }
             }
@@ -1422,6 +1451,12 @@ k_persistent(Params p) {
         // levels: it merges no hot bits and keeps no frontier bits for the next level's pulls
         const bool lite = !DIR && !dense && P < kLiteShares;
         const bool keep_fb = !DIR && p.fb_pull && !lite;  // this level's compaction keeps frontier bits
+        // the host sizes the private queues for every level its options let keep them; a level
+        // beyond that (which it never launches) stops the run with an error instead of writing past
+        if (!dense && !(DIR && bottom_up) && (int64_t)ntiles * kGrain > p.cand_cap) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) flag_internal(c);
+            return;  // every workgroup takes this branch at the same level
+        }
         // reset this level's compaction state (last used two levels ago)
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             st_rel(&c->kept[np], 0);
@@ -1454,6 +1489,7 @@ k_persistent(Params p) {
         if (DIR && bottom_up) {
             if (blockIdx.x < P) bottom_up_share(p, l, blockIdx.x, P, ntiles, lds);
         } else if (blockIdx.x < P) {
+            if (p.split_search) search_starts(p, l, blockIdx.x, P, ntiles, n_l);
             [[clang::always_inline]] expand_share(p, l, blockIdx.x, P, ntiles, n_l, e_l, lds, dense, lite);
         }
         // a lite level's compaction needs only its own workgroups' expansion, so only they
@@ -1545,6 +1581,7 @@ __global__ void __launch_bounds__(kBlock) k_level_expand(Params p, int l, int nt
     const int par = l & 1, np = (l + 1) & 1;
     if (blockIdx.x == 0 && threadIdx.x == 0) st_rel(&p.ctrl->kept[np], 0);
     if (threadIdx.x == 0) p.desc[par][blockIdx.x] = 0ull;
+    if (p.split_search) search_starts(p, l, blockIdx.x, gridDim.x, ntiles, n_l);
     expand_share(p, l, blockIdx.x, gridDim.x, ntiles, n_l, e_l, lds_s.w);
 }
 
@@ -1694,6 +1731,7 @@ hipError_t launch_prim_compact(const int32_t* offsets, int32_t n, const int32_t*
     p.offsets = offsets;
     p.n = n;
     p.max_tiles = tstart_cap;
+    p.cand_cap = (int64_t)ntiles * kGrain;
     p.owner = const_cast<int32_t*>(owner);
     p.cand = const_cast<int32_t*>(cand);
     p.cnt = const_cast<int32_t*>(cnt);

@@ -1,11 +1,13 @@
 """Serving loop: resident graphs, admission by memory, continuous batching.
 
 Queries (graph, source) arrive over time.  The scheduler admits them as
-execution slots and device memory allow: every in-flight run holds a
-workspace (plus its output arrays) charged against a byte budget, and
-workspaces are pooled per graph.  Queued queries for the same low-diameter
-graph are merged into one batched multi-source run (up to 256 sources,
-uint8 levels); other queries run single-source on their own stream.
+execution slots and device memory allow: workspaces are pooled per graph and
+charged against a byte budget while they exist, and every in-flight run also
+charges its output array until it completes; idle workspaces of other graphs
+are evicted when a query needs room.  Queued queries for the same
+low-diameter graph are merged into one batched multi-source run (up to 256
+sources, uint8 levels, and no more than fit in a set share of the budget);
+other queries run single-source on their own stream.
 Queries that arrive while others are on the GPU are admitted as soon as a
 slot and memory free up, so their work overlaps on the device.
 
@@ -60,12 +62,15 @@ class Scheduler:
     """Continuous-batching request loop over an executor."""
 
     def __init__(self, executor, budget_bytes: int, max_inflight: int = 4, batch_max: int = 256,
-                 batch_min: int = 2, clock: Callable[[], float] = time.perf_counter):
+                 batch_min: int = 2, clock: Callable[[], float] = time.perf_counter, batch_share: float = 0.5,
+                 keep_results: bool = True):
         self.ex = executor
         self.budget = int(budget_bytes)
         self.max_inflight = max_inflight
         self.batch_max = batch_max
         self.batch_min = batch_min
+        self.batch_share = batch_share      # a batch (workspace + output) takes at most this part of the budget
+        self.keep_results = keep_results    # False: answers are dropped once delivered (long runs)
         self.clock = clock
         self.used = 0
         self.pool: dict[tuple[str, int], list] = collections.defaultdict(list)  # idle workspaces
@@ -76,24 +81,35 @@ class Scheduler:
         self.stats = collections.Counter()
 
     # ---- memory ---------------------------------------------------------------------------
-    def _cost(self, info: GraphInfo, k: int) -> int:
-        out = info.n * k if k > 1 else 8 * info.n
-        return (info.ws_bytes_batch if k > 1 else info.ws_bytes_single) + out
+    @staticmethod
+    def _ws_cost(info: GraphInfo, kind: int) -> int:
+        return info.ws_bytes_batch if kind > 1 else info.ws_bytes_single
+
+    @staticmethod
+    def _out_cost(info: GraphInfo, k: int) -> int:
+        return info.n * k if k > 1 else 4 * info.n     # uint8 [n][k], or int32 levels
+
+    def _batch_cap(self, info: GraphInfo) -> int:
+        """Most sources one batch on this graph may take within its share of the budget."""
+        room = int(self.budget * self.batch_share) - info.ws_bytes_batch
+        return max(0, min(self.batch_max, room // max(info.n, 1)))
 
     def _acquire(self, name: str, k: int):
-        """An idle workspace for (graph, k-class), or a new one if the budget allows."""
+        """An idle workspace for (graph, k-class), or a new one, plus the run's output, if the
+        budget allows (evicting idle workspaces of other graphs); None otherwise."""
         info = self.ex.info[name]
         kind = 256 if k > 1 else 1
-        if self.pool[(name, kind)]:
-            return self.pool[(name, kind)].pop()
-        cost = self._cost(info, kind)
-        while self.used + cost > self.budget and self._evict_one(exclude=(name, kind)):
+        pooled = bool(self.pool[(name, kind)])
+        need = self._out_cost(info, k) + (0 if pooled else self._ws_cost(info, kind))
+        while self.used + need > self.budget and self._evict_one(exclude=(name, kind)):
             pass
-        if self.used + cost > self.budget:
+        if self.used + need > self.budget:
             return None
+        self.used += need
+        if pooled:
+            return self.pool[(name, kind)].pop()
         ws = self.ex.create(name, kind)
-        self.used += cost
-        self.pool_bytes[id(ws)] = cost
+        self.pool_bytes[id(ws)] = self._ws_cost(info, kind)
         self.stats["workspaces_created"] += 1
         return ws
 
@@ -117,8 +133,9 @@ class Scheduler:
             q = self.pending.popleft()
             info = self.ex.info[q.graph]
             group = [q]
-            if info.batchable:
-                same = [p for p in self.pending if p.graph == q.graph][: self.batch_max - 1]
+            cap = self._batch_cap(info) if info.batchable else 0
+            if cap >= self.batch_min:
+                same = [p for p in self.pending if p.graph == q.graph][: cap - 1]
                 if len(same) + 1 >= self.batch_min:
                     group += same
             k = len(group)
@@ -128,7 +145,7 @@ class Scheduler:
                 ws = self._acquire(q.graph, 1)
             if ws is None:
                 if not self.inflight and not any(self.pool.values()):
-                    need = self._cost(info, 1)
+                    need = self._ws_cost(info, 1) + self._out_cost(info, 1)
                     raise RuntimeError(f"query on {q.graph} needs {need} bytes; the budget is {self.budget}")
                 skipped.append(q)      # memory is short for this graph: let other queries through
                 continue
@@ -139,22 +156,23 @@ class Scheduler:
                 p.admitted = now
                 p.batched = k > 1
             kind = 256 if k > 1 else 1
+            out = self._out_cost(info, k)
             try:
                 handle = self.ex.launch(ws, q.graph, [p.source for p in group])
             except Exception as exc:  # a failed launch answers its queries with the error
-                self._fail(group, ws, kind, None, exc)
+                self._fail(group, ws, kind, None, exc, out)
                 continue
-            self.inflight.append((handle, ws, q.graph, kind, group))
+            self.inflight.append((handle, ws, q.graph, kind, group, out))
             self.stats["batches" if k > 1 else "singles"] += 1
         while skipped:
             self.pending.appendleft(skipped.pop())
 
-    def _fail(self, group, ws, kind, handle, exc):
+    def _fail(self, group, ws, kind, handle, exc, out_bytes):
         """Answer `group` with an error and drop its workspace, whose state is unknown."""
         if handle is not None and hasattr(self.ex, "abandon"):
             self.ex.abandon(handle)
         cost = self.pool_bytes.pop(id(ws), 0)
-        self.used -= cost
+        self.used -= cost + out_bytes
         try:
             self.ex.destroy(ws)
         except Exception:
@@ -170,15 +188,16 @@ class Scheduler:
     def _reap(self):
         still = []
         for item in self.inflight:
-            handle, ws, name, kind, group = item
+            handle, ws, name, kind, group, out = item
             try:
                 if not self.ex.ready(handle):
                     still.append(item)
                     continue
                 results = self.ex.collect(handle)
             except Exception as exc:
-                self._fail(group, ws, kind, handle, exc)
+                self._fail(group, ws, kind, handle, exc, out)
                 continue
+            self.used -= out
             self._release(name, kind, ws)
             if results is None:
                 # the batch overflowed: answer its queries one by one
@@ -190,7 +209,7 @@ class Scheduler:
             now = self.clock()
             for p, r in zip(group, results):
                 p.finished = now
-                p.result = r
+                p.result = r if self.keep_results else None
                 self.done.append(p)
         self.inflight = still
 

@@ -1,0 +1,59 @@
+"""Workspace sizing on the GPU: a workspace starts with private queues for the
+default options (levels of up to m / 12 edges keep queues, larger ones are
+dense) and grows them when a run's mode, options or roots need more.  One
+workspace then runs every such configuration in turn, each bit-exact."""
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+from tests.gpu_util import assert_same, run_single
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2209_08764_amd import (BFS_MODE_AUTO, BFS_MODE_DIRECTION, BFS_MODE_INSENSITIVE,  # noqa: E402
+                                  BFS_MODE_LEVEL, BFS_OPT_DENSE_EDGES, BFS_OPT_MODE, BFS_OPT_PUSH_EDGES,
+                                  BFS_OPT_SMALL_EDGES, Graph, Workspace, bfs_workspace_bytes)
+
+
+def test_default_workspace_is_sized_for_dense_levels():
+    g = gg.rmat(16, seed=51)
+    G = Graph(g.offsets, g.cols)
+    b = bfs_workspace_bytes(G.handle, 1)
+    # per-vertex arrays (32.5 B per vertex with the roots), statistics (2 MiB) and queues for a
+    # twelfth of the edges
+    assert b < 32.5 * g.n + g.m / 12 * 4 + 4 * 2048 * 4 + (3 << 20)
+    assert b > 32 * g.n + g.m / 12 * 4
+
+
+def test_one_workspace_grows_through_every_configuration():
+    g = gg.rmat(15, seed=52)
+    G = Graph(g.offsets, g.cols)
+    ws = Workspace(G)
+    srcs = [int(x) for x in gg.pick_sources(g, 2, seed=53)]
+    steps = [
+        {BFS_OPT_MODE: BFS_MODE_AUTO},
+        {BFS_OPT_DENSE_EDGES: 0},                               # every level keeps queues
+        {BFS_OPT_DENSE_EDGES: g.m // 12, BFS_OPT_PUSH_EDGES: g.m},  # every level pushes with queues
+        {BFS_OPT_PUSH_EDGES: g.m // 12, BFS_OPT_MODE: BFS_MODE_DIRECTION},
+        {BFS_OPT_MODE: BFS_MODE_LEVEL},
+        {BFS_OPT_MODE: BFS_MODE_INSENSITIVE, BFS_OPT_SMALL_EDGES: 1 << 30},
+        {BFS_OPT_MODE: BFS_MODE_AUTO, BFS_OPT_SMALL_EDGES: 4096},
+    ]
+    for opts in steps:
+        for k, v in opts.items():
+            ws.set(k, v)
+        for s in srcs:
+            lv, par = run_single(ws, s)
+            assert_same(lv, par, g, [s])
+    # every vertex a root: the roots' queues span the whole vertex set
+    roots = np.arange(g.n, dtype=np.int32)
+    lv, par = ws.run_multiroot(roots)
+    ws.sync()
+    assert np.all(lv.cpu().numpy() == 0) and np.array_equal(par.cpu().numpy(), roots)
+    some = roots[::97]
+    lv, par = ws.run_multiroot(some)
+    ws.sync()
+    want_l, want_p = oracle.bfs(g.offsets, g.cols, some)
+    assert np.array_equal(lv.cpu().numpy(), want_l) and np.array_equal(par.cpu().numpy(), want_p)

@@ -81,7 +81,8 @@ def test_every_answer_matches_the_oracle(graphs):
 
 def test_budget_is_never_exceeded_and_small_budgets_serialise(graphs):
     ex = FakeExecutor(graphs)
-    one = max(i.ws_bytes_batch + 256 * i.n for i in ex.info.values())
+    # room for the largest single-source workspace and its output, so not for every graph at once
+    one = max(i.ws_bytes_single + 4 * i.n for i in ex.info.values())
     sch = Scheduler(ex, budget_bytes=one + 10, max_inflight=4, clock=ex.clock)
     qs = poisson_queries(graphs, _nonisolated(graphs), rate=0, count=60, seed=2)   # all at once
     orig_acquire = sch._acquire
@@ -104,6 +105,27 @@ def test_batch_size_is_capped(graphs):
     sch.run(qs)
     assert max(k for _, k in ex.launched) == 16
     assert sum(k for _, k in ex.launched) == 100
+
+
+def test_batches_stay_within_their_share_of_the_budget(graphs):
+    ex = FakeExecutor({"a": graphs["a"]})
+    info = ex.info["a"]
+    budget = 2 * (info.ws_bytes_batch + 10 * info.n) + 1    # a batch may hold 10 sources
+    sch = Scheduler(ex, budget_bytes=budget, max_inflight=2, clock=ex.clock)
+    qs = poisson_queries({"a": 0}, _nonisolated(graphs), rate=0, count=100, seed=3)
+    sch.run(qs)
+    assert max(k for _, k in ex.launched) == 10
+    assert sum(k for _, k in ex.launched) == 100
+    assert all(q.result is not None for q in qs)
+
+
+def test_results_can_be_dropped_once_delivered(graphs):
+    ex = FakeExecutor(graphs)
+    sch = Scheduler(ex, budget_bytes=10 ** 9, max_inflight=3, clock=ex.clock, keep_results=False)
+    qs = poisson_queries(graphs, _nonisolated(graphs), rate=2e5, count=100, seed=5)
+    sch.run(qs)
+    assert all(q.result is None and q.error is None and q.finished >= q.arrival for q in qs)
+    assert sch.used == sum(sch.pool_bytes.values())   # no output is still charged
 
 
 def test_queries_keep_arrival_order_within_a_graph(graphs):
