@@ -207,6 +207,34 @@ bfs_status_t bfs_run_multiroot(bfs_workspace_t ws, const int32_t* roots, int32_t
 bfs_status_t bfs_run_batch(bfs_workspace_t ws, const int32_t* sources, int32_t k, uint8_t* level,
                            void* stream);
 
+/*
+ * Single-source search that allocates nothing, for callers that cannot
+ * allocate device memory: code under HIP graph capture, serving loops that
+ * must not allocate, harnesses that forbid it.  Same result as bfs_run
+ * (BFS_MODE_AUTO with default options) on graph g, with no workspace: the
+ * search's scratch is a fixed 64 MiB device array inside the library, one
+ * per device, held from the first bfs_init on that device until the
+ * process ends.
+ *   level[n], parent[n] (device, int32; parent may be NULL): as in bfs_run.
+ *   status (device, one int32, may be NULL): receives BFS_OK or BFS_EDEVICE
+ *   when the search ends (stream-ordered), the device status bfs_sync would
+ *   report for a workspace run.
+ * Asynchronous on stream: the call launches kernels only (no allocation,
+ * copy, memset or synchronisation), so it may be captured into a HIP graph.
+ * The scratch holds what the last call left; every call on one device uses
+ * the same array, so calls that overlap on a device (other streams, other
+ * threads, replays of captured calls) race and must be ordered by the
+ * caller.  The first call after a call on a different graph also clears the
+ * scratch's frontier and queue arrays.
+ * Errors: EINVAL (null graph or level), ERANGE (source), ENOMEM if the
+ * graph's search needs more scratch than the array holds (about
+ * 28.5 n + m / 3 bytes + 2 MiB: e.g. n = 2^20 with m up to about 100 M
+ * directed entries, or n = 2^21 with m up to about 15 M, fits;
+ * bfs_last_error gives both sizes), EHIP.
+ */
+bfs_status_t bfs_run_noalloc(bfs_graph_t g, int32_t source, int32_t* level, int32_t* parent,
+                             int32_t* status, void* stream);
+
 /* Wait for the workspace's last run; returns its device status. */
 bfs_status_t bfs_sync(bfs_workspace_t ws);
 

@@ -21,7 +21,7 @@ from ._lib import (BFS_DEVICE_PTRS, BFS_HOST_PTRS, BFS_HOT_FILTER, BFS_LEAN, BFS
 
 __all__ = [
     "bfs_init", "bfs_graph_free", "bfs_graph_info", "bfs_graph_aux_bytes", "bfs_workspace_bytes", "bfs_workspace_create",
-    "bfs_workspace_free", "bfs_workspace_set_option", "bfs_workspace_grid_capacity", "bfs_run", "bfs_run_multiroot", "bfs_run_batch",
+    "bfs_workspace_free", "bfs_workspace_set_option", "bfs_workspace_grid_capacity", "bfs_run", "bfs_run_multiroot", "bfs_run_batch", "bfs_run_noalloc",
     "bfs_sync", "bfs_last_stats", "bfs_last_level_stats", "bfs_last_level_times", "bfs_kernel_times", "bfs_status_str",
     "bfs_prim_compact",
     "bfs_prim_grain", "bfs_probe_rate_kernel", "bfs_autotune", "bfs_workspace_get_tuning", "Graph", "Workspace", "BFSError",
@@ -148,6 +148,15 @@ def bfs_run_batch(ws: int, sources, level, stream=None) -> None:
     pl = _dptr(level, torch.uint8, "level")
     _lib.check(_lib.load().bfs_run_batch(ws, sources.ctypes.data, sources.size, pl, _stream_ptr(stream)),
                "bfs_run_batch")
+
+
+def bfs_run_noalloc(g: int, source: int, level, parent=None, status=None, stream=None) -> None:
+    """Single-source search on graph handle g from the library's static scratch (allocates nothing)."""
+    torch = _torch()
+    pl = _dptr(level, torch.int32, "level")
+    pp = _dptr(parent, torch.int32, "parent") if parent is not None else None
+    ps = _dptr(status, torch.int32, "status") if status is not None else None
+    _lib.check(_lib.load().bfs_run_noalloc(g, int(source), pl, pp, ps, _stream_ptr(stream)), "bfs_run_noalloc")
 
 
 def bfs_sync(ws: int) -> None:

@@ -115,6 +115,8 @@ _SIGS = {
                                            ctypes.c_void_p, ctypes.c_void_p]),
     "bfs_run_batch": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                        ctypes.c_void_p]),
+    "bfs_run_noalloc": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_void_p]),
     "bfs_sync": (ctypes.c_int32, [ctypes.c_void_p]),
     "bfs_last_stats": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(bfs_stats_t)]),
     "bfs_last_level_stats": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,

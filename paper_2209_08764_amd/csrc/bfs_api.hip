@@ -7,12 +7,14 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <functional>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -93,6 +95,7 @@ struct bfs_graph_s {
     int32_t* hot_vid = nullptr; // vertex id of each hot number
     int32_t hot_count = 0;      // hot vertices
     int32_t hot_words = 0;      // words of a workspace's hot-bit arrays (0: no filter)
+    uint64_t uid = 0;           // distinct for every graph made resident in this process
 };
 
 struct bfs_workspace_s {
@@ -540,6 +543,86 @@ bfs_status_t setup_batch(bfs_workspace_s* ws) {
 
 }  // namespace
 
+// ---- scratch of the search that allocates nothing ---------------------------------------
+// One fixed array per device, held from the library's first graph on that
+// device until the process ends.  Host code never uses its name as an
+// address: the device address comes from hipGetSymbolAddress, once per device.
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+
+struct StaticScratch {
+    std::mutex mu;
+    unsigned char* ptr[kMaxDevices] = {};  // device address of `scratch` on each device
+    int grid_cap[kMaxDevices] = {};        // co-resident workgroups of the level loop there
+    uint64_t last_uid[kMaxDevices] = {};   // graph of the last search that used it (0: none)
+};
+StaticScratch g_static;
+
+// Looks up the device's copy of the scratch array (with that device current),
+// once per device.
+bfs_status_t static_scratch_setup(int device) {
+    if (device < 0 || device >= kMaxDevices) return fail(BFS_EHIP, "device %d beyond the library's %d", device, kMaxDevices);
+    std::lock_guard<std::mutex> lk(g_static.mu);
+    if (g_static.ptr[device]) return BFS_OK;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+        return fail(BFS_EHIP, "hipGetSymbolAddress(scratch) on device %d: %s", device, hipGetErrorString(e));
+    const int cap = persistent_grid_capacity(device);
+    if (cap <= 0) return fail(BFS_EHIP, "could not size the persistent grid on device %d", device);
+    g_static.grid_cap[device] = cap;
+    g_static.ptr[device] = static_cast<unsigned char*>(ptr);
+    return BFS_OK;
+}
+
+// Lays the arrays of one single-source search of g out from base, each
+// 256-byte aligned, in p's workspace fields (base == nullptr: sizes only).
+// Returns the bytes used.
+size_t carve_single(const bfs_graph_s* g, unsigned char* base, Params* p) {
+    const size_t n = (size_t)g->n;
+    const size_t T = (size_t)((std::max<int64_t>(g->m, g->n) + kGrain - 1) / kGrain + 2);
+    const size_t W = (n + 31) / 32;
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> void* {
+        void* q = base ? base + off : nullptr;
+        off += (std::max<size_t>(bytes, 1) + 255) & ~size_t(255);
+        return q;
+    };
+    p->bitmap = static_cast<uint32_t*>(take(W * 4));
+    p->fbits[0] = static_cast<uint32_t*>(take(W * 4));
+    p->fbits[1] = static_cast<uint32_t*>(take(W * 4));
+    p->snap = static_cast<uint32_t*>(take(W * 4));
+    p->hot[0] = p->hot[1] = nullptr;
+    if (g->colx) {
+        p->hot[0] = static_cast<uint32_t*>(take((size_t)g->hot_words * 4));
+        p->hot[1] = static_cast<uint32_t*>(take((size_t)g->hot_words * 4));
+    }
+    p->owner = static_cast<int32_t*>(take(n * 4));
+    for (int i = 0; i < 2; ++i) {
+        p->f_rs[i] = static_cast<int32_t*>(take((n + 2) * 4));
+        p->f_ex[i] = static_cast<int32_t*>(take((n + 2) * 4));
+        p->f_v[i] = static_cast<int32_t*>(take((n + 2) * 4));
+        p->tstart[i] = static_cast<int32_t*>(take(T * 4));
+        p->desc[i] = static_cast<unsigned long long*>(take(T * 8));
+    }
+    p->cand_cap = default_cand(g->m, g->n);
+    p->cand = static_cast<int32_t*>(take((size_t)p->cand_cap * 4));
+    p->cnt = static_cast<int32_t*>(take(2 * T * 4));
+    p->ctrl = static_cast<Ctrl*>(take(sizeof(Ctrl)));
+    p->xbar = static_cast<XBar*>(take(sizeof(XBar)));
+    p->stat_nl = static_cast<int32_t*>(take((size_t)kStatCap * 4));
+    p->stat_el = static_cast<int32_t*>(take((size_t)kStatCap * 4));
+    p->stat_ts = static_cast<uint64_t*>(take(3 * (size_t)kStatCap * 8));
+    p->max_tiles = (int32_t)T;
+    return off;
+}
+
+}  // namespace
+
 // Hot-vertex filter of a resident graph: number the (at most kHotBits) vertices
 // of highest degree, ties by id; each edge's entry of colx holds its target,
 // or -1 - the target's hot number, and hot_vid maps hot numbers back to ids.
@@ -645,9 +728,14 @@ bfs_status_t bfs_init(const int32_t* offsets, const int32_t* cols, int32_t n, in
         bfs_status_t st = validate_csr(po, pc, n, m);
         if (st) return st;
     }
+    int device = 0;
+    HIP_TRY(hipGetDevice(&device));
+    if (bfs_status_t st = static_scratch_setup(device)) return st;
     auto* g = new (std::nothrow) bfs_graph_s();
     if (!g) return fail(BFS_ENOMEM, "host allocation failed");
-    HIP_TRY(hipGetDevice(&g->device));
+    static std::atomic<uint64_t> next_uid{1};
+    g->uid = next_uid.fetch_add(1);
+    g->device = device;
     g->n = n;
     g->m = m;
     if (dev) {
@@ -959,6 +1047,60 @@ bfs_status_t bfs_run_multiroot(bfs_workspace_t ws, const int32_t* roots, int32_t
     if (!ws) return fail(BFS_EINVAL, "null workspace");
     if (!roots || k < 1 || k > ws->g->n) return fail(BFS_EINVAL, "need 1 <= k <= n roots");
     return run_common(ws, roots, k, 0, level, parent, stream);
+}
+
+bfs_status_t bfs_run_noalloc(bfs_graph_t g, int32_t source, int32_t* level, int32_t* parent, int32_t* status,
+                             void* stream) {
+    if (!g) return fail(BFS_EINVAL, "null graph");
+    if (!level) return fail(BFS_EINVAL, "null level array");
+    if (source < 0 || source >= g->n) return fail(BFS_ERANGE, "source %d outside [0, %d)", source, g->n);
+    Params p{};
+    const size_t need = carve_single(g, nullptr, &p);
+    if (need > kStaticScratchBytes)
+        return fail(BFS_ENOMEM, "the graph (n = %d, m = %lld) needs %zu bytes of search scratch; the static scratch "
+                    "holds %zu", g->n, (long long)g->m, need, kStaticScratchBytes);
+    if (g->device < 0 || g->device >= kMaxDevices) return fail(BFS_EHIP, "device %d beyond the library's", g->device);
+    unsigned char* base = nullptr;
+    int cap = 0;
+    bool scrub = false;
+    {
+        std::lock_guard<std::mutex> lk(g_static.mu);
+        base = g_static.ptr[g->device];
+        cap = g_static.grid_cap[g->device];
+        scrub = g_static.last_uid[g->device] != g->uid;
+        g_static.last_uid[g->device] = g->uid;
+    }
+    if (!base) return fail(BFS_EHIP, "no static scratch on device %d", g->device);
+    HIP_TRY(hipSetDevice(g->device));
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    carve_single(g, base, &p);
+    // the defaults of BFS_MODE_AUTO, as in a fresh workspace
+    p.offsets = g->offsets;
+    p.cols = g->cols;
+    p.colx = g->colx;
+    p.hot_vid = g->hot_vid;
+    p.hot_count = g->colx ? g->hot_count : 0;
+    p.hot_words = g->colx ? g->hot_words : 0;
+    p.n = g->n;
+    p.m = g->m;
+    p.level = level;
+    p.parent = parent;
+    p.roots = nullptr;
+    p.single_root = source;
+    p.nroots = 1;
+    p.small_edges = kDefaultSmallEdges;
+    p.push_edges = (int32_t)std::min<int64_t>(g->m / kLevelSplit, INT32_MAX);
+    p.dense_edges = (int32_t)std::min<int64_t>(std::max<int64_t>(g->m / kLevelSplit, 1), INT32_MAX);
+    p.bu_alpha = 14;
+    p.bu_beta = 24;
+    p.fb_pull = parent != nullptr;
+    p.spin_ticks = kSpinTicks;
+    const int grid = default_grid(cap, g->m);
+    if (scrub) HIP_TRY(launch_scrub(p, s));
+    HIP_TRY(launch_prep(p, 1, parent != nullptr, s));
+    HIP_TRY(launch_persistent(p, grid, s));
+    if (status) HIP_TRY(launch_status(p.ctrl, status, s));
+    return BFS_OK;
 }
 
 bfs_status_t bfs_sync(bfs_workspace_t ws) {

@@ -181,6 +181,8 @@ hipError_t launch_prep(const Params& p, int prep_shares, bool fill_parent, hipSt
 hipError_t launch_hot_gather(const int32_t* cols, int64_t m, const int32_t* hidx, int32_t* colx, int32_t n,
                              hipStream_t s);
 hipError_t launch_persistent(const Params& p, int grid, hipStream_t s);
+hipError_t launch_scrub(const Params& p, hipStream_t s);
+hipError_t launch_status(const Ctrl* c, int32_t* out, hipStream_t s);
 hipError_t launch_level_roots(const Params& p, int shares, hipStream_t s);
 hipError_t launch_level_compact(const Params& p, int l, int ntiles, int shares, hipStream_t s);
 hipError_t launch_level_expand(const Params& p, int l, int ntiles, int shares, hipStream_t s);

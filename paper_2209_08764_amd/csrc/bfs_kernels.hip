@@ -1301,6 +1301,33 @@ __global__ void __launch_bounds__(kBlock) k_prep(Params p, int prep_shares, int 
     }
 }
 
+// Gives the frontier, start-point, queue and descriptor arrays of a search's
+// scratch defined contents (zeros; owner = -1 for "no slot"), as a freshly
+// created workspace has them, so that nothing left by an earlier search of
+// another graph in the same memory can hold an out-of-range index.
+__global__ void __launch_bounds__(kBlock) k_scrub(Params p) {
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t nv = (int64_t)p.n + 2;
+    for (int64_t i = tid; i < nv; i += stride) {
+#pragma unroll
+        for (int k = 0; k < 2; ++k) p.f_v[k][i] = p.f_rs[k][i] = p.f_ex[k][i] = 0;
+    }
+    for (int64_t i = tid; i < p.n; i += stride) p.owner[i] = -1;
+    for (int64_t t = tid; t < p.max_tiles; t += stride) {
+        p.tstart[0][t] = p.tstart[1][t] = 0;
+        p.desc[0][t] = p.desc[1][t] = 0ull;
+        p.cnt[t] = p.cnt[p.max_tiles + t] = 0;
+    }
+    for (int64_t i = tid; i < p.cand_cap; i += stride) p.cand[i] = 0;
+}
+
+// Device status of the search that ran before it on the stream: BFS_OK, or
+// BFS_EDEVICE if a wait of the level loop timed out or found an inconsistency.
+__global__ void k_status(const Ctrl* c, int32_t* out) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) out[0] = c->error == 0 ? 0 : BFS_EDEVICE_CODE;
+}
+
 // Roots become the private queues of level -1: root i sits in slot i, and
 // share b of the roots' P_r shares owns slots [tb * kGrain, te * kGrain).
 __device__ void roots_range(const Params& p, int P, int64_t first, int64_t stride) {
@@ -1680,6 +1707,17 @@ hipError_t launch_hot_gather(const int32_t* cols, int64_t m, const int32_t* hidx
 
 hipError_t launch_prep(const Params& p, int prep_shares, bool fill_parent, hipStream_t s) {
     hipLaunchKernelGGL(k_prep, dim3(fill_grid(p.n)), dim3(kBlock), 0, s, p, prep_shares, fill_parent ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_scrub(const Params& p, hipStream_t s) {
+    const int64_t items = p.cand_cap > (int64_t)p.n + 2 ? p.cand_cap : (int64_t)p.n + 2;
+    hipLaunchKernelGGL(k_scrub, dim3(fill_grid(items)), dim3(kBlock), 0, s, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_status(const Ctrl* c, int32_t* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_status, dim3(1), dim3(64), 0, s, c, out);
     return hipGetLastError();
 }
 
