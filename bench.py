@@ -274,6 +274,27 @@ def traffic_from(paths, workload: str = "rmat24", kernel: str = "k_persistent<fa
     return out
 
 
+def profile_c4(args):
+    """The batched workload alone, for counter runs: R-MAT scale 22, 256 sources, the tuned
+    launch shape from the package's tuning cache, `--steps` batches."""
+    import torch
+
+    from graphgen import workloads as W
+    from paper_2209_08764_amd import Graph, Workspace, _lib
+    _lib.load()
+    g, srcs = W.c4_rmat22()
+    G = Graph(g.offsets, g.cols)
+    ws = Workspace(G, max_sources=256)
+    tune = ws.autotune(srcs, batch=True, cache=TUNE_CACHE)
+    out = torch.empty(g.n * 256, dtype=torch.uint8, device="cuda")
+    for _ in range(args.steps):
+        ws.run_batch(srcs, out)
+        ws.sync()
+    print(json.dumps({"profile_c4": "rmat22 x 256 sources", "batches": args.steps,
+                      "tuned": {k: tune.get(k) for k in ("batch_grain", "batch_tile", "batch_pull", "batch_levels",
+                                                         "cached")}}), flush=True)
+
+
 def calib_copy(args):
     """A plain device copy of known size: the reference for scaling rocprofv3's HBM counters."""
     import torch
@@ -286,9 +307,10 @@ def calib_copy(args):
     print(json.dumps({"calib_copy_bytes": nbytes, "launches": 4}), flush=True)
 
 
-def level_record(ws, small_edges: int = 4096, small_n: int = 4096):
-    """Per-level (n_l, e_l, expand us, compact us, single-workgroup?) of the workspace's last
-    run, from the level statistics and the device timestamps."""
+def level_record(ws, small_edges: int = 16384, small_n: int = 4096):
+    """Per-level (n_l, e_l, expand us, compact us, group level?) of the workspace's last run,
+    from the level statistics and the device timestamps (a group level's compact us is its
+    barrier)."""
     n_l, e_l = ws.level_stats()
     ex_us, co_us = ws.level_times()
     k = min(len(n_l), len(ex_us))
@@ -313,7 +335,7 @@ def bench_c1(torch, W, Graph, Workspace):
     return {"workload": "rmat16 (scale 16, EF 16), 1 source", "us_per_search": round(t * 1e3, 1),
             "kernel_us": round(float(np.median(kms)) * 1e3, 1), "gteps": round(mc_half / (t * 1e-3) / 1e9, 3),
             "levels": st["levels"], "small_levels": st["small_levels"], "grid": st["grid"],
-            "per_level_nl_el_expand_us_compact_us_single_wg": per_level}
+            "per_level_nl_el_expand_us_compact_us_group": per_level}
 
 
 def bench_c2(torch, W, Graph, Workspace):
@@ -353,9 +375,10 @@ def bench_c2(torch, W, Graph, Workspace):
             "split_search_ms_per_search": round(t_search, 2),
             "small_levels": st["small_levels"], "gteps": round(st["edges"] / 2 / (t * 1e-3) / 1e9, 3),
             "closed_form_levels_ok": closed_l, "closed_form_parents_ok": closed_p,
-            "us_per_level_single_workgroup": us(one), "levels_single_workgroup": len(one),
+            "us_per_level_group": us(one), "levels_group": len(one),
             "us_per_level_grid": us(grid_lv), "levels_grid": len(grid_lv),
-            "per_level_sample_nl_el_expand_us_compact_us_single_wg": rec[:4] + rec[2040:2052] + rec[4090:4100]}
+            "per_level_sample_nl_el_expand_us_compact_us_group": rec[:4] + rec[500:504] + rec[1020:1028] +
+            rec[2040:2052] + rec[4090:4100]}
 
 
 class EnergyMeter:
@@ -697,6 +720,34 @@ def probe_ceiling(torch, n: int, count: int = 1 << 28, reps: int = 5) -> dict:
     return out
 
 
+def run_only(args):
+    """Some of the other workloads alone, for quick measurements (no headline line)."""
+    import torch
+
+    from graphgen import workloads as W
+    from paper_2209_08764_amd import Graph, Workspace, _lib
+    _lib.load()
+    torch.cuda.set_device(0)
+    out = {}
+    for name in [x.strip() for x in args.only.split(",") if x.strip()]:
+        log(name)
+        if name == "c1":
+            out[name] = bench_c1(torch, W, Graph, Workspace)
+        elif name == "c2":
+            out[name] = bench_c2(torch, W, Graph, Workspace)
+        elif name == "c4":
+            out[name] = bench_c4(torch, W, Graph, Workspace)
+        elif name == "multiroot":
+            out[name] = bench_multiroot(torch, Graph, Workspace)
+        elif name == "c5":
+            out[name] = bench_c5(torch, W, args.serve_queries)
+        else:
+            sys.exit(f"unknown workload {name}")
+        log(f"  {dict((k, v) for k, v in out[name].items() if not k.startswith('per_level'))}")
+        torch.cuda.empty_cache()
+    print(json.dumps({"only": out}), flush=True)
+
+
 def run(args):
     import torch
 
@@ -889,9 +940,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=1, help="untimed passes before them")
     ap.add_argument("--scale", type=int, default=24)
     ap.add_argument("--quick", action="store_true", help="headline workload only")
+    ap.add_argument("--only", default="", help="comma-separated extras to run without the headline "
+                                               "(c1, c2, c4, multiroot, c5); prints them and exits")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--serve-queries", type=int, default=10000, help="queries in the serving run (0 skips it)")
     ap.add_argument("--calib-copy", action="store_true", help="only run a 1 GiB device copy (counter calibration)")
+    ap.add_argument("--profile-c4", action="store_true", help="only run --steps batches of the batched workload "
+                                                              "(counter runs)")
     ap.add_argument("--rocpd-summary", nargs="+", metavar="DB", help="summarise rocprofv3 result databases and exit")
     ap.add_argument("--rocpd-dispatches", nargs=4, metavar=("KERNEL", "SKIP", "TAKE", "DB"),
                     help="duration statistics of dispatches [SKIP, SKIP+TAKE) of KERNEL in start order, and exit")
@@ -915,6 +970,12 @@ def main():
         sys.exit(2)
     if args.calib_copy:
         calib_copy(args)
+        return
+    if args.profile_c4:
+        profile_c4(args)
+        return
+    if args.only:
+        run_only(args)
         return
     run(args)
 

@@ -66,7 +66,9 @@ typedef struct bfs_workspace_s* bfs_workspace_t;  /* scratch for one in-flight r
 
 /* Options */
 #define BFS_OPT_MODE        1  /* one of BFS_MODE_* (default AUTO) */
-#define BFS_OPT_SMALL_EDGES 2  /* largest e_l run by a single workgroup (0 disables; default 4096) */
+#define BFS_OPT_SMALL_EDGES 2  /* levels with at most this many edges (capped at 16384) and at most
+                                  4096 frontier vertices run on a small group of workgroups with one
+                                  barrier among them per level (0 disables; default 16384) */
 #define BFS_OPT_GRID        3  /* workgroups of the level loop (0 = one per 16384 edges, a multiple
                                   of 8, at least 64 and at most what the GPU holds at once) */
 #define BFS_OPT_PROFILE     4  /* 1: time the main kernel with HIP events (bfs_stats_t.kernel_ms) */
@@ -89,6 +91,7 @@ typedef struct bfs_workspace_s* bfs_workspace_t;  /* scratch for one in-flight r
                                   has none to find) and scans at least this many edges records its
                                   new vertices as bits instead of private-queue entries and
                                   linearises them in vertex order (0 = never; default m / 12) */
+#define BFS_OPT_GROUP      14  /* workgroups of that group (1..1024, at most the grid; 0 = default 16) */
 #define BFS_OPT_SPLIT      13  /* how each level's equal shares find their start points
                                   (Analysis, Find-StartExpPoint): 0 = every frontier vertex
                                   writes itself as the start of the shares beginning inside its

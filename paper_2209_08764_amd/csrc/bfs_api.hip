@@ -61,18 +61,17 @@ hipError_t dalloc(T** p, size_t count) {
 // queues needs its edges rounded up to whole sub-tiles.  Dense levels keep
 // none, so with the default thresholds only levels up to m / 12 edges do;
 // per-level launches, direction optimisation (whose bottom-up levels queue up
-// to n vertices) and dense levels switched off may queue any level.  Single-
-// workgroup levels put what exceeds their LDS (at most small_edges entries)
-// there too, and the roots sit there as the queues of level -1.
+// to n vertices) and dense levels switched off may queue any level.  The
+// roots sit there as the queues of level -1.
 int64_t cand_need(int64_t m, int64_t n, int32_t mode, int64_t push_edges, int64_t dense_edges, int64_t small_edges,
                   int64_t nroots, bool parents) {
     if (mode == BFS_MODE_PLAIN) return kGrain;  // the plain comparator keeps no queues
     int64_t e;
     if (mode == BFS_MODE_LEVEL || mode == BFS_MODE_DIRECTION || dense_edges <= 0) e = std::max(m, n);
     else e = std::min(std::max(parents ? push_edges : 0, dense_edges - 1), m);
-    const int64_t e_small = small_edges > 0 ? std::min(small_edges, m) : 0;
+    (void)small_edges;  // group levels append to their own arrays
     auto tiles = [](int64_t x) { return (x + kGrain - 1) / kGrain; };
-    return std::max<int64_t>({tiles(e), tiles(e_small), tiles(nroots), 1}) * kGrain;
+    return std::max<int64_t>({tiles(e), tiles(nroots), 1}) * kGrain;
 }
 
 // Private-queue entries a workspace starts with: enough for BFS_MODE_AUTO with
@@ -125,6 +124,9 @@ struct bfs_workspace_s {
     uint64_t* stat_ts = nullptr;
     int32_t* roots = nullptr;
     int32_t* plain_fv[2] = {nullptr, nullptr};
+    int32_t* gv[2] = {nullptr, nullptr};   // group levels' frontier entries
+    int32_t* grs[2] = {nullptr, nullptr};
+    int32_t* gd[2] = {nullptr, nullptr};
     // batched buffers
     unsigned long long* b_fr = nullptr;
     unsigned long long* b_nx = nullptr;
@@ -158,6 +160,7 @@ struct bfs_workspace_s {
     bool profiled = false;
     int32_t mode = BFS_MODE_AUTO;
     int32_t small_edges = kDefaultSmallEdges;
+    int32_t group = kGroupMax;
     int32_t bu_alpha = 14;
     int32_t bu_beta = 24;
     int32_t push_edges = -1;  // -1: m / kLevelSplit of the workspace's graph
@@ -271,6 +274,12 @@ Params make_params(bfs_workspace_s* ws, int32_t* level, int32_t* parent) {
     p.stat_el = ws->stat_el;
     p.stat_ts = ws->stat_ts;
     p.small_edges = ws->small_edges;
+    p.group = ws->group;
+    for (int i = 0; i < 2; ++i) {
+        p.gv[i] = ws->gv[i];
+        p.grs[i] = ws->grs[i];
+        p.gd[i] = ws->gd[i];
+    }
     // Pushing costs one atomic per scanned edge into an unsettled vertex; pulling
     // costs about one row read per new vertex but long ones when the frontier is
     // small next to what it discovers.  Levels below an eighth of the graph push.
@@ -611,6 +620,11 @@ size_t carve_single(const bfs_graph_s* g, unsigned char* base, Params* p) {
     }
     p->cand_cap = default_cand(g->m, g->n);
     p->cand = static_cast<int32_t*>(take((size_t)p->cand_cap * 4));
+    for (int i = 0; i < 2; ++i) {
+        p->gv[i] = static_cast<int32_t*>(take((size_t)kGroupCap * 4));
+        p->grs[i] = static_cast<int32_t*>(take((size_t)kGroupCap * 4));
+        p->gd[i] = static_cast<int32_t*>(take((size_t)kGroupCap * 4));
+    }
     p->cnt = static_cast<int32_t*>(take(2 * T * 4));
     p->ctrl = static_cast<Ctrl*>(take(sizeof(Ctrl)));
     p->xbar = static_cast<XBar*>(take(sizeof(XBar)));
@@ -817,6 +831,7 @@ size_t bfs_workspace_bytes(bfs_graph_t g, int32_t max_sources) {
     b += (size_t)default_cand(g->m, g->n) * 4;  // private queues (default options; see bfs.h)
     b += 2 * T * 4;                    // counts, bottom-up edge totals
     b += 2 * T * 8;                    // descriptors
+    b += 6 * (size_t)kGroupCap * 4;    // group levels' frontier entries x2
     b += sizeof(Ctrl) + sizeof(XBar) + 2 * (size_t)kStatCap * 4 + 3 * (size_t)kStatCap * 8 + n * 4;  // ctrl, barrier, stats, roots
     if (max_sources > 1) {
         const size_t BT = (size_t)batch_max_tiles(g), D = (size_t)batch_desc_cap(g);
@@ -839,7 +854,8 @@ bfs_status_t bfs_workspace_free(bfs_workspace_t ws) {
                     ws->stat_el, ws->stat_ts, ws->roots, ws->plain_fv[0], ws->plain_fv[1], ws->b_fr, ws->b_nx, ws->b_vis,
                     ws->b_act[0], ws->b_act[1], ws->b_act_ex[0], ws->b_act_ex[1], ws->b_tstart[0],
                     ws->b_tstart[1], ws->b_desc[0], ws->b_desc[1], ws->b_act_bits, ws->b_sources,
-                    ws->b_act_rs[0], ws->b_act_rs[1], ws->b_nz_v, ws->b_nz_ts};
+                    ws->b_act_rs[0], ws->b_act_rs[1], ws->b_nz_v, ws->b_nz_ts, ws->gv[0], ws->gv[1], ws->grs[0],
+                    ws->grs[1], ws->gd[0], ws->gd[1]};
     if (ws->b_exec) (void)hipGraphExecDestroy(ws->b_exec);
     if (ws->b_graph) (void)hipGraphDestroy(ws->b_graph);
     if (ws->b_args) (void)hipFree(ws->b_args);
@@ -889,6 +905,9 @@ bfs_status_t bfs_workspace_create(bfs_graph_t g, int32_t max_sources, bfs_worksp
         A(dalloc(&ws->f_v[i], n + 2));
         A(dalloc(&ws->tstart[i], (size_t)T));
         A(dalloc(&ws->desc[i], (size_t)T));
+        A(dalloc(&ws->gv[i], (size_t)kGroupCap));
+        A(dalloc(&ws->grs[i], (size_t)kGroupCap));
+        A(dalloc(&ws->gd[i], (size_t)kGroupCap));
     }
     ws->cand_cap = default_cand(g->m, g->n);
     A(dalloc(&ws->cand, (size_t)ws->cand_cap));
@@ -1025,6 +1044,10 @@ bfs_status_t bfs_workspace_set_option(bfs_workspace_t ws, int32_t option, int64_
             ws->b_uv = (int32_t)(value / kBlock);
             return setup_batch(ws);
         }
+        case BFS_OPT_GROUP:
+            if (value < 0 || value > 1024) return fail(BFS_EINVAL, "group must be in [0, 1024]");
+            ws->group = value == 0 ? kGroupMax : (int32_t)value;
+            return BFS_OK;
         case BFS_OPT_SPLIT:
             if (value != 0 && value != 1) return fail(BFS_EINVAL, "split must be 0 (scatter) or 1 (binary search)");
             ws->split_search = (int32_t)value;
@@ -1089,6 +1112,7 @@ bfs_status_t bfs_run_noalloc(bfs_graph_t g, int32_t source, int32_t* level, int3
     p.single_root = source;
     p.nroots = 1;
     p.small_edges = kDefaultSmallEdges;
+    p.group = kGroupMax;
     p.push_edges = (int32_t)std::min<int64_t>(g->m / kLevelSplit, INT32_MAX);
     p.dense_edges = (int32_t)std::min<int64_t>(std::max<int64_t>(g->m / kLevelSplit, 1), INT32_MAX);
     p.bu_alpha = 14;

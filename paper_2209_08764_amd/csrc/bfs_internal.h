@@ -14,10 +14,11 @@ constexpr int kGrain = kBlock * kVT;      // edges per sub-tile (the share granu
 constexpr int kSlice = kGrain + 1;        // frontier entries a sub-tile can touch
 constexpr int kPre = (kSlice + kBlock - 1) / kBlock;  // slice entries each thread prefetches
 constexpr int kVTS = 8;                   // edges per thread per round, single-workgroup levels
-constexpr int kSmallN = 4096;             // frontier capacity of single-workgroup levels (LDS)
-constexpr int kSmallC = 4096;             // candidates held in LDS in single-workgroup levels
+constexpr int kSmallN = 4096;             // frontier capacity of group levels (staged in LDS)
+constexpr int kGroupCap = 16384;          // most edges a group level scans (and entries it appends)
+constexpr int kGroupMax = 16;             // default workgroups of the group
 constexpr int kStatCap = 1 << 16;         // per-level statistics kept
-constexpr int kDefaultSmallEdges = kBlock * kVTS;  // one round of the lone workgroup
+constexpr int kDefaultSmallEdges = kGroupCap;
 constexpr int kPullScan = 32;             // neighbours a lane tests before a row goes to the whole workgroup
 
 // Hot-vertex filter: the kHotBits vertices of highest degree carry a number
@@ -30,7 +31,7 @@ constexpr int kLiteShares = 32;            // fewer active workgroups: no hot or
 constexpr int kHotTarget = -2;             // a gathered edge whose target is hot, id not yet looked up
 
 // LDS words used by the level loop (the two layouts share one allocation).
-constexpr int kLdsSmall = 3 * kSmallN + 1 + kSmallC;   // frontier (v, rs, ex) + claimed vertices
+constexpr int kLdsSmall = 3 * kSmallN + 1;             // group levels' frontier (v, rs, ex)
 constexpr int kLdsLarge = 2 * 2 * kSlice + kHotWords;  // double-buffered sub-tile slices (ex, rs - ex), hot bits
 constexpr int kLdsWords = (kLdsSmall > kLdsLarge ? kLdsSmall : kLdsLarge) + 2 * kWaves + 8;
 
@@ -38,22 +39,24 @@ constexpr int kLdsWords = (kLdsSmall > kLdsLarge ? kLdsSmall : kLdsLarge) + 2 * 
 // Every field is accessed with agent-scope atomics (coherent across XCDs).
 struct Ctrl {
     unsigned long long bar;   // grid-barrier arrivals, monotone within a launch
+    unsigned long long g_cnt[3];  // group levels: (vertices reached << 32) | frontier entries
+                                  // appended, for level l + 1 in slot (l + 1) % 3
     unsigned int unused[2];
     int nl[2];                // next frontier size (vertices of degree >= 1), per parity
     int el[2];                // next frontier edge total, per parity
     int kept[2];              // vertices reaching that level (any degree), per parity
     int levels;               // frontiers processed (max level + 1)
     int error;                // 0, or a BFS_E* code set on the device
-    int small_levels;         // levels run by a single workgroup
+    int small_levels;         // levels run by the group of workgroups
     int resume;               // level at which the full grid resumes
-    int heartbeat;            // bumped by a lone workgroup so waiting ones keep waiting
+    int heartbeat;            // bumped by the group so waiting workgroups keep waiting
     int plain_next;           // PLAIN mode: next-frontier counter
     int b_nact[2];            // batched: active vertices of a level, per parity
     int b_eact[2];            // batched: their edge total, per parity
     int blevel;               // batched: level whose expansion runs next
     int bdone;                // batched: no active vertex left (or overflow)
     int batch_overflow;       // batched: a level reached 255
-    int r_nl, r_el, r_kept;   // frontier handed back by a lone workgroup (level = resume)
+    int r_nl, r_el, r_kept;   // frontier handed back by the group (level = resume)
     int nz_count;             // batched: vertices of degree >= 1
     int bu_levels;            // levels run bottom-up
     int pad[4];
@@ -107,8 +110,13 @@ struct Params {
     const int32_t* roots;     // device array, or null for a single root
     int32_t single_root;
     int32_t nroots;
+    // group levels: next-frontier entries (vertex, row start, degree), kGroupCap per parity
+    int32_t* gv[2];
+    int32_t* grs[2];
+    int32_t* gd[2];
+    int32_t group;            // workgroups of the group (at most the grid)
     // tuning
-    int32_t small_edges;      // 0 disables single-workgroup levels
+    int32_t small_edges;      // 0 disables group levels
     int32_t push_edges;       // levels with at most this many edges push parents, larger ones pull
     // direction optimisation (persistent loop only)
     uint32_t* fbits[2];       // frontier bits: exactly the level-l vertices of degree >= 1 in fbits[l & 1]

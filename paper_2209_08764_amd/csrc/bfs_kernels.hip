@@ -1050,56 +1050,198 @@ __device__ __forceinline__ void bottom_up_share(const Params& p, int l, int b, i
     lds_barrier();
 }
 
-// ---- a stretch of small levels run by one workgroup out of LDS -----------------------------
-// Entered at level l with the frontier in global memory (parity l & 1).
-// Leaves with the frontier of level ctrl->resume in global memory and its
-// size in the resume slot.  Alone on the GPU, the workgroup claims each new
-// vertex with a returning atomic OR on the visited bitmap, so every vertex
-// is queued exactly once and no de-duplication pass is needed; the
-// frontier (ids, row starts, degree sums) stays in LDS and is written to
-// global memory only when the stretch ends.  Parents are pushed: every edge
-// into a vertex reached in this level offers its source (atomic minimum).
-// An edge that loses the claim tells such a vertex from an older one by its
-// level, which is l + 1 or still unwritten (-1) only for this level's.
-__device__ void small_levels(const Params& p, int l, int n_l, int e_l, int* lds) {
+// ---- a stretch of small levels run by a group of workgroups ---------------------------------
+// While a level has at most kSmallN frontier vertices and at most min(small_edges, kGroupCap)
+// edges, the first G workgroups of the grid (the group) run it and the rest of the grid waits at
+// the next grid barrier: the paper's P_l = min(P, W_l) with P_l small and one barrier of the
+// group per level.  Each frontier sits in global memory as (vertex, row start, degree) entries;
+// every member stages all of them in LDS, takes their exclusive degree sums (the Parallel-Prefix-
+// Sum) and scans its equal share [r e / G, (r + 1) e / G) of the level's edges (Find-StartExpPoint
+// by the wave-row owner search).  Each target is claimed by a compare-and-swap of its level from
+// -1 to l + 1, while its row offsets are read alongside: exactly one edge claims each new vertex,
+// so no de-duplication pass is needed, and the claim appends the vertex with its row start and
+// degree to the next frontier, in a slot range reserved by one atomic per member.  A claim that
+// finds l + 1 is another edge into a vertex of this level: with parents, every such edge pushes
+// its source (atomic minimum).  New vertices get their visited bits (which only the levels on the
+// whole grid test) when the next level starts.  Entered at level l with the frontier in the
+// parity-l arrays (f_v, f_rs, f_ex); leaves with the frontier of level ctrl->resume there.
+__device__ __forceinline__ void group_handover(const Params& p, int l, int n, int e_l, int kept, int done, int G,
+                                               int rank, bool staged, int* lds) {
+    const int par = l & 1;
+    int* s_v = lds;
+    int* s_rs = lds + kSmallN;
+    int* s_ex = lds + 2 * kSmallN;
+    int* s_wave = lds_wave(lds);
+    const int a = (int)(((int64_t)rank * n) / G), b = (int)(((int64_t)(rank + 1) * n) / G);
+    if (staged) {
+        for (int i = a + (int)threadIdx.x; i < b; i += kBlock) {
+            const int ex = s_ex[i];
+            p.f_v[par][i] = s_v[i];
+            p.f_rs[par][i] = s_rs[i];
+            p.f_ex[par][i] = ex;
+            scatter_starts(p, p.tstart[par], i, ex, s_ex[i + 1] - ex);
+        }
+    } else {
+        // too many entries for LDS: every member scans all degrees in chunks for its own range
+        const int32_t* gd = p.gd[par];
+        int run = 0;
+        for (int c0 = 0; c0 < n; c0 += kBlock * kVTS) {
+            int d[kVTS], ts = 0;
+            const int i0 = c0 + (int)threadIdx.x * kVTS;
+#pragma unroll
+            for (int k = 0; k < kVTS; ++k) {
+                d[k] = i0 + k < n ? gd[i0 + k] : 0;
+                ts += d[k];
+            }
+            int S;
+            int e = run + block_excl_scan(ts, s_wave, &S);
+#pragma unroll
+            for (int k = 0; k < kVTS; ++k) {
+                const int i = i0 + k;
+                if (i >= a && i < b) {
+                    p.f_v[par][i] = p.gv[par][i];
+                    p.f_rs[par][i] = p.grs[par][i];
+                    p.f_ex[par][i] = e;
+                    scatter_starts(p, p.tstart[par], i, e, d[k]);
+                }
+                e += d[k];
+            }
+            run += S;
+        }
+    }
+    if (rank == 0 && threadIdx.x == 0) {
+        if (n <= p.n) p.f_ex[par][n] = e_l;
+        else flag_internal(p.ctrl);
+        st_rel(&p.ctrl->r_nl, n);
+        st_rel(&p.ctrl->r_el, e_l);
+        st_rel(&p.ctrl->r_kept, kept);
+        st_rel(&p.ctrl->resume, l);
+        __hip_atomic_fetch_add(&p.ctrl->small_levels, done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+}
+
+__device__ void group_levels(const Params& p, int l, int n_l, int e_l, int kept, int G, int rank, XGroup& xg,
+                             int* lds) {
     int* s_v = lds;                        // frontier ids
     int* s_rs = lds + kSmallN;             // row starts
     int* s_ex = lds + 2 * kSmallN;         // exclusive degree sums (+ total)
-    int* s_cand = lds + 3 * kSmallN + 1;   // vertices claimed in the level (first kSmallC)
     int* s_wave = lds_wave(lds);
     int* s_wave2 = lds_wave2(lds);
-    int* s_misc = lds_misc(lds);           // [0] claim counter
-    {
-        const int par = l & 1;
-        for (int i = threadIdx.x; i < n_l; i += kBlock) {
-            s_v[i] = p.f_v[par][i];
-            s_rs[i] = p.f_rs[par][i];
-            s_ex[i] = p.f_ex[par][i];
-        }
-        if (threadIdx.x == 0) s_ex[n_l] = e_l;
-        __syncthreads();
-    }
-    int done_levels = 0;
+    int* s_misc = lds_misc(lds);
+    int* s_flag = lds + kLdsWords - 1;
+    const int cap = min(p.small_edges, kGroupCap);
+    bool first = true;
+    int done = 0;
     for (;;) {
-        const int np = (l + 1) & 1;
-        if (threadIdx.x == 0) {
-            if (l < kStatCap) p.stat_ts[3 * l] = now_ticks();
-            s_misc[0] = 0;
-        }
-        lds_barrier();
-        // expand level l: every frontier edge, kBlock * kVTS per round; a lane that flips a
-        // vertex's visited bit owns it
-        for (int base0 = 0; base0 < e_l; base0 += kBlock * kVTS) {
-            int v[kVTS], u[kVTS], gg[kVTS], own[kVTS];
+        const int par = l & 1, np = (l + 1) & 1;
+        int n;
+        // the append counter read two levels ago is written again next level
+        if (rank == 0 && threadIdx.x == 0) st_rel(&p.ctrl->g_cnt[(l + 2) % 3], 0ull);
+        if (first) {
+            // the level the grid handed over: entries with their exclusive sums in f_*[par]
+            n = n_l;
+            for (int i = threadIdx.x; i < n; i += kBlock) {
+                s_v[i] = p.f_v[par][i];
+                s_rs[i] = p.f_rs[par][i];
+                s_ex[i] = p.f_ex[par][i];
+            }
+            if (threadIdx.x == 0) s_ex[n] = e_l;
+            __syncthreads();
+        } else {
+            static_assert(kBlock * kVTS == kSmallN, "thread t stages entries [t kVTS, (t + 1) kVTS)");
+            // the count and every entry slot this member can stage are read together (slots
+            // past the count hold stale entries and are ignored), so staging takes one round trip
+            const int i0 = (int)threadIdx.x * kVTS;
+            int sv[kVTS], srs[kVTS], sd[kVTS];
+            const unsigned long long gc = ld_acq(&p.ctrl->g_cnt[l % 3]);
 #pragma unroll
-            for (int i = 0; i < kVTS; ++i) gg[i] = min(base0 + i * kBlock + (int)threadIdx.x, e_l - 1);
-            search_owners<kVTS>(s_ex, n_l, gg, own);
+            for (int k = 0; k < kVTS; ++k) {
+                sv[k] = p.gv[par][i0 + k];
+                srs[k] = p.grs[par][i0 + k];
+                sd[k] = p.gd[par][i0 + k];
+            }
+            n = (int)(gc & 0xffffffffull);
+            kept = (int)(gc >> 32);
+            const int a = (int)(((int64_t)rank * n) / G), b = (int)(((int64_t)(rank + 1) * n) / G);
+            if (n == 0 || n > kSmallN) {
+                // nothing left, or too many entries to stage: the grid takes over, with the
+                // entries' visited bits set (a share per member) and e_l from their degrees
+                int tot = 0;
+                for (int i = threadIdx.x; i < n; i += kBlock) {
+                    tot += p.gd[par][i];
+                    const int v = p.gv[par][i];
+                    if (i >= a && i < b && (unsigned)v < (unsigned)p.n)
+                        __hip_atomic_fetch_or(&p.bitmap[v >> 5], 1u << (v & 31), __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+                }
+                int S;
+                block_excl_scan(tot, s_wave, &S);
+                if (rank == 0 && threadIdx.x == 0 && l < kStatCap && kept > 0) {
+                    p.stat_nl[l] = kept;
+                    p.stat_el[l] = S;
+                    st_rel(&p.ctrl->levels, l + 1);
+                }
+                group_handover(p, l, n, S, kept, done, G, rank, false, lds);
+                return;
+            }
+            // stage the entries and scan their degrees; each member sets the visited bits of its
+            // share of them
+            int d[kVTS], ts = 0;
+#pragma unroll
+            for (int k = 0; k < kVTS; ++k) {
+                const int i = i0 + k;
+                d[k] = 0;
+                if (i < n) {
+                    s_v[i] = sv[k];
+                    s_rs[i] = srs[k];
+                    d[k] = sd[k];
+                    if (i >= a && i < b && (unsigned)sv[k] < (unsigned)p.n)
+                        __hip_atomic_fetch_or(&p.bitmap[sv[k] >> 5], 1u << (sv[k] & 31), __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+                }
+                ts += d[k];
+            }
+            int S;
+            int e = block_excl_scan(ts, s_wave, &S);
+#pragma unroll
+            for (int k = 0; k < kVTS; ++k) {
+                if (i0 + k < n) s_ex[i0 + k] = e;
+                e += d[k];
+            }
+            if (threadIdx.x == 0) s_ex[n] = S;
+            e_l = S;
+            __syncthreads();
+        }
+        if (rank == 0 && threadIdx.x == 0) {
+            if (l < kStatCap) {
+                p.stat_ts[3 * l] = now_ticks();
+                if (kept > 0) {
+                    p.stat_nl[l] = kept;
+                    p.stat_el[l] = e_l;
+                }
+            }
+            if (kept > 0) st_rel(&p.ctrl->levels, l + 1);
+            st_rel(&p.ctrl->heartbeat, l);
+        }
+        if (!first && e_l > cap) {
+            group_handover(p, l, n, e_l, kept, done, G, rank, true, lds);
+            return;
+        }
+        // expand this member's share of the level's edges
+        const int g0 = (int)(((int64_t)rank * e_l) / G), g1 = (int)(((int64_t)(rank + 1) * e_l) / G);
+        for (int base0 = g0; base0 < g1; base0 += kBlock * kVTS) {
+            int own[kVTS];
+            static_assert(kVTS == 2 * kVT, "two calls of the row search cover a round");
+            owners_of_rows(s_ex, n, base0, own);
+            owners_of_rows(s_ex, n, base0 + kVT * kBlock, own + kVT);
+            int v[kVTS], u[kVTS];
 #pragma unroll
             for (int i = 0; i < kVTS; ++i) {
                 const int g = base0 + i * kBlock + threadIdx.x;
                 v[i] = -1;
                 u[i] = -1;
-                if (g < e_l) {
+                if (g < g1) {
                     const int lo = own[i];
                     u[i] = s_v[lo];
                     const int idx = s_rs[lo] + (g - s_ex[lo]);
@@ -1111,136 +1253,82 @@ __device__ void small_levels(const Params& p, int l, int n_l, int e_l, int* lds)
                     }
                 }
             }
-            bool fresh[kVTS];
+            // claims, with the claimed rows' offsets read while they are in flight (a visited-
+            // bitmap test in front of them cost a round trip more than the claims it saved)
+            int old[kVTS], rs[kVTS], re[kVTS];
 #pragma unroll
             for (int i = 0; i < kVTS; ++i) {
-                fresh[i] = false;
+                old[i] = -2;
+                rs[i] = re[i] = 0;
                 if (v[i] >= 0) {
-                    const uint32_t bit = 1u << (v[i] & 31);
-                    const uint32_t old = __hip_atomic_fetch_or(&p.bitmap[v[i] >> 5], bit, __ATOMIC_RELAXED,
-                                                               __HIP_MEMORY_SCOPE_AGENT);
-                    fresh[i] = !(old & bit);
+                    int expect = -1;
+                    __hip_atomic_compare_exchange_strong(&p.level[v[i]], &expect, l + 1, __ATOMIC_RELAXED,
+                                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    old[i] = expect;
+                    rs[i] = p.offsets[v[i]];
+                    re[i] = p.offsets[v[i] + 1];
                 }
             }
             if (p.parent) {
 #pragma unroll
-                for (int i = 0; i < kVTS; ++i) {
-                    if (v[i] >= 0 && !fresh[i]) {
-                        const int lv = p.level[v[i]];
-                        if (lv != -1 && lv != l + 1) v[i] = -1;  // reached before this level
-                    }
-                }
-#pragma unroll
                 for (int i = 0; i < kVTS; ++i)
-                    if (v[i] >= 0) parent_push(p, v[i], u[i]);
+                    if (old[i] == -1 || old[i] == l + 1) parent_push(p, v[i], u[i]);
             }
+            // slots of the new vertices with an edge in the next frontier; one atomic per member
+            int slot[kVTS];
+            int wt = 0, wr = 0;
 #pragma unroll
             for (int i = 0; i < kVTS; ++i) {
-                const uint64_t bb = ballot(fresh[i]);
-                int base = 0;
-                if (lane_id() == 0 && bb) base = atomicAdd(&s_misc[0], __popcll(bb));
-                base = __shfl(base, 0);
-                if (fresh[i]) {
-                    p.level[v[i]] = l + 1;
-                    const int s = base + mbcnt(bb);
-                    if (s < kSmallC) s_cand[s] = v[i];
-                    else if ((int64_t)s < p.cand_cap) p.cand[s] = v[i];
-                    else flag_internal(p.ctrl);
-                }
+                const bool fresh = old[i] == -1;
+                const uint64_t bb = ballot(fresh && re[i] > rs[i]);
+                slot[i] = wt + mbcnt(bb);
+                wt += __popcll(bb);
+                wr += __popcll(ballot(fresh));
             }
-        }
-        __syncthreads();  // full: the level's stores are complete before the next level pulls parents
-        const int ncand = s_misc[0];
-        if (threadIdx.x == 0 && l < kStatCap) p.stat_ts[3 * l + 1] = now_ticks();
-        // the next frontier from the claimed vertices (degree >= 1), parents pulled
-        int outc = 0, outs = 0;
-        bool hand = false;
-        for (int base0 = 0; base0 < ncand; base0 += kBlock * kVTS) {
-            int v[kVTS], rs[kVTS], d[kVTS];
-            int tc = 0, ts = 0;
-#pragma unroll
-            for (int i = 0; i < kVTS; ++i) {
-                const int idx = base0 + i * kBlock + threadIdx.x;
-                v[i] = -1;
-                rs[i] = d[i] = 0;
-                if (idx < ncand) {
-                    const int vv = idx < kSmallC ? s_cand[idx] : p.cand[idx];
-                    if ((unsigned)vv >= (unsigned)p.n) {
-                        flag_internal(p.ctrl);
-                    } else {
-                        v[i] = vv;
-                        rs[i] = p.offsets[vv];
-                        d[i] = p.offsets[vv + 1] - rs[i];
-                        if (d[i] > 0) { ++tc; ts += d[i]; }
-                    }
-                }
+            if (lane_id() == 0) {
+                s_wave[wave_id()] = wt;
+                s_wave2[wave_id()] = wr;
             }
-            int C, S;
-            const int c_ex = block_excl_scan(tc, s_wave, &C);
-            const int s_ex2 = block_excl_scan(ts, s_wave2, &S);
-            // a one-chunk level knows its totals here; larger ones always hand over
-            const int tot_c = outc + C, tot_s = outs + S;
-            if (base0 == 0)
-                hand = ncand > kBlock * kVTS || tot_c == 0 || tot_c > kSmallN || tot_s > p.small_edges;
-            int pos = outc + c_ex, e = outs + s_ex2;
-#pragma unroll
-            for (int i = 0; i < kVTS; ++i) {
-                if (v[i] >= 0 && d[i] > 0) {
-                    if (pos < kSmallN) {
-                        s_v[pos] = v[i];
-                        s_rs[pos] = rs[i];
-                        s_ex[pos] = e;
-                    }
-                    if (hand) {
-                        if ((unsigned)pos < (unsigned)p.n) {
-                            p.f_v[np][pos] = v[i];
-                            p.f_rs[np][pos] = rs[i];
-                            p.f_ex[np][pos] = e;
-                            scatter_starts(p, p.tstart[np], pos, e, d[i]);
-                        } else {
-                            flag_internal(p.ctrl);
-                        }
-                    }
-                    ++pos;
-                    e += d[i];
-                }
-            }
-            outc = tot_c;
-            outs = tot_s;
             lds_barrier();
-        }
-        if (ncand == 0) hand = true;
-        if (threadIdx.x == 0 && l < kStatCap) p.stat_ts[3 * l + 2] = now_ticks();
-        ++l;
-        ++done_levels;
-        if (threadIdx.x == 0) {
-            if (ncand > 0 && l < kStatCap) {
-                p.stat_nl[l] = ncand;
-                p.stat_el[l] = outs;
-            }
-            if (ncand > 0) st_rel(&p.ctrl->levels, l + 1);
-            st_rel(&p.ctrl->heartbeat, l);
-        }
-        n_l = outc;
-        e_l = outs;
-        if (hand) {
-            // hand the frontier back through the resume slot: the parity slots
-            // may still be read by workgroups that have not left the level the
-            // stretch started at
             if (threadIdx.x == 0) {
-                if (outc <= p.n) p.f_ex[np][outc] = outs;
-                st_rel(&p.ctrl->r_nl, n_l);
-                st_rel(&p.ctrl->r_el, e_l);
-                st_rel(&p.ctrl->r_kept, ncand);
-                st_rel(&p.ctrl->resume, l);
-                __hip_atomic_fetch_add(&p.ctrl->small_levels, done_levels, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
+                int tt = 0, tr = 0;
+#pragma unroll
+                for (int q = 0; q < kWaves; ++q) {
+                    tt += s_wave[q];
+                    tr += s_wave2[q];
+                }
+                const unsigned long long add = ((unsigned long long)tr << 32) | (unsigned)tt;
+                const unsigned long long was =
+                    add ? __hip_atomic_fetch_add(&p.ctrl->g_cnt[(l + 1) % 3], add, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT)
+                        : 0ull;
+                s_misc[0] = (int)(was & 0xffffffffull);
             }
-            __syncthreads();
-            return;
+            lds_barrier();
+            int wbase = s_misc[0];
+            for (int q = 0; q < wave_id(); ++q) wbase += s_wave[q];
+#pragma unroll
+            for (int i = 0; i < kVTS; ++i) {
+                if (old[i] == -1 && re[i] > rs[i]) {
+                    const int s = wbase + slot[i];
+                    if (s < kGroupCap) {
+                        p.gv[np][s] = v[i];
+                        p.grs[np][s] = rs[i];
+                        p.gd[np][s] = re[i] - rs[i];
+                    } else {
+                        flag_internal(p.ctrl);
+                    }
+                }
+            }
+            lds_barrier();  // s_wave and s_misc are reused by the next round
         }
-        if (threadIdx.x == 0) s_ex[n_l] = e_l;
-        lds_barrier();
+        if (rank == 0 && threadIdx.x == 0 && l < kStatCap) p.stat_ts[3 * l + 1] = now_ticks();
+        // the group's barrier: every member's claims, entries and counts are visible after it
+        if (!sub_barrier(p.ctrl, p.xbar, xg.xcd, 2ull * l + 2, G, true, p.spin_ticks, s_flag)) return;
+        if (rank == 0 && threadIdx.x == 0 && l < kStatCap) p.stat_ts[3 * l + 2] = now_ticks();
+        ++l;
+        ++done;
+        first = false;
     }
 }
 
@@ -1298,6 +1386,7 @@ __global__ void __launch_bounds__(kBlock) k_prep(Params p, int prep_shares, int 
         c->plain_next = 0;
         c->r_nl = c->r_el = c->r_kept = 0;
         c->bu_levels = 0;
+        c->g_cnt[0] = c->g_cnt[1] = c->g_cnt[2] = 0ull;
     }
 }
 
@@ -1444,16 +1533,21 @@ k_persistent(Params p) {
         }
         if (n_l == 0) break;
         reached_edges += e_l;
-        if (p.small_edges > 0 && n_l <= kSmallN && e_l <= p.small_edges) {
-            if (blockIdx.x == 0) {
-                [[clang::always_inline]] small_levels(p, l, n_l, e_l, lds);
+        if (p.small_edges > 0 && n_l <= kSmallN && e_l <= min(p.small_edges, kGroupCap)) {
+            const int Gs = max(1, min(p.group, G));
+            if ((int)blockIdx.x < Gs) {
+                [[clang::always_inline]] group_levels(p, l, n_l, e_l, kept, Gs, blockIdx.x, xg, lds);
             }
             if (!xcd_barrier(c, p.xbar, xg, p.spin_ticks, s_flag)) return;
+            // every member has read the append counters: the next stretch, at least one grid
+            // level away, starts from zero
+            if (blockIdx.x == 0 && threadIdx.x == 0)
+                for (int k = 0; k < 3; ++k) st_rel(&c->g_cnt[k], 0ull);
             l = ld_acq(&c->resume);
             n_l = ld_acq(&c->r_nl);
             e_l = ld_acq(&c->r_el);
             kept = ld_acq(&c->r_kept);
-            fbits_ok = false;  // levels run out of LDS keep no frontier or hot bits
+            fbits_ok = false;  // group levels keep no frontier or hot bits
             hot_ok = false;
             bottom_up = false;
             continue;
@@ -1547,7 +1641,7 @@ k_persistent(Params p) {
             int n_next, e_next;
             block_excl_scan(tn, lds_wave(lds), &n_next);
             block_excl_scan(te_sum, lds_wave2(lds), &e_next);
-            const bool next_small = p.small_edges > 0 && n_next <= kSmallN && e_next <= p.small_edges;
+            const bool next_small = p.small_edges > 0 && n_next <= kSmallN && e_next <= min(p.small_edges, kGroupCap);
             if (n_next > 0 && !next_small && (int64_t)n_next * p.bu_beta >= p.n) {
                 if (!xcd_barrier(c, p.xbar, xg, p.spin_ticks, s_flag)) return;
                 if (rec) p.stat_ts[3 * l + 2] = now_ticks();

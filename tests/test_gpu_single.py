@@ -238,9 +238,10 @@ def test_errors(rmat14):
 
 
 def test_small_stretches_handing_over_to_the_full_grid():
-    # Low-degree sources on a larger R-MAT: the lone workgroup runs one or two
-    # small levels and hands a large frontier back to the whole grid (the
-    # hand-over must not disturb workgroups still reading the entry level).
+    # Low-degree sources on a larger R-MAT: the group runs one or two small
+    # levels and hands a large frontier back to the whole grid (the hand-over
+    # must not disturb workgroups still reading the entry level), from LDS or,
+    # past 4096 entries, from its global entry arrays.
     g = gg.rmat(18, seed=41)
     G = Graph(g.offsets, g.cols)
     deg = g.degrees()
@@ -291,3 +292,21 @@ def test_default_grid_follows_graph_size():
     run_single(ws, int(gg.pick_sources(big, 1, seed=3)[0]))
     want = max(64, (big.m // 16384 + 7) // 8 * 8)
     assert 64 < want < 512 and ws.stats()["grid"] == want  # below what two workgroups per CU allow
+
+
+@pytest.mark.parametrize("group", [1, 2, 5, 16, 64])
+def test_group_sizes_do_not_change_results(group):
+    # small levels run on `group` workgroups (capped at the grid): high-diameter graphs whose
+    # levels stay small throughout, and R-MAT levels that enter and leave the group
+    cases = [(gg.grid(64, 64), [0, 2080]), (gg.grid(1, 3000), [0, 1500]), (gg.grid(200, 90), [0, 9000]),
+             (gg.powerlaw_forest(1 << 13, seed=3), None), (gg.rmat(14, seed=21), None)]
+    for g, srcs in cases:
+        G = Graph(g.offsets, g.cols)
+        for small in (16384, 1 << 30, 3000):
+            ws = Workspace(G, group=group, small_edges=small)
+            for s in (srcs if srcs is not None else gg.pick_sources(g, 2, seed=group)):
+                lv, par = run_single(ws, s)
+                assert_same(lv, par, g, [s])
+                assert ws.stats()["status"] == 0
+            lv, _ = run_single(ws, int(srcs[0]) if srcs is not None else 0, want_parent=False)
+            assert np.array_equal(lv, oracle.bfs(g.offsets, g.cols, int(srcs[0]) if srcs is not None else 0)[0])
