@@ -213,12 +213,17 @@ __device__ inline bool xcd_barrier(Ctrl* c, XBar* xb, const XGroup& g, uint64_t 
 // launch.  Grid barriers count every workgroup of the launch, so a lite level
 // uses this one for both of its barriers, and no workgroup arrives at a grid
 // barrier meanwhile.
+//
+// release = false: the workgroup wrote nothing since the last barrier that others read with plain
+// loads (only atomics, which are coherent on every XCD), so it skips the write-back of its XCD's
+// L2 and only waits until its own atomics have been performed before arriving.
 __device__ inline bool sub_barrier(Ctrl* c, XBar* xb, int xcd, unsigned long long gen, int P, bool participate,
-                                   uint64_t spin_ticks, int* s_flag) {
+                                   uint64_t spin_ticks, int* s_flag, bool release = true) {
+    if (!release) __builtin_amdgcn_s_waitcnt(0);  // this wave's atomics have been performed
     __syncthreads();
     if (threadIdx.x == 0) {
         if (participate) {
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            if (release) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             const unsigned long long a =
                 __hip_atomic_fetch_add(&xb->pcnt[0], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (a == (unsigned long long)P - 1) {

@@ -16,7 +16,7 @@ constexpr int kPre = (kSlice + kBlock - 1) / kBlock;  // slice entries each thre
 constexpr int kVTS = 8;                   // edges per thread per round, single-workgroup levels
 constexpr int kSmallN = 4096;             // frontier capacity of group levels (staged in LDS)
 constexpr int kGroupCap = 16384;          // most edges a group level scans (and entries it appends)
-constexpr int kGroupMax = 16;             // default workgroups of the group
+constexpr int kGroupMax = 32;             // default workgroups of the group
 constexpr int kStatCap = 1 << 16;         // per-level statistics kept
 constexpr int kDefaultSmallEdges = kGroupCap;
 constexpr int kPullScan = 32;             // neighbours a lane tests before a row goes to the whole workgroup
@@ -39,8 +39,13 @@ constexpr int kLdsWords = (kLdsSmall > kLdsLarge ? kLdsSmall : kLdsLarge) + 2 * 
 // Every field is accessed with agent-scope atomics (coherent across XCDs).
 struct Ctrl {
     unsigned long long bar;   // grid-barrier arrivals, monotone within a launch
-    unsigned long long g_cnt[3];  // group levels: (vertices reached << 32) | frontier entries
-                                  // appended, for level l + 1 in slot (l + 1) % 3
+    // group levels, the frontier of level l in slot l % 3: (edges << 32) | entries,
+    // (vertices reached << 32) | entries spilled past a member's LDS, the largest member's
+    // edges, and the next free position of the global entry arrays
+    unsigned long long g_ne[3];
+    unsigned long long g_rs[3];
+    unsigned long long g_mx[3];
+    unsigned long long g_pos[3];
     unsigned int unused[2];
     int nl[2];                // next frontier size (vertices of degree >= 1), per parity
     int el[2];                // next frontier edge total, per parity

@@ -1053,61 +1053,70 @@ __device__ __forceinline__ void bottom_up_share(const Params& p, int l, int b, i
 // ---- a stretch of small levels run by a group of workgroups ---------------------------------
 // While a level has at most kSmallN frontier vertices and at most min(small_edges, kGroupCap)
 // edges, the first G workgroups of the grid (the group) run it and the rest of the grid waits at
-// the next grid barrier: the paper's P_l = min(P, W_l) with P_l small and one barrier of the
-// group per level.  Each frontier sits in global memory as (vertex, row start, degree) entries;
-// every member stages all of them in LDS, takes their exclusive degree sums (the Parallel-Prefix-
-// Sum) and scans its equal share [r e / G, (r + 1) e / G) of the level's edges (Find-StartExpPoint
-// by the wave-row owner search).  Each target is claimed by a compare-and-swap of its level from
-// -1 to l + 1, while its row offsets are read alongside: exactly one edge claims each new vertex,
-// so no de-duplication pass is needed, and the claim appends the vertex with its row start and
-// degree to the next frontier, in a slot range reserved by one atomic per member.  A claim that
-// finds l + 1 is another edge into a vertex of this level: with parents, every such edge pushes
-// its source (atomic minimum).  New vertices get their visited bits (which only the levels on the
-// whole grid test) when the next level starts.  Entered at level l with the frontier in the
-// parity-l arrays (f_v, f_rs, f_ex); leaves with the frontier of level ctrl->resume there.
+// the next grid barrier: the paper's P_l = min(P, W_l) with P_l small, and one barrier of the
+// group per level.  Each target is claimed by a compare-and-swap of its level from -1 to l + 1,
+// with its row offsets read alongside: exactly one edge claims each new vertex, so no
+// de-duplication pass is needed.  A claim that finds l + 1 is another edge into a vertex of this
+// level: with parents, every such edge pushes its source (atomic minimum).
+//
+// The claiming member keeps each new vertex (id, row start, degree) in its own LDS, and the
+// level's totals (entries, edges, vertices reached, the largest member's edges, LDS overflow) add
+// up in counters read after the barrier.  When the members' shares of the next level's edges are
+// even, each member expands the vertices it claimed (no exchange at all); otherwise every member
+// writes its claims to global entry arrays, the group meets once more, and every member stages
+// all entries in LDS, takes their exclusive degree sums (the Parallel-Prefix-Sum) and scans an
+// equal share [r e / G, (r + 1) e / G) of the edges (Find-StartExpPoint by the wave-row owner
+// search).  Entered at level l with the frontier in the parity-l arrays (f_v, f_rs, f_ex); leaves
+// with the frontier of level ctrl->resume there.  New vertices get their visited bits (which only
+// the levels on the whole grid test) from the member expanding them.
+constexpr int kLocalCap = 2048;   // claims a member keeps in LDS per level
+constexpr int kLdsNext = 3 * kSmallN + 1;   // LDS offset of the members' claims (v | rs | d)
+static_assert(kLdsNext + 3 * kLocalCap + 2 * kWaves + 8 <= kLdsWords, "claims fit in LDS");
+
+// Barrier generations (monotone within a launch): a lite level l uses 4l + 5 and 4l + 6; a
+// group level l its exchange 4l + 4 and its end 4l + 7.
+__device__ __forceinline__ unsigned long long gen_lite(int l, int k) { return 4ull * l + 4 + k; }
+__device__ __forceinline__ unsigned long long gen_exchange(int l) { return 4ull * l + 4; }
+__device__ __forceinline__ unsigned long long gen_group_end(int l) { return 4ull * l + 7; }
+
 __device__ __forceinline__ void group_handover(const Params& p, int l, int n, int e_l, int kept, int done, int G,
-                                               int rank, bool staged, int* lds) {
+                                               int rank, int* lds) {
+    // every entry of level l is in the global entry arrays: every member scans all degrees in
+    // chunks and writes the frontier arrays, and the visited bits, of its own range (the levels
+    // on the whole grid need the bits of every vertex reached so far)
     const int par = l & 1;
-    int* s_v = lds;
-    int* s_rs = lds + kSmallN;
-    int* s_ex = lds + 2 * kSmallN;
     int* s_wave = lds_wave(lds);
     const int a = (int)(((int64_t)rank * n) / G), b = (int)(((int64_t)(rank + 1) * n) / G);
-    if (staged) {
-        for (int i = a + (int)threadIdx.x; i < b; i += kBlock) {
-            const int ex = s_ex[i];
-            p.f_v[par][i] = s_v[i];
-            p.f_rs[par][i] = s_rs[i];
-            p.f_ex[par][i] = ex;
-            scatter_starts(p, p.tstart[par], i, ex, s_ex[i + 1] - ex);
-        }
-    } else {
-        // too many entries for LDS: every member scans all degrees in chunks for its own range
-        const int32_t* gd = p.gd[par];
-        int run = 0;
-        for (int c0 = 0; c0 < n; c0 += kBlock * kVTS) {
-            int d[kVTS], ts = 0;
-            const int i0 = c0 + (int)threadIdx.x * kVTS;
+    const int32_t* gd = p.gd[par];
+    int run = 0;
+    for (int c0 = 0; c0 < n; c0 += kBlock * kVTS) {
+        int d[kVTS], ts = 0;
+        const int i0 = c0 + (int)threadIdx.x * kVTS;
 #pragma unroll
-            for (int k = 0; k < kVTS; ++k) {
-                d[k] = i0 + k < n ? gd[i0 + k] : 0;
-                ts += d[k];
-            }
-            int S;
-            int e = run + block_excl_scan(ts, s_wave, &S);
-#pragma unroll
-            for (int k = 0; k < kVTS; ++k) {
-                const int i = i0 + k;
-                if (i >= a && i < b) {
-                    p.f_v[par][i] = p.gv[par][i];
-                    p.f_rs[par][i] = p.grs[par][i];
-                    p.f_ex[par][i] = e;
-                    scatter_starts(p, p.tstart[par], i, e, d[k]);
-                }
-                e += d[k];
-            }
-            run += S;
+        for (int k = 0; k < kVTS; ++k) {
+            d[k] = i0 + k < n ? gd[i0 + k] : 0;
+            ts += d[k];
         }
+        int S;
+        int e = run + block_excl_scan(ts, s_wave, &S);
+#pragma unroll
+        for (int k = 0; k < kVTS; ++k) {
+            const int i = i0 + k;
+            if (i >= a && i < b) {
+                const int v = p.gv[par][i];
+                p.f_v[par][i] = v;
+                p.f_rs[par][i] = p.grs[par][i];
+                p.f_ex[par][i] = e;
+                scatter_starts(p, p.tstart[par], i, e, d[k]);
+                if ((unsigned)v < (unsigned)p.n)
+                    __hip_atomic_fetch_or(&p.bitmap[v >> 5], 1u << (v & 31), __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
+                else
+                    flag_internal(p.ctrl);
+            }
+            e += d[k];
+        }
+        run += S;
     }
     if (rank == 0 && threadIdx.x == 0) {
         if (n <= p.n) p.f_ex[par][n] = e_l;
@@ -1123,24 +1132,35 @@ __device__ __forceinline__ void group_handover(const Params& p, int l, int n, in
 
 __device__ void group_levels(const Params& p, int l, int n_l, int e_l, int kept, int G, int rank, XGroup& xg,
                              int* lds) {
-    int* s_v = lds;                        // frontier ids
+    int* s_v = lds;                        // frontier being expanded: ids
     int* s_rs = lds + kSmallN;             // row starts
     int* s_ex = lds + 2 * kSmallN;         // exclusive degree sums (+ total)
+    int* s_nv = lds + kLdsNext;            // this member's claims: ids
+    int* s_nrs = s_nv + kLocalCap;         // row starts
+    int* s_nd = s_nrs + kLocalCap;         // degrees
     int* s_wave = lds_wave(lds);
     int* s_wave2 = lds_wave2(lds);
-    int* s_misc = lds_misc(lds);
+    int* s_misc = lds_misc(lds);           // [0] claims this level, [1] global base, [2..4] totals
     int* s_flag = lds + kLdsWords - 1;
+    Ctrl* c = p.ctrl;
     const int cap = min(p.small_edges, kGroupCap);
     bool first = true;
     int done = 0;
+    int mine = 0;                          // claims of the previous level kept in LDS
     for (;;) {
         const int par = l & 1, np = (l + 1) & 1;
-        int n;
-        // the append counter read two levels ago is written again next level
-        if (rank == 0 && threadIdx.x == 0) st_rel(&p.ctrl->g_cnt[(l + 2) % 3], 0ull);
+        // the counters of the frontier two levels back are used again by the next level
+        if (rank == 0 && threadIdx.x == 0) {
+            const int k = (l + 2) % 3;
+            st_rel(&c->g_ne[k], 0ull);
+            st_rel(&c->g_rs[k], 0ull);
+            st_rel(&c->g_mx[k], 0ull);
+            st_rel(&c->g_pos[k], 0ull);
+        }
+        int n, nloc, g0, g1;
         if (first) {
             // the level the grid handed over: entries with their exclusive sums in f_*[par]
-            n = n_l;
+            n = nloc = n_l;
             for (int i = threadIdx.x; i < n; i += kBlock) {
                 s_v[i] = p.f_v[par][i];
                 s_rs[i] = p.f_rs[par][i];
@@ -1148,93 +1168,128 @@ __device__ void group_levels(const Params& p, int l, int n_l, int e_l, int kept,
             }
             if (threadIdx.x == 0) s_ex[n] = e_l;
             __syncthreads();
+            g0 = (int)(((int64_t)rank * e_l) / G);
+            g1 = (int)(((int64_t)(rank + 1) * e_l) / G);
         } else {
-            static_assert(kBlock * kVTS == kSmallN, "thread t stages entries [t kVTS, (t + 1) kVTS)");
-            // the count and every entry slot this member can stage are read together (slots
-            // past the count hold stale entries and are ignored), so staging takes one round trip
-            const int i0 = (int)threadIdx.x * kVTS;
-            int sv[kVTS], srs[kVTS], sd[kVTS];
-            const unsigned long long gc = ld_acq(&p.ctrl->g_cnt[l % 3]);
-#pragma unroll
-            for (int k = 0; k < kVTS; ++k) {
-                sv[k] = p.gv[par][i0 + k];
-                srs[k] = p.grs[par][i0 + k];
-                sd[k] = p.gd[par][i0 + k];
-            }
-            n = (int)(gc & 0xffffffffull);
-            kept = (int)(gc >> 32);
-            const int a = (int)(((int64_t)rank * n) / G), b = (int)(((int64_t)(rank + 1) * n) / G);
-            if (n == 0 || n > kSmallN) {
-                // nothing left, or too many entries to stage: the grid takes over, with the
-                // entries' visited bits set (a share per member) and e_l from their degrees
-                int tot = 0;
-                for (int i = threadIdx.x; i < n; i += kBlock) {
-                    tot += p.gd[par][i];
-                    const int v = p.gv[par][i];
-                    if (i >= a && i < b && (unsigned)v < (unsigned)p.n)
-                        __hip_atomic_fetch_or(&p.bitmap[v >> 5], 1u << (v & 31), __ATOMIC_RELAXED,
-                                              __HIP_MEMORY_SCOPE_AGENT);
-                }
-                int S;
-                block_excl_scan(tot, s_wave, &S);
-                if (rank == 0 && threadIdx.x == 0 && l < kStatCap && kept > 0) {
-                    p.stat_nl[l] = kept;
-                    p.stat_el[l] = S;
-                    st_rel(&p.ctrl->levels, l + 1);
-                }
-                group_handover(p, l, n, S, kept, done, G, rank, false, lds);
-                return;
-            }
-            // stage the entries and scan their degrees; each member sets the visited bits of its
-            // share of them
-            int d[kVTS], ts = 0;
-#pragma unroll
-            for (int k = 0; k < kVTS; ++k) {
-                const int i = i0 + k;
-                d[k] = 0;
-                if (i < n) {
-                    s_v[i] = sv[k];
-                    s_rs[i] = srs[k];
-                    d[k] = sd[k];
-                    if (i >= a && i < b && (unsigned)sv[k] < (unsigned)p.n)
-                        __hip_atomic_fetch_or(&p.bitmap[sv[k] >> 5], 1u << (sv[k] & 31), __ATOMIC_RELAXED,
-                                              __HIP_MEMORY_SCOPE_AGENT);
-                }
-                ts += d[k];
-            }
-            int S;
-            int e = block_excl_scan(ts, s_wave, &S);
-#pragma unroll
-            for (int k = 0; k < kVTS; ++k) {
-                if (i0 + k < n) s_ex[i0 + k] = e;
-                e += d[k];
-            }
-            if (threadIdx.x == 0) s_ex[n] = S;
-            e_l = S;
-            __syncthreads();
-        }
-        if (rank == 0 && threadIdx.x == 0) {
-            if (l < kStatCap) {
-                p.stat_ts[3 * l] = now_ticks();
-                if (kept > 0) {
+            const unsigned long long ne = ld_acq(&c->g_ne[l % 3]);
+            const unsigned long long rs = ld_acq(&c->g_rs[l % 3]);
+            const unsigned long long mx = ld_acq(&c->g_mx[l % 3]);
+            n = (int)(ne & 0xffffffffull);
+            e_l = (int)(ne >> 32);
+            kept = (int)(rs >> 32);
+            const int spilled = (int)(rs & 0xffffffffull);
+            if (rank == 0 && threadIdx.x == 0) {
+                if (l < kStatCap && kept > 0) {
                     p.stat_nl[l] = kept;
                     p.stat_el[l] = e_l;
                 }
+                if (kept > 0) st_rel(&c->levels, l + 1);
+                st_rel(&c->heartbeat, l);
             }
-            if (kept > 0) st_rel(&p.ctrl->levels, l + 1);
-            st_rel(&p.ctrl->heartbeat, l);
+            const bool leave = n == 0 || n > kSmallN || e_l > cap;
+            // the members' own claims are expanded where they are when no member holds more than
+            // half again the average share of the level's edges (or a few hundred edges at all)
+            const int64_t avg = (int64_t)e_l / G;
+            const bool local = !leave && spilled == 0 && (int64_t)mx <= avg + avg / 2 + 128;
+            if (!local && n > 0) {
+                // every member's claims go to the global entry arrays, behind those that spilled
+                if (threadIdx.x == 0)
+                    s_misc[1] = mine ? (int)__hip_atomic_fetch_add(&c->g_pos[l % 3], (unsigned long long)mine,
+                                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                     : 0;
+                __syncthreads();
+                const int base = s_misc[1];
+                for (int i = threadIdx.x; i < mine; i += kBlock) {
+                    if (base + i < kGroupCap) {
+                        p.gv[par][base + i] = s_nv[i];
+                        p.grs[par][base + i] = s_nrs[i];
+                        p.gd[par][base + i] = s_nd[i];
+                    } else {
+                        flag_internal(c);
+                    }
+                }
+                if (!sub_barrier(c, p.xbar, xg.xcd, gen_exchange(l), G, true, p.spin_ticks, s_flag)) return;
+            }
+            if (leave) {
+                group_handover(p, l, n, e_l, kept, done, G, rank, lds);
+                return;
+            }
+            if (local) {
+                // this member's own claims become its frontier
+                nloc = mine;
+                int d[kVTS / 2], ts = 0;
+                const int i0 = (int)threadIdx.x * (kVTS / 2);
+                static_assert(kBlock * (kVTS / 2) == kLocalCap, "thread t moves claims [4t, 4t + 4)");
+#pragma unroll
+                for (int k = 0; k < kVTS / 2; ++k) {
+                    const int i = i0 + k;
+                    d[k] = 0;
+                    if (i < nloc) {
+                        s_v[i] = s_nv[i];
+                        s_rs[i] = s_nrs[i];
+                        d[k] = s_nd[i];
+                    }
+                    ts += d[k];
+                }
+                int S;
+                int e = block_excl_scan(ts, s_wave, &S);
+#pragma unroll
+                for (int k = 0; k < kVTS / 2; ++k) {
+                    if (i0 + k < nloc) s_ex[i0 + k] = e;
+                    e += d[k];
+                }
+                if (threadIdx.x == 0) s_ex[nloc] = S;
+                g0 = 0;
+                g1 = S;
+            } else {
+                // all entries, from the global arrays
+                nloc = n;
+                static_assert(kBlock * kVTS == kSmallN, "thread t stages entries [t kVTS, (t + 1) kVTS)");
+                int d[kVTS], ts = 0;
+                const int i0 = (int)threadIdx.x * kVTS;
+#pragma unroll
+                for (int k = 0; k < kVTS; ++k) {
+                    const int i = i0 + k;
+                    d[k] = 0;
+                    if (i < n) {
+                        s_v[i] = p.gv[par][i];
+                        s_rs[i] = p.grs[par][i];
+                        d[k] = p.gd[par][i];
+                    }
+                    ts += d[k];
+                }
+                int S;
+                int e = block_excl_scan(ts, s_wave, &S);
+#pragma unroll
+                for (int k = 0; k < kVTS; ++k) {
+                    if (i0 + k < n) s_ex[i0 + k] = e;
+                    e += d[k];
+                }
+                if (threadIdx.x == 0) s_ex[n] = S;
+                g0 = (int)(((int64_t)rank * S) / G);
+                g1 = (int)(((int64_t)(rank + 1) * S) / G);
+            }
+            __syncthreads();
+            // visited bits of the entries this member expands (local) or of its share (global)
+            const int a = local ? 0 : (int)(((int64_t)rank * n) / G);
+            const int b = local ? nloc : (int)(((int64_t)(rank + 1) * n) / G);
+            for (int i = a + (int)threadIdx.x; i < b; i += kBlock) {
+                const int v = s_v[i];
+                if ((unsigned)v < (unsigned)p.n)
+                    __hip_atomic_fetch_or(&p.bitmap[v >> 5], 1u << (v & 31), __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
+            }
         }
-        if (!first && e_l > cap) {
-            group_handover(p, l, n, e_l, kept, done, G, rank, true, lds);
-            return;
-        }
-        // expand this member's share of the level's edges
-        const int g0 = (int)(((int64_t)rank * e_l) / G), g1 = (int)(((int64_t)(rank + 1) * e_l) / G);
+        if (rank == 0 && threadIdx.x == 0 && l < kStatCap) p.stat_ts[3 * l] = now_ticks();
+        if (threadIdx.x == 0) s_misc[0] = 0;
+        lds_barrier();
+        // expand this member's edges [g0, g1) of its staged entries [0, nloc)
+        int my_e = 0, my_r = 0;
         for (int base0 = g0; base0 < g1; base0 += kBlock * kVTS) {
             int own[kVTS];
             static_assert(kVTS == 2 * kVT, "two calls of the row search cover a round");
-            owners_of_rows(s_ex, n, base0, own);
-            owners_of_rows(s_ex, n, base0 + kVT * kBlock, own + kVT);
+            owners_of_rows(s_ex, nloc, base0, own);
+            owners_of_rows(s_ex, nloc, base0 + kVT * kBlock, own + kVT);
             int v[kVTS], u[kVTS];
 #pragma unroll
             for (int i = 0; i < kVTS; ++i) {
@@ -1249,7 +1304,7 @@ __device__ void group_levels(const Params& p, int l, int n_l, int e_l, int kept,
                         v[i] = p.cols[idx];
                         if ((unsigned)v[i] >= (unsigned)p.n) v[i] = -1;
                     } else {
-                        flag_internal(p.ctrl);
+                        flag_internal(c);
                     }
                 }
             }
@@ -1274,57 +1329,85 @@ __device__ void group_levels(const Params& p, int l, int n_l, int e_l, int kept,
                 for (int i = 0; i < kVTS; ++i)
                     if (old[i] == -1 || old[i] == l + 1) parent_push(p, v[i], u[i]);
             }
-            // slots of the new vertices with an edge in the next frontier; one atomic per member
+            // the new vertices with an edge go to this member's LDS, slots reserved per wave;
+            // past kLocalCap they spill to the global entry arrays
             int slot[kVTS];
-            int wt = 0, wr = 0;
+            int wt = 0;
 #pragma unroll
             for (int i = 0; i < kVTS; ++i) {
                 const bool fresh = old[i] == -1;
                 const uint64_t bb = ballot(fresh && re[i] > rs[i]);
                 slot[i] = wt + mbcnt(bb);
                 wt += __popcll(bb);
-                wr += __popcll(ballot(fresh));
+                my_r += fresh ? 1 : 0;
+                my_e += fresh ? re[i] - rs[i] : 0;
             }
-            if (lane_id() == 0) {
-                s_wave[wave_id()] = wt;
-                s_wave2[wave_id()] = wr;
+            int wbase = 0, gbase = 0;
+            if (lane_id() == 0 && wt) {
+                wbase = atomicAdd(&s_misc[0], wt);
+                const int sp = wbase + wt - max(wbase, kLocalCap);
+                if (sp > 0)
+                    gbase = (int)__hip_atomic_fetch_add(&c->g_pos[(l + 1) % 3], (unsigned long long)sp,
+                                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
-            lds_barrier();
-            if (threadIdx.x == 0) {
-                int tt = 0, tr = 0;
-#pragma unroll
-                for (int q = 0; q < kWaves; ++q) {
-                    tt += s_wave[q];
-                    tr += s_wave2[q];
-                }
-                const unsigned long long add = ((unsigned long long)tr << 32) | (unsigned)tt;
-                const unsigned long long was =
-                    add ? __hip_atomic_fetch_add(&p.ctrl->g_cnt[(l + 1) % 3], add, __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_AGENT)
-                        : 0ull;
-                s_misc[0] = (int)(was & 0xffffffffull);
-            }
-            lds_barrier();
-            int wbase = s_misc[0];
-            for (int q = 0; q < wave_id(); ++q) wbase += s_wave[q];
+            wbase = __shfl(wbase, 0);
+            gbase = __shfl(gbase, 0);
 #pragma unroll
             for (int i = 0; i < kVTS; ++i) {
                 if (old[i] == -1 && re[i] > rs[i]) {
                     const int s = wbase + slot[i];
-                    if (s < kGroupCap) {
-                        p.gv[np][s] = v[i];
-                        p.grs[np][s] = rs[i];
-                        p.gd[np][s] = re[i] - rs[i];
+                    if (s < kLocalCap) {
+                        s_nv[s] = v[i];
+                        s_nrs[s] = rs[i];
+                        s_nd[s] = re[i] - rs[i];
                     } else {
-                        flag_internal(p.ctrl);
+                        const int gs = gbase + s - max(wbase, kLocalCap);
+                        if (gs < kGroupCap) {
+                            p.gv[np][gs] = v[i];
+                            p.grs[np][gs] = rs[i];
+                            p.gd[np][gs] = re[i] - rs[i];
+                        } else {
+                            flag_internal(c);
+                        }
                     }
                 }
             }
-            lds_barrier();  // s_wave and s_misc are reused by the next round
+        }
+        // the member's totals for the next level
+        {
+            const int we = wave_incl_scan(my_e), wr = wave_incl_scan(my_r);
+            if (lane_id() == 63) {
+                s_wave[wave_id()] = we;
+                s_wave2[wave_id()] = wr;
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                int te = 0, tr = 0;
+#pragma unroll
+                for (int q = 0; q < kWaves; ++q) {
+                    te += s_wave[q];
+                    tr += s_wave2[q];
+                }
+                const int claims = s_misc[0];
+                const int sp = max(claims - kLocalCap, 0);
+                const int k = (l + 1) % 3;
+                if (claims)
+                    __hip_atomic_fetch_add(&c->g_ne[k], ((unsigned long long)te << 32) | (unsigned)claims,
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (tr || sp)
+                    __hip_atomic_fetch_add(&c->g_rs[k], ((unsigned long long)tr << 32) | (unsigned)sp,
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (te) __hip_atomic_fetch_max(&c->g_mx[k], (unsigned long long)te, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+                s_misc[2] = min(claims, kLocalCap);
+                s_misc[3] = sp;
+            }
+            __syncthreads();
+            mine = s_misc[2];
         }
         if (rank == 0 && threadIdx.x == 0 && l < kStatCap) p.stat_ts[3 * l + 1] = now_ticks();
-        // the group's barrier: every member's claims, entries and counts are visible after it
-        if (!sub_barrier(p.ctrl, p.xbar, xg.xcd, 2ull * l + 2, G, true, p.spin_ticks, s_flag)) return;
+        // only claims that spilled to the global entry arrays are plain stores other members read
+        if (!sub_barrier(c, p.xbar, xg.xcd, gen_group_end(l), G, true, p.spin_ticks, s_flag, s_misc[3] > 0)) return;
         if (rank == 0 && threadIdx.x == 0 && l < kStatCap) p.stat_ts[3 * l + 2] = now_ticks();
         ++l;
         ++done;
@@ -1386,7 +1469,7 @@ __global__ void __launch_bounds__(kBlock) k_prep(Params p, int prep_shares, int 
         c->plain_next = 0;
         c->r_nl = c->r_el = c->r_kept = 0;
         c->bu_levels = 0;
-        c->g_cnt[0] = c->g_cnt[1] = c->g_cnt[2] = 0ull;
+        for (int k = 0; k < 3; ++k) c->g_ne[k] = c->g_rs[k] = c->g_mx[k] = c->g_pos[k] = 0ull;
     }
 }
 
@@ -1542,7 +1625,12 @@ k_persistent(Params p) {
             // every member has read the append counters: the next stretch, at least one grid
             // level away, starts from zero
             if (blockIdx.x == 0 && threadIdx.x == 0)
-                for (int k = 0; k < 3; ++k) st_rel(&c->g_cnt[k], 0ull);
+                for (int k = 0; k < 3; ++k) {
+                    st_rel(&c->g_ne[k], 0ull);
+                    st_rel(&c->g_rs[k], 0ull);
+                    st_rel(&c->g_mx[k], 0ull);
+                    st_rel(&c->g_pos[k], 0ull);
+                }
             l = ld_acq(&c->resume);
             n_l = ld_acq(&c->r_nl);
             e_l = ld_acq(&c->r_el);
@@ -1616,7 +1704,7 @@ k_persistent(Params p) {
         // a lite level's compaction needs only its own workgroups' expansion, so only they
         // meet here; the others wait for the level's end
         if (lite) {
-            if (blockIdx.x < P && !sub_barrier(c, p.xbar, xg.xcd, 2ull * l + 1, P, true, p.spin_ticks, s_flag))
+            if (blockIdx.x < P && !sub_barrier(c, p.xbar, xg.xcd, gen_lite(l, 1), P, true, p.spin_ticks, s_flag))
                 return;
             hot_ok = false;
         } else if (!xcd_barrier(c, p.xbar, xg, p.spin_ticks, s_flag)) {
@@ -1670,7 +1758,7 @@ k_persistent(Params p) {
         }
         fbits_ok = DIR || fb_write;  // top-down: fbits[np] holds exactly the next frontier
         if (lite) {
-            if (!sub_barrier(c, p.xbar, xg.xcd, 2ull * l + 2, P, blockIdx.x < P, p.spin_ticks, s_flag)) return;
+            if (!sub_barrier(c, p.xbar, xg.xcd, gen_lite(l, 2), P, blockIdx.x < P, p.spin_ticks, s_flag)) return;
         } else if (!xcd_barrier(c, p.xbar, xg, p.spin_ticks, s_flag)) {
             return;
         }
