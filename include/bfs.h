@@ -91,7 +91,7 @@ typedef struct bfs_workspace_s* bfs_workspace_t;  /* scratch for one in-flight r
                                   has none to find) and scans at least this many edges records its
                                   new vertices as bits instead of private-queue entries and
                                   linearises them in vertex order (0 = never; default m / 12) */
-#define BFS_OPT_GROUP      14  /* workgroups of that group (1..1024, at most the grid; 0 = default 32) */
+#define BFS_OPT_GROUP      14  /* workgroups of that group (1..64, at most the grid; 0 = default 32) */
 #define BFS_OPT_SPLIT      13  /* how each level's equal shares find their start points
                                   (Analysis, Find-StartExpPoint): 0 = every frontier vertex
                                   writes itself as the start of the shares beginning inside its

@@ -1045,7 +1045,7 @@ bfs_status_t bfs_workspace_set_option(bfs_workspace_t ws, int32_t option, int64_
             return setup_batch(ws);
         }
         case BFS_OPT_GROUP:
-            if (value < 0 || value > 1024) return fail(BFS_EINVAL, "group must be in [0, 1024]");
+            if (value < 0 || value > kGroupLimit) return fail(BFS_EINVAL, "group must be in [0, %d]", kGroupLimit);
             ws->group = value == 0 ? kGroupMax : (int32_t)value;
             return BFS_OK;
         case BFS_OPT_SPLIT:

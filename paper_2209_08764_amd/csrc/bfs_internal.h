@@ -17,6 +17,7 @@ constexpr int kVTS = 8;                   // edges per thread per round, single-
 constexpr int kSmallN = 4096;             // frontier capacity of group levels (staged in LDS)
 constexpr int kGroupCap = 16384;          // most edges a group level scans (and entries it appends)
 constexpr int kGroupMax = 32;             // default workgroups of the group
+constexpr int kGroupLimit = 64;           // most workgroups a group may have
 constexpr int kStatCap = 1 << 16;         // per-level statistics kept
 constexpr int kDefaultSmallEdges = kGroupCap;
 constexpr int kPullScan = 32;             // neighbours a lane tests before a row goes to the whole workgroup
