@@ -119,6 +119,7 @@ struct bfs_workspace_s {
     unsigned long long* desc[2] = {nullptr, nullptr};
     Ctrl* ctrl = nullptr;
     XBar* xbar = nullptr;
+    Aux* aux = nullptr;
     int32_t* stat_nl = nullptr;
     int32_t* stat_el = nullptr;
     uint64_t* stat_ts = nullptr;
@@ -270,6 +271,7 @@ Params make_params(bfs_workspace_s* ws, int32_t* level, int32_t* parent) {
     p.cnt = ws->cnt;
     p.ctrl = ws->ctrl;
     p.xbar = ws->xbar;
+    p.aux = ws->aux;
     p.stat_nl = ws->stat_nl;
     p.stat_el = ws->stat_el;
     p.stat_ts = ws->stat_ts;
@@ -628,6 +630,7 @@ size_t carve_single(const bfs_graph_s* g, unsigned char* base, Params* p) {
     p->cnt = static_cast<int32_t*>(take(2 * T * 4));
     p->ctrl = static_cast<Ctrl*>(take(sizeof(Ctrl)));
     p->xbar = static_cast<XBar*>(take(sizeof(XBar)));
+    p->aux = static_cast<Aux*>(take(sizeof(Aux)));
     p->stat_nl = static_cast<int32_t*>(take((size_t)kStatCap * 4));
     p->stat_el = static_cast<int32_t*>(take((size_t)kStatCap * 4));
     p->stat_ts = static_cast<uint64_t*>(take(3 * (size_t)kStatCap * 8));
@@ -832,7 +835,7 @@ size_t bfs_workspace_bytes(bfs_graph_t g, int32_t max_sources) {
     b += 2 * T * 4;                    // counts, bottom-up edge totals
     b += 2 * T * 8;                    // descriptors
     b += 6 * (size_t)kGroupCap * 4;    // group levels' frontier entries x2
-    b += sizeof(Ctrl) + sizeof(XBar) + 2 * (size_t)kStatCap * 4 + 3 * (size_t)kStatCap * 8 + n * 4;  // ctrl, barrier, stats, roots
+    b += sizeof(Ctrl) + sizeof(XBar) + sizeof(Aux) + 2 * (size_t)kStatCap * 4 + 3 * (size_t)kStatCap * 8 + n * 4;  // ctrl, barrier, stats, roots
     if (max_sources > 1) {
         const size_t BT = (size_t)batch_max_tiles(g), D = (size_t)batch_desc_cap(g);
         b += 3 * n * 32;               // frontier/next/visited masks
@@ -850,7 +853,7 @@ bfs_status_t bfs_workspace_free(bfs_workspace_t ws) {
     if (ws->has_run) (void)hipEventSynchronize(ws->ev_done);
     void* ptrs[] = {ws->bitmap, ws->hot[0], ws->hot[1], ws->fbits[0], ws->fbits[1], ws->snap, ws->owner, ws->f_rs[0], ws->f_rs[1], ws->f_ex[0], ws->f_ex[1], ws->f_v[0],
                     ws->f_v[1], ws->tstart[0],
-                    ws->tstart[1], ws->cand, ws->cnt, ws->desc[0], ws->desc[1], ws->ctrl, ws->xbar, ws->stat_nl,
+                    ws->tstart[1], ws->cand, ws->cnt, ws->desc[0], ws->desc[1], ws->ctrl, ws->xbar, ws->aux, ws->stat_nl,
                     ws->stat_el, ws->stat_ts, ws->roots, ws->plain_fv[0], ws->plain_fv[1], ws->b_fr, ws->b_nx, ws->b_vis,
                     ws->b_act[0], ws->b_act[1], ws->b_act_ex[0], ws->b_act_ex[1], ws->b_tstart[0],
                     ws->b_tstart[1], ws->b_desc[0], ws->b_desc[1], ws->b_act_bits, ws->b_sources,
@@ -914,6 +917,7 @@ bfs_status_t bfs_workspace_create(bfs_graph_t g, int32_t max_sources, bfs_worksp
     A(dalloc(&ws->cnt, 2 * (size_t)T));    // queue lengths, then bottom-up edge totals
     A(dalloc(&ws->ctrl, 1));
     A(dalloc(&ws->xbar, 1));
+    A(dalloc(&ws->aux, 1));
     A(dalloc(&ws->stat_nl, kStatCap));
     A(dalloc(&ws->stat_el, kStatCap));
     A(dalloc(&ws->stat_ts, 3 * (size_t)kStatCap));

@@ -82,6 +82,26 @@ struct XBar {
     unsigned long long pgen[kMaxXcd * kXLine];    // generation of those barriers, one copy per XCD
 };
 
+// What the persistent level loop needs only now and then (per level, per barrier, per stretch of
+// group levels): behind one pointer, filled by k_prep, so that the loop does not keep these
+// values in scalar registers throughout.
+struct Aux {
+    int32_t* stat_nl;
+    int32_t* stat_el;
+    uint64_t* stat_ts;
+    const int32_t* roots;
+    XBar* xbar;
+    uint32_t* snap;
+    int32_t* gv[2];
+    int32_t* grs[2];
+    int32_t* gd[2];
+    int32_t small_edges;
+    int32_t bu_alpha;
+    int32_t bu_beta;
+    int32_t insensitive;
+    int32_t group;
+};
+
 struct Params {
     // graph
     const int32_t* offsets;
@@ -138,6 +158,8 @@ struct Params {
     int32_t split_search;     // 1: each share finds its sub-tile start points by binary search
                               // instead of the compaction scattering them (Find-StartExpPoint)
     uint64_t spin_ticks;      // s_memrealtime ticks a wait may last without progress
+    Aux* aux;                 // device copy of the fields above that the persistent loop reads
+                              // through it (k_prep writes it)
 };
 
 // Batched multi-source search (up to 256 sources, 4 x 64-bit masks per vertex).

@@ -807,7 +807,7 @@ struct DenseIn {
 __device__ __forceinline__ DenseIn dense_load(const Params& p, int v) {
     DenseIn r;
     const int vb = min(v, p.n - 1);  // n >= 1; a vertex below n keeps its own data
-    r.w = p.bitmap[vb >> 5] & ~p.snap[vb >> 5];
+    r.w = p.bitmap[vb >> 5] & ~p.aux->snap[vb >> 5];
 #pragma unroll
     for (int k = 0; k <= kVT; ++k) r.off[k] = p.offsets[min(vb + k, p.n)];
     return r;
@@ -1087,7 +1087,7 @@ __device__ __forceinline__ void group_handover(const Params& p, int l, int n, in
     const int par = l & 1;
     int* s_wave = lds_wave(lds);
     const int a = (int)(((int64_t)rank * n) / G), b = (int)(((int64_t)(rank + 1) * n) / G);
-    const int32_t* gd = p.gd[par];
+    const int32_t* gd = p.aux->gd[par];
     int run = 0;
     for (int c0 = 0; c0 < n; c0 += kBlock * kVTS) {
         int d[kVTS], ts = 0;
@@ -1103,9 +1103,9 @@ __device__ __forceinline__ void group_handover(const Params& p, int l, int n, in
         for (int k = 0; k < kVTS; ++k) {
             const int i = i0 + k;
             if (i >= a && i < b) {
-                const int v = p.gv[par][i];
+                const int v = p.aux->gv[par][i];
                 p.f_v[par][i] = v;
-                p.f_rs[par][i] = p.grs[par][i];
+                p.f_rs[par][i] = p.aux->grs[par][i];
                 p.f_ex[par][i] = e;
                 scatter_starts(p, p.tstart[par], i, e, d[k]);
                 if ((unsigned)v < (unsigned)p.n)
@@ -1143,7 +1143,7 @@ __device__ void group_levels(const Params& p, int l, int n_l, int e_l, int kept,
     int* s_misc = lds_misc(lds);           // [0] claims this level, [1] global base, [2..4] totals
     int* s_flag = lds + kLdsWords - 1;
     Ctrl* c = p.ctrl;
-    const int cap = min(p.small_edges, kGroupCap);
+    const int cap = min(p.aux->small_edges, kGroupCap);
     bool first = true;
     int done = 0;
     int mine = 0;                          // claims of the previous level kept in LDS
@@ -1180,8 +1180,8 @@ __device__ void group_levels(const Params& p, int l, int n_l, int e_l, int kept,
             const int spilled = (int)(rs & 0xffffffffull);
             if (rank == 0 && threadIdx.x == 0) {
                 if (l < kStatCap && kept > 0) {
-                    p.stat_nl[l] = kept;
-                    p.stat_el[l] = e_l;
+                    p.aux->stat_nl[l] = kept;
+                    p.aux->stat_el[l] = e_l;
                 }
                 if (kept > 0) st_rel(&c->levels, l + 1);
                 st_rel(&c->heartbeat, l);
@@ -1201,14 +1201,14 @@ __device__ void group_levels(const Params& p, int l, int n_l, int e_l, int kept,
                 const int base = s_misc[1];
                 for (int i = threadIdx.x; i < mine; i += kBlock) {
                     if (base + i < kGroupCap) {
-                        p.gv[par][base + i] = s_nv[i];
-                        p.grs[par][base + i] = s_nrs[i];
-                        p.gd[par][base + i] = s_nd[i];
+                        p.aux->gv[par][base + i] = s_nv[i];
+                        p.aux->grs[par][base + i] = s_nrs[i];
+                        p.aux->gd[par][base + i] = s_nd[i];
                     } else {
                         flag_internal(c);
                     }
                 }
-                if (!sub_barrier(c, p.xbar, xg.xcd, gen_exchange(l), G, true, p.spin_ticks, s_flag)) return;
+                if (!sub_barrier(c, p.aux->xbar, xg.xcd, gen_exchange(l), G, true, p.spin_ticks, s_flag)) return;
             }
             if (leave) {
                 group_handover(p, l, n, e_l, kept, done, G, rank, lds);
@@ -1252,9 +1252,9 @@ __device__ void group_levels(const Params& p, int l, int n_l, int e_l, int kept,
                     const int i = i0 + k;
                     d[k] = 0;
                     if (i < n) {
-                        s_v[i] = p.gv[par][i];
-                        s_rs[i] = p.grs[par][i];
-                        d[k] = p.gd[par][i];
+                        s_v[i] = p.aux->gv[par][i];
+                        s_rs[i] = p.aux->grs[par][i];
+                        d[k] = p.aux->gd[par][i];
                     }
                     ts += d[k];
                 }
@@ -1280,7 +1280,7 @@ __device__ void group_levels(const Params& p, int l, int n_l, int e_l, int kept,
                                           __HIP_MEMORY_SCOPE_AGENT);
             }
         }
-        if (rank == 0 && threadIdx.x == 0 && l < kStatCap) p.stat_ts[3 * l] = now_ticks();
+        if (rank == 0 && threadIdx.x == 0 && l < kStatCap) p.aux->stat_ts[3 * l] = now_ticks();
         if (threadIdx.x == 0) s_misc[0] = 0;
         lds_barrier();
         // expand this member's edges [g0, g1) of its staged entries [0, nloc)
@@ -1363,9 +1363,9 @@ __device__ void group_levels(const Params& p, int l, int n_l, int e_l, int kept,
                     } else {
                         const int gs = gbase + s - max(wbase, kLocalCap);
                         if (gs < kGroupCap) {
-                            p.gv[np][gs] = v[i];
-                            p.grs[np][gs] = rs[i];
-                            p.gd[np][gs] = re[i] - rs[i];
+                            p.aux->gv[np][gs] = v[i];
+                            p.aux->grs[np][gs] = rs[i];
+                            p.aux->gd[np][gs] = re[i] - rs[i];
                         } else {
                             flag_internal(c);
                         }
@@ -1405,10 +1405,10 @@ __device__ void group_levels(const Params& p, int l, int n_l, int e_l, int kept,
             __syncthreads();
             mine = s_misc[2];
         }
-        if (rank == 0 && threadIdx.x == 0 && l < kStatCap) p.stat_ts[3 * l + 1] = now_ticks();
+        if (rank == 0 && threadIdx.x == 0 && l < kStatCap) p.aux->stat_ts[3 * l + 1] = now_ticks();
         // only claims that spilled to the global entry arrays are plain stores other members read
-        if (!sub_barrier(c, p.xbar, xg.xcd, gen_group_end(l), G, true, p.spin_ticks, s_flag, s_misc[3] > 0)) return;
-        if (rank == 0 && threadIdx.x == 0 && l < kStatCap) p.stat_ts[3 * l + 2] = now_ticks();
+        if (!sub_barrier(c, p.aux->xbar, xg.xcd, gen_group_end(l), G, true, p.spin_ticks, s_flag, s_misc[3] > 0)) return;
+        if (rank == 0 && threadIdx.x == 0 && l < kStatCap) p.aux->stat_ts[3 * l + 2] = now_ticks();
         ++l;
         ++done;
         first = false;
@@ -1456,6 +1456,23 @@ __global__ void __launch_bounds__(kBlock) k_prep(Params p, int prep_shares, int 
     constexpr int64_t xwords = sizeof(XBar) / sizeof(unsigned long long);
     for (int64_t w = tid; w < xwords; w += stride) reinterpret_cast<unsigned long long*>(p.xbar)[w] = 0ull;
     if (tid == 0) {
+        Aux* a = p.aux;
+        a->stat_nl = p.stat_nl;
+        a->stat_el = p.stat_el;
+        a->stat_ts = p.stat_ts;
+        a->roots = p.roots;
+        a->xbar = p.xbar;
+        a->snap = p.snap;
+        for (int k = 0; k < 2; ++k) {
+            a->gv[k] = p.gv[k];
+            a->grs[k] = p.grs[k];
+            a->gd[k] = p.gd[k];
+        }
+        a->small_edges = p.small_edges;
+        a->bu_alpha = p.bu_alpha;
+        a->bu_beta = p.bu_beta;
+        a->insensitive = p.insensitive;
+        a->group = p.group;
         Ctrl* c = p.ctrl;
         c->bar = 0;
         c->nl[0] = c->nl[1] = 0;
@@ -1505,7 +1522,7 @@ __global__ void k_status(const Ctrl* c, int32_t* out) {
 __device__ void roots_range(const Params& p, int P, int64_t first, int64_t stride) {
     const int rtiles = (p.nroots + kGrain - 1) / kGrain;
     for (int64_t i = first; i < p.nroots; i += stride) {
-        const int r = p.roots ? p.roots[i] : p.single_root;
+        const int r = p.aux->roots ? p.aux->roots[i] : p.single_root;
         p.level[r] = 0;
         if (p.parent) p.parent[r] = r;
         p.owner[r] = (int)i;
@@ -1579,15 +1596,15 @@ k_persistent(Params p) {
     [[clang::always_inline]] roots_range(p, Pr, (int64_t)blockIdx.x * kBlock + threadIdx.x, (int64_t)G * kBlock);
     // the first barrier is the flat one; it also counts the workgroups on each XCD
     XGroup xg{0, 1, 1};
-    if (threadIdx.x == 0) xbar_join(p.xbar, xcd_id());
+    if (threadIdx.x == 0) xbar_join(p.aux->xbar, xcd_id());
     if (!grid_barrier(c, p.spin_ticks, s_flag)) return;
-    if (threadIdx.x == 0) xg = xbar_group(p.xbar, xcd_id());
+    if (threadIdx.x == 0) xg = xbar_group(p.aux->xbar, xcd_id());
     bool ok = true;
     if (blockIdx.x < Pr) {
         [[clang::always_inline]] ok = compact_share(p, -1, blockIdx.x, Pr, rtiles, false, true, lds);
     }
     if (!ok) return;
-    if (!xcd_barrier(c, p.xbar, xg, p.spin_ticks, s_flag)) return;
+    if (!xcd_barrier(c, p.aux->xbar, xg, p.spin_ticks, s_flag)) return;
 
     // The size of each level is read once, right after the barrier that
     // publishes it, into loop-carried values: the slot it came from may be
@@ -1609,19 +1626,19 @@ k_persistent(Params p) {
     for (;;) {
         const int par = l & 1;
         const bool rec = blockIdx.x == 0 && threadIdx.x == 0 && l < kStatCap;
-        if (rec) p.stat_ts[3 * l] = now_ticks();
+        if (rec) p.aux->stat_ts[3 * l] = now_ticks();
         if (blockIdx.x == 0 && threadIdx.x == 0 && kept > 0) {
-            if (l < kStatCap) { p.stat_nl[l] = kept; p.stat_el[l] = e_l; }
+            if (l < kStatCap) { p.aux->stat_nl[l] = kept; p.aux->stat_el[l] = e_l; }
             st_rel(&c->levels, l + 1);
         }
         if (n_l == 0) break;
         reached_edges += e_l;
-        if (p.small_edges > 0 && n_l <= kSmallN && e_l <= min(p.small_edges, kGroupCap)) {
-            const int Gs = max(1, min(p.group, G));
+        if (p.aux->small_edges > 0 && n_l <= kSmallN && e_l <= min(p.aux->small_edges, kGroupCap)) {
+            const int Gs = max(1, min(p.aux->group, G));
             if ((int)blockIdx.x < Gs) {
                 [[clang::always_inline]] group_levels(p, l, n_l, e_l, kept, Gs, blockIdx.x, xg, lds);
             }
-            if (!xcd_barrier(c, p.xbar, xg, p.spin_ticks, s_flag)) return;
+            if (!xcd_barrier(c, p.aux->xbar, xg, p.spin_ticks, s_flag)) return;
             // every member has read the append counters: the next stretch, at least one grid
             // level away, starts from zero
             if (blockIdx.x == 0 && threadIdx.x == 0)
@@ -1644,13 +1661,13 @@ k_persistent(Params p) {
         // unreached vertices (by alpha), return when the frontier is small (by beta)
         if (DIR) {
             const int64_t unreached = p.m - reached_edges;
-            bottom_up = fbits_ok && (bottom_up ? (int64_t)n_l * p.bu_beta >= p.n
-                                               : (int64_t)e_l * p.bu_alpha > unreached);
+            bottom_up = fbits_ok && (bottom_up ? (int64_t)n_l * p.aux->bu_beta >= p.n
+                                               : (int64_t)e_l * p.aux->bu_alpha > unreached);
         }
         const int ntiles = bottom_up ? (p.n + kGrain - 1) / kGrain : (int)(((int64_t)e_l + kGrain - 1) / kGrain);
         // P_l = min(P, W_l); the work-insensitive variant splits every level over all P
         // workgroups (one share per look-back descriptor), most of them empty on small levels
-        const int P = p.insensitive ? min(G, p.max_tiles) : shares_for(ntiles, G);
+        const int P = p.aux->insensitive ? min(G, p.max_tiles) : shares_for(ntiles, G);
         const int np = (l + 1) & 1;
         const bool push = p.parent && e_l <= p.push_edges;
         // a dense level keeps its new frontier as bits and compacts it in vertex order
@@ -1684,7 +1701,7 @@ k_persistent(Params p) {
         if ((DIR && !fbits_ok) || (!dense && fb_write && fb_dirty[np]))
             for (int w = blockIdx.x * kBlock + threadIdx.x; w < fwords; w += G * kBlock) p.fbits[np][w] = 0u;
         if (dense)  // the visited bits before the level; the compaction writes every word of fbits[np]
-            for (int w = blockIdx.x * kBlock + threadIdx.x; w < fwords; w += G * kBlock) p.snap[w] = p.bitmap[w];
+            for (int w = blockIdx.x * kBlock + threadIdx.x; w < fwords; w += G * kBlock) p.aux->snap[w] = p.bitmap[w];
         if (fb_write) fb_dirty[np] = true;
         // A dense level drops a hot target only by its hot bits; where those miss visited
         // vertices (the roots and single-workgroup levels set none), each such edge would
@@ -1694,7 +1711,7 @@ k_persistent(Params p) {
             rebuild_hot_bits(p, p.hot[par], blockIdx.x * kBlock + threadIdx.x, G * kBlock);
             hot_ok = true;
         }
-        if (dense && !xcd_barrier(c, p.xbar, xg, p.spin_ticks, s_flag)) return;
+        if (dense && !xcd_barrier(c, p.aux->xbar, xg, p.spin_ticks, s_flag)) return;
         if (DIR && bottom_up) {
             if (blockIdx.x < P) bottom_up_share(p, l, blockIdx.x, P, ntiles, lds);
         } else if (blockIdx.x < P) {
@@ -1704,18 +1721,18 @@ k_persistent(Params p) {
         // a lite level's compaction needs only its own workgroups' expansion, so only they
         // meet here; the others wait for the level's end
         if (lite) {
-            if (blockIdx.x < P && !sub_barrier(c, p.xbar, xg.xcd, gen_lite(l, 1), P, true, p.spin_ticks, s_flag))
+            if (blockIdx.x < P && !sub_barrier(c, p.aux->xbar, xg.xcd, gen_lite(l, 1), P, true, p.spin_ticks, s_flag))
                 return;
             hot_ok = false;
-        } else if (!xcd_barrier(c, p.xbar, xg, p.spin_ticks, s_flag)) {
+        } else if (!xcd_barrier(c, p.aux->xbar, xg, p.spin_ticks, s_flag)) {
             return;
         }
         if (dense && p.hot_words > 0) {
             merge_hot_discoveries(p, p.hot[par], p.hot[np], (int64_t)blockIdx.x * kBlock + threadIdx.x,
                                   (int64_t)G * kBlock);
-            if (!xcd_barrier(c, p.xbar, xg, p.spin_ticks, s_flag)) return;
+            if (!xcd_barrier(c, p.aux->xbar, xg, p.spin_ticks, s_flag)) return;
         }
-        if (rec) p.stat_ts[3 * l + 1] = now_ticks();
+        if (rec) p.aux->stat_ts[3 * l + 1] = now_ticks();
         if (DIR)  // this level's frontier bits have been read: clear them for level l + 2
             for (int w = blockIdx.x * kBlock + threadIdx.x; w < fwords; w += G * kBlock) p.fbits[par][w] = 0u;
         if (DIR && bottom_up) {
@@ -1729,10 +1746,10 @@ k_persistent(Params p) {
             int n_next, e_next;
             block_excl_scan(tn, lds_wave(lds), &n_next);
             block_excl_scan(te_sum, lds_wave2(lds), &e_next);
-            const bool next_small = p.small_edges > 0 && n_next <= kSmallN && e_next <= min(p.small_edges, kGroupCap);
-            if (n_next > 0 && !next_small && (int64_t)n_next * p.bu_beta >= p.n) {
-                if (!xcd_barrier(c, p.xbar, xg, p.spin_ticks, s_flag)) return;
-                if (rec) p.stat_ts[3 * l + 2] = now_ticks();
+            const bool next_small = p.aux->small_edges > 0 && n_next <= kSmallN && e_next <= min(p.aux->small_edges, kGroupCap);
+            if (n_next > 0 && !next_small && (int64_t)n_next * p.aux->bu_beta >= p.n) {
+                if (!xcd_barrier(c, p.aux->xbar, xg, p.spin_ticks, s_flag)) return;
+                if (rec) p.aux->stat_ts[3 * l + 2] = now_ticks();
                 ++l;
                 n_l = n_next;
                 e_l = e_next;
@@ -1758,11 +1775,11 @@ k_persistent(Params p) {
         }
         fbits_ok = DIR || fb_write;  // top-down: fbits[np] holds exactly the next frontier
         if (lite) {
-            if (!sub_barrier(c, p.xbar, xg.xcd, gen_lite(l, 2), P, blockIdx.x < P, p.spin_ticks, s_flag)) return;
-        } else if (!xcd_barrier(c, p.xbar, xg, p.spin_ticks, s_flag)) {
+            if (!sub_barrier(c, p.aux->xbar, xg.xcd, gen_lite(l, 2), P, blockIdx.x < P, p.spin_ticks, s_flag)) return;
+        } else if (!xcd_barrier(c, p.aux->xbar, xg, p.spin_ticks, s_flag)) {
             return;
         }
-        if (rec) p.stat_ts[3 * l + 2] = now_ticks();
+        if (rec) p.aux->stat_ts[3 * l + 2] = now_ticks();
         ++l;
         n_l = ld_acq(&c->nl[np]);
         e_l = ld_acq(&c->el[np]);
