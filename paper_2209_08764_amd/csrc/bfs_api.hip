@@ -138,6 +138,7 @@ struct bfs_workspace_s {
     int32_t* b_tstart[2] = {nullptr, nullptr};
     unsigned long long* b_desc[2] = {nullptr, nullptr};
     uint32_t* b_act_bits = nullptr;
+    unsigned long long* b_fr_hot = nullptr;  // hot vertices' frontier masks (graphs with hot numbering)
     int32_t* b_nz_v = nullptr;
     int32_t* b_nz_ts = nullptr;
     int32_t* b_sources = nullptr;
@@ -481,6 +482,10 @@ BatchParams make_batch_params(bfs_workspace_s* ws) {
         bp.desc[i] = ws->b_desc[i];
     }
     bp.act_bits = ws->b_act_bits;
+    bp.colx = ws->g->colx;
+    bp.hot_vid = ws->g->hot_vid;
+    bp.hot_count = ws->g->colx ? ws->g->hot_count : 0;
+    bp.fr_hot = ws->b_fr_hot;
     bp.nz_v = ws->b_nz_v;
     bp.nz_ts = ws->b_nz_ts;
     bp.sources = ws->b_sources;
@@ -641,8 +646,11 @@ size_t carve_single(const bfs_graph_s* g, unsigned char* base, Params* p) {
 }  // namespace
 
 // Hot-vertex filter of a resident graph: number the (at most kHotBits) vertices
-// of highest degree, ties by id; each edge's entry of colx holds its target,
-// or -1 - the target's hot number, and hot_vid maps hot numbers back to ids.
+// of highest degree, ties by id, in id order (numbering them by degree packs the
+// hubs' hot bits into a few words, which then cost the expansion more in atomic
+// contention than the batched pull gains from the denser masks); each edge's
+// entry of colx holds its target, or -1 - the target's hot number, and hot_vid
+// maps hot numbers back to ids.
 static bfs_status_t build_hot_filter(bfs_graph_s* g, const int32_t* host_offsets, hipStream_t s) {
     const int32_t n = g->n;
     std::vector<int32_t> ho;
@@ -843,6 +851,7 @@ size_t bfs_workspace_bytes(bfs_graph_t g, int32_t max_sources) {
         b += 3 * BT * 4;               // sub-tile starts x2, over all edges
         b += 2 * D * 8;                // update descriptors x2
         b += ((n + 31) / 32 + 1) * 4 + (n + 1) * 4 + 256 * 4 + sizeof(BatchArgs);  // active bits, nz list, sources
+        if (g->colx) b += (size_t)g->hot_count * 32;  // hot vertices' frontier masks
     }
     return b;
 }
@@ -856,7 +865,7 @@ bfs_status_t bfs_workspace_free(bfs_workspace_t ws) {
                     ws->tstart[1], ws->cand, ws->cnt, ws->desc[0], ws->desc[1], ws->ctrl, ws->xbar, ws->aux, ws->stat_nl,
                     ws->stat_el, ws->stat_ts, ws->roots, ws->plain_fv[0], ws->plain_fv[1], ws->b_fr, ws->b_nx, ws->b_vis,
                     ws->b_act[0], ws->b_act[1], ws->b_act_ex[0], ws->b_act_ex[1], ws->b_tstart[0],
-                    ws->b_tstart[1], ws->b_desc[0], ws->b_desc[1], ws->b_act_bits, ws->b_sources,
+                    ws->b_tstart[1], ws->b_desc[0], ws->b_desc[1], ws->b_act_bits, ws->b_fr_hot, ws->b_sources,
                     ws->b_act_rs[0], ws->b_act_rs[1], ws->b_nz_v, ws->b_nz_ts, ws->gv[0], ws->gv[1], ws->grs[0],
                     ws->grs[1], ws->gd[0], ws->gd[1]};
     if (ws->b_exec) (void)hipGraphExecDestroy(ws->b_exec);
@@ -936,6 +945,7 @@ bfs_status_t bfs_workspace_create(bfs_graph_t g, int32_t max_sources, bfs_worksp
             A(dalloc(&ws->b_desc[i], (size_t)ws->b_desc_cap));
         }
         A(dalloc(&ws->b_act_bits, (n + 31) / 32 + 1));
+        if (g->colx) A(dalloc(&ws->b_fr_hot, (size_t)g->hot_count * 4));
         A(dalloc(&ws->b_nz_v, n + 1));
         A(dalloc(&ws->b_nz_ts, (size_t)ws->b_max_tiles));
         A(dalloc(&ws->b_sources, 256));

@@ -17,6 +17,9 @@
 //           look-back over update tiles (the Sizes prefix sum again).
 //   next    one lane advances the level and stops the loop when no vertex is
 //           active or a level would not fit in a byte.
+//   hotmask before a pull level on a graph with hot-vertex numbering: the
+//           hot vertices' masks copied into a compact array indexed by hot
+//           number, which the pull gathers from instead of F.
 //
 // OR is commutative and idempotent, so the result does not depend on the
 // order of the atomics or on push versus pull.  The level loop is replayed
@@ -355,6 +358,9 @@ __global__ void __launch_bounds__(kBlock) k_batch_expand(BatchParams p) {
         return;
     }
     // ---- pull over every row that still misses a source ----
+    // A hot neighbour's masks come from the compact copy of the hot vertices' masks (a few MiB
+    // that the L2 mostly holds), zero when it is not active; the others from F, behind the
+    // active bitmap.
     const int nz = ld_acq(&c->nz_count);
     const int ntiles = (int)((p.m + G - 1) / G);
     const int P = ntiles < (int)gridDim.x ? ntiles : (int)gridDim.x;
@@ -399,12 +405,19 @@ __global__ void __launch_bounds__(kBlock) k_batch_expand(BatchParams p) {
             if (g < g1) {
                 const int lo = own[r];
                 if (sl[2 * SL + lo]) {
-                    const int u = p.cols[g];
-                    if ((unsigned)u < (unsigned)p.n && ((p.act_bits[u >> 5] >> (u & 31)) & 1u)) {
+                    const int x = p.fr_hot ? p.colx[g] : p.cols[g];
+                    const unsigned long long* src = nullptr;
+                    if (x < 0) {
+                        const int h = -1 - x;
+                        if (h < p.hot_count) src = p.fr_hot + (int64_t)h * 4;
+                    } else if (x < p.n && ((p.act_bits[x >> 5] >> (x & 31)) & 1u)) {
+                        src = p.fr + (int64_t)x * 4;
+                    }
+                    if (src) {
 #pragma unroll
                         for (int w = 0; w < 4; ++w) {
                             if (w < W) {
-                                const unsigned long long f = p.fr[(int64_t)u * 4 + w];
+                                const unsigned long long f = src[w];
                                 if (f) atomicOr(&lds.acc[lo * 4 + w], f);
                             }
                         }
@@ -430,6 +443,24 @@ __global__ void __launch_bounds__(kBlock) k_batch_expand(BatchParams p) {
                 }
             }
         }
+    }
+}
+
+// Before a pull level: the masks of the hot vertices, in hot-number order, zero for those not
+// active (the level whose expansion runs next is ctrl->blevel).
+__global__ void __launch_bounds__(kBlock) k_batch_hotmask(BatchParams p) {
+    Ctrl* c = p.ctrl;
+    if (!p.fr_hot || ld_acq(&c->bdone)) return;
+    const int l = ld_acq(&c->blevel);
+    if (ld_acq(&c->b_eact[l & 1]) <= p.args->pull_edges) return;  // a push level gathers nothing
+    const int W = p.args->words;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; h < p.hot_count; h += stride) {
+        const int v = p.hot_vid[h];
+        const bool act = (unsigned)v < (unsigned)p.n && ((p.act_bits[v >> 5] >> (v & 31)) & 1u);
+#pragma unroll
+        for (int w = 0; w < 4; ++w)
+            if (w < W) p.fr_hot[h * 4 + w] = act ? p.fr[(int64_t)v * 4 + w] : 0ull;
     }
 }
 
@@ -525,6 +556,7 @@ hipError_t launch_batch_start(const BatchParams& p, hipStream_t s) {
     hipLaunchKernelGGL(k_batch_seed, dim3(1), dim3(64), 0, s, p);
     launch_update(p, s);
     hipLaunchKernelGGL(k_batch_next, dim3(1), dim3(64), 0, s, p);
+    if (p.fr_hot) hipLaunchKernelGGL(k_batch_hotmask, dim3(bfill_grid(p.hot_count)), dim3(kBlock), 0, s, p);
     return hipGetLastError();
 }
 
@@ -534,6 +566,7 @@ hipError_t launch_batch_level(const BatchParams& p, int grid, hipStream_t s) {
     launch_expand(p, grid, s);
     launch_update(p, s);
     hipLaunchKernelGGL(k_batch_next, dim3(1), dim3(64), 0, s, p);
+    if (p.fr_hot) hipLaunchKernelGGL(k_batch_hotmask, dim3(bfill_grid(p.hot_count)), dim3(kBlock), 0, s, p);
     return hipGetLastError();
 }
 

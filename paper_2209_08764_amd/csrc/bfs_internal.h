@@ -200,6 +200,12 @@ struct BatchParams {
     int32_t* nz_ts;           // sub-tile start points over all edges [0, m) in nz_v
     unsigned long long* desc[2];  // look-back descriptors of the update tiles, per parity
     const int32_t* sources;   // the k sources (device)
+    // hot-vertex numbering of the graph (null colx: none): pull levels read the neighbour stream
+    // colx and gather a hot neighbour's frontier masks from the compact fr_hot[hot_count][4]
+    const int32_t* colx;
+    const int32_t* hot_vid;
+    int32_t hot_count;
+    unsigned long long* fr_hot;
     Ctrl* ctrl;
     int32_t* stat_nl;
     int32_t* stat_el;

@@ -127,3 +127,16 @@ def test_bad_launch_shape_rejected(rmat13):
     single = Workspace(G)
     with pytest.raises(BFSError):
         single.set(_lib.BFS_OPT_BATCH_GRAIN, 512)
+
+
+@pytest.mark.parametrize("pull", [0, 100000, -1])
+@pytest.mark.parametrize("k", [64, 200, 256])
+def test_hot_numbered_graph_pull_levels(pull, k):
+    # with the hot-vertex numbering, pull levels gather hot neighbours' masks from the compact
+    # copy refreshed before each pull level (hot vertices that are not active hold zero there)
+    g = gg.rmat(14, seed=61)
+    G = Graph(g.offsets, g.cols, hot=True)
+    assert G.aux_bytes > 0
+    ws = Workspace(G, max_sources=256, batch_pull=pull, batch_levels=3)
+    _check(ws, g, gg.pick_sources(g, k, seed=pull + k))
+    _check(ws, g, gg.pick_sources(g, k, seed=pull + k + 1))   # masks left by the previous batch
