@@ -55,6 +55,8 @@ typedef struct bfs_workspace_s* bfs_workspace_t;  /* scratch for one in-flight r
 #define BFS_VALIDATE    4u  /* check the CSR on the host (O(m log m); meant for tests) */
 #define BFS_HOT_FILTER  8u  /* always build the hot-vertex filter (see bfs_init) */
 #define BFS_LEAN       16u  /* never build it (no per-edge memory beyond the CSR) */
+#define BFS_SORT_ROWS  32u  /* sort every row ascending first, into a copy the library owns (the
+                               caller's arrays are not modified; 4 B per edge more) */
 
 /* Execution modes (bfs_workspace_set_option(ws, BFS_OPT_MODE, ...)). */
 #define BFS_MODE_AUTO        0  /* one persistent launch; single-workgroup levels while small */
@@ -129,6 +131,8 @@ typedef struct {
  *   unchanged).  This costs 4 B per edge plus 4 B
  *   per hot vertex of device memory (bfs_graph_aux_bytes) and a host pass
  *   over the degrees.
+ *   With BFS_SORT_ROWS the rows need not be sorted: a device segmented sort
+ *   writes a sorted copy that the graph uses (BFS_VALIDATE then checks that).
  * Errors: EINVAL (null pointers, n < 0, m < 0, both or neither pointer flag,
  *         both BFS_HOT_FILTER and BFS_LEAN), EBADCSR (BFS_VALIDATE failed),
  *         ENOMEM, EHIP.

@@ -61,9 +61,10 @@ def bfs_status_str(status: int) -> str:
 
 
 def bfs_init(offsets, cols, flags: int | None = None, stream=None, validate: bool = False,
-             hot: bool | None = None) -> int:
+             hot: bool | None = None, sort_rows: bool = False) -> int:
     """Make a CSR graph resident; numpy arrays are copied, device tensors borrowed.
-    hot: None = the library's size rule for the hot-vertex filter, True/False = force it on/off."""
+    hot: None = the library's size rule for the hot-vertex filter, True/False = force it on/off.
+    sort_rows: rows need not be sorted; the library sorts a copy (BFS_SORT_ROWS)."""
     torch = _torch()
     lib = _lib.load()
     out = ctypes.c_void_p()
@@ -85,6 +86,8 @@ def bfs_init(offsets, cols, flags: int | None = None, stream=None, validate: boo
         fl |= BFS_VALIDATE
     if hot is not None:
         fl |= BFS_HOT_FILTER if hot else BFS_LEAN
+    if sort_rows:
+        fl |= _lib.BFS_SORT_ROWS
     _lib.check(lib.bfs_init(po, pc, n, m, fl, _stream_ptr(stream), ctypes.byref(out)), "bfs_init")
     return out.value
 
@@ -236,13 +239,13 @@ class Graph:
     """A device-resident graph (owns the handle and keeps borrowed tensors alive)."""
 
     def __init__(self, offsets, cols, device="cuda", validate: bool = False, copy: bool = False,
-                 hot: bool | None = None):
+                 hot: bool | None = None, sort_rows: bool = False):
         torch = _torch()
         if isinstance(offsets, np.ndarray) and not copy:
             offsets = torch.from_numpy(np.ascontiguousarray(offsets, dtype=np.int32)).to(device)
             cols = torch.from_numpy(np.ascontiguousarray(cols, dtype=np.int32)).to(device)
         self._keep = (offsets, cols)
-        self.handle = bfs_init(offsets, cols, validate=validate, hot=hot)
+        self.handle = bfs_init(offsets, cols, validate=validate, hot=hot, sort_rows=sort_rows)
         self.n, self.m = bfs_graph_info(self.handle)
         self.aux_bytes = bfs_graph_aux_bytes(self.handle)
         self.offsets = offsets

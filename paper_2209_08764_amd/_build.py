@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbfs.so")
-SOURCES = ["bfs_kernels.hip", "bfs_batch.hip", "bfs_api.hip", "bfs_probe.hip"]
+SOURCES = ["bfs_kernels.hip", "bfs_batch.hip", "bfs_api.hip", "bfs_probe.hip", "bfs_sort.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

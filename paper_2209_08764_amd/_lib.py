@@ -27,6 +27,7 @@ BFS_DEVICE_PTRS = 2
 BFS_VALIDATE = 4
 BFS_HOT_FILTER = 8
 BFS_LEAN = 16
+BFS_SORT_ROWS = 32
 
 BFS_MODE_AUTO = 0
 BFS_MODE_LEVEL = 1

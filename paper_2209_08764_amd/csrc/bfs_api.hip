@@ -89,7 +89,8 @@ struct bfs_graph_s {
     int64_t m = 0;
     int32_t* offsets = nullptr;
     int32_t* cols = nullptr;
-    bool owned = false;
+    bool owned = false;         // offsets and cols are the library's copies
+    bool owned_cols = false;    // cols is the library's (rows sorted from the caller's)
     int32_t* colx = nullptr;    // hot-vertex filter: each edge's target, or -1 - its hot number
     int32_t* hot_vid = nullptr; // vertex id of each hot number
     int32_t hot_count = 0;      // hot vertices
@@ -734,8 +735,9 @@ bfs_status_t bfs_init(const int32_t* offsets, const int32_t* cols, int32_t n, in
     if (n < 0 || m < 0 || m > INT32_MAX) return fail(BFS_EINVAL, "n or m out of range");
     const bool host = flags & BFS_HOST_PTRS, dev = flags & BFS_DEVICE_PTRS;
     if (host == dev) return fail(BFS_EINVAL, "exactly one of BFS_HOST_PTRS / BFS_DEVICE_PTRS");
-    if (flags & ~(BFS_HOST_PTRS | BFS_DEVICE_PTRS | BFS_VALIDATE | BFS_HOT_FILTER | BFS_LEAN))
+    if (flags & ~(BFS_HOST_PTRS | BFS_DEVICE_PTRS | BFS_VALIDATE | BFS_HOT_FILTER | BFS_LEAN | BFS_SORT_ROWS))
         return fail(BFS_EINVAL, "unknown flag");
+    const bool sort_rows = flags & BFS_SORT_ROWS;
     if ((flags & BFS_HOT_FILTER) && (flags & BFS_LEAN)) return fail(BFS_EINVAL, "BFS_HOT_FILTER and BFS_LEAN together");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     if (flags & BFS_VALIDATE) {
@@ -749,6 +751,17 @@ bfs_status_t bfs_init(const int32_t* offsets, const int32_t* cols, int32_t n, in
             if (m) HIP_TRY(hipMemcpy(hc.data(), cols, sizeof(int32_t) * (size_t)m, hipMemcpyDeviceToHost));
             po = ho.data();
             pc = hc.data();
+        } else if (sort_rows) {
+            hc.assign(cols, cols + m);
+            pc = hc.data();
+        }
+        if (sort_rows) {
+            // what the device sort will produce, checked here (offsets first, so that the rows exist)
+            if (po[0] != 0 || (int64_t)po[n] != m) return fail(BFS_EBADCSR, "offsets do not span [0, m)");
+            for (int32_t v = 0; v < n; ++v) {
+                if (po[v + 1] < po[v]) return fail(BFS_EBADCSR, "offsets decrease at vertex %d", v);
+                std::sort(hc.begin() + po[v], hc.begin() + po[v + 1]);
+            }
         }
         bfs_status_t st = validate_csr(po, pc, n, m);
         if (st) return st;
@@ -779,6 +792,22 @@ bfs_status_t bfs_init(const int32_t* offsets, const int32_t* cols, int32_t n, in
         if (m) HIP_TRY(hipMemcpyAsync(g->cols, cols, sizeof(int32_t) * (size_t)m, hipMemcpyHostToDevice, s));
         HIP_TRY(hipStreamSynchronize(s));
     }
+    if (sort_rows && m > 0) {
+        int32_t* sorted = nullptr;
+        if (dalloc(&sorted, (size_t)m) != hipSuccess) {
+            bfs_graph_free(g);
+            return fail(BFS_ENOMEM, "device allocation of the sorted rows failed");
+        }
+        const hipError_t e = sort_rows_device(g->offsets, g->cols, sorted, n, m, s);
+        if (e != hipSuccess) {
+            (void)hipFree(sorted);
+            bfs_graph_free(g);
+            return fail(BFS_EHIP, "sorting the rows: %s", hipGetErrorString(e));
+        }
+        if (g->owned) (void)hipFree(g->cols);  // the unsorted upload
+        g->cols = sorted;
+        g->owned_cols = !g->owned;
+    }
     const bool want_hot = !(flags & BFS_LEAN) && ((flags & BFS_HOT_FILTER) || m >= kHotMinEdges) && n > 0 && m > 0;
     if (want_hot) {
         bfs_status_t st = build_hot_filter(g, host ? offsets : nullptr, s);
@@ -795,6 +824,8 @@ bfs_status_t bfs_graph_free(bfs_graph_t g) {
     if (!g) return fail(BFS_EINVAL, "null graph");
     if (g->owned) {
         (void)hipFree(g->offsets);
+        (void)hipFree(g->cols);
+    } else if (g->owned_cols) {
         (void)hipFree(g->cols);
     }
     if (g->colx) (void)hipFree(g->colx);

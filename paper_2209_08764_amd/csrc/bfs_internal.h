@@ -243,4 +243,8 @@ hipError_t launch_batch_start(const BatchParams& p, hipStream_t s);
 hipError_t launch_batch_level(const BatchParams& p, int grid, hipStream_t s);
 int batch_grid_capacity(int device, int bvt);
 
+// bfs_sort.hip: every row of the CSR sorted ascending into cols_out (synchronous on s)
+hipError_t sort_rows_device(const int32_t* offsets, const int32_t* cols_in, int32_t* cols_out, int32_t n, int64_t m,
+                            hipStream_t s);
+
 }  // namespace s3bfs
