@@ -16,9 +16,9 @@ from __future__ import annotations
 from . import erdos_renyi, grid, pick_sources, powerlaw_forest, rmat
 
 # C5 serving: queries arrive at a fixed Poisson rate, 0.7 x the closed-loop (saturated) rate of
-# the serving loop on one MI355X (181.4 queries/s, all queries queued at once, measured once with
-# this graph set), under a 2 GB admission budget for workspaces and outputs.
-C5_RATE_QPS = 127.0
+# the serving loop on one MI355X (417.3 queries/s, all queries queued at once, measured once with
+# this graph set and scheduler), under a 2 GB admission budget for workspaces and outputs.
+C5_RATE_QPS = 292.0
 C5_BUDGET_BYTES = 2_000_000_000
 
 SEEDS = {

@@ -96,12 +96,14 @@ class Scheduler:
 
     def _acquire(self, name: str, k: int):
         """An idle workspace for (graph, k-class), or a new one, plus the run's output, if the
-        budget allows (evicting idle workspaces of other graphs); None otherwise."""
+        budget allows; None otherwise.  A single-source run may evict idle workspaces of other
+        graphs (batched ones first); a batch only uses what is free, so that the large batched
+        workspaces never push out the single-source ones every graph keeps needing."""
         info = self.ex.info[name]
         kind = 256 if k > 1 else 1
         pooled = bool(self.pool[(name, kind)])
         need = self._out_cost(info, k) + (0 if pooled else self._ws_cost(info, kind))
-        while self.used + need > self.budget and self._evict_one(exclude=(name, kind)):
+        while kind == 1 and self.used + need > self.budget and self._evict_one(exclude=(name, kind)):
             pass
         if self.used + need > self.budget:
             return None
@@ -114,13 +116,15 @@ class Scheduler:
         return ws
 
     def _evict_one(self, exclude) -> bool:
-        for key, lst in self.pool.items():
-            if key != exclude and lst:
-                ws = lst.pop()
-                self.used -= self.pool_bytes.pop(id(ws))
-                self.ex.destroy(ws)
-                self.stats["workspaces_evicted"] += 1
-                return True
+        """Frees one idle workspace other than `exclude`'s: a batched one if there is any."""
+        for batched in (True, False):
+            for key, lst in self.pool.items():
+                if key != exclude and lst and (key[1] > 1) == batched:
+                    ws = lst.pop()
+                    self.used -= self.pool_bytes.pop(id(ws))
+                    self.ex.destroy(ws)
+                    self.stats["workspaces_evicted"] += 1
+                    return True
         return False
 
     def _release(self, name: str, kind: int, ws):

@@ -171,3 +171,37 @@ def test_failed_requests_do_not_stop_the_loop(graphs):
         assert np.array_equal(q.result, oracle.bfs_levels(g.offsets, g.cols, q.source))
     # failed runs gave their workspaces back to the budget
     assert sch.used == sum(sch.pool_bytes.values())
+
+
+def test_batches_use_free_budget_and_singles_evict_batches_first(graphs):
+    ex = FakeExecutor(graphs)
+    info = ex.info
+    one_batch = max(i.ws_bytes_batch + 256 * i.n for i in info.values())
+    singles = sum(i.ws_bytes_single + 4 * i.n for i in info.values())
+    sch = Scheduler(ex, budget_bytes=singles + one_batch, max_inflight=2, clock=ex.clock, batch_share=1.0)
+    orig_evict, orig_acquire = sch._evict_one, sch._acquire
+    events = []
+
+    def evict(exclude):
+        idle_batched = sum(len(v) for key, v in sch.pool.items() if key[1] > 1 and key != exclude)
+        kinds_before = {key: len(v) for key, v in sch.pool.items()}
+        ok = orig_evict(exclude)
+        gone = [key for key, v in sch.pool.items() if len(v) < kinds_before.get(key, 0)]
+        events.append((idle_batched, gone))
+        return ok
+
+    def acquire(name, k):
+        before = len(events)
+        ws = orig_acquire(name, k)
+        if k > 1:
+            assert len(events) == before          # a batch never evicts
+        return ws
+
+    sch._evict_one, sch._acquire = evict, acquire
+    qs = poisson_queries(graphs, _nonisolated(graphs), rate=5e4, count=400, seed=9)
+    sch.run(qs)
+    assert all(q.result is not None for q in qs)
+    assert sch.used <= sch.budget and sch.stats["batches"] > 0
+    for idle_batched, gone in events:
+        if gone and gone[0][1] == 1:
+            assert idle_batched == 0              # singles go only when no batched workspace is idle
