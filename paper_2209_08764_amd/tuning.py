@@ -32,11 +32,20 @@ def graph_signature(graph) -> str:
     return f"n={graph.n},m={graph.m},iso={iso},dmax={mx},d2={m2}"
 
 
-def cache_key(ws, k: int, batch: bool) -> str:
+def device_signature() -> str:
+    """The GPU a tuning applies to: its architecture and compute-unit count (the marketing name
+    is not always readable)."""
     import torch
-    dev = torch.cuda.get_device_name() if torch.cuda.is_available() else "cpu"
+    if not torch.cuda.is_available():
+        return "cpu"
+    props = torch.cuda.get_device_properties(torch.cuda.current_device())
+    arch = getattr(props, "gcnArchName", "") or torch.cuda.get_device_name()
+    return f"{arch.split(':')[0]}/{props.multi_processor_count}cu"
+
+
+def cache_key(ws, k: int, batch: bool) -> str:
     kind = f"batch{k}" if batch else "single"
-    return f"{dev}|{graph_signature(ws.graph)}|{kind}"
+    return f"{device_signature()}|{graph_signature(ws.graph)}|{kind}"
 
 
 def _load(path):
