@@ -1655,6 +1655,27 @@ k_persistent(Params p) {
             fbits_ok = false;  // group levels keep no frontier or hot bits
             hot_ok = false;
             bottom_up = false;
+            // Direction mode: when the level the group hands over is one that Beamer's rule
+            // sends bottom-up, its frontier bits are rebuilt from the handed-over queue (the
+            // other buffer cleared), rather than expanding it top-down over its hubs
+            if (DIR && n_l > 0 && !(n_l <= kSmallN && e_l <= min(p.aux->small_edges, kGroupCap)) &&
+                (int64_t)e_l * p.aux->bu_alpha > p.m - reached_edges - e_l) {
+                for (int w = blockIdx.x * kBlock + threadIdx.x; w < fwords; w += G * kBlock) {
+                    p.fbits[0][w] = 0u;
+                    p.fbits[1][w] = 0u;
+                }
+                if (!xcd_barrier(c, p.aux->xbar, xg, p.spin_ticks, s_flag)) return;
+                const int32_t* fv = p.f_v[l & 1];
+                uint32_t* fb = p.fbits[l & 1];
+                for (int i = blockIdx.x * kBlock + threadIdx.x; i < n_l; i += G * kBlock) {
+                    const int v = fv[i];
+                    if ((unsigned)v < (unsigned)p.n)
+                        __hip_atomic_fetch_or(&fb[v >> 5], 1u << (v & 31), __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+                }
+                if (!xcd_barrier(c, p.aux->xbar, xg, p.spin_ticks, s_flag)) return;
+                fbits_ok = true;
+            }
             continue;
         }
         // Beamer's rule: go bottom-up once the frontier's edges outweigh those of the

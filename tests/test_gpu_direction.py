@@ -68,3 +68,18 @@ def test_direction_with_hot_filter():
         for s in gg.pick_sources(g, 3, seed=4):
             lv, par = run_single(ws, s)
             assert_same(lv, par, g, int(s))
+
+
+@pytest.mark.parametrize("name", ["rmat16", "rmat18", "er"])
+def test_levels_handed_over_by_the_group_can_go_bottom_up(graphs, name):
+    # forced bottom-up with group levels on: every level the group of workgroups does not run
+    # goes bottom-up, the ones it hands over included (their frontier bits are rebuilt from the
+    # handed-over queue)
+    g, G = graphs[name]
+    ws = Workspace(G, mode=BFS_MODE_DIRECTION, **FORCE)
+    for s in gg.pick_sources(g, 3, seed=12):
+        lv, par = run_single(ws, s)
+        assert_same(lv, par, g, int(s))
+        st = ws.stats()
+        assert st["small_levels"] > 0 and st["bottom_up_levels"] > 0
+        assert st["levels"] == st["small_levels"] + st["bottom_up_levels"], (int(s), st)
