@@ -94,6 +94,10 @@ typedef struct bfs_workspace_s* bfs_workspace_t;  /* scratch for one in-flight r
                                   new vertices as bits instead of private-queue entries and
                                   linearises them in vertex order (0 = never; default m / 12) */
 #define BFS_OPT_GROUP      14  /* workgroups of that group (1..64, at most the grid; 0 = default 32) */
+#define BFS_OPT_BATCH_REPLAYS 15 /* batched search: replays of the captured level loop each run
+                                    enqueues before the one-workgroup finish (-1 = enough for the
+                                    most levels a completed batched run of this workspace needed,
+                                    32 before the first, default; 0..256 = exactly that many) */
 #define BFS_OPT_SPLIT      13  /* how each level's equal shares find their start points
                                   (Analysis, Find-StartExpPoint): 0 = every frontier vertex
                                   writes itself as the start of the shares beginning inside its
@@ -208,8 +212,12 @@ bfs_status_t bfs_run_multiroot(bfs_workspace_t ws, const int32_t* roots, int32_t
  *   of v from sources[j], 255 if unreached.
  * The workspace must have been created with max_sources >= k.  Levels >= 255
  * do not fit: the run stops and bfs_sync returns BFS_EOVERFLOW (the int32
- * single-source path answers those sources).  Synchronises with stream
- * between replays of its captured level loop.
+ * single-source path answers those sources).
+ * Asynchronous on stream: the call enqueues a reset, replays of the captured
+ * level loop (see BFS_OPT_BATCH_REPLAYS) and one single-workgroup kernel that
+ * runs whatever levels the replays left, and returns without waiting for the
+ * device; level is complete in stream order.  Device-side failures and
+ * overflow are reported by bfs_sync.
  */
 bfs_status_t bfs_run_batch(bfs_workspace_t ws, const int32_t* sources, int32_t k, uint8_t* level,
                            void* stream);

@@ -17,7 +17,7 @@ from ._lib import (BFS_DEVICE_PTRS, BFS_HOST_PTRS, BFS_HOT_FILTER, BFS_LEAN, BFS
                    BFS_MODE_INSENSITIVE, BFS_MODE_LEVEL, BFS_OPT_BU_ALPHA, BFS_OPT_BU_BETA, BFS_OPT_DENSE_EDGES,
                    BFS_MODE_PLAIN, BFS_OPT_BATCH_GRAIN, BFS_OPT_BATCH_LEVELS, BFS_OPT_BATCH_PULL, BFS_OPT_BATCH_TILE,
                    BFS_OPT_GRID, BFS_OPT_MODE, BFS_OPT_PROFILE, BFS_OPT_PUSH_EDGES, BFS_OPT_SMALL_EDGES,
-                   BFS_OPT_GROUP, BFS_OPT_SPLIT, BFS_TUNE_BATCH, BFS_TUNE_SINGLE, BFS_VALIDATE, BFSError, bfs_stats_t, bfs_tune_t)
+                   BFS_OPT_BATCH_REPLAYS, BFS_OPT_GROUP, BFS_OPT_SPLIT, BFS_TUNE_BATCH, BFS_TUNE_SINGLE, BFS_VALIDATE, BFSError, bfs_stats_t, bfs_tune_t)
 
 __all__ = [
     "bfs_init", "bfs_graph_free", "bfs_graph_info", "bfs_graph_aux_bytes", "bfs_workspace_bytes", "bfs_workspace_create",
@@ -28,7 +28,7 @@ __all__ = [
     "BFS_MODE_AUTO", "BFS_MODE_LEVEL", "BFS_MODE_PLAIN", "BFS_MODE_INSENSITIVE", "BFS_MODE_DIRECTION",
     "BFS_OPT_BU_ALPHA", "BFS_OPT_BU_BETA", "BFS_OPT_DENSE_EDGES", "BFS_OPT_MODE",
     "BFS_OPT_SMALL_EDGES", "BFS_OPT_GRID", "BFS_OPT_PROFILE", "BFS_OPT_BATCH_PULL", "BFS_OPT_PUSH_EDGES", "BFS_OPT_BATCH_LEVELS",
-    "BFS_OPT_BATCH_GRAIN", "BFS_OPT_BATCH_TILE", "BFS_OPT_SPLIT", "BFS_OPT_GROUP", "BFS_TUNE_BATCH", "BFS_TUNE_SINGLE", "BFS_HOST_PTRS",
+    "BFS_OPT_BATCH_GRAIN", "BFS_OPT_BATCH_TILE", "BFS_OPT_SPLIT", "BFS_OPT_GROUP", "BFS_OPT_BATCH_REPLAYS", "BFS_TUNE_BATCH", "BFS_TUNE_SINGLE", "BFS_HOST_PTRS",
     "BFS_DEVICE_PTRS", "BFS_VALIDATE", "BFS_HOT_FILTER", "BFS_LEAN",
 ]
 
@@ -276,7 +276,8 @@ class Workspace:
                  "batch_pull": BFS_OPT_BATCH_PULL, "push_edges": BFS_OPT_PUSH_EDGES,
                  "batch_levels": BFS_OPT_BATCH_LEVELS, "batch_grain": BFS_OPT_BATCH_GRAIN,
                  "batch_tile": BFS_OPT_BATCH_TILE, "bu_alpha": BFS_OPT_BU_ALPHA, "bu_beta": BFS_OPT_BU_BETA,
-                 "dense_edges": BFS_OPT_DENSE_EDGES, "split_search": BFS_OPT_SPLIT, "group": BFS_OPT_GROUP}
+                 "dense_edges": BFS_OPT_DENSE_EDGES, "split_search": BFS_OPT_SPLIT, "group": BFS_OPT_GROUP,
+                 "batch_replays": BFS_OPT_BATCH_REPLAYS}
         for k, v in opts.items():
             bfs_workspace_set_option(self.handle, names[k], v)
 

@@ -49,6 +49,7 @@ BFS_OPT_BU_BETA = 11
 BFS_OPT_DENSE_EDGES = 12
 BFS_OPT_SPLIT = 13
 BFS_OPT_GROUP = 14
+BFS_OPT_BATCH_REPLAYS = 15
 
 BFS_TUNE_BATCH = 1
 BFS_TUNE_SINGLE = 2

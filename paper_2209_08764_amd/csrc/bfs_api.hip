@@ -150,6 +150,9 @@ struct bfs_workspace_s {
     int32_t b_bvt = kBVTDefault;         // edges per thread of an expansion sub-tile
     int32_t b_uv = kUVDefault;           // vertices per thread of an update tile
     int32_t batch_levels = 8;            // levels per replay of the captured loop
+    int32_t batch_replays = -1;          // replays per run (-1: enough for the deepest run seen)
+    int32_t b_seen = 0;                  // most levels a completed batched run needed (0: none yet)
+    bool last_batch = false;             // the last run was batched
     hipStream_t own_stream = nullptr;    // the workspace's private stream (set-up and capture)
     hipGraphExec_t b_exec = nullptr;
     hipGraph_t b_graph = nullptr;
@@ -429,6 +432,7 @@ bfs_status_t run_common(bfs_workspace_s* ws, const int32_t* roots_host, int32_t 
     ws->profiled = false;
     ws->last_mode = ws->mode;
     ws->host_status = BFS_OK;
+    ws->last_batch = false;
     int mode = ws->mode;
     if (mode == BFS_MODE_LEVEL) {
         st = run_level_mode(ws, p, s);
@@ -1067,6 +1071,10 @@ bfs_status_t bfs_workspace_set_option(bfs_workspace_t ws, int32_t option, int64_
             if (value < 0 || value > INT32_MAX) return fail(BFS_EINVAL, "bad dense threshold");
             ws->dense_edges = (int32_t)value;
             return BFS_OK;
+        case BFS_OPT_BATCH_REPLAYS:
+            if (value < -1 || value > 256) return fail(BFS_EINVAL, "replays per batched run must be in [-1, 256]");
+            ws->batch_replays = (int32_t)value;
+            return BFS_OK;
         case BFS_OPT_BATCH_LEVELS: {
             if (value < 1 || value > 256) return fail(BFS_EINVAL, "levels per replay must be in [1, 256]");
             if (bfs_status_t q = quiesce(ws)) return q;
@@ -1179,6 +1187,8 @@ bfs_status_t bfs_sync(bfs_workspace_t ws) {
     HIP_TRY(hipEventSynchronize(ws->ev_done));
     if (ws->host_status != BFS_OK) return ws->host_status;
     HIP_TRY(hipMemcpy(ws->h_ctrl, ws->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
+    if (ws->last_batch && !ws->h_ctrl->error && !ws->h_ctrl->batch_overflow)
+        ws->b_seen = std::max(ws->b_seen, (int32_t)ws->h_ctrl->levels);
     if (ws->h_ctrl->error)
         return fail(BFS_EDEVICE, "device-side failure (code %d: %s)", ws->h_ctrl->error,
                     ws->h_ctrl->error == -9 ? "malformed frontier" : "a wait timed out");
@@ -1354,15 +1364,15 @@ bfs_status_t bfs_run_batch(bfs_workspace_t ws, const int32_t* sources, int32_t k
         HIP_TRY(hipEventRecord(pe->first, s));
     }
     HIP_TRY(launch_batch_start(bp, s));
-    // replay the captured levels until the device reports that nothing is active
-    const int64_t max_replays = (int64_t)ws->g->n / std::max(ws->batch_levels, 1) + 2;
-    for (int64_t r = 0;; ++r) {
-        HIP_TRY(hipGraphLaunch(ws->b_exec, s));
-        HIP_TRY(hipMemcpyAsync(ws->h_ctrl, ws->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        if (ws->h_ctrl->bdone || ws->h_ctrl->error) break;
-        if (r > max_replays) return fail(BFS_EDEVICE, "batched level loop did not finish");
-    }
+    // Replays of the captured levels, as many as the deepest completed run of this workspace
+    // needed (32 levels before the first), then one workgroup that finishes whatever levels
+    // are left: the call never waits for the device, and the search is complete in stream
+    // order.  Levels after the stop cost a replay's launches, not its work.
+    const int depth = ws->b_seen > 0 ? ws->b_seen : 32;
+    const int replays = ws->batch_replays >= 0 ? ws->batch_replays
+                                               : (depth + ws->batch_levels - 1) / ws->batch_levels;
+    for (int r = 0; r < replays; ++r) HIP_TRY(hipGraphLaunch(ws->b_exec, s));
+    HIP_TRY(launch_batch_finish(bp, s));
     if (pe) {
         HIP_TRY(hipEventRecord(pe->second, s));
         ws->profiled = true;
@@ -1371,8 +1381,7 @@ bfs_status_t bfs_run_batch(bfs_workspace_t ws, const int32_t* sources, int32_t k
     HIP_TRY(hipEventRecord(ws->ev_done, s));
     ws->last_stream = s;
     ws->has_run = true;
-    if (ws->h_ctrl->error) return fail(BFS_EDEVICE, "device-side failure in the batched search (code %d)", ws->h_ctrl->error);
-    if (ws->h_ctrl->batch_overflow) return fail(BFS_EOVERFLOW, "a batched level reached 255");
+    ws->last_batch = true;
     return BFS_OK;
 }
 

@@ -23,7 +23,9 @@
 //
 // OR is commutative and idempotent, so the result does not depend on the
 // order of the atomics or on push versus pull.  The level loop is replayed
-// from a captured hipGraph; every kernel returns at once after the stop.
+// from a captured hipGraph; every kernel returns at once after the stop.  A
+// one-workgroup kernel behind the replays runs whatever levels they left, so
+// the host never waits between replays.
 #include "bfs_device.h"
 
 #include <hip/hip_runtime.h>
@@ -152,11 +154,11 @@ __global__ void k_batch_seed(BatchParams p) {
     }
 }
 
-// Dense update after the expansion of level l (l = -1: the seeds).
+// Dense update after the expansion of level l (l = -1: the seeds): update tile `tile` of
+// `ntiles` (the tiles' look-back chains them in index order).
 template <int BVT, int UV>
-__global__ void __launch_bounds__(kBlock) k_batch_update(BatchParams p) {
+__device__ __forceinline__ void batch_update_tile(const BatchParams& p, int tile, int ntiles, UpdLds<UV>& lds) {
     constexpr int UT = kBlock * UV;
-    __shared__ UpdLds<UV> lds;
     Ctrl* c = p.ctrl;
     if (ld_acq(&c->bdone)) return;
     const int l = ld_acq(&c->blevel);
@@ -165,7 +167,6 @@ __global__ void __launch_bounds__(kBlock) k_batch_update(BatchParams p) {
     int* s_wave2 = lds.misc + kWaves;
     int* s_b = lds.misc + 2 * kWaves;
     uint32_t* s_bits = reinterpret_cast<uint32_t*>(lds.misc + 2 * kWaves + 16);
-    const int tile = blockIdx.x;
     const int v0 = tile * UT + threadIdx.x * UV;
     const int W = p.args->words;
     const int K = p.args->k;
@@ -253,7 +254,7 @@ __global__ void __launch_bounds__(kBlock) k_batch_update(BatchParams p) {
             s_b[0] = pc;
             s_b[1] = ps;
             s_b[2] = ok;
-            if (ok && tile == (int)gridDim.x - 1) {
+            if (ok && tile == ntiles - 1) {
                 st_rel(&c->b_nact[np], pc + C);
                 st_rel(&c->b_eact[np], ps + S);
                 p.act_ex[np][pc + C] = ps + S;
@@ -286,12 +287,18 @@ __global__ void __launch_bounds__(kBlock) k_batch_update(BatchParams p) {
     }
 }
 
-// Expansion of level l: push over the active edges or pull over all rows.
+template <int BVT, int UV>
+__global__ void __launch_bounds__(kBlock) k_batch_update(BatchParams p) {
+    __shared__ UpdLds<UV> lds;
+    batch_update_tile<BVT, UV>(p, blockIdx.x, gridDim.x, lds);
+}
+
+// Expansion of level l: push over the active edges or pull over all rows, as workgroup b of
+// nb.
 template <int BVT>
-__global__ void __launch_bounds__(kBlock) k_batch_expand(BatchParams p) {
+__device__ __forceinline__ void batch_expand(const BatchParams& p, int b, int nb, ExpLds<BVT>& lds) {
     constexpr int G = kBlock * BVT;
     constexpr int SL = ExpLds<BVT>::kSl;
-    __shared__ ExpLds<BVT> lds;
     Ctrl* c = p.ctrl;
     if (ld_acq(&c->bdone)) return;
     const int l = ld_acq(&c->blevel);
@@ -301,16 +308,16 @@ __global__ void __launch_bounds__(kBlock) k_batch_expand(BatchParams p) {
     const int W = p.args->words;
     const int K = p.args->k;
     // descriptors of this level's update (last used two levels ago)
-    for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < p.utiles; t += (int64_t)gridDim.x * kBlock)
+    for (int64_t t = (int64_t)b * kBlock + threadIdx.x; t < p.utiles; t += (int64_t)nb * kBlock)
         p.desc[(l + 1) & 1][t] = 0ull;
     int* sl = lds.sl;
     if (e_a <= p.args->pull_edges) {
         // ---- push over the active list ----
         const int ntiles = (int)(((int64_t)e_a + G - 1) / G);
-        const int P = ntiles < (int)gridDim.x ? ntiles : (int)gridDim.x;
-        if ((int)blockIdx.x >= P) return;
+        const int P = ntiles < nb ? ntiles : nb;
+        if (b >= P) return;
         int tb, te;
-        bshare_range(blockIdx.x, P, ntiles, &tb, &te);
+        bshare_range(b, P, ntiles, &tb, &te);
         const int32_t* ts = p.act_ts[par];
         for (int t = tb; t < te; ++t) {
             const int j0 = ts[t];
@@ -363,10 +370,10 @@ __global__ void __launch_bounds__(kBlock) k_batch_expand(BatchParams p) {
     // active bitmap.
     const int nz = ld_acq(&c->nz_count);
     const int ntiles = (int)((p.m + G - 1) / G);
-    const int P = ntiles < (int)gridDim.x ? ntiles : (int)gridDim.x;
-    if ((int)blockIdx.x >= P) return;
+    const int P = ntiles < nb ? ntiles : nb;
+    if (b >= P) return;
     int tb, te;
-    bshare_range(blockIdx.x, P, ntiles, &tb, &te);
+    bshare_range(b, P, ntiles, &tb, &te);
     unsigned long long full[4];
 #pragma unroll
     for (int w = 0; w < 4; ++w)
@@ -446,16 +453,21 @@ __global__ void __launch_bounds__(kBlock) k_batch_expand(BatchParams p) {
     }
 }
 
+template <int BVT>
+__global__ void __launch_bounds__(kBlock) k_batch_expand(BatchParams p) {
+    __shared__ ExpLds<BVT> lds;
+    batch_expand<BVT>(p, blockIdx.x, gridDim.x, lds);
+}
+
 // Before a pull level: the masks of the hot vertices, in hot-number order, zero for those not
-// active (the level whose expansion runs next is ctrl->blevel).
-__global__ void __launch_bounds__(kBlock) k_batch_hotmask(BatchParams p) {
+// active (the level whose expansion runs next is ctrl->blevel); thread `first` of `stride`.
+__device__ __forceinline__ void batch_hotmask(const BatchParams& p, int64_t first, int64_t stride) {
     Ctrl* c = p.ctrl;
     if (!p.fr_hot || ld_acq(&c->bdone)) return;
     const int l = ld_acq(&c->blevel);
     if (ld_acq(&c->b_eact[l & 1]) <= p.args->pull_edges) return;  // a push level gathers nothing
     const int W = p.args->words;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; h < p.hot_count; h += stride) {
+    for (int64_t h = first; h < p.hot_count; h += stride) {
         const int v = p.hot_vid[h];
         const bool act = (unsigned)v < (unsigned)p.n && ((p.act_bits[v >> 5] >> (v & 31)) & 1u);
 #pragma unroll
@@ -464,9 +476,12 @@ __global__ void __launch_bounds__(kBlock) k_batch_hotmask(BatchParams p) {
     }
 }
 
-// Advances the level; stops the loop when nothing is active or a level overflowed.
-__global__ void k_batch_next(BatchParams p) {
-    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+__global__ void __launch_bounds__(kBlock) k_batch_hotmask(BatchParams p) {
+    batch_hotmask(p, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, (int64_t)gridDim.x * blockDim.x);
+}
+
+// Advances the level; stops the loop when nothing is active or a level overflowed (one lane).
+__device__ __forceinline__ void batch_next(const BatchParams& p) {
     Ctrl* c = p.ctrl;
     if (c->bdone) return;
     const int l = c->blevel + 1;
@@ -480,6 +495,37 @@ __global__ void k_batch_next(BatchParams p) {
         c->levels = l + 1;
     }
     if (na == 0 || c->batch_overflow || c->error) c->bdone = 1;
+}
+
+__global__ void k_batch_next(BatchParams p) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) batch_next(p);
+}
+
+// The levels that the replays enqueued before it left, on one workgroup: expansion, the
+// update tiles in index order, the level step and the hot masks, with a workgroup barrier
+// between them.  Returns at once when the search has already stopped.  It needs no other
+// workgroup to be resident, and it ends: every level either activates a vertex at a new
+// depth, which stops at 255, or stops the loop.
+template <int BVT, int UV>
+__global__ void __launch_bounds__(kBlock) k_batch_finish(BatchParams p) {
+    __shared__ union {
+        ExpLds<BVT> e;
+        UpdLds<UV> u;
+    } lds;
+    Ctrl* c = p.ctrl;
+    for (;;) {
+        __syncthreads();
+        if (ld_acq(&c->bdone)) return;
+        batch_expand<BVT>(p, 0, 1, lds.e);
+        for (int t = 0; t < p.utiles; ++t) {
+            __syncthreads();
+            batch_update_tile<BVT, UV>(p, t, p.utiles, lds.u);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) batch_next(p);
+        __syncthreads();
+        batch_hotmask(p, threadIdx.x, kBlock);
+    }
 }
 
 // ---- host launchers ----------------------------------------------------------------------------
@@ -557,6 +603,22 @@ hipError_t launch_batch_start(const BatchParams& p, hipStream_t s) {
     launch_update(p, s);
     hipLaunchKernelGGL(k_batch_next, dim3(1), dim3(64), 0, s, p);
     if (p.fr_hot) hipLaunchKernelGGL(k_batch_hotmask, dim3(bfill_grid(p.hot_count)), dim3(kBlock), 0, s, p);
+    return hipGetLastError();
+}
+
+template <int BVT>
+static void launch_finish_b(const BatchParams& p, hipStream_t s) {
+    if (p.uv == 2) hipLaunchKernelGGL((k_batch_finish<BVT, 2>), dim3(1), dim3(kBlock), 0, s, p);
+    else if (p.uv == 8) hipLaunchKernelGGL((k_batch_finish<BVT, 8>), dim3(1), dim3(kBlock), 0, s, p);
+    else hipLaunchKernelGGL((k_batch_finish<BVT, 4>), dim3(1), dim3(kBlock), 0, s, p);
+}
+
+// Whatever levels remain after the replays, on one workgroup (a no-op once the loop stopped).
+hipError_t launch_batch_finish(const BatchParams& p, hipStream_t s) {
+    if (!tiling_ok(p)) return hipErrorInvalidValue;
+    if (p.bvt == 1) launch_finish_b<1>(p, s);
+    else if (p.bvt == 4) launch_finish_b<4>(p, s);
+    else launch_finish_b<2>(p, s);
     return hipGetLastError();
 }
 

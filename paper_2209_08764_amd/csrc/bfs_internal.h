@@ -241,6 +241,7 @@ hipError_t launch_prim_compact(const int32_t* offsets, int32_t n, const int32_t*
 hipError_t launch_batch_setup(const BatchParams& p, int grid, hipStream_t s);
 hipError_t launch_batch_start(const BatchParams& p, hipStream_t s);
 hipError_t launch_batch_level(const BatchParams& p, int grid, hipStream_t s);
+hipError_t launch_batch_finish(const BatchParams& p, hipStream_t s);
 int batch_grid_capacity(int device, int bvt);
 
 // bfs_sort.hip: every row of the CSR sorted ascending into cols_out (synchronous on s)

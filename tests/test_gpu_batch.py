@@ -74,6 +74,7 @@ def test_overflow_on_long_paths():
     ws = Workspace(G, max_sources=4)
     with pytest.raises(BFSError) as e:
         ws.run_batch([0, 10])
+        ws.sync()                       # the run does not wait: bfs_sync reports the overflow
     assert e.value.status == _lib.BFS_EOVERFLOW
     # sources whose eccentricity fits are fine
     _check(ws, path, [150, 140])
@@ -140,3 +141,53 @@ def test_hot_numbered_graph_pull_levels(pull, k):
     ws = Workspace(G, max_sources=256, batch_pull=pull, batch_levels=3)
     _check(ws, g, gg.pick_sources(g, k, seed=pull + k))
     _check(ws, g, gg.pick_sources(g, k, seed=pull + k + 1))   # masks left by the previous batch
+
+
+@pytest.mark.parametrize("replays", [0, 1, 2])
+@pytest.mark.parametrize("levels", [1, 3])
+def test_levels_left_by_the_replays_finish_on_one_workgroup(replays, levels):
+    # fewer replays than levels: the one-workgroup finish runs the rest (all of them with
+    # none), push and pull levels, hot masks and ragged update tiles included
+    parts = [gg.rmat(11, seed=8), gg.grid(45, 23), gg.powerlaw_forest(1500, seed=6)]
+    g, _ = gg.disjoint_union(parts)
+    for hot in (False, True):
+        G = Graph(g.offsets, g.cols, hot=hot)
+        for pull in (-1, 0, 2000):
+            ws = Workspace(G, max_sources=256, batch_levels=levels, batch_replays=replays, batch_pull=pull)
+            _check(ws, g, gg.pick_sources(g, 129, seed=replays + 10 * levels))
+            assert ws.stats()["levels"] > replays * levels
+
+
+def test_overflow_found_by_the_finish():
+    n = 300
+    path = gg.from_edges(n, [(i, i + 1) for i in range(n - 1)])
+    ws = Workspace(Graph(path.offsets, path.cols), max_sources=4, batch_replays=1)
+    with pytest.raises(BFSError) as e:
+        ws.run_batch([0, 10])
+        ws.sync()
+    assert e.value.status == _lib.BFS_EOVERFLOW
+    _check(ws, path, [150, 140])
+
+
+def test_batched_run_returns_before_the_device_finishes():
+    # R-MAT 20 with 256 sources takes milliseconds on the device; the call only enqueues
+    g = gg.rmat(20, seed=77)
+    G = Graph(g.offsets, g.cols)
+    ws = Workspace(G, max_sources=256)
+    srcs = gg.pick_sources(g, 256, seed=4)
+    level = torch.empty(g.n * 256, dtype=torch.uint8, device="cuda")
+    ws.run_batch(srcs, level)
+    ws.sync()                           # learns the depth, so the next run enqueues no extra replay
+    pending = []
+    for _ in range(3):
+        ws.run_batch(srcs, level)
+        ev = torch.cuda.Event()
+        ev.record()
+        pending.append(not ev.query())  # the device is still searching when the call returns
+        ws.sync()
+    assert all(pending)
+    got = level.cpu().numpy().reshape(g.n, 256)
+    for j in (0, 101, 255):
+        want = oracle.bfs_levels(g.offsets, g.cols, int(srcs[j]))
+        want8 = np.where(want < 0, 255, want).astype(np.uint8)
+        assert np.array_equal(got[:, j], want8)
