@@ -274,6 +274,28 @@ def traffic_from(paths, workload: str = "rmat24", kernel: str = "k_persistent<fa
     return out
 
 
+def counter_summary(kernel: str, paths):
+    """Per-dispatch averages of the counters collected for `kernel` (a substring of its name)."""
+    import sqlite3
+    out = {"kernel": kernel}
+    for path in paths:
+        con = sqlite3.connect(path)
+        for name, val, cnt in con.execute("select counter_name, avg(value), count(*) from counters_collection "
+                                          "where kernel_name like ? group by counter_name", (f"%{kernel}%",)):
+            out[name] = {"avg_per_dispatch": round(float(val), 1), "dispatches": int(cnt)}
+    print(json.dumps(out))
+    return out
+
+
+def ws_options(pairs):
+    """NAME=VALUE pairs of --ws-opt as Workspace keyword options."""
+    out = {}
+    for pair in pairs:
+        name, _, value = pair.partition("=")
+        out[name.strip()] = int(value)
+    return out
+
+
 def profile_c4(args):
     """The batched workload alone, for counter runs: R-MAT scale 22, 256 sources, the tuned
     launch shape from the package's tuning cache, `--steps` batches."""
@@ -766,7 +788,8 @@ def run(args):
     g, sources = W.c3_rmat24(scale=args.scale, nsrc=64)
     log(f"  n={g.n} m={g.m} in {time.perf_counter() - t:.1f} s")
     G = Graph(g.offsets, g.cols)
-    ws = Workspace(G, profile=1)
+    ablation = ws_options(args.ws_opt)
+    ws = Workspace(G, profile=1, **ablation)
     n = g.n
     level = torch.empty(n, dtype=torch.int32, device="cuda")
     parent = torch.empty(n, dtype=torch.int32, device="cuda")
@@ -795,7 +818,8 @@ def run(args):
     kt = float(np.mean(kms)) if len(kms) else float("nan")
     achieved = kb / (kt * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": stored_traffic("rmat24"),
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None if ablation else stored_traffic("rmat24"),
                 "traffic_source": "stored rocprofv3 FETCH_SIZE + WRITE_SIZE runs of this kernel code "
                                   "(profiles/traffic_persistent_rmat24.json, keyed by source hash; "
                                   "null once the code changes)",
@@ -925,7 +949,8 @@ def run(args):
                    "edgefactor": 16, "abcd": [0.57, 0.19, 0.19, 0.05], "symmetrised": True, "permuted": True,
                    "sources": len(sources), "sources_timed_per_step": len(sources),
                    "step": "one pass over all sources, one search at a time", "mode": "auto",
-                   "hot_vertex_filter": True, "gteps_edges": "undirected edges in the component"},
+                   "hot_vertex_filter": True, "gteps_edges": "undirected edges in the component",
+                   **({"ablation_workspace_options": ablation} if ablation else {})},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "extras": extras,
@@ -950,12 +975,20 @@ def main():
     ap.add_argument("--rocpd-summary", nargs="+", metavar="DB", help="summarise rocprofv3 result databases and exit")
     ap.add_argument("--rocpd-dispatches", nargs=4, metavar=("KERNEL", "SKIP", "TAKE", "DB"),
                     help="duration statistics of dispatches [SKIP, SKIP+TAKE) of KERNEL in start order, and exit")
+    ap.add_argument("--ws-opt", action="append", default=[], metavar="NAME=VALUE",
+                    help="workspace option of the headline run (an ablation: e.g. dense_edges=0); repeatable")
+    ap.add_argument("--counter-summary", nargs="+", metavar=("KERNEL", "DB"),
+                    help="per-dispatch averages of every counter of KERNEL in rocprofv3 counter databases, "
+                         "and exit")
     ap.add_argument("--traffic-from", nargs=4, metavar="DB",
                     help="FETCH_SIZE and WRITE_SIZE databases of the bench run, then of --calib-copy: write the "
                          "search kernel's HBM traffic per launch to profiles/ and exit")
     args = ap.parse_args()
     if args.traffic_from:
         traffic_from(args.traffic_from)
+        return
+    if args.counter_summary:
+        counter_summary(args.counter_summary[0], args.counter_summary[1:])
         return
     if args.rocpd_dispatches:
         k, skip, take, db = args.rocpd_dispatches
