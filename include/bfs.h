@@ -96,8 +96,9 @@ typedef struct bfs_workspace_s* bfs_workspace_t;  /* scratch for one in-flight r
 #define BFS_OPT_GROUP      14  /* workgroups of that group (1..64, at most the grid; 0 = default 32) */
 #define BFS_OPT_BATCH_REPLAYS 15 /* batched search: replays of the captured level loop each run
                                     enqueues before the one-workgroup finish (-1 = enough for the
-                                    most levels a completed batched run of this workspace needed,
-                                    32 before the first, default; 0..256 = exactly that many) */
+                                    most levels a completed batched run of this workspace, or of any
+                                    workspace on its graph, needed, 32 before the first, default;
+                                    0..256 = exactly that many) */
 #define BFS_OPT_SPLIT      13  /* how each level's equal shares find their start points
                                   (Analysis, Find-StartExpPoint): 0 = every frontier vertex
                                   writes itself as the start of the shares beginning inside its

@@ -96,6 +96,7 @@ struct bfs_graph_s {
     int32_t hot_count = 0;      // hot vertices
     int32_t hot_words = 0;      // words of a workspace's hot-bit arrays (0: no filter)
     uint64_t uid = 0;           // distinct for every graph made resident in this process
+    std::atomic<int32_t> batch_depth{0};  // most levels a completed batched run on it needed
 };
 
 struct bfs_workspace_s {
@@ -1187,8 +1188,13 @@ bfs_status_t bfs_sync(bfs_workspace_t ws) {
     HIP_TRY(hipEventSynchronize(ws->ev_done));
     if (ws->host_status != BFS_OK) return ws->host_status;
     HIP_TRY(hipMemcpy(ws->h_ctrl, ws->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
-    if (ws->last_batch && !ws->h_ctrl->error && !ws->h_ctrl->batch_overflow)
-        ws->b_seen = std::max(ws->b_seen, (int32_t)ws->h_ctrl->levels);
+    if (ws->last_batch && !ws->h_ctrl->error && !ws->h_ctrl->batch_overflow) {
+        const int32_t lv = ws->h_ctrl->levels;
+        ws->b_seen = std::max(ws->b_seen, lv);
+        int32_t d = ws->g->batch_depth.load(std::memory_order_relaxed);
+        while (d < lv && !ws->g->batch_depth.compare_exchange_weak(d, lv, std::memory_order_relaxed)) {
+        }
+    }
     if (ws->h_ctrl->error)
         return fail(BFS_EDEVICE, "device-side failure (code %d: %s)", ws->h_ctrl->error,
                     ws->h_ctrl->error == -9 ? "malformed frontier" : "a wait timed out");
@@ -1364,11 +1370,13 @@ bfs_status_t bfs_run_batch(bfs_workspace_t ws, const int32_t* sources, int32_t k
         HIP_TRY(hipEventRecord(pe->first, s));
     }
     HIP_TRY(launch_batch_start(bp, s));
-    // Replays of the captured levels, as many as the deepest completed run of this workspace
-    // needed (32 levels before the first), then one workgroup that finishes whatever levels
-    // are left: the call never waits for the device, and the search is complete in stream
-    // order.  Levels after the stop cost a replay's launches, not its work.
-    const int depth = ws->b_seen > 0 ? ws->b_seen : 32;
+    // Replays of the captured levels, as many as the deepest completed run of this workspace,
+    // or else of any workspace on the graph, needed (32 levels before the first), then one
+    // workgroup that finishes whatever levels are left: the call never waits for the device,
+    // and the search is complete in stream order.  Levels after the stop cost a replay's
+    // launches, not its work.
+    const int32_t seen = std::max(ws->b_seen, ws->g->batch_depth.load(std::memory_order_relaxed));
+    const int depth = seen > 0 ? seen : 32;
     const int replays = ws->batch_replays >= 0 ? ws->batch_replays
                                                : (depth + ws->batch_levels - 1) / ws->batch_levels;
     for (int r = 0; r < replays; ++r) HIP_TRY(hipGraphLaunch(ws->b_exec, s));
