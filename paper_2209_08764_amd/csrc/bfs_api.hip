@@ -1187,7 +1187,9 @@ bfs_status_t bfs_sync(bfs_workspace_t ws) {
     HIP_TRY(hipSetDevice(ws->device));
     HIP_TRY(hipEventSynchronize(ws->ev_done));
     if (ws->host_status != BFS_OK) return ws->host_status;
-    HIP_TRY(hipMemcpy(ws->h_ctrl, ws->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
+    // on the workspace's own non-blocking stream: waits for nothing else in flight on the device
+    HIP_TRY(hipMemcpyAsync(ws->h_ctrl, ws->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, ws->own_stream));
+    HIP_TRY(hipStreamSynchronize(ws->own_stream));
     if (ws->last_batch && !ws->h_ctrl->error && !ws->h_ctrl->batch_overflow) {
         const int32_t lv = ws->h_ctrl->levels;
         ws->b_seen = std::max(ws->b_seen, lv);

@@ -6,8 +6,12 @@ charged against a byte budget while they exist, and every in-flight run also
 charges its output array until it completes; idle workspaces of other graphs
 are evicted when a query needs room.  Queued queries for the same
 low-diameter graph are merged into one batched multi-source run (up to 256
-sources, uint8 levels, and no more than fit in a set share of the budget);
-other queries run single-source on their own stream.
+sources, uint8 levels, and no more than fit in a set share of the budget)
+when that is cheaper than running them one by one: the scheduler keeps the
+device time of single and batched runs per graph, and a batch of k needs
+k x (single time) >= (batch time), since a batch's passes over the graph cost
+nearly the same for 4 sources as for 256.  Other queries run single-source on
+their own stream.
 Queries that arrive while others are on the GPU are admitted as soon as a
 slot and memory free up, so their work overlaps on the device.
 
@@ -23,7 +27,6 @@ batching logic is testable without a GPU.
 from __future__ import annotations
 
 import collections
-import concurrent.futures
 import dataclasses
 import time
 from typing import Callable
@@ -79,6 +82,7 @@ class Scheduler:
         self.pending: collections.deque[Query] = collections.deque()
         self.done: list[Query] = []
         self.stats = collections.Counter()
+        self.cost: dict[tuple[str, bool], float] = {}  # device seconds per run, (graph, batched)
 
     # ---- memory ---------------------------------------------------------------------------
     @staticmethod
@@ -130,6 +134,19 @@ class Scheduler:
     def _release(self, name: str, kind: int, ws):
         self.pool[(name, kind)].append(ws)
 
+    def _learn(self, name: str, batched: bool, seconds):
+        """Running mean (weight 1/4 for the newest) of a run's device time."""
+        if seconds is None or seconds <= 0:
+            return
+        key = (name, batched)
+        old = self.cost.get(key)
+        self.cost[key] = seconds if old is None else 0.75 * old + 0.25 * seconds
+
+    def _worth_batching(self, name: str, k: int) -> bool:
+        """A batch of k is cheaper than k single runs (unknown until both have been timed)."""
+        ts, tb = self.cost.get((name, False)), self.cost.get((name, True))
+        return ts is None or tb is None or k * ts >= tb
+
     # ---- scheduling -------------------------------------------------------------------------
     def _admit(self):
         skipped = collections.deque()
@@ -140,7 +157,7 @@ class Scheduler:
             cap = self._batch_cap(info) if info.batchable else 0
             if cap >= self.batch_min:
                 same = [p for p in self.pending if p.graph == q.graph][: cap - 1]
-                if len(same) + 1 >= self.batch_min:
+                if len(same) + 1 >= self.batch_min and self._worth_batching(q.graph, len(same) + 1):
                     group += same
             k = len(group)
             ws = self._acquire(q.graph, k)
@@ -201,6 +218,8 @@ class Scheduler:
             except Exception as exc:
                 self._fail(group, ws, kind, handle, exc, out)
                 continue
+            if hasattr(self.ex, "device_seconds"):
+                self._learn(name, kind > 1, self.ex.device_seconds(handle))
             self.used -= out
             self._release(name, kind, ws)
             if results is None:
@@ -286,7 +305,6 @@ class GpuExecutor:
         self.max_inflight = max_inflight
         self.streams = [torch.cuda.Stream() for _ in range(max_inflight)]
         self.free_streams = list(range(max_inflight))
-        self.pool = concurrent.futures.ThreadPoolExecutor(max_workers=max_inflight)
         self.grid = None
         for name, g in graphs.items():
             G = Graph(g.offsets, g.cols)
@@ -330,60 +348,49 @@ class GpuExecutor:
         torch = self.torch
         stream = self.streams[si]
         n = self.graphs[name].n
-        if len(sources) == 1:
-            level = torch.empty(n, dtype=torch.int32, device="cuda")
-            with torch.cuda.stream(stream):
-                ws.run(sources[0], level=level, stream=stream, want_parent=False)
-                ev = torch.cuda.Event()
-                ev.record(stream)
-            return ("single", si, ev, level, None)
-        out = torch.empty(n * len(sources), dtype=torch.uint8, device="cuda")
-
-        def work():
-            from . import BFSError, _lib
-            with torch.cuda.stream(stream):
-                try:
-                    ws.run_batch(sources, out, stream=stream)
-                except BFSError as e:
-                    if e.status != _lib.BFS_EOVERFLOW:
-                        raise
-                    return ("overflow", None)
-                ev = torch.cuda.Event()
-                ev.record(stream)
-            return ("ok", ev)
-
-        return ("batch", si, self.pool.submit(work), out, len(sources))
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        with torch.cuda.stream(stream):
+            t0.record(stream)
+            if len(sources) == 1:
+                out = torch.empty(n, dtype=torch.int32, device="cuda")
+                ws.run(sources[0], level=out, stream=stream, want_parent=False)
+            else:
+                out = torch.empty(n * len(sources), dtype=torch.uint8, device="cuda")
+                ws.run_batch(sources, out, stream=stream)   # returns at once; overflow shows at sync
+            t1.record(stream)
+        return (si, ws, t0, t1, out, len(sources))
 
     def abandon(self, h):
         """Give back the stream of a run whose launch or collection failed."""
-        si = h[1]
+        si = h[0]
         if si not in self.free_streams:
             self.free_streams.append(si)
 
     def ready(self, h):
-        kind, si, ev, out, k = h
-        if kind == "batch":
-            if not ev.done():
-                return False
-            status, ev = ev.result()
-            if status == "overflow":
-                return True
-        return ev.query()
+        return h[3].query()
+
+    def device_seconds(self, h):
+        """Device time of a completed run (its stream's events)."""
+        return h[2].elapsed_time(h[3]) * 1e-3
 
     def collect(self, h):
+        from . import BFSError, _lib
         torch = self.torch
-        kind, si, ev, out, k = h
+        si, ws, t0, t1, out, k = h
         self.abandon(h)
-        if kind == "single":
+        if k == 1:
+            # the levels are complete in stream order; a host synchronisation per query would
+            # also wait for whatever shares a hardware queue with the workspace's private stream
             return [out]
-        if ev.result()[0] == "overflow":
+        try:
+            ws.sync()            # a batch's overflow (and device-side failures) surface here
+        except BFSError as e:
+            if e.status != _lib.BFS_EOVERFLOW:
+                raise
             return None          # a level did not fit in a byte: the scheduler re-queues the sources
-        cols = out.view(-1, k)
-        res = []
-        for j in range(k):
-            c = cols[:, j].to(torch.int32)
-            res.append(torch.where(c == 255, torch.full_like(c, -1), c))
-        return res
+        lv = out.view(-1, k).to(torch.int32)
+        lv[lv == 255] = -1
+        return [lv[:, j] for j in range(k)]
 
     def idle(self, s):
         time.sleep(s)

@@ -205,3 +205,39 @@ def test_batches_use_free_budget_and_singles_evict_batches_first(graphs):
     for idle_batched, gone in events:
         if gone and gone[0][1] == 1:
             assert idle_batched == 0              # singles go only when no batched workspace is idle
+
+
+class TimedExecutor(FakeExecutor):
+    """Reports device time: a single run costs 1 unit, a batch 20 units whatever its size."""
+
+    unit = 1e-4
+
+    def launch(self, ws, name, sources):
+        g = self.graphs[name]
+        res = [oracle.bfs_levels(g.offsets, g.cols, s) for s in sources]
+        cost = self.unit * (20 if len(sources) > 1 else 1)
+        self.launched.append((name, len(sources)))
+        return (self.now + cost, res, cost)
+
+    def device_seconds(self, h):
+        return h[2]
+
+
+
+def test_batches_only_when_cheaper_than_single_runs(graphs):
+    ex = TimedExecutor({"a": graphs["a"]})
+    sch = Scheduler(ex, budget_bytes=10 ** 9, max_inflight=1, clock=ex.clock)
+    srcs = _nonisolated(graphs)["a"]
+    # a lone query (times a single run), a burst of 5 (no batch time yet: batched, and timed),
+    # another 5 (5 singles cost less than a batch), then 30 (a batch costs less)
+    waves = [(0.0, 1), (0.01, 5), (0.02, 5), (0.03, 30)]
+    qs = []
+    for t, count in waves:
+        for _ in range(count):
+            qs.append(Query(len(qs), "a", int(srcs[(7 * len(qs)) % len(srcs)]), t))
+    sch.run(qs)
+    for q in qs:
+        assert np.array_equal(q.result, oracle.bfs_levels(graphs["a"].offsets, graphs["a"].cols, q.source))
+    assert sch.cost[("a", False)] == pytest.approx(ex.unit)
+    assert sch.cost[("a", True)] == pytest.approx(20 * ex.unit)
+    assert [k for _, k in ex.launched] == [1, 5, 1, 1, 1, 1, 1, 30]
