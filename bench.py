@@ -446,7 +446,7 @@ class EnergyMeter:
 
 def energy_compare(torch, Graph, Workspace, graphs, seconds: float = 4.0) -> dict:
     """The paper's work-sensitivity claim on this GPU: energy per search of the work-sized level
-    loop (BFS_MODE_AUTO: P_l = min(P, W_l) workgroups, single-workgroup levels) against the
+    loop (BFS_MODE_AUTO: P_l = min(P, W_l) workgroups, group levels) against the
     work-insensitive variant (every workgroup active at every level), plus idle power."""
     from paper_2209_08764_amd import BFS_MODE_AUTO, BFS_MODE_INSENSITIVE
     try:

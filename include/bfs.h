@@ -59,7 +59,7 @@ typedef struct bfs_workspace_s* bfs_workspace_t;  /* scratch for one in-flight r
                                caller's arrays are not modified; 4 B per edge more) */
 
 /* Execution modes (bfs_workspace_set_option(ws, BFS_OPT_MODE, ...)). */
-#define BFS_MODE_AUTO        0  /* one persistent launch; single-workgroup levels while small */
+#define BFS_MODE_AUTO        0  /* one persistent launch; small levels on a group of workgroups */
 #define BFS_MODE_LEVEL       1  /* one launch pair per level, grid sized to the level's edges */
 #define BFS_MODE_PLAIN       2  /* plain per-level kernel: one thread per frontier vertex */
 #define BFS_MODE_INSENSITIVE 3  /* persistent, every workgroup active at every step */
@@ -110,7 +110,7 @@ typedef struct {
     int32_t levels;          /* frontiers processed: max level + 1 */
     int32_t mode;            /* BFS_MODE_* actually used */
     int32_t grid;            /* workgroups launched for the level loop */
-    int32_t small_levels;    /* levels run by a single workgroup */
+    int32_t small_levels;    /* levels run by the group of workgroups (small levels) */
     int64_t reached;         /* vertices with a level (sum of n_l) */
     int64_t edges;           /* adjacency entries scanned (sum of e_l) */
     double  kernel_ms;       /* main-kernel time if BFS_OPT_PROFILE, else -1 */
@@ -305,7 +305,7 @@ typedef struct {
 } bfs_tune_t;
 
 #define BFS_TUNE_BATCH  1u  /* tune the batched launch: grain, update tile, pull threshold, replay length */
-#define BFS_TUNE_SINGLE 2u  /* tune single-source runs: grid, single-workgroup, push and dense thresholds */
+#define BFS_TUNE_SINGLE 2u  /* tune single-source runs: grid, group-level, push and dense thresholds */
 
 /*
  * Times candidate settings on the workspace's own graph and keeps the

@@ -13,7 +13,7 @@ constexpr int kVT = 4;                    // edges per thread in one sub-tile
 constexpr int kGrain = kBlock * kVT;      // edges per sub-tile (the share granularity), 2048
 constexpr int kSlice = kGrain + 1;        // frontier entries a sub-tile can touch
 constexpr int kPre = (kSlice + kBlock - 1) / kBlock;  // slice entries each thread prefetches
-constexpr int kVTS = 8;                   // edges per thread per round, single-workgroup levels
+constexpr int kVTS = 8;                   // edges (or staged entries) per thread per round, group levels
 constexpr int kSmallN = 4096;             // frontier capacity of group levels (staged in LDS)
 constexpr int kGroupCap = 16384;          // most edges a group level scans (and entries it appends)
 constexpr int kGroupMax = 32;             // default workgroups of the group

@@ -25,9 +25,9 @@
 // persistent kernel runs all levels in one launch with grid barriers between
 // phases; only ceil(e_l / kGrain) workgroups have work in a phase
 // (P_l = min(P, W_l)), levels with few workgroups synchronise only those, and
-// while a level is small a single workgroup runs it alone out of LDS,
-// synchronising with __syncthreads only, so the rest of the grid idles: a
-// level occupies only as many cores as its work can use.
+// while a level is small a group of workgroups runs it out of LDS with one
+// barrier of its own per level, so the rest of the grid idles: a level
+// occupies only as many cores as its work can use.
 #include "bfs_device.h"
 
 #include <hip/hip_runtime.h>
@@ -1617,7 +1617,7 @@ k_persistent(Params p) {
     // compact_share (the roots do); edges of vertices reached so far, for the switch rule
     bool fbits_ok = true, bottom_up = false;
     // hot[l & 1] holds exactly the hot vertices visited up to level l: the expansion keeps
-    // it so once it is, but the roots and single-workgroup levels set no hot bits
+    // it so once it is, but the roots and group levels set no hot bits
     bool hot_ok = false;
     // top-down loop: fbits[x] holds bits a later writer must clear first
     bool fb_dirty[2] = {p.fb_pull != 0, false};
@@ -1712,7 +1712,7 @@ k_persistent(Params p) {
         for (int t = blockIdx.x * kBlock + threadIdx.x; t < max(P, Pd); t += G * kBlock) p.desc[par][t] = 0ull;
         // Frontier bits.  Direction mode: fbits[np] is zero when a level starts (its own
         // level cleared it after reading it), except right after a stretch of
-        // single-workgroup levels, which keep none; that level runs top-down, so nothing
+        // group levels, which keep none; that level runs top-down, so nothing
         // writes fbits[np] before its compaction and it can be cleared now.  Top-down
         // loop: the previous level's pulls were the last readers of fbits[np], and this
         // level's compaction is its first writer; a level that writes none leaves the buffer
@@ -1725,7 +1725,7 @@ k_persistent(Params p) {
             for (int w = blockIdx.x * kBlock + threadIdx.x; w < fwords; w += G * kBlock) p.aux->snap[w] = p.bitmap[w];
         if (fb_write) fb_dirty[np] = true;
         // A dense level drops a hot target only by its hot bits; where those miss visited
-        // vertices (the roots and single-workgroup levels set none), each such edge would
+        // vertices (the roots and group levels set none), each such edge would
         // set a visited bit again, which the snapshot then does not count as new, so the
         // bits are rebuilt here from the visited bitmap (exactly the vertices of levels <= l)
         if (dense && p.hot_words > 0 && !hot_ok) {
@@ -1784,7 +1784,7 @@ k_persistent(Params p) {
             }
         } else {
             // pulls test the frontier bits of level l (2 MiB for 2^24 vertices) instead of the
-            // level array when they are exact: not right after single-workgroup levels
+            // level array when they are exact: not right after group levels
             const uint32_t* fpull = (!DIR && p.fb_pull && fbits_ok) ? p.fbits[par] : nullptr;
             if (dense) {
                 if (blockIdx.x < Pd) [[clang::always_inline]] ok = dense_compact_share(p, l, blockIdx.x, Pd, lds, fpull);

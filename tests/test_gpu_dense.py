@@ -4,7 +4,7 @@ A pull level with at least BFS_OPT_DENSE_EDGES edges records its new
 vertices in the frontier bitmap instead of private queues and compacts them
 by vertex range.  These cases force that path on every eligible level
 (threshold 1), switch it off (0), and cross it with the parent rules,
-single-workgroup levels, grid sizes, multi-root runs, isolated vertices and
+group levels, grid sizes, multi-root runs, isolated vertices and
 level-only runs: levels and min-id parents stay bit-exact.
 """
 import numpy as np

@@ -40,7 +40,7 @@ def _noalloc(G, s, want_parent=True):
 
 def test_noalloc_matches_bfs_run_twice_second_smaller():
     big = gg.rmat(16, 16, seed=41)         # 2^16 vertices, ~1.8 M entries: several tiles per level
-    small = gg.grid(70, 33)                # high diameter: single-workgroup levels and a ragged tail
+    small = gg.grid(70, 33)                # high diameter: group levels and a ragged tail
     cases = [(big, int(gg.pick_sources(big, 1, seed=42)[0])), (small, 5)]
     # the larger graph with the hot-vertex filter, so its scratch holds the hot-bit arrays too
     graphs = [Graph(big.offsets, big.cols, hot=True), Graph(small.offsets, small.cols)]
