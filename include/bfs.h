@@ -93,7 +93,7 @@ typedef struct bfs_workspace_s* bfs_workspace_t;  /* scratch for one in-flight r
                                   has none to find) and scans at least this many edges records its
                                   new vertices as bits instead of private-queue entries and
                                   linearises them in vertex order (0 = never; default m / 12) */
-#define BFS_OPT_GROUP      14  /* workgroups of that group (1..64, at most the grid; 0 = default 32) */
+#define BFS_OPT_GROUP      14  /* workgroups of that group (1..64, at most the grid; 0 = default 48) */
 #define BFS_OPT_BATCH_REPLAYS 15 /* batched search: replays of the captured level loop each run
                                     enqueues before the one-workgroup finish (-1 = enough for the
                                     most levels a completed batched run of this workspace, or of any

@@ -16,7 +16,7 @@ constexpr int kPre = (kSlice + kBlock - 1) / kBlock;  // slice entries each thre
 constexpr int kVTS = 8;                   // edges (or staged entries) per thread per round, group levels
 constexpr int kSmallN = 4096;             // frontier capacity of group levels (staged in LDS)
 constexpr int kGroupCap = 16384;          // most edges a group level scans (and entries it appends)
-constexpr int kGroupMax = 32;             // default workgroups of the group
+constexpr int kGroupMax = 48;             // default workgroups of the group
 constexpr int kGroupLimit = 64;           // most workgroups a group may have
 constexpr int kStatCap = 1 << 16;         // per-level statistics kept
 constexpr int kDefaultSmallEdges = kGroupCap;
