@@ -776,8 +776,8 @@ def run(args):
     import graphgen as gg
     from graphgen import workloads as W
     from paper_2209_08764_amd import (BFS_MODE_AUTO, BFS_MODE_DIRECTION, BFS_MODE_INSENSITIVE, BFS_MODE_LEVEL,
-                                      BFS_MODE_PLAIN, BFS_OPT_MODE, BFS_OPT_PROFILE, BFS_OPT_SPLIT, Graph, Workspace,
-                                      _lib)
+                                      BFS_MODE_PLAIN, BFS_OPT_DENSE_EDGES, BFS_OPT_MODE, BFS_OPT_PROFILE, BFS_OPT_SPLIT,
+                                      Graph, Workspace, _lib)
 
     _lib.load()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
@@ -865,6 +865,16 @@ def run(args):
         extras["split_scatter_gteps_hm_same_sources"] = round(hm_gteps(step_ms[:, :16], mc_half[:16]), 3)
         ws.set(BFS_OPT_SPLIT, 0)
         log(f"split by binary search: {extras['split_search_gteps_hm']} GTEPS")
+        # the paper's private queues and Owner test on every level (no dense levels), same launch
+        ws.set(BFS_OPT_DENSE_EDGES, 0)
+        for s in sub[:2]:
+            ws.run(int(s), level, parent)
+        ws.sync()
+        sm, _, _ = time_passes(ws, level, parent, sub, 1, torch)
+        extras["queues_every_level_gteps_hm"] = round(hm_gteps(sm, mc_half[:16]), 3)
+        extras["queues_every_level_ms_median"] = round(float(np.median(sm)), 3)
+        ws.set(BFS_OPT_DENSE_EDGES, g.m // 12)   # the default threshold again
+        log(f"private queues and Owner test on every level: {extras['queues_every_level_gteps_hm']} GTEPS")
         # energy: work-sized against work-insensitive levels, on this graph and on the grid
         log("energy: work-sensitive vs work-insensitive (R-MAT 24, grid 4096^2)")
         gg2, _ = W.c2_grid4096()
