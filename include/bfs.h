@@ -166,9 +166,17 @@ int64_t bfs_graph_aux_bytes(bfs_graph_t g);
 size_t bfs_workspace_bytes(bfs_graph_t g, int32_t max_sources);
 
 /* Allocate a workspace (all scratch of one run).  One workspace serves one
-   run at a time; give each concurrent stream its own.  Errors: EINVAL,
-   ENOMEM, EHIP. */
+   run at a time; give each concurrent stream its own.  Its device memory is
+   one piece of bfs_workspace_bytes (plus alignment), taken from a memory pool
+   the library keeps per device where the device supports stream-ordered
+   allocation, on a stream of the workspace's own; creation queues the
+   clearing work there and returns without waiting for the device (runs on
+   any stream are ordered after it).  Errors: EINVAL, ENOMEM, EHIP. */
 bfs_status_t bfs_workspace_create(bfs_graph_t g, int32_t max_sources, bfs_workspace_t* out);
+/* Waits for the workspace's last run, then gives its memory back to the pool
+   in stream order, without waiting for other work on the device.  The pool
+   keeps up to 4 GiB of freed memory per device for later workspaces; the
+   workspace's stream and pinned host block are kept for reuse too. */
 bfs_status_t bfs_workspace_free(bfs_workspace_t ws);
 
 /* Workgroups of the persistent level loop that the device holds at once: the largest useful

@@ -104,6 +104,12 @@ struct bfs_workspace_s {
     int device = 0;
     int32_t max_sources = 1;
     int32_t max_tiles = 0;
+    // device memory: one arena, from the library's stream-ordered pool where the device has one
+    void* arena = nullptr;
+    size_t arena_bytes = 0, arena_used = 0;
+    bool arena_pooled = false;
+    int32_t* cand_grown = nullptr;  // a private-queue array that outgrew the arena's
+    bool cand_pooled = false;
     int64_t cand_cap = 0;   // entries of the private-queue array (grown when a run needs more)
     int32_t grid_cap = 0;
     // single-source buffers
@@ -158,10 +164,11 @@ struct bfs_workspace_s {
     hipGraphExec_t b_exec = nullptr;
     hipGraph_t b_graph = nullptr;
     BatchArgs* b_args = nullptr;         // per-run arguments the captured kernels read
-    BatchArgs* h_args = nullptr;         // pinned staging copy
     // host side
     Ctrl* h_ctrl = nullptr;  // pinned
     hipEvent_t ev_done = nullptr, ev0 = nullptr, ev1 = nullptr;
+    hipEvent_t ev_ready = nullptr;  // the set-up work queued on own_stream at creation
+    bool init_pending = false;      // runs on other streams still have to wait for it
     hipStream_t last_stream = nullptr;
     bool has_run = false;
     bool profiled = false;
@@ -188,6 +195,147 @@ struct bfs_workspace_s {
 };
 
 namespace {
+
+// ---- workspace memory ---------------------------------------------------------------------
+// A workspace's device arrays are slices of one arena.  Where the device supports
+// stream-ordered allocation the arena comes from a pool the library keeps per device and is
+// allocated and freed on the workspace's own stream, so creating or dropping a workspace waits
+// for nothing else in flight (a plain hipFree may wait for the whole device); freed arenas stay
+// in the pool, up to kPoolKeep bytes per device, for the next workspace.
+constexpr int kPoolDevices = 64;
+constexpr uint64_t kPoolKeep = uint64_t(4) << 30;
+constexpr size_t kSliceAlign = 256;
+
+struct ArenaPools {
+    std::mutex mu;
+    hipMemPool_t pool[kPoolDevices] = {};
+    bool tried[kPoolDevices] = {};
+};
+ArenaPools g_pools;
+
+hipMemPool_t arena_pool(int device) {
+    if (device < 0 || device >= kPoolDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_pools.mu);
+    if (!g_pools.tried[device]) {
+        g_pools.tried[device] = true;
+        int supported = 0;
+        if (hipDeviceGetAttribute(&supported, hipDeviceAttributeMemoryPoolsSupported, device) == hipSuccess &&
+            supported) {
+            hipMemPoolProps props;
+            std::memset(&props, 0, sizeof(props));
+            props.allocType = hipMemAllocationTypePinned;
+            props.handleTypes = hipMemHandleTypeNone;
+            props.location.type = hipMemLocationTypeDevice;
+            props.location.id = device;
+            hipMemPool_t pool = nullptr;
+            if (hipMemPoolCreate(&pool, &props) == hipSuccess) {
+                uint64_t keep = kPoolKeep;
+                (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+                g_pools.pool[device] = pool;
+            }
+        }
+    }
+    return g_pools.pool[device];
+}
+
+// Device memory of `bytes` on `stream`'s device: from the pool (*pooled = true), ready in stream
+// order on `stream` (work on other streams must be ordered after it: workspaces do so through
+// ev_ready), or, without a pool, from hipMalloc.
+hipError_t pool_alloc(int device, hipStream_t stream, size_t bytes, void** out, bool* pooled) {
+    *out = nullptr;
+    *pooled = false;
+    if (hipMemPool_t pool = arena_pool(device)) {
+        if (hipMallocFromPoolAsync(out, bytes, pool, stream) == hipSuccess) {
+            *pooled = true;
+            return hipSuccess;
+        }
+        *out = nullptr;
+    }
+    return hipMalloc(out, bytes);
+}
+
+void pool_free(void* ptr, bool pooled, hipStream_t stream) {
+    if (!ptr) return;
+    if (pooled) (void)hipFreeAsync(ptr, stream);
+    else (void)hipFree(ptr);
+}
+
+// The next aligned slice of the workspace's arena for `count` elements.
+template <typename T>
+hipError_t take(bfs_workspace_s* ws, T** p, size_t count) {
+    const size_t b = (std::max<size_t>(count, 1) * sizeof(T) + kSliceAlign - 1) / kSliceAlign * kSliceAlign;
+    *p = nullptr;
+    if (!ws->arena || ws->arena_used + b > ws->arena_bytes) return hipErrorOutOfMemory;
+    *p = reinterpret_cast<T*>(static_cast<unsigned char*>(ws->arena) + ws->arena_used);
+    ws->arena_used += b;
+    return hipSuccess;
+}
+
+// Pinned host copies of the control block: hipHostFree can wait for the whole device, so a
+// dropped workspace's block goes to a free list for the next workspace instead.
+struct PinnedCtrl {
+    std::mutex mu;
+    std::vector<Ctrl*> free;
+};
+PinnedCtrl g_pinned;
+
+hipError_t pinned_ctrl_take(Ctrl** p) {
+    {
+        std::lock_guard<std::mutex> lk(g_pinned.mu);
+        if (!g_pinned.free.empty()) {
+            *p = g_pinned.free.back();
+            g_pinned.free.pop_back();
+            return hipSuccess;
+        }
+    }
+    return hipHostMalloc(reinterpret_cast<void**>(p), sizeof(Ctrl), hipHostMallocDefault);
+}
+
+void pinned_ctrl_give(Ctrl* p) {
+    if (!p) return;
+    std::lock_guard<std::mutex> lk(g_pinned.mu);
+    g_pinned.free.push_back(p);
+}
+
+// Workspace streams are kept too: destroying one waits for the work queued on it (the arena's
+// stream-ordered free among it), which can sit behind other streams' kernels on a shared
+// hardware queue.  A dropped workspace's stream serves the next workspace on its device.
+struct StreamPool {
+    std::mutex mu;
+    std::vector<hipStream_t> free[kPoolDevices];
+};
+StreamPool g_streams;
+
+hipError_t stream_take(int device, hipStream_t* s) {
+    if (device >= 0 && device < kPoolDevices) {
+        std::lock_guard<std::mutex> lk(g_streams.mu);
+        auto& f = g_streams.free[device];
+        if (!f.empty()) {
+            *s = f.back();
+            f.pop_back();
+            return hipSuccess;
+        }
+    }
+    return hipStreamCreateWithFlags(s, hipStreamNonBlocking);
+}
+
+void stream_give(int device, hipStream_t s) {
+    if (!s) return;
+    if (device < 0 || device >= kPoolDevices) {
+        (void)hipStreamDestroy(s);
+        return;
+    }
+    std::lock_guard<std::mutex> lk(g_streams.mu);
+    g_streams.free[device].push_back(s);
+}
+
+// Orders a run on stream s after the workspace's set-up (queued on its own stream at creation).
+bfs_status_t wait_ready(bfs_workspace_s* ws, hipStream_t s) {
+    if (!ws->init_pending) return BFS_OK;
+    HIP_TRY(hipStreamWaitEvent(s, ws->ev_ready, 0));
+    if (hipEventQuery(ws->ev_ready) == hipSuccess) ws->init_pending = false;
+    return BFS_OK;
+}
 
 bfs_status_t validate_csr(const int32_t* off, const int32_t* cols, int32_t n, int64_t m) {
     if (off[0] != 0) return fail(BFS_EBADCSR, "offsets[0] = %d, expected 0", off[0]);
@@ -228,17 +376,19 @@ int64_t ws_cand_need(const bfs_workspace_s* ws, int64_t nroots, bool parents) {
 bfs_status_t ensure_cand(bfs_workspace_s* ws, int64_t need) {
     if (need <= ws->cand_cap) return BFS_OK;
     if (ws->has_run) HIP_TRY(hipEventSynchronize(ws->ev_done));
-    int32_t* grown = nullptr;
-    if (dalloc(&grown, (size_t)need) != hipSuccess)
+    void* grown = nullptr;
+    bool pooled = false;
+    if (pool_alloc(ws->device, ws->own_stream, sizeof(int32_t) * (size_t)need, &grown, &pooled) != hipSuccess)
         return fail(BFS_ENOMEM, "growing the private queues to %lld entries failed", (long long)need);
     hipError_t e = hipMemsetAsync(grown, 0, sizeof(int32_t) * (size_t)need, ws->own_stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ws->own_stream);
     if (e != hipSuccess) {
-        (void)hipFree(grown);
+        pool_free(grown, pooled, ws->own_stream);
         return fail(BFS_EHIP, "clearing the private queues: %s", hipGetErrorString(e));
     }
-    (void)hipFree(ws->cand);
-    ws->cand = grown;
+    pool_free(ws->cand_grown, ws->cand_pooled, ws->own_stream);  // the arena's slice just goes unused
+    ws->cand_grown = ws->cand = static_cast<int32_t*>(grown);
+    ws->cand_pooled = pooled;
     ws->cand_cap = need;
     return BFS_OK;
 }
@@ -413,6 +563,7 @@ bfs_status_t run_common(bfs_workspace_s* ws, const int32_t* roots_host, int32_t 
     if (st) return st;
     HIP_TRY(hipSetDevice(ws->device));
     if (roots_host && (k < 1 || k > ws->g->n)) return fail(BFS_EINVAL, "need 1 <= k <= n roots");
+    if ((st = wait_ready(ws, s))) return st;
     st = ensure_cand(ws, ws_cand_need(ws, roots_host ? k : 1, parent != nullptr));
     if (st) return st;
     Params p = make_params(ws, level, parent);
@@ -555,9 +706,8 @@ bfs_status_t setup_batch(bfs_workspace_s* ws) {
     ws->b_grid_cap = batch_grid_capacity(ws->device, ws->b_bvt);
     if (ws->b_grid_cap <= 0) return fail(BFS_EHIP, "could not size the batched grid");
     ws->b_utiles = (int32_t)(((int64_t)ws->g->n + (int64_t)kBlock * ws->b_uv - 1) / ((int64_t)kBlock * ws->b_uv));
-    *ws->h_args = BatchArgs{nullptr, 0, 0, batch_pull_edges(ws), 0};
     const BatchParams bp = make_batch_params(ws);
-    HIP_TRY(hipMemcpyAsync(ws->b_args, ws->h_args, sizeof(BatchArgs), hipMemcpyHostToDevice, os));
+    HIP_TRY(launch_batch_args(ws->b_args, BatchArgs{nullptr, 0, 0, batch_pull_edges(ws), 0}, os));
     HIP_TRY(launch_batch_setup(bp, ws->b_grid_cap, os));
     HIP_TRY(hipStreamSynchronize(os));
     return capture_batch(ws);
@@ -896,22 +1046,16 @@ bfs_status_t bfs_workspace_free(bfs_workspace_t ws) {
     if (!ws) return fail(BFS_EINVAL, "null workspace");
     (void)hipSetDevice(ws->device);
     if (ws->has_run) (void)hipEventSynchronize(ws->ev_done);
-    void* ptrs[] = {ws->bitmap, ws->hot[0], ws->hot[1], ws->fbits[0], ws->fbits[1], ws->snap, ws->owner, ws->f_rs[0], ws->f_rs[1], ws->f_ex[0], ws->f_ex[1], ws->f_v[0],
-                    ws->f_v[1], ws->tstart[0],
-                    ws->tstart[1], ws->cand, ws->cnt, ws->desc[0], ws->desc[1], ws->ctrl, ws->xbar, ws->aux, ws->stat_nl,
-                    ws->stat_el, ws->stat_ts, ws->roots, ws->plain_fv[0], ws->plain_fv[1], ws->b_fr, ws->b_nx, ws->b_vis,
-                    ws->b_act[0], ws->b_act[1], ws->b_act_ex[0], ws->b_act_ex[1], ws->b_tstart[0],
-                    ws->b_tstart[1], ws->b_desc[0], ws->b_desc[1], ws->b_act_bits, ws->b_fr_hot, ws->b_sources,
-                    ws->b_act_rs[0], ws->b_act_rs[1], ws->b_nz_v, ws->b_nz_ts, ws->gv[0], ws->gv[1], ws->grs[0],
-                    ws->grs[1], ws->gd[0], ws->gd[1]};
     if (ws->b_exec) (void)hipGraphExecDestroy(ws->b_exec);
     if (ws->b_graph) (void)hipGraphDestroy(ws->b_graph);
-    if (ws->b_args) (void)hipFree(ws->b_args);
-    if (ws->h_args) (void)hipHostFree(ws->h_args);
-    if (ws->own_stream) (void)hipStreamDestroy(ws->own_stream);
-    for (void* q : ptrs)
+    for (void* q : {static_cast<void*>(ws->plain_fv[0]), static_cast<void*>(ws->plain_fv[1])})
         if (q) (void)hipFree(q);
-    if (ws->h_ctrl) (void)hipHostFree(ws->h_ctrl);
+    // the arena (and a grown queue array) go back on the workspace's own stream, behind its last use
+    pool_free(ws->cand_grown, ws->cand_pooled, ws->own_stream);
+    pool_free(ws->arena, ws->arena_pooled, ws->own_stream);
+    stream_give(ws->device, ws->own_stream);
+    pinned_ctrl_give(ws->h_ctrl);
+    if (ws->ev_ready) (void)hipEventDestroy(ws->ev_ready);
     if (ws->ev_done) (void)hipEventDestroy(ws->ev_done);
     if (ws->ev0) (void)hipEventDestroy(ws->ev0);
     if (ws->ev1) (void)hipEventDestroy(ws->ev1);
@@ -936,60 +1080,69 @@ bfs_status_t bfs_workspace_create(bfs_graph_t g, int32_t max_sources, bfs_worksp
     const size_t n = (size_t)g->n;
     const int64_t T = tiles_for(g);
     ws->max_tiles = (int32_t)T;
-    bool okk = true;
-    auto A = [&](hipError_t e) { okk = okk && e == hipSuccess; };
-    A(dalloc(&ws->bitmap, (n + 31) / 32));
-    A(dalloc(&ws->fbits[0], (n + 31) / 32));
-    A(dalloc(&ws->fbits[1], (n + 31) / 32));
-    A(dalloc(&ws->snap, (n + 31) / 32));
-    if (g->colx) {
-        A(dalloc(&ws->hot[0], (size_t)g->hot_words));
-        A(dalloc(&ws->hot[1], (size_t)g->hot_words));
+    // everything is set up on the workspace's own stream (no device-wide synchronisation)
+    if (stream_take(ws->device, &ws->own_stream) != hipSuccess) {
+        bfs_workspace_free(ws);
+        return fail(BFS_EHIP, "could not create the workspace stream");
     }
-    A(dalloc(&ws->owner, n));
+    // one arena: the bytes bfs_workspace_bytes counts, plus each slice's alignment
+    const size_t want = bfs_workspace_bytes(g, max_sources) + 64 * kSliceAlign;
+    bool okk = pool_alloc(ws->device, ws->own_stream, want, &ws->arena, &ws->arena_pooled) == hipSuccess;
+    if (okk) ws->arena_bytes = want;
+    auto A = [&](hipError_t e) { okk = okk && e == hipSuccess; };
+    A(take(ws, &ws->bitmap, (n + 31) / 32));
+    A(take(ws, &ws->fbits[0], (n + 31) / 32));
+    A(take(ws, &ws->fbits[1], (n + 31) / 32));
+    A(take(ws, &ws->snap, (n + 31) / 32));
+    if (g->colx) {
+        A(take(ws, &ws->hot[0], (size_t)g->hot_words));
+        A(take(ws, &ws->hot[1], (size_t)g->hot_words));
+    }
+    A(take(ws, &ws->owner, n));
     for (int i = 0; i < 2; ++i) {
-        A(dalloc(&ws->f_rs[i], n + 2));
-        A(dalloc(&ws->f_ex[i], n + 2));
-        A(dalloc(&ws->f_v[i], n + 2));
-        A(dalloc(&ws->tstart[i], (size_t)T));
-        A(dalloc(&ws->desc[i], (size_t)T));
-        A(dalloc(&ws->gv[i], (size_t)kGroupCap));
-        A(dalloc(&ws->grs[i], (size_t)kGroupCap));
-        A(dalloc(&ws->gd[i], (size_t)kGroupCap));
+        A(take(ws, &ws->f_rs[i], n + 2));
+        A(take(ws, &ws->f_ex[i], n + 2));
+        A(take(ws, &ws->f_v[i], n + 2));
+        A(take(ws, &ws->tstart[i], (size_t)T));
+        A(take(ws, &ws->desc[i], (size_t)T));
+        A(take(ws, &ws->gv[i], (size_t)kGroupCap));
+        A(take(ws, &ws->grs[i], (size_t)kGroupCap));
+        A(take(ws, &ws->gd[i], (size_t)kGroupCap));
     }
     ws->cand_cap = default_cand(g->m, g->n);
-    A(dalloc(&ws->cand, (size_t)ws->cand_cap));
-    A(dalloc(&ws->cnt, 2 * (size_t)T));    // queue lengths, then bottom-up edge totals
-    A(dalloc(&ws->ctrl, 1));
-    A(dalloc(&ws->xbar, 1));
-    A(dalloc(&ws->aux, 1));
-    A(dalloc(&ws->stat_nl, kStatCap));
-    A(dalloc(&ws->stat_el, kStatCap));
-    A(dalloc(&ws->stat_ts, 3 * (size_t)kStatCap));
-    A(dalloc(&ws->roots, n));
+    A(take(ws, &ws->cand, (size_t)ws->cand_cap));
+    A(take(ws, &ws->cnt, 2 * (size_t)T));    // queue lengths, then bottom-up edge totals
+    A(take(ws, &ws->ctrl, 1));
+    A(take(ws, &ws->xbar, 1));
+    A(take(ws, &ws->aux, 1));
+    A(take(ws, &ws->stat_nl, kStatCap));
+    A(take(ws, &ws->stat_el, kStatCap));
+    A(take(ws, &ws->stat_ts, 3 * (size_t)kStatCap));
+    A(take(ws, &ws->roots, n));
     if (max_sources > 1) {
         ws->b_max_tiles = (int32_t)batch_max_tiles(g);
         ws->b_desc_cap = (int32_t)batch_desc_cap(g);
-        A(dalloc(&ws->b_fr, n * 4));
-        A(dalloc(&ws->b_nx, n * 4));
-        A(dalloc(&ws->b_vis, n * 4));
+        A(take(ws, &ws->b_fr, n * 4));
+        A(take(ws, &ws->b_nx, n * 4));
+        A(take(ws, &ws->b_vis, n * 4));
         for (int i = 0; i < 2; ++i) {
-            A(dalloc(&ws->b_act[i], n + 2));
-            A(dalloc(&ws->b_act_rs[i], n + 2));
-            A(dalloc(&ws->b_act_ex[i], n + 2));
-            A(dalloc(&ws->b_tstart[i], (size_t)ws->b_max_tiles));
-            A(dalloc(&ws->b_desc[i], (size_t)ws->b_desc_cap));
+            A(take(ws, &ws->b_act[i], n + 2));
+            A(take(ws, &ws->b_act_rs[i], n + 2));
+            A(take(ws, &ws->b_act_ex[i], n + 2));
+            A(take(ws, &ws->b_tstart[i], (size_t)ws->b_max_tiles));
+            A(take(ws, &ws->b_desc[i], (size_t)ws->b_desc_cap));
         }
-        A(dalloc(&ws->b_act_bits, (n + 31) / 32 + 1));
-        if (g->colx) A(dalloc(&ws->b_fr_hot, (size_t)g->hot_count * 4));
-        A(dalloc(&ws->b_nz_v, n + 1));
-        A(dalloc(&ws->b_nz_ts, (size_t)ws->b_max_tiles));
-        A(dalloc(&ws->b_sources, 256));
+        A(take(ws, &ws->b_act_bits, (n + 31) / 32 + 1));
+        if (g->colx) A(take(ws, &ws->b_fr_hot, (size_t)g->hot_count * 4));
+        A(take(ws, &ws->b_nz_v, n + 1));
+        A(take(ws, &ws->b_nz_ts, (size_t)ws->b_max_tiles));
+        A(take(ws, &ws->b_sources, 256));
+        A(take(ws, &ws->b_args, 1));
     }
-    if (okk && hipHostMalloc(reinterpret_cast<void**>(&ws->h_ctrl), sizeof(Ctrl), hipHostMallocDefault) != hipSuccess)
-        okk = false;
+    if (okk && pinned_ctrl_take(&ws->h_ctrl) != hipSuccess) okk = false;
     if (okk && (hipEventCreate(&ws->ev_done) != hipSuccess || hipEventCreate(&ws->ev0) != hipSuccess ||
-                hipEventCreate(&ws->ev1) != hipSuccess))
+                hipEventCreate(&ws->ev1) != hipSuccess ||
+                hipEventCreateWithFlags(&ws->ev_ready, hipEventDisableTiming) != hipSuccess))
         okk = false;
     if (!okk) {
         bfs_workspace_free(ws);
@@ -1000,12 +1153,7 @@ bfs_status_t bfs_workspace_create(bfs_graph_t g, int32_t max_sources, bfs_worksp
         bfs_workspace_free(ws);
         return fail(BFS_EHIP, "could not size the persistent grid");
     }
-    // defined contents everywhere, so no stale or never-written entry can hold an out-of-range
-    // index; everything is set up on the workspace's own stream (no device-wide synchronisation)
-    if (hipStreamCreateWithFlags(&ws->own_stream, hipStreamNonBlocking) != hipSuccess) {
-        bfs_workspace_free(ws);
-        return fail(BFS_EHIP, "could not create the workspace stream");
-    }
+    // defined contents everywhere, so no stale or never-written entry can hold an out-of-range index
     hipStream_t os = ws->own_stream;
     bool zok = hipMemsetAsync(ws->cnt, 0, sizeof(int32_t) * 2 * (size_t)T, os) == hipSuccess &&
                hipMemsetAsync(ws->cand, 0, sizeof(int32_t) * (size_t)ws->cand_cap, os) == hipSuccess &&
@@ -1016,16 +1164,15 @@ bfs_status_t bfs_workspace_create(bfs_graph_t g, int32_t max_sources, bfs_worksp
               hipMemsetAsync(ws->f_ex[i], 0, sizeof(int32_t) * (n + 2), os) == hipSuccess &&
               hipMemsetAsync(ws->f_v[i], 0, sizeof(int32_t) * (n + 2), os) == hipSuccess &&
               hipMemsetAsync(ws->desc[i], 0, sizeof(unsigned long long) * (size_t)T, os) == hipSuccess;
-    if (!zok || hipMemsetAsync(ws->ctrl, 0, sizeof(Ctrl), os) != hipSuccess || hipStreamSynchronize(os) != hipSuccess) {
+    // the clears stay queued on the workspace's stream: a synchronisation here would also wait
+    // for whatever shares its hardware queue; runs on other streams wait for ev_ready instead
+    if (!zok || hipMemsetAsync(ws->ctrl, 0, sizeof(Ctrl), os) != hipSuccess ||
+        hipEventRecord(ws->ev_ready, os) != hipSuccess) {
         bfs_workspace_free(ws);
         return fail(BFS_EHIP, "hipMemset failed");
     }
+    ws->init_pending = true;
     if (max_sources > 1) {
-        if (dalloc(&ws->b_args, 1) != hipSuccess ||
-            hipHostMalloc(reinterpret_cast<void**>(&ws->h_args), sizeof(BatchArgs), hipHostMallocDefault) != hipSuccess) {
-            bfs_workspace_free(ws);
-            return fail(BFS_EHIP, "could not prepare the batched search");
-        }
         bfs_status_t cst = setup_batch(ws);
         if (cst) {
             bfs_workspace_free(ws);
@@ -1356,13 +1503,13 @@ bfs_status_t bfs_run_batch(bfs_workspace_t ws, const int32_t* sources, int32_t k
     bfs_status_t st = check_busy(ws, s);
     if (st) return st;
     HIP_TRY(hipSetDevice(ws->device));
+    if ((st = wait_ready(ws, s))) return st;
     ws->host_stats = false;
     ws->profiled = false;
     ws->last_mode = BFS_MODE_AUTO;
     ws->host_status = BFS_OK;
     HIP_TRY(hipMemcpyAsync(ws->b_sources, sources, sizeof(int32_t) * (size_t)k, hipMemcpyHostToDevice, s));
-    *ws->h_args = BatchArgs{level, k, (k + 63) / 64, batch_pull_edges(ws), 0};
-    HIP_TRY(hipMemcpyAsync(ws->b_args, ws->h_args, sizeof(BatchArgs), hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_batch_args(ws->b_args, BatchArgs{level, k, (k + 63) / 64, batch_pull_edges(ws), 0}, s));
     const BatchParams bp = make_batch_params(ws);
     const int grid = batch_grid(ws);
     std::pair<hipEvent_t, hipEvent_t>* pe = nullptr;

@@ -595,6 +595,17 @@ hipError_t launch_batch_setup(const BatchParams& p, int grid, hipStream_t s) {
     return hipGetLastError();
 }
 
+// A run's arguments, passed by value: each launch carries its own copy, so calls queued back to
+// back on one stream cannot see each other's.
+__global__ void k_batch_args(BatchArgs* dst, BatchArgs a) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *dst = a;
+}
+
+hipError_t launch_batch_args(BatchArgs* dst, const BatchArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_args, dim3(1), dim3(64), 0, s, dst, a);
+    return hipGetLastError();
+}
+
 // Per run: reset, seed, and the update that turns the seeds into level 0.
 hipError_t launch_batch_start(const BatchParams& p, hipStream_t s) {
     if (!tiling_ok(p)) return hipErrorInvalidValue;

@@ -239,6 +239,7 @@ hipError_t launch_prim_compact(const int32_t* offsets, int32_t n, const int32_t*
                                hipStream_t s);
 
 hipError_t launch_batch_setup(const BatchParams& p, int grid, hipStream_t s);
+hipError_t launch_batch_args(BatchArgs* dst, const BatchArgs& a, hipStream_t s);
 hipError_t launch_batch_start(const BatchParams& p, hipStream_t s);
 hipError_t launch_batch_level(const BatchParams& p, int grid, hipStream_t s);
 hipError_t launch_batch_finish(const BatchParams& p, hipStream_t s);

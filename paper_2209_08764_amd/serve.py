@@ -114,7 +114,9 @@ class Scheduler:
         self.used += need
         if pooled:
             return self.pool[(name, kind)].pop()
+        t0 = self.clock()
         ws = self.ex.create(name, kind)
+        self.stats["create_ms"] += (self.clock() - t0) * 1e3
         self.pool_bytes[id(ws)] = self._ws_cost(info, kind)
         self.stats["workspaces_created"] += 1
         return ws
@@ -126,7 +128,9 @@ class Scheduler:
                 if key != exclude and lst and (key[1] > 1) == batched:
                     ws = lst.pop()
                     self.used -= self.pool_bytes.pop(id(ws))
+                    t0 = self.clock()
                     self.ex.destroy(ws)
+                    self.stats["destroy_ms"] += (self.clock() - t0) * 1e3
                     self.stats["workspaces_evicted"] += 1
                     return True
         return False
@@ -388,8 +392,15 @@ class GpuExecutor:
             if e.status != _lib.BFS_EOVERFLOW:
                 raise
             return None          # a level did not fit in a byte: the scheduler re-queues the sources
-        lv = out.view(-1, k).to(torch.int32)
-        lv[lv == 255] = -1
+        # converted on the run's own stream: `out` belongs to that stream's memory, which the
+        # next run there may reuse as soon as this returns; the caller's stream then waits
+        stream = self.streams[si]
+        with torch.cuda.stream(stream):
+            lv = out.view(-1, k).to(torch.int32)
+            lv.masked_fill_(lv == 255, -1)
+        cur = torch.cuda.current_stream()
+        cur.wait_stream(stream)
+        lv.record_stream(cur)
         return [lv[:, j] for j in range(k)]
 
     def idle(self, s):

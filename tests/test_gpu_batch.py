@@ -191,3 +191,19 @@ def test_batched_run_returns_before_the_device_finishes():
         want = oracle.bfs_levels(g.offsets, g.cols, int(srcs[j]))
         want8 = np.where(want < 0, 255, want).astype(np.uint8)
         assert np.array_equal(got[:, j], want8)
+
+
+def test_batched_runs_queued_back_to_back_keep_their_own_arguments(rmat13):
+    # two batched runs on one stream with no synchronisation between them, different k and
+    # outputs: each run's arguments travel with its own launch
+    g, G = rmat13
+    ws = Workspace(G, max_sources=256)
+    a = gg.pick_sources(g, 200, seed=21)
+    b = gg.pick_sources(g, 37, seed=22)
+    out_a = ws.run_batch(a)
+    out_b = ws.run_batch(b)
+    ws.sync()
+    for out, srcs in ((out_a, a), (out_b, b)):
+        got = out.cpu().numpy().reshape(g.n, len(srcs))
+        want, ovf = oracle.bfs_batch_u8(g.offsets, g.cols, srcs)
+        assert not ovf and np.array_equal(got, want)
