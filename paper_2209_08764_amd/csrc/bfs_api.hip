@@ -288,7 +288,7 @@ hipError_t pinned_ctrl_take(Ctrl** p) {
             return hipSuccess;
         }
     }
-    return hipHostMalloc(reinterpret_cast<void**>(p), sizeof(Ctrl), hipHostMallocDefault);
+    return hipHostMalloc(reinterpret_cast<void**>(p), sizeof(Ctrl), hipHostMallocPortable);  // any device may reuse it
 }
 
 void pinned_ctrl_give(Ctrl* p) {
