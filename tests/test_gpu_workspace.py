@@ -57,3 +57,34 @@ def test_one_workspace_grows_through_every_configuration():
     ws.sync()
     want_l, want_p = oracle.bfs(g.offsets, g.cols, some)
     assert np.array_equal(lv.cpu().numpy(), want_l) and np.array_equal(par.cpu().numpy(), want_p)
+
+
+def test_create_and_free_wait_for_nothing_else_on_the_device():
+    # a search of tens of milliseconds runs on another stream while a workspace is dropped and
+    # another made: neither waits for it, and the new workspace still answers correctly
+    import time
+    big = gg.grid(2048, 2048)
+    long_ws = Workspace(Graph(big.offsets, big.cols))
+    g = gg.rmat(14, seed=5)
+    G = Graph(g.offsets, g.cols)
+    ws = Workspace(G)
+    src = int(gg.pick_sources(g, 1, seed=6)[0])
+    run_single(ws, src)
+    lv_big = torch.empty(big.n, dtype=torch.int32, device="cuda")
+    other = torch.cuda.Stream()
+    long_ws.run(0, level=lv_big, stream=other, want_parent=False)   # warm-up
+    long_ws.sync()
+    long_ws.run(0, level=lv_big, stream=other, want_parent=False)
+    t0 = time.perf_counter()
+    ws.free()
+    t1 = time.perf_counter()
+    ws2 = Workspace(G)
+    t2 = time.perf_counter()
+    done = torch.cuda.Event()
+    done.record(other)
+    still_running = not done.query()
+    assert still_running, "the long search ended before the measurement; it proves nothing"
+    assert t1 - t0 < 0.010 and t2 - t1 < 0.010, (t1 - t0, t2 - t1)
+    lv, par = run_single(ws2, src)
+    assert_same(lv, par, g, [src])
+    long_ws.sync()
