@@ -19,11 +19,13 @@
  *     mapped for the device); "host" pointers are ordinary host memory.
  *   - Runs are asynchronous on the given HIP stream (a hipStream_t passed
  *     as void*; NULL is the null stream) unless stated otherwise.  A fault
- *     that happens on the device is reported by the next call on the same
- *     workspace (bfs_sync, bfs_last_stats or another run).
- *   - Graphs must be symmetric (undirected), with rows sorted ascending and
- *     0 <= cols[i] < n; n and m must fit in int32.  Self-loops and duplicate
- *     entries do not change the result.  BFS_VALIDATE checks all of this.
+ *     that happens on the device during a run is reported by bfs_sync or
+ *     bfs_last_stats on that workspace before its next run (a run starts
+ *     from a clean device status).
+ *   - Graphs must be symmetric (undirected), with rows sorted ascending (or
+ *     BFS_SORT_ROWS at bfs_init) and 0 <= cols[i] < n; n and m must fit in
+ *     int32.  Self-loops and duplicate entries do not change the result.
+ *     BFS_VALIDATE checks all of this.
  */
 #ifndef S3BFS_BFS_H
 #define S3BFS_BFS_H
