@@ -866,6 +866,7 @@ def run(args):
         ws.set(BFS_OPT_SPLIT, 0)
         log(f"split by binary search: {extras['split_search_gteps_hm']} GTEPS")
         # the paper's private queues and Owner test on every level (no dense levels), same launch
+        dense_default = ws.tuning()["dense_edges"]
         ws.set(BFS_OPT_DENSE_EDGES, 0)
         for s in sub[:2]:
             ws.run(int(s), level, parent)
@@ -873,7 +874,7 @@ def run(args):
         sm, _, _ = time_passes(ws, level, parent, sub, 1, torch)
         extras["queues_every_level_gteps_hm"] = round(hm_gteps(sm, mc_half[:16]), 3)
         extras["queues_every_level_ms_median"] = round(float(np.median(sm)), 3)
-        ws.set(BFS_OPT_DENSE_EDGES, g.m // 12)   # the default threshold again
+        ws.set(BFS_OPT_DENSE_EDGES, dense_default)   # the default threshold again
         log(f"private queues and Owner test on every level: {extras['queues_every_level_gteps_hm']} GTEPS")
         # energy: work-sized against work-insensitive levels, on this graph and on the grid
         log("energy: work-sensitive vs work-insensitive (R-MAT 24, grid 4096^2)")

@@ -81,7 +81,7 @@ typedef struct bfs_workspace_s* bfs_workspace_t;  /* scratch for one in-flight r
 #define BFS_OPT_BATCH_LEVELS 7 /* batched search: levels per replay of the captured loop (default 8) */
 #define BFS_OPT_PUSH_EDGES  6  /* levels with at most this many edges push parents (atomic
                                   minimum per edge); larger ones pull them from sorted rows
-                                  (default m / 12) */
+                                  (default m / 24) */
 #define BFS_OPT_BATCH_GRAIN 8  /* batched search: edges per expansion sub-tile, the grain of
                                   the equal edge split (512, 1024 or 2048; default 1024) */
 #define BFS_OPT_BATCH_TILE  9  /* batched search: vertices per tile of the dense update pass
@@ -94,7 +94,7 @@ typedef struct bfs_workspace_s* bfs_workspace_t;  /* scratch for one in-flight r
 #define BFS_OPT_DENSE_EDGES 12 /* BFS_MODE_AUTO / INSENSITIVE: a level that pulls its parents (or
                                   has none to find) and scans at least this many edges records its
                                   new vertices as bits instead of private-queue entries and
-                                  linearises them in vertex order (0 = never; default m / 12) */
+                                  linearises them in vertex order (0 = never; default m / 24) */
 #define BFS_OPT_GROUP      14  /* workgroups of that group (1..64, at most the grid; 0 = default 48) */
 #define BFS_OPT_BATCH_REPLAYS 15 /* batched search: replays of the captured level loop each run
                                     enqueues before the one-workgroup finish (-1 = enough for the
@@ -161,7 +161,7 @@ int64_t bfs_graph_aux_bytes(bfs_graph_t g);
 /* Device bytes a workspace for up to max_sources batched sources needs
    (max_sources = 1: single-source and multi-root runs only). 0 on error.
    Its private queues are sized for BFS_MODE_AUTO with the default options
-   (levels of up to m / 12 edges keep queues; larger ones are dense) and one
+   (levels of up to m / 24 edges keep queues; larger ones are dense) and one
    root.  A run whose mode, options or roots let larger levels keep queues
    (BFS_MODE_LEVEL, BFS_MODE_DIRECTION, BFS_OPT_DENSE_EDGES = 0 or a higher
    threshold, more roots) first grows them, up to 4 B per edge. */

@@ -45,11 +45,11 @@ constexpr uint64_t kSpinTicks = 300000000ull;  // 3 s at the 100 MHz s_memrealti
 // Default split of levels by their edges: up to m / kLevelSplit a level pushes
 // its parents (an atomic minimum per edge into an unsettled vertex); above it
 // the level pulls them from sorted rows and keeps its new vertices as bits.
-// Pushing pays for small levels and for frontiers of a few hubs, whose new
-// vertices include other hubs with rows too long to scan.  Measured on R-MAT
-// scale 24 over 64 sources: m / 8 gave 4.27 ms, m / 12 4.19, m / 16 4.20,
-// m / 24 4.27 per search.
-constexpr int64_t kLevelSplit = 12;
+// Pushing pays for small levels; a level of a few thousand hubs with tens of
+// millions of edges is cheaper pulled, since each new vertex finds a hub a few
+// entries into its row.  Measured on R-MAT scale 24 over 64 sources (harmonic
+// mean GTEPS): m / 12 65.4, m / 24 66.4, m / 32 66.3, m / 48 66.1, m / 96 65.1.
+constexpr int64_t kLevelSplit = 24;
 
 template <typename T>
 hipError_t dalloc(T** p, size_t count) {
@@ -59,7 +59,7 @@ hipError_t dalloc(T** p, size_t count) {
 // Entries of the private-queue array that a run needs.  Share b of a level
 // keeps its queue in cand[tb * kGrain, te * kGrain), so a level that keeps
 // queues needs its edges rounded up to whole sub-tiles.  Dense levels keep
-// none, so with the default thresholds only levels up to m / 12 edges do;
+// none, so with the default thresholds only levels up to m / kLevelSplit edges do;
 // per-level launches, direction optimisation (whose bottom-up levels queue up
 // to n vertices) and dense levels switched off may queue any level.  The
 // roots sit there as the queues of level -1.
@@ -1688,7 +1688,7 @@ bfs_status_t bfs_autotune(bfs_workspace_t ws, const int32_t* sources, int32_t k,
         // push and dense thresholds move together: a level above the split pulls its
         // parents and keeps its new vertices as bits (or, last, never as bits)
         std::vector<P> splits;
-        for (int64_t d : {32, 16, 12, 8, 4}) {
+        for (int64_t d : {48, 32, 24, 16, 12, 8}) {
             const int64_t e = std::min<int64_t>(std::max<int64_t>(m / d, 1), INT32_MAX);
             splits.push_back({e, e});
         }

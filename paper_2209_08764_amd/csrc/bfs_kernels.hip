@@ -111,6 +111,11 @@ __device__ __forceinline__ void parent_push(const Params& p, int v, int u) {
 
 __device__ __forceinline__ bool frontier_bit(const uint32_t* fb, int c) { return (fb[c >> 5] >> (c & 31)) & 1u; }
 
+// Whether c is at level l: its frontier bit, or its level where the bits are not kept.
+__device__ __forceinline__ bool at_level(const Params& p, int c, int l, const uint32_t* fb) {
+    return fb ? frontier_bit(fb, c) : p.level[c] == l;
+}
+
 // First neighbour at level l among the first kPullScan of the row, -2 if
 // none there but the row is longer, -1 if the row has none at all.
 __device__ __forceinline__ int first_parent_lane(const Params& p, int rs, int d, int l, const uint32_t* fb) {
@@ -529,17 +534,21 @@ __device__ void expand_share(const Params& p, int l, int b, int P, int ntiles, i
 }
 
 // Pulls the parents of one chunk's new vertices (kVT per thread, v = -1 for
-// none).  Rows whose first kPullScan neighbours hold no parent go to the
-// whole workgroup.  Uses the LDS slice buffers; called by the whole workgroup.
+// none).  The first kFirst neighbours of every row are tested at once; the
+// rows still open then go to a list in LDS, one per lane, so that no lane
+// scans its rows one after another while the rest of its wave waits; a lane
+// tests kPullScan more neighbours, and the few rows longer than that are
+// scanned by one wave each, 64 neighbours per step.  Uses the LDS slice
+// buffers; called by the whole workgroup.
 __device__ __forceinline__ void pull_parents_chunk(const Params& p, const int* v, const int* rs, const int* d, int l,
                                                    const uint32_t* fpull, int* lds) {
-    int* s_hard = lds;                // (v, rs, d) triples
-    int* s_red = lds + 3 * kGrain;    // kWaves + 1 ints
-    int* s_nh = s_red + kWaves + 1;
-    if (threadIdx.x == 0) *s_nh = 0;
+    int* s_row = lds;                 // (v, row start, length) of the open rows, then of the long ones
+    int* s_cnt = lds + 3 * kGrain;    // open rows, long rows
+    if (threadIdx.x == 0) {
+        s_cnt[0] = 0;
+        s_cnt[1] = 0;
+    }
     lds_barrier();
-    // the first kFirst neighbours of all kVT rows at once, then the next kPullScan of each
-    // row still open, one row at a time
     constexpr int kFirst = 2;
     int c[kVT][kFirst];
     bool h[kVT][kFirst];
@@ -576,25 +585,61 @@ __device__ __forceinline__ void pull_parents_chunk(const Params& p, const int* v
 #pragma unroll
             for (int q = kFirst - 1; q >= 0; --q)
                 if (h[i][q]) f = c[i][q];
-            // rows scanned past position kFirst + kPullScan go on from kPullScan, which
-            // repeats a few neighbours known to miss
-            if (f < 0 && d[i] > kFirst) f = first_parent_lane(p, rs[i] + kFirst, d[i] - kFirst, l, fpull);
-            if (f == -2) {
-                const int h = atomicAdd(s_nh, 1);
-                s_hard[3 * h] = v[i];
-                s_hard[3 * h + 1] = rs[i];
-                s_hard[3 * h + 2] = d[i];
+            if (f < 0 && d[i] > kFirst) {  // open: the rest of the row from position kFirst
+                const int o = atomicAdd(&s_cnt[0], 1);
+                s_row[3 * o] = v[i];
+                s_row[3 * o + 1] = rs[i] + kFirst;
+                s_row[3 * o + 2] = d[i] - kFirst;
             } else {
                 p.parent[v[i]] = f;
             }
         }
     }
     lds_barrier();
-    const int nh = *s_nh;
-    for (int h = 0; h < nh; ++h) {
-        const int hv = s_hard[3 * h], hrs = s_hard[3 * h + 1], hd = s_hard[3 * h + 2];
-        const int f = first_parent_wg(p, hrs, hd, l, fpull, s_red);
-        if (threadIdx.x == 0) p.parent[hv] = f;
+    const int nopen = s_cnt[0];
+    for (int j0 = 0; j0 < nopen; j0 += kBlock) {
+        const int j = j0 + (int)threadIdx.x;
+        int rv = -1, rr = 0, rd = 0;
+        if (j < nopen) {
+            rv = s_row[3 * j];
+            rr = s_row[3 * j + 1];
+            rd = s_row[3 * j + 2];
+        }
+        // this round's entries are all read before long rows are written over the list's
+        // front (long-row slot < rows taken so far <= j0 + kBlock)
+        lds_barrier();
+        if (rv >= 0) {
+            const int f = first_parent_lane(p, rr, rd, l, fpull);
+            if (f == -2) {
+                const int o = atomicAdd(&s_cnt[1], 1);
+                s_row[3 * o] = rv;
+                s_row[3 * o + 1] = rr;
+                s_row[3 * o + 2] = rd;
+            } else {
+                p.parent[rv] = f;
+            }
+        }
+    }
+    lds_barrier();
+    const int nlong = s_cnt[1];
+    for (int o = wave_id(); o < nlong; o += kWaves) {
+        const int hv = s_row[3 * o], hrs = s_row[3 * o + 1], hd = s_row[3 * o + 2];
+        int f = -1;
+        for (int base = kPullScan; base < hd; base += 64) {
+            const int q = base + lane_id();
+            int x = -1;
+            bool hit = false;
+            if (q < hd) {
+                x = p.cols[hrs + q];
+                hit = (unsigned)x < (unsigned)p.n && at_level(p, x, l, fpull);
+            }
+            const uint64_t bb = ballot(hit);
+            if (bb) {
+                f = __shfl(x, __builtin_ctzll(bb));
+                break;
+            }
+        }
+        if (lane_id() == 0) p.parent[hv] = f;
     }
     lds_barrier();
 }

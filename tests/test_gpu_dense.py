@@ -98,6 +98,44 @@ def test_dense_threshold_rejects_negative():
     ws = Workspace(Graph(g.offsets, g.cols))
     with pytest.raises(BFSError):
         bfs_workspace_set_option(ws.handle, BFS_OPT_DENSE_EDGES, -1)
-    assert ws.tuning()["dense_edges"] == max(g.m // 12, 1)
+    assert ws.tuning()["dense_edges"] == max(g.m // 24, 1)
     bfs_workspace_set_option(ws.handle, BFS_OPT_DENSE_EDGES, 0)
     assert ws.tuning()["dense_edges"] == 0
+
+
+def late_parent_graph(k: int = 6000, fillers: int = 3000, f: int = 64, seed: int = 9):
+    """New vertices whose only level-l neighbours sit late in their sorted rows.
+
+    The source (the largest id) reaches f frontier vertices with the next-largest ids;
+    each of the k vertices 0..k-1 joins one or two of them and r distinct filler vertices
+    whose ids lie between, so its first level-1 neighbour is at row position r.  r takes
+    values on both sides of every scan boundary (2, 34, 34 + 64 * j) up to 600, so a
+    parent pull meets rows found at once, rows a lane finishes, and rows scanned 64 at a
+    time; all k vertices are new at level 2 and fill whole 2048-vertex chunks.
+    """
+    rng = np.random.default_rng(seed)
+    n = k + fillers + f + 1
+    s = n - 1
+    fr = np.arange(n - 1 - f, n - 1)
+    r_vals = np.array([0, 1, 2, 3, 5, 8, 20, 31, 33, 34, 35, 36, 40, 64, 97, 98, 99, 100, 161, 162, 300, 600])
+    src, dst = [np.full(f, s)], [fr]
+    for x in range(k):
+        r = int(r_vals[x % r_vals.size]) if x % 5 else int(rng.integers(0, 40))
+        par = rng.choice(fr, size=1 + (x % 2), replace=False)
+        fill = k + rng.choice(fillers, size=r, replace=False)
+        nb = np.concatenate([par, fill])
+        src.append(np.full(nb.size, x))
+        dst.append(nb)
+    g = gg.csr_from_pairs(n, np.concatenate(src), np.concatenate(dst), name="late_parents")
+    return g, s
+
+
+@pytest.mark.parametrize("dense", [1, 0])
+@pytest.mark.parametrize("grid", [0, 1, 5])
+def test_parents_found_late_in_long_rows(dense, grid):
+    g, s = late_parent_graph()
+    # every level a grid level that pulls its parents
+    ws = Workspace(Graph(g.offsets, g.cols), dense_edges=dense, push_edges=0, small_edges=0, grid=grid)
+    lv, par = run_single(ws, s)
+    want = assert_same(lv, par, g, [s])
+    assert int((want[0] == 2).sum()) == 6000

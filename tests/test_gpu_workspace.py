@@ -1,5 +1,5 @@
 """Workspace sizing on the GPU: a workspace starts with private queues for the
-default options (levels of up to m / 12 edges keep queues, larger ones are
+default options (levels of up to m / 24 edges keep queues, larger ones are
 dense) and grows them when a run's mode, options or roots need more.  One
 workspace then runs every such configuration in turn, each bit-exact."""
 import numpy as np
@@ -22,9 +22,9 @@ def test_default_workspace_is_sized_for_dense_levels():
     G = Graph(g.offsets, g.cols)
     b = bfs_workspace_bytes(G.handle, 1)
     # per-vertex arrays (32.5 B per vertex with the roots), statistics (2 MiB) and queues for a
-    # twelfth of the edges
-    assert b < 32.5 * g.n + g.m / 12 * 4 + 4 * 2048 * 4 + (3 << 20)
-    assert b > 32 * g.n + g.m / 12 * 4
+    # 24th of the edges
+    assert b < 32.5 * g.n + g.m / 24 * 4 + 4 * 2048 * 4 + (3 << 20)
+    assert b > 32 * g.n + g.m / 24 * 4
 
 
 def test_one_workspace_grows_through_every_configuration():
@@ -35,8 +35,8 @@ def test_one_workspace_grows_through_every_configuration():
     steps = [
         {BFS_OPT_MODE: BFS_MODE_AUTO},
         {BFS_OPT_DENSE_EDGES: 0},                               # every level keeps queues
-        {BFS_OPT_DENSE_EDGES: g.m // 12, BFS_OPT_PUSH_EDGES: g.m},  # every level pushes with queues
-        {BFS_OPT_PUSH_EDGES: g.m // 12, BFS_OPT_MODE: BFS_MODE_DIRECTION},
+        {BFS_OPT_DENSE_EDGES: g.m // 24, BFS_OPT_PUSH_EDGES: g.m},  # every level pushes with queues
+        {BFS_OPT_PUSH_EDGES: g.m // 24, BFS_OPT_MODE: BFS_MODE_DIRECTION},
         {BFS_OPT_MODE: BFS_MODE_LEVEL},
         {BFS_OPT_MODE: BFS_MODE_INSENSITIVE, BFS_OPT_SMALL_EDGES: 1 << 30},
         {BFS_OPT_MODE: BFS_MODE_AUTO, BFS_OPT_SMALL_EDGES: 4096},
