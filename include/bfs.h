@@ -81,7 +81,8 @@ typedef struct bfs_workspace_s* bfs_workspace_t;  /* scratch for one in-flight r
 #define BFS_OPT_BATCH_LEVELS 7 /* batched search: levels per replay of the captured loop (default 8) */
 #define BFS_OPT_PUSH_EDGES  6  /* levels with at most this many edges push parents (atomic
                                   minimum per edge); larger ones pull them from sorted rows
-                                  (default m / 24) */
+                                  (default m / 24; m / 12 under BFS_MODE_LEVEL and
+                                  BFS_MODE_DIRECTION) */
 #define BFS_OPT_BATCH_GRAIN 8  /* batched search: edges per expansion sub-tile, the grain of
                                   the equal edge split (512, 1024 or 2048; default 1024) */
 #define BFS_OPT_BATCH_TILE  9  /* batched search: vertices per tile of the dense update pass

@@ -49,7 +49,10 @@ constexpr uint64_t kSpinTicks = 300000000ull;  // 3 s at the 100 MHz s_memrealti
 // millions of edges is cheaper pulled, since each new vertex finds a hub a few
 // entries into its row.  Measured on R-MAT scale 24 over 64 sources (harmonic
 // mean GTEPS): m / 12 65.4, m / 24 66.4, m / 32 66.3, m / 48 66.1, m / 96 65.1.
+// Per-level launches and direction optimisation have no dense levels, and
+// their pulls test the level array, so they keep pushing up to m / 12.
 constexpr int64_t kLevelSplit = 24;
+constexpr int64_t kLevelSplitNoDense = 12;
 
 template <typename T>
 hipError_t dalloc(T** p, size_t count) {
@@ -362,7 +365,9 @@ int32_t dense_edges_of(const bfs_workspace_s* ws) {
 }
 
 int32_t push_edges_of(const bfs_workspace_s* ws) {
-    return ws->push_edges >= 0 ? ws->push_edges : (int32_t)std::min<int64_t>(ws->g->m / kLevelSplit, INT32_MAX);
+    const bool no_dense = ws->mode == BFS_MODE_DIRECTION || ws->mode == BFS_MODE_LEVEL;
+    const int64_t split = no_dense ? kLevelSplitNoDense : kLevelSplit;
+    return ws->push_edges >= 0 ? ws->push_edges : (int32_t)std::min<int64_t>(ws->g->m / split, INT32_MAX);
 }
 
 // Private-queue entries a run of ws with its current mode and options needs.
@@ -1556,7 +1561,7 @@ void current_tuning(const bfs_workspace_s* ws, bfs_tune_t* t) {
     t->batch_pull = ws->batch_pull >= -1 ? ws->batch_pull : batch_pull_edges(ws);
     t->grid = ws->grid_opt;
     t->small_edges = ws->small_edges;
-    t->push_edges = ws->push_edges >= 0 ? ws->push_edges : (int32_t)std::min<int64_t>(ws->g->m / kLevelSplit, INT32_MAX);
+    t->push_edges = push_edges_of(ws);
     t->dense_edges = dense_edges_of(ws);
 }
 
