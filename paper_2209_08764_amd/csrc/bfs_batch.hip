@@ -58,6 +58,22 @@ __device__ __forceinline__ void bscatter(const BatchParams& p, int32_t* ts, int 
     for (; t < tend; ++t) ts[t] = pos;
 }
 
+// A vertex's four 64-bit mask words (32-byte aligned), read as two 16-byte loads whatever the
+// batch's word count: the loads then carry no branches, each of which would make the next load
+// wait for the one before it.  Words past the batch's count may hold an earlier batch's bits and
+// are never used.
+struct alignas(16) Mask2 {
+    unsigned long long a, b;
+};
+__device__ __forceinline__ void load_mask(const unsigned long long* src, unsigned long long* f) {
+    const Mask2* q = reinterpret_cast<const Mask2*>(src);
+    const Mask2 lo = q[0], hi = q[1];
+    f[0] = lo.a;
+    f[1] = lo.b;
+    f[2] = hi.a;
+    f[3] = hi.b;
+}
+
 template <int BVT>
 struct ExpLds {
     static constexpr int kSl = kBlock * BVT + 1;   // slice entries of one sub-tile
@@ -339,27 +355,37 @@ __device__ __forceinline__ void batch_expand(const BatchParams& p, int b, int nb
 #pragma unroll
             for (int r = 0; r < BVT; ++r) gg[r] = min(g0 + r * kBlock + (int)threadIdx.x, g1 - 1);
             search_owners<BVT>(sl, nv, gg, own);
+            // every edge's target and source masks are read before any atomic goes out
+            int tv[BVT];
+            bool okr[BVT];
+            unsigned long long f[BVT][4];
+#pragma unroll
+            for (int r = 0; r < BVT; ++r) {  // from a clamped position, checked afterwards
+                const int g = g0 + r * kBlock + threadIdx.x;
+                const int lo = own[r];
+                const int idx = sl[SL + lo] + (g - sl[lo]);
+                okr[r] = (unsigned)idx < (unsigned)p.m;
+                tv[r] = p.cols[okr[r] ? idx : 0];
+                if (g >= g1) okr[r] = true, tv[r] = -1;  // no edge: nothing to flag
+            }
+#pragma unroll
+            for (int r = 0; r < BVT; ++r)
+                if (!okr[r]) {
+                    bflag(c);
+                    tv[r] = -1;
+                }
 #pragma unroll
             for (int r = 0; r < BVT; ++r) {
-                const int g = g0 + r * kBlock + threadIdx.x;
-                if (g < g1) {
-                    const int lo = own[r];
-                    const int idx = sl[SL + lo] + (g - sl[lo]);
-                    const int u = sl[2 * SL + lo];
-                    if ((unsigned)idx >= (unsigned)p.m) {
-                        bflag(c);
-                        continue;
-                    }
-                    const int v = p.cols[idx];
-                    if ((unsigned)v >= (unsigned)p.n) continue;
+                const int u = sl[2 * SL + own[r]];
+                const bool ok = (unsigned)tv[r] < (unsigned)p.n;
+                if (ok) load_mask(p.fr + (int64_t)u * 4, f[r]);
+                else f[r][0] = f[r][1] = f[r][2] = f[r][3] = 0ull;
+            }
 #pragma unroll
-                    for (int w = 0; w < 4; ++w) {
-                        if (w < W) {
-                            const unsigned long long f = p.fr[(int64_t)u * 4 + w];
-                            if (f) atomicOr(&p.nx[(int64_t)v * 4 + w], f);
-                        }
-                    }
-                }
+            for (int r = 0; r < BVT; ++r) {
+#pragma unroll
+                for (int w = 0; w < 4; ++w)
+                    if (w < W && f[r][w]) atomicOr(&p.nx[(int64_t)tv[r] * 4 + w], f[r][w]);
             }
         }
         return;
@@ -394,9 +420,11 @@ __device__ __forceinline__ void batch_expand(const BatchParams& p, int b, int nb
             sl[i] = p.offsets[v];
             sl[SL + i] = v;
             bool need = false;
+            unsigned long long vw[4];
+            load_mask(p.vis + (int64_t)v * 4, vw);
 #pragma unroll
             for (int w = 0; w < 4; ++w)
-                if (w < W) need |= p.vis[(int64_t)v * 4 + w] != full[w];
+                if (w < W) need |= vw[w] != full[w];
             sl[2 * SL + i] = need;
 #pragma unroll
             for (int w = 0; w < 4; ++w) lds.acc[i * 4 + w] = 0ull;
@@ -406,31 +434,45 @@ __device__ __forceinline__ void batch_expand(const BatchParams& p, int b, int nb
 #pragma unroll
         for (int r = 0; r < BVT; ++r) gg[r] = (int)min(g0 + r * kBlock + (int64_t)threadIdx.x, g1 - 1);
         search_owners<BVT>(sl, nv, gg, own);
+        // the neighbours of this lane's edges, then their activity, then their masks: each
+        // step's loads for all BVT edges go out together, and the ORs into LDS come last
+        int xs[BVT];
+        bool open[BVT];
 #pragma unroll
         for (int r = 0; r < BVT; ++r) {
             const int64_t g = g0 + r * kBlock + threadIdx.x;
-            if (g < g1) {
-                const int lo = own[r];
-                if (sl[2 * SL + lo]) {
-                    const int x = p.fr_hot ? p.colx[g] : p.cols[g];
-                    const unsigned long long* src = nullptr;
-                    if (x < 0) {
-                        const int h = -1 - x;
-                        if (h < p.hot_count) src = p.fr_hot + (int64_t)h * 4;
-                    } else if (x < p.n && ((p.act_bits[x >> 5] >> (x & 31)) & 1u)) {
-                        src = p.fr + (int64_t)x * 4;
-                    }
-                    if (src) {
+            open[r] = g < g1 && sl[2 * SL + own[r]];
+            xs[r] = open[r] ? (p.fr_hot ? p.colx[g] : p.cols[g]) : INT32_MAX;
+        }
+        uint32_t ab[BVT];
 #pragma unroll
-                        for (int w = 0; w < 4; ++w) {
-                            if (w < W) {
-                                const unsigned long long f = src[w];
-                                if (f) atomicOr(&lds.acc[lo * 4 + w], f);
-                            }
-                        }
-                    }
-                }
+        for (int r = 0; r < BVT; ++r) {  // active bits from a clamped word, used only for x in [0, n)
+            const int x = xs[r];
+            ab[r] = p.act_bits[(x >= 0 && x < p.n ? x : 0) >> 5];
+        }
+        const unsigned long long* src[BVT];
+#pragma unroll
+        for (int r = 0; r < BVT; ++r) {
+            const int x = xs[r];
+            src[r] = nullptr;
+            if (x < 0) {
+                const int h = -1 - x;
+                if (h < p.hot_count) src[r] = p.fr_hot + (int64_t)h * 4;
+            } else if (x < p.n && ((ab[r] >> (x & 31)) & 1u)) {
+                src[r] = p.fr + (int64_t)x * 4;
             }
+        }
+        unsigned long long f[BVT][4];
+#pragma unroll
+        for (int r = 0; r < BVT; ++r) {
+            if (src[r]) load_mask(src[r], f[r]);
+            else f[r][0] = f[r][1] = f[r][2] = f[r][3] = 0ull;
+        }
+#pragma unroll
+        for (int r = 0; r < BVT; ++r) {
+#pragma unroll
+            for (int w = 0; w < 4; ++w)
+                if (w < W && f[r][w]) atomicOr(&lds.acc[own[r] * 4 + w], f[r][w]);
         }
         lds_barrier();
         // hand the accumulated masks to N: rows cut by the sub-tile's ends may also be
