@@ -194,48 +194,71 @@ __device__ __forceinline__ void batch_update_tile(const BatchParams& p, int tile
     int tc = 0, ts = 0;
     int act[UV], deg[UV], rs[UV];
     unsigned long long nw[UV][4];
+    // this thread's UV vertices in phases, each phase's loads together: next-level masks,
+    // then the visited masks of those reached, then the row offsets of the new ones
+    unsigned long long nn[UV][4], vw[UV][4];
+    bool any[UV];
+#pragma unroll
+    for (int i = 0; i < UV; ++i) {
+        const int v = v0 + i;
+        load_mask(p.nx + (int64_t)(v < p.n ? v : 0) * 4, nn[i]);
+        any[i] = false;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            if (w >= W || v >= p.n) nn[i][w] = 0ull;
+            any[i] |= nn[i][w] != 0ull;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < UV; ++i) {
+        if (any[i]) load_mask(p.vis + (int64_t)(v0 + i) * 4, vw[i]);
+        else vw[i][0] = vw[i][1] = vw[i][2] = vw[i][3] = 0ull;
+    }
+    bool fresh[UV];
 #pragma unroll
     for (int i = 0; i < UV; ++i) {
         const int v = v0 + i;
         act[i] = 0;
         deg[i] = 0;
         rs[i] = 0;
+        fresh[i] = false;
 #pragma unroll
-        for (int w = 0; w < 4; ++w) nw[i][w] = 0ull;
-        if (v < p.n) {
-            unsigned long long any = 0ull;
-            unsigned long long nn[4];
+        for (int w = 0; w < 4; ++w) {
+            nw[i][w] = nn[i][w] & ~vw[i][w];
+            fresh[i] |= nw[i][w] != 0ull;
+        }
+        if (any[i]) {
 #pragma unroll
             for (int w = 0; w < 4; ++w) {
-                nn[w] = w < W ? p.nx[(int64_t)v * 4 + w] : 0ull;
-                any |= nn[w];
-            }
-            if (any) {
-                unsigned long long fresh = 0ull;
-#pragma unroll
-                for (int w = 0; w < 4; ++w) {
-                    if (w < W) {
-                        const unsigned long long vw = p.vis[(int64_t)v * 4 + w];
-                        nw[i][w] = nn[w] & ~vw;
-                        fresh |= nw[i][w];
-                        p.nx[(int64_t)v * 4 + w] = 0ull;
-                        if (nw[i][w]) p.vis[(int64_t)v * 4 + w] = vw | nw[i][w];
-                        p.fr[(int64_t)v * 4 + w] = nw[i][w];
-                    }
+                if (w < W) {
+                    p.nx[(int64_t)v * 4 + w] = 0ull;
+                    if (nw[i][w]) p.vis[(int64_t)v * 4 + w] = vw[i][w] | nw[i][w];
+                    p.fr[(int64_t)v * 4 + w] = nw[i][w];
                 }
-                if (fresh) {
-                    if (!fits) {
-                        __hip_atomic_store(&c->batch_overflow, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    } else {
-                        act[i] = 1;
-                        rs[i] = p.offsets[v];
-                        deg[i] = p.offsets[v + 1] - rs[i];
-                        atomicOr(&s_bits[(threadIdx.x * UV + i) >> 5], 1u << ((threadIdx.x * UV + i) & 31));
-                        if (deg[i] > 0) {
-                            ++tc;
-                            ts += deg[i];
-                        }
-                    }
+            }
+        }
+    }
+    int o0[UV], o1[UV];
+#pragma unroll
+    for (int i = 0; i < UV; ++i) {
+        if (fresh[i] && fits) {
+            o0[i] = p.offsets[v0 + i];
+            o1[i] = p.offsets[v0 + i + 1];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < UV; ++i) {
+        if (fresh[i]) {
+            if (!fits) {
+                __hip_atomic_store(&c->batch_overflow, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                act[i] = 1;
+                rs[i] = o0[i];
+                deg[i] = o1[i] - o0[i];
+                atomicOr(&s_bits[(threadIdx.x * UV + i) >> 5], 1u << ((threadIdx.x * UV + i) & 31));
+                if (deg[i] > 0) {
+                    ++tc;
+                    ts += deg[i];
                 }
             }
         }
