@@ -207,3 +207,16 @@ def test_batched_runs_queued_back_to_back_keep_their_own_arguments(rmat13):
         got = out.cpu().numpy().reshape(g.n, len(srcs))
         want, ovf = oracle.bfs_batch_u8(g.offsets, g.cols, srcs)
         assert not ovf and np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("pull", [-1, 0, None])
+def test_smaller_batches_after_a_full_one(pull):
+    # a batch of 256 sources fills all four mask words of every vertex it reaches; later batches
+    # with fewer words (100 sources: 2, 40: 1) on the same workspace read those words as part of
+    # each 32-byte gather but never use them
+    g = gg.rmat(14, seed=67)
+    G = Graph(g.offsets, g.cols, hot=True)
+    opts = {} if pull is None else {"batch_pull": pull}
+    ws = Workspace(G, max_sources=256, **opts)
+    for k in (256, 100, 40, 256, 1):
+        _check(ws, g, gg.pick_sources(g, k, seed=300 + k))
