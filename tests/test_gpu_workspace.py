@@ -1,7 +1,8 @@
-"""Workspace sizing on the GPU: a workspace starts with private queues for the
+"""Workspaces on the GPU: a workspace starts with private queues for the
 default options (levels of up to m / 24 edges keep queues, larger ones are
 dense) and grows them when a run's mode, options or roots need more.  One
-workspace then runs every such configuration in turn, each bit-exact."""
+workspace then runs every such configuration in turn, each bit-exact.  A
+workspace still in flight refuses a run from another stream (BFS_EBUSY)."""
 import numpy as np
 import pytest
 
@@ -88,3 +89,27 @@ def test_create_and_free_wait_for_nothing_else_on_the_device():
     lv, par = run_single(ws2, src)
     assert_same(lv, par, g, [src])
     long_ws.sync()
+
+
+def test_run_from_another_stream_while_in_flight_is_refused():
+    # a search of the 2048 x 2048 grid (4095 levels) runs for tens of milliseconds; the
+    # workspace refuses a run from another stream until it has finished, accepts one on the
+    # same stream (stream order), and afterwards accepts any stream
+    from paper_2209_08764_amd import BFSError, _lib, bfs_run
+    g = gg.grid(2048, 2048)
+    ws = Workspace(Graph(g.offsets, g.cols))
+    level = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    parent = torch.empty_like(level)
+    a, b = torch.cuda.Stream(), torch.cuda.Stream()
+    bfs_run(ws.handle, 0, level, parent, stream=a)
+    with pytest.raises(BFSError) as err:
+        bfs_run(ws.handle, 0, level, parent, stream=b)
+    assert err.value.status == _lib.BFS_EBUSY
+    bfs_run(ws.handle, 0, level, parent, stream=a)        # same stream: queued behind the first
+    a.synchronize()
+    bfs_run(ws.handle, g.n - 1, level, parent, stream=b)
+    b.synchronize()
+    ws.sync()
+    assert ws.stats()["status"] == 0
+    lv = level.cpu().numpy()
+    assert lv[0] == 2 * 2047 and lv[g.n - 1] == 0
