@@ -1,8 +1,10 @@
 /*
  * bfs_test.h -- entry points of libbfs that serve its tests and its
  * measurements, not its users: one primitive of the level loop run on its
- * own, and a kernel that measures the device's random-probe rate.  They
- * follow the conventions of bfs.h (status codes, device pointers, streams).
+ * own, a kernel that measures the device's random-probe rate, and a time
+ * limit for the level loop's waits that tests of failure handling shorten.
+ * They follow the conventions of bfs.h (status codes, device pointers,
+ * streams).
  */
 #ifndef S3BFS_BFS_TEST_H
 #define S3BFS_BFS_TEST_H
@@ -62,6 +64,22 @@ int32_t bfs_prim_grain(void);
  */
 bfs_status_t bfs_probe_rate_kernel(const int32_t* idx, int64_t count, const uint32_t* table,
                                    int64_t table_words, int32_t shift, int32_t* sink, void* stream);
+
+/* ---- failure handling ----------------------------------------------------------------- */
+
+/*
+ * Time limit, in ticks of the 100 MHz device clock, of every wait in the
+ * persistent level loop of ws's single-source and multi-root runs
+ * (BFS_MODE_AUTO, BFS_MODE_INSENSITIVE, BFS_MODE_DIRECTION: grid, XCD and
+ * group barriers, look-back over the shares; per-level launches and batched
+ * runs keep the default).  A wait that sees no progress for that long
+ * records a device failure, every workgroup then leaves the kernel at its
+ * next wait, and the run reports BFS_EDEVICE (bfs_sync, bfs_last_stats);
+ * the next run starts clean.  ticks = 0 restores the default (3 s).  For
+ * tests that force that path without faulting or hanging the device.
+ * EINVAL for a null workspace.
+ */
+bfs_status_t bfs_workspace_set_spin_ticks(bfs_workspace_t ws, uint64_t ticks);
 
 #ifdef __cplusplus
 }

@@ -140,6 +140,7 @@ _SIGS = {
     "bfs_workspace_get_tuning": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(bfs_tune_t)]),
     "bfs_probe_rate_kernel": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
                                                ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
+    "bfs_workspace_set_spin_ticks": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_uint64]),
 }
 
 EXPORTED = tuple(_SIGS)

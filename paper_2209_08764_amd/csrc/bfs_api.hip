@@ -186,6 +186,7 @@ struct bfs_workspace_s {
     int32_t profile = 0;
     int32_t batch_pull = -2;  // -2: library default
     int32_t split_search = 0; // BFS_OPT_SPLIT
+    uint64_t spin_ticks = 0;  // time limit of the persistent loop's waits (0: kSpinTicks); tests only
     // last run
     int32_t last_mode = 0;
     int32_t last_grid = 0;
@@ -602,6 +603,7 @@ bfs_status_t run_common(bfs_workspace_s* ws, const int32_t* roots_host, int32_t 
         }
         p.fb_pull = !p.direction && p.parent != nullptr;
         p.dense_edges = p.direction ? 0 : dense_edges_of(ws);
+        if (ws->spin_ticks) p.spin_ticks = ws->spin_ticks;
         const int grid = grid_for(ws);
         const int rtiles = (p.nroots + kGrain - 1) / kGrain;
         HIP_TRY(launch_prep(p, std::min(rtiles, grid), p.parent != nullptr, s));
@@ -1463,6 +1465,12 @@ bfs_status_t bfs_last_level_times(bfs_workspace_t ws, int32_t cap, double* expan
 int32_t bfs_prim_grain(void) { return kGrain; }
 
 int32_t bfs_workspace_grid_capacity(bfs_workspace_t ws) { return ws ? ws->grid_cap : 0; }
+
+bfs_status_t bfs_workspace_set_spin_ticks(bfs_workspace_t ws, uint64_t ticks) {
+    if (!ws) return fail(BFS_EINVAL, "null workspace");
+    ws->spin_ticks = ticks;
+    return BFS_OK;
+}
 
 bfs_status_t bfs_prim_compact(const int32_t* offsets, int32_t n, const int32_t* owner, const int32_t* cand,
                               const int32_t* cnt, int32_t ntiles, int32_t* out_v, int32_t* out_rs, int32_t* out_ex,

@@ -310,3 +310,24 @@ def test_group_sizes_do_not_change_results(group):
                 assert ws.stats()["status"] == 0
             lv, _ = run_single(ws, int(srcs[0]) if srcs is not None else 0, want_parent=False)
             assert np.array_equal(lv, oracle.bfs(g.offsets, g.cols, int(srcs[0]) if srcs is not None else 0)[0])
+
+
+def test_a_wait_that_times_out_is_reported_and_the_next_run_is_clean():
+    # a 1-tick limit on the persistent loop's waits makes the first wait that is not over
+    # within its first 32 polls record a device failure; every workgroup leaves at its next
+    # wait, the run reports BFS_EDEVICE, and the next run (default limit) is bit-exact
+    from paper_2209_08764_amd import BFSError, _lib
+    g = gg.rmat(20, seed=73)
+    ws = Workspace(Graph(g.offsets, g.cols))
+    s = int(gg.pick_sources(g, 1, seed=74)[0])
+    lib = _lib.load()
+    _lib.check(lib.bfs_workspace_set_spin_ticks(ws.handle, 1), "bfs_workspace_set_spin_ticks")
+    ws.run(s)
+    with pytest.raises(BFSError) as err:
+        ws.sync()
+    assert err.value.status == _lib.BFS_EDEVICE
+    assert ws.stats()["status"] == _lib.BFS_EDEVICE
+    _lib.check(lib.bfs_workspace_set_spin_ticks(ws.handle, 0), "bfs_workspace_set_spin_ticks")
+    lv, par = run_single(ws, s)
+    assert_same(lv, par, g, [s])
+    assert ws.stats()["status"] == 0
