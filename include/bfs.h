@@ -102,6 +102,9 @@ typedef struct bfs_workspace_s* bfs_workspace_t;  /* scratch for one in-flight r
                                     most levels a completed batched run of this workspace, or of any
                                     workspace on its graph, needed, 32 before the first, default;
                                     0..256 = exactly that many) */
+#define BFS_OPT_HOST_STATUS 16 /* 1: every single-source or multi-root run also copies its device
+                                  status into the workspace's pinned host block, on the run's
+                                  stream, for bfs_run_status (default 0: no copy) */
 #define BFS_OPT_SPLIT      13  /* how each level's equal shares find their start points
                                   (Analysis, Find-StartExpPoint): 0 = every frontier vertex
                                   writes itself as the start of the shares beginning inside its
@@ -264,6 +267,19 @@ bfs_status_t bfs_run_noalloc(bfs_graph_t g, int32_t source, int32_t* level, int3
 
 /* Wait for the workspace's last run; returns its device status. */
 bfs_status_t bfs_sync(bfs_workspace_t ws);
+
+/*
+ * The device status of the workspace's last single-source or multi-root run
+ * without waiting for anything: for callers (a server) that learn of a run's
+ * completion from their own event on its stream, where a host wait on the
+ * workspace would also wait for other work queued on the same hardware
+ * queue.  Needs BFS_OPT_HOST_STATUS = 1 when the run was launched.  *status
+ * receives BFS_OK or BFS_EDEVICE (or the run's launch error) once the run's
+ * work has completed; until then the call returns BFS_EBUSY.  EINVAL for a
+ * null argument, without the option, or after a batched run.  An addition:
+ * the paper's search has no device of its own to fail.
+ */
+bfs_status_t bfs_run_status(bfs_workspace_t ws, int32_t* status);
 
 /* Statistics of the last run (synchronises with it first). */
 bfs_status_t bfs_last_stats(bfs_workspace_t ws, bfs_stats_t* out);

@@ -17,18 +17,19 @@ from ._lib import (BFS_DEVICE_PTRS, BFS_HOST_PTRS, BFS_HOT_FILTER, BFS_LEAN, BFS
                    BFS_MODE_INSENSITIVE, BFS_MODE_LEVEL, BFS_OPT_BU_ALPHA, BFS_OPT_BU_BETA, BFS_OPT_DENSE_EDGES,
                    BFS_MODE_PLAIN, BFS_OPT_BATCH_GRAIN, BFS_OPT_BATCH_LEVELS, BFS_OPT_BATCH_PULL, BFS_OPT_BATCH_TILE,
                    BFS_OPT_GRID, BFS_OPT_MODE, BFS_OPT_PROFILE, BFS_OPT_PUSH_EDGES, BFS_OPT_SMALL_EDGES,
-                   BFS_OPT_BATCH_REPLAYS, BFS_OPT_GROUP, BFS_OPT_SPLIT, BFS_TUNE_BATCH, BFS_TUNE_SINGLE, BFS_VALIDATE, BFSError, bfs_stats_t, bfs_tune_t)
+                   BFS_OPT_BATCH_REPLAYS, BFS_OPT_GROUP, BFS_OPT_HOST_STATUS, BFS_OPT_SPLIT, BFS_TUNE_BATCH,
+                   BFS_TUNE_SINGLE, BFS_VALIDATE, BFSError, bfs_stats_t, bfs_tune_t)
 
 __all__ = [
     "bfs_init", "bfs_graph_free", "bfs_graph_info", "bfs_graph_aux_bytes", "bfs_workspace_bytes", "bfs_workspace_create",
     "bfs_workspace_free", "bfs_workspace_set_option", "bfs_workspace_grid_capacity", "bfs_run", "bfs_run_multiroot", "bfs_run_batch", "bfs_run_noalloc",
-    "bfs_sync", "bfs_last_stats", "bfs_last_level_stats", "bfs_last_level_times", "bfs_kernel_times", "bfs_status_str",
+    "bfs_sync", "bfs_run_status", "bfs_last_stats", "bfs_last_level_stats", "bfs_last_level_times", "bfs_kernel_times", "bfs_status_str",
     "bfs_prim_compact",
     "bfs_prim_grain", "bfs_probe_rate_kernel", "bfs_autotune", "bfs_workspace_get_tuning", "Graph", "Workspace", "BFSError",
     "BFS_MODE_AUTO", "BFS_MODE_LEVEL", "BFS_MODE_PLAIN", "BFS_MODE_INSENSITIVE", "BFS_MODE_DIRECTION",
     "BFS_OPT_BU_ALPHA", "BFS_OPT_BU_BETA", "BFS_OPT_DENSE_EDGES", "BFS_OPT_MODE",
     "BFS_OPT_SMALL_EDGES", "BFS_OPT_GRID", "BFS_OPT_PROFILE", "BFS_OPT_BATCH_PULL", "BFS_OPT_PUSH_EDGES", "BFS_OPT_BATCH_LEVELS",
-    "BFS_OPT_BATCH_GRAIN", "BFS_OPT_BATCH_TILE", "BFS_OPT_SPLIT", "BFS_OPT_GROUP", "BFS_OPT_BATCH_REPLAYS", "BFS_TUNE_BATCH", "BFS_TUNE_SINGLE", "BFS_HOST_PTRS",
+    "BFS_OPT_BATCH_GRAIN", "BFS_OPT_BATCH_TILE", "BFS_OPT_SPLIT", "BFS_OPT_GROUP", "BFS_OPT_BATCH_REPLAYS", "BFS_OPT_HOST_STATUS", "BFS_TUNE_BATCH", "BFS_TUNE_SINGLE", "BFS_HOST_PTRS",
     "BFS_DEVICE_PTRS", "BFS_VALIDATE", "BFS_HOT_FILTER", "BFS_LEAN",
 ]
 
@@ -166,6 +167,13 @@ def bfs_sync(ws: int) -> None:
     _lib.check(_lib.load().bfs_sync(ws), "bfs_sync")
 
 
+def bfs_run_status(ws: int) -> int:
+    """Device status of the last run (needs BFS_OPT_HOST_STATUS); BFSError(BFS_EBUSY) while it runs."""
+    st = ctypes.c_int32()
+    _lib.check(_lib.load().bfs_run_status(ws, ctypes.byref(st)), "bfs_run_status")
+    return int(st.value)
+
+
 def bfs_last_stats(ws: int) -> dict:
     st = bfs_stats_t()
     _lib.check(_lib.load().bfs_last_stats(ws, ctypes.byref(st)), "bfs_last_stats")
@@ -277,7 +285,7 @@ class Workspace:
                  "batch_levels": BFS_OPT_BATCH_LEVELS, "batch_grain": BFS_OPT_BATCH_GRAIN,
                  "batch_tile": BFS_OPT_BATCH_TILE, "bu_alpha": BFS_OPT_BU_ALPHA, "bu_beta": BFS_OPT_BU_BETA,
                  "dense_edges": BFS_OPT_DENSE_EDGES, "split_search": BFS_OPT_SPLIT, "group": BFS_OPT_GROUP,
-                 "batch_replays": BFS_OPT_BATCH_REPLAYS}
+                 "batch_replays": BFS_OPT_BATCH_REPLAYS, "host_status": BFS_OPT_HOST_STATUS}
         for k, v in opts.items():
             bfs_workspace_set_option(self.handle, names[k], v)
 
@@ -314,6 +322,9 @@ class Workspace:
 
     def sync(self):
         bfs_sync(self.handle)
+
+    def run_status(self) -> int:
+        return bfs_run_status(self.handle)
 
     def tuning(self) -> dict:
         return bfs_workspace_get_tuning(self.handle)

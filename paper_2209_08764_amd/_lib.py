@@ -50,6 +50,7 @@ BFS_OPT_DENSE_EDGES = 12
 BFS_OPT_SPLIT = 13
 BFS_OPT_GROUP = 14
 BFS_OPT_BATCH_REPLAYS = 15
+BFS_OPT_HOST_STATUS = 16
 
 BFS_TUNE_BATCH = 1
 BFS_TUNE_SINGLE = 2
@@ -141,6 +142,7 @@ _SIGS = {
     "bfs_probe_rate_kernel": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
                                                ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
     "bfs_workspace_set_spin_ticks": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_uint64]),
+    "bfs_run_status": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
 }
 
 EXPORTED = tuple(_SIGS)

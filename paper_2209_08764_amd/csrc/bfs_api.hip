@@ -187,6 +187,8 @@ struct bfs_workspace_s {
     int32_t batch_pull = -2;  // -2: library default
     int32_t split_search = 0; // BFS_OPT_SPLIT
     uint64_t spin_ticks = 0;  // time limit of the persistent loop's waits (0: kSpinTicks); tests only
+    bool host_status_copy = false;  // BFS_OPT_HOST_STATUS
+    bool status_copied = false;  // the last run copied its status to h_ctrl->error
     // last run
     int32_t last_mode = 0;
     int32_t last_grid = 0;
@@ -622,6 +624,12 @@ bfs_status_t run_common(bfs_workspace_s* ws, const int32_t* roots_host, int32_t 
         st = BFS_OK;
     }
     ws->host_status = st;
+    // the run's device status into the pinned block, in stream order, for bfs_run_status
+    ws->status_copied = false;
+    if (st == BFS_OK && ws->host_status_copy) {
+        HIP_TRY(hipMemcpyAsync(&ws->h_ctrl->error, &ws->ctrl->error, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        ws->status_copied = true;
+    }
     HIP_TRY(hipEventRecord(ws->ev_done, s));
     ws->last_stream = s;
     ws->has_run = true;
@@ -1226,6 +1234,10 @@ bfs_status_t bfs_workspace_set_option(bfs_workspace_t ws, int32_t option, int64_
             if (value < 0 || value > INT32_MAX) return fail(BFS_EINVAL, "bad dense threshold");
             ws->dense_edges = (int32_t)value;
             return BFS_OK;
+        case BFS_OPT_HOST_STATUS:
+            if (value != 0 && value != 1) return fail(BFS_EINVAL, "BFS_OPT_HOST_STATUS is 0 or 1");
+            ws->host_status_copy = value != 0;
+            return BFS_OK;
         case BFS_OPT_BATCH_REPLAYS:
             if (value < -1 || value > 256) return fail(BFS_EINVAL, "replays per batched run must be in [-1, 256]");
             ws->batch_replays = (int32_t)value;
@@ -1355,6 +1367,27 @@ bfs_status_t bfs_sync(bfs_workspace_t ws) {
         return fail(BFS_EDEVICE, "device-side failure (code %d: %s)", ws->h_ctrl->error,
                     ws->h_ctrl->error == -9 ? "malformed frontier" : "a wait timed out");
     if (ws->h_ctrl->batch_overflow) return fail(BFS_EOVERFLOW, "batched search reached level 255");
+    return BFS_OK;
+}
+
+bfs_status_t bfs_run_status(bfs_workspace_t ws, int32_t* status) {
+    if (!ws || !status) return fail(BFS_EINVAL, "null argument");
+    if (!ws->has_run) {
+        *status = BFS_OK;
+        return BFS_OK;
+    }
+    if (ws->host_status != BFS_OK) {
+        *status = ws->host_status;
+        return BFS_OK;
+    }
+    if (!ws->status_copied)
+        return fail(BFS_EINVAL, "the last run was batched or launched without BFS_OPT_HOST_STATUS");
+    HIP_TRY(hipSetDevice(ws->device));
+    const hipError_t q = hipEventQuery(ws->ev_done);
+    if (q == hipErrorNotReady) return fail(BFS_EBUSY, "the run is still in flight");
+    if (q != hipSuccess) return fail(BFS_EHIP, "hipEventQuery: %s", hipGetErrorString(q));
+    const int32_t e = __atomic_load_n(&ws->h_ctrl->error, __ATOMIC_ACQUIRE);
+    *status = e ? BFS_EDEVICE : BFS_OK;
     return BFS_OK;
 }
 
@@ -1552,6 +1585,7 @@ bfs_status_t bfs_run_batch(bfs_workspace_t ws, const int32_t* sources, int32_t k
     ws->last_stream = s;
     ws->has_run = true;
     ws->last_batch = true;
+    ws->status_copied = false;
     return BFS_OK;
 }
 

@@ -331,9 +331,11 @@ class GpuExecutor:
                                         ws_bytes_batch=bfs_workspace_bytes(G.handle, 256))
 
     def create(self, name, kind):
-        from . import BFS_OPT_GRID
+        from . import BFS_OPT_GRID, BFS_OPT_HOST_STATUS
         ws = self.Workspace(self.graphs[name], max_sources=kind)
         ws.set(BFS_OPT_GRID, self.grid)
+        if kind == 1:  # single runs leave their device status where collect reads it without a wait
+            ws.set(BFS_OPT_HOST_STATUS, 1)
         ws.name = name
         return ws
 
@@ -384,7 +386,11 @@ class GpuExecutor:
         self.abandon(h)
         if k == 1:
             # the levels are complete in stream order; a host synchronisation per query would
-            # also wait for whatever shares a hardware queue with the workspace's private stream
+            # also wait for whatever shares a hardware queue with the workspace's private stream,
+            # so the run's device status comes from the copy it made before t1, without a wait
+            st = ws.run_status()
+            if st != _lib.BFS_OK:
+                raise BFSError(st, "bfs_run", "device-side failure of a single run")
             return [out]
         try:
             ws.sync()            # a batch's overflow (and device-side failures) surface here

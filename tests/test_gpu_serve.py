@@ -68,3 +68,35 @@ def test_budget_below_two_workspaces(setup):
         assert np.array_equal(q.result.cpu().numpy(), oracle.bfs_levels(g.offsets, g.cols, q.source))
     assert sch.used <= budget
     sch.close()
+
+
+def test_device_failures_of_single_runs_fail_their_queries_only():
+    # the single-run workspaces of one graph get a 1-tick limit on their waits, so every single
+    # run there fails on the device; the executor reads that status without a host wait and the
+    # scheduler answers those queries with an error while it keeps serving the other graph
+    from paper_2209_08764_amd import _lib
+    graphs = {"big": gg.rmat(20, seed=73), "small": gg.rmat(12, seed=5)}
+    ex = GpuExecutor(graphs, max_inflight=2)
+    create = ex.create
+
+    def create_failing(name, kind):
+        ws = create(name, kind)
+        if name == "big" and kind == 1:
+            _lib.check(_lib.load().bfs_workspace_set_spin_ticks(ws.handle, 1), "bfs_workspace_set_spin_ticks")
+        return ws
+
+    ex.create = create_failing
+    nonisolated = {k: np.flatnonzero(np.diff(g.offsets)) for k, g in graphs.items()}
+    qs = poisson_queries(graphs, nonisolated, rate=200.0, count=24, seed=19)
+    sch = Scheduler(ex, budget_bytes=4 << 30, max_inflight=2)
+    sch.run(qs)
+    torch.cuda.synchronize()
+    failed = [q for q in qs if q.error is not None]
+    assert failed and all(q.graph == "big" and not q.batched for q in failed), [(q.graph, q.error) for q in failed]
+    assert sch.stats["failed_queries"] == len(failed)
+    for q in qs:
+        if q.error is None:
+            g = graphs[q.graph]
+            assert np.array_equal(q.result.cpu().numpy(), oracle.bfs_levels(g.offsets, g.cols, q.source)), q.qid
+    assert any(q.graph == "small" and q.error is None for q in qs)
+    sch.close()

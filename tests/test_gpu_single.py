@@ -331,3 +331,28 @@ def test_a_wait_that_times_out_is_reported_and_the_next_run_is_clean():
     lv, par = run_single(ws, s)
     assert_same(lv, par, g, [s])
     assert ws.stats()["status"] == 0
+
+
+def test_run_status_reads_the_device_status_without_a_wait():
+    from paper_2209_08764_amd import BFSError, _lib
+    g = gg.rmat(20, seed=75)
+    G = Graph(g.offsets, g.cols)
+    s = int(gg.pick_sources(g, 1, seed=76)[0])
+    plain = Workspace(G)
+    plain.run(s)
+    torch.cuda.synchronize()
+    with pytest.raises(BFSError) as err:        # the option was not set for that run
+        plain.run_status()
+    assert err.value.status == _lib.BFS_EINVAL
+    ws = Workspace(G, host_status=1)
+    ws.run(s)
+    torch.cuda.synchronize()
+    assert ws.run_status() == _lib.BFS_OK
+    _lib.check(_lib.load().bfs_workspace_set_spin_ticks(ws.handle, 1), "bfs_workspace_set_spin_ticks")
+    ws.run(s)
+    torch.cuda.synchronize()
+    assert ws.run_status() == _lib.BFS_EDEVICE
+    _lib.check(_lib.load().bfs_workspace_set_spin_ticks(ws.handle, 0), "bfs_workspace_set_spin_ticks")
+    lv, par = run_single(ws, s)
+    assert ws.run_status() == _lib.BFS_OK
+    assert_same(lv, par, g, [s])
