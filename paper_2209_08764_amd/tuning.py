@@ -2,13 +2,15 @@
 
 The search itself runs in the library (bfs_autotune times real runs of the
 workspace's graph and keeps the fastest settings).  This module only
-remembers the outcome per (device, graph shape, batch size) in a JSON file,
-so a later process applies the stored settings without timing anything.
-Settings never change results, only speed, so a stale or mismatched entry
-costs time at worst.
+remembers the outcome per (device, graph shape, batch size, kernel code) in
+a JSON file, so a later process applies the stored settings without timing
+anything.  Settings never change results, only speed, so a stale or
+mismatched entry costs time at worst.
 """
 from __future__ import annotations
 
+import functools
+import hashlib
 import json
 import os
 
@@ -43,9 +45,28 @@ def device_signature() -> str:
     return f"{arch.split(':')[0]}/{props.multi_processor_count}cu"
 
 
+_KERNEL_SOURCES = ("bfs_kernels.hip", "bfs_batch.hip", "bfs_device.h", "bfs_internal.h")
+
+
+@functools.lru_cache(maxsize=1)
+def code_signature() -> str:
+    """The kernels a tuning is timed with: a hash of their sources as the package ships them
+    (empty without them), so that settings tuned for other kernels are timed again."""
+    csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+    h = hashlib.sha256()
+    for name in _KERNEL_SOURCES:
+        try:
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(f.read())
+        except OSError:
+            return ""
+    return h.hexdigest()[:12]
+
+
 def cache_key(ws, k: int, batch: bool) -> str:
     kind = f"batch{k}" if batch else "single"
-    return f"{device_signature()}|{graph_signature(ws.graph)}|{kind}"
+    code = code_signature()
+    return f"{device_signature()}|{graph_signature(ws.graph)}|{kind}" + (f"|code={code}" if code else "")
 
 
 def _load(path):

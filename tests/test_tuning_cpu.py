@@ -50,7 +50,7 @@ def test_first_call_times_and_stores_then_reuses(calls, tmp_path):
     assert not r1["cached"] and calls["tune"] == [(1234, [0, 1, 3], _lib.BFS_TUNE_BATCH)]
     stored = json.load(open(cache))
     (key,) = stored
-    assert key.endswith("|n=4,m=6,iso=1,dmax=3,d2=14|batch3")
+    assert f"|n=4,m=6,iso=1,dmax=3,d2=14|batch3|code={tuning.code_signature()}" in key
     r2 = tuning.autotune(_ws([1, 2, 0, 3]), [3, 1, 0], cache=cache)
     assert r2["cached"] and len(calls["tune"]) == 1
     applied = {o: v for _, o, v in calls["set"]}
@@ -75,3 +75,18 @@ def test_unreadable_cache_is_ignored(calls, tmp_path):
     p.write_text("{not json")
     r = tuning.autotune(_ws([1, 2]), [0, 1], cache=str(p))
     assert not r["cached"] and len(json.load(open(p))) == 1
+
+
+def test_code_signature_hashes_the_shipped_kernels():
+    sig = tuning.code_signature()
+    assert len(sig) == 12 and int(sig, 16) >= 0
+
+
+def test_entries_of_other_kernel_code_are_timed_again(calls, tmp_path, monkeypatch):
+    cache = str(tmp_path / "t.json")
+    monkeypatch.setattr(tuning, "code_signature", lambda: "aaaaaaaaaaaa")
+    tuning.autotune(_ws([1, 2, 0, 3]), [0, 1, 3], cache=cache)
+    assert tuning.autotune(_ws([1, 2, 0, 3]), [0, 1, 3], cache=cache)["cached"]
+    monkeypatch.setattr(tuning, "code_signature", lambda: "bbbbbbbbbbbb")
+    assert not tuning.autotune(_ws([1, 2, 0, 3]), [0, 1, 3], cache=cache)["cached"]
+    assert len(calls["tune"]) == 2 and len(json.load(open(cache))) == 2
